@@ -1,0 +1,186 @@
+"""Benchmark of the Friends-of-Friends hot path on one MI355X.
+
+A step is one pass of the whole hot path over the resident input: fof_build_grid (cell
+binning) + fof_link (labels) + fof_groups (catalogue with centres of mass).  The default
+workload is the 512^3 Zel'dovich box with 50,000 NFW clumps (L = 512, b = 0.2, min size 20).
+
+Prints ONE JSON line (rank 0) with the metric, the per-stage times, the HBM roofline of the
+link pass and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--config 2] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per particle (what the method must move): link reads the sorted
+# position (12) and the original index (4) and writes one label (4).
+LINK_BYTES_PER_PARTICLE = 20
+BUILD_BYTES_PER_PARTICLE = 28
+GROUPS_BYTES_PER_PARTICLE = 20
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(box, zmax):
+    """The oracle as it stands, single-threaded, on the particles with z < zmax treated as a
+    periodic 512 x 512 x zmax box (same density, clumps and linking length)."""
+    import numpy as np
+
+    import oracle
+
+    sel = box.pos[:, 2] < np.float32(zmax)
+    pos = np.ascontiguousarray(box.pos[sel])
+    L = (box.L[0], box.L[1], float(zmax))
+    t0 = time.perf_counter()
+    root, _ = oracle.fof(pos, L, box.b)
+    oracle.groups(pos, root, L, box.min_size)
+    dt = time.perf_counter() - t0
+    return dict(value=pos.shape[0] / dt / 1e6, unit="Mparticles/s", cores=1, kind="oracle",
+                seconds=round(dt, 3),
+                sample=f"particles with z < {zmax} of the same box ({pos.shape[0]}), "
+                       f"treated as a periodic {L[0]:g}x{L[1]:g}x{L[2]:g} box; labels + groups")
+
+
+def copy_bandwidth(torch, dev, nbytes=2 << 30):
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 5 / 1e3
+    del a, b
+    return 2 * nbytes / t / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-zmax", type=float, default=32.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2510_26851_amd import Plan
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    box = W.make(args.config)
+    log(f"generated {box.name}: n={box.n} L={box.L} b={box.b} in {time.perf_counter() - t0:.1f}s")
+
+    pos = torch.from_numpy(box.pos).to(dev)
+    vel = torch.from_numpy(box.vel).to(dev) if box.vel is not None else None
+    plan = Plan([box.n], [(box.L, box.b)], device=dev)
+    root = torch.empty(box.n, dtype=torch.int32, device=dev)
+    cap = box.n
+    out = dict(group_id=torch.empty(box.n, dtype=torch.int32, device=dev),
+               n_groups=torch.empty(1, dtype=torch.int32, device=dev),
+               sizes=torch.empty(cap, dtype=torch.int32, device=dev),
+               com=torch.empty((cap, 3), dtype=torch.float64, device=dev))
+    if vel is not None:
+        out["vmean"] = torch.empty((cap, 3), dtype=torch.float64, device=dev)
+        out["sigv"] = torch.empty(cap, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+
+    def step(e=None):
+        if e:
+            e[0].record(stream)
+        plan.build_grid(pos)
+        if e:
+            e[1].record(stream)
+        plan.link(root)
+        if e:
+            e[2].record(stream)
+        plan.groups(box.min_size, vel=vel, cap=cap, out=out)
+        if e:
+            e[3].record(stream)
+
+    for k in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {k + 1}/{args.warmup} done")
+    if plan.status() != 0:
+        raise SystemExit(f"device status {plan.status()}")
+    ng = int(out["n_groups"].item())
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {wall:.3f}s")
+
+    st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
+                   for e in ev])
+    build_ms, link_ms, groups_ms = (float(np.median(st[:, j])) for j in range(3))
+    link_mean_ms = float(np.mean(st[:, 1]))
+    ms_per_step = wall / args.steps * 1e3
+    value = box.n / (ms_per_step / 1e3) / 1e6
+    achieved = LINK_BYTES_PER_PARTICLE * box.n / (link_mean_ms / 1e3) / 1e9
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"copy bandwidth {copy_gbs:.0f} GB/s")
+
+    line = {
+        "metric": "Mparticles/s end-to-end FoF (build_grid + link + groups)",
+        "value": round(value, 2),
+        "unit": "Mparticles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": box.name, "n": box.n, "L": box.L[0], "b": box.b,
+                   "min_size": box.min_size, "n_groups": ng},
+        "stages_ms": {"build_grid": round(build_ms, 4), "link": round(link_ms, 4),
+                      "groups": round(groups_ms, 4)},
+        "hbm_frac_end_to_end": round((BUILD_BYTES_PER_PARTICLE + LINK_BYTES_PER_PARTICLE +
+                                      GROUPS_BYTES_PER_PARTICLE) * box.n /
+                                     (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": {"kernel": "fof_link (k_link + k_compress)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_particle": LINK_BYTES_PER_PARTICLE,
+                     "avg_ms": round(link_mean_ms, 4)},
+        "copy_gbs": round(copy_gbs, 1),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        line["cpu_baseline"] = cpu_baseline(box, args.cpu_zmax)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * fof.h -- C ABI of the MI355X Friends-of-Friends library (libfof.so).
+ *
+ * The library finds Friends-of-Friends groups in periodic boxes of float32 particles: two
+ * particles are friends when their minimum-image separation is below the linking length b,
+ * and groups are the connected components of the friend relation (paper: Sec. 2, steps
+ * (i)-(vi); Sec. 2.2 linked-cell grid; Alg. 2).  The forward pass is exact; gradients
+ * (Sec. 3) are separate calls.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked (dev) are device pointers on the device that owns `stream`; pointers
+ *    marked (host) are host memory.  The caller owns every buffer.  No call allocates,
+ *    frees, synchronises or prints: all device work is enqueued on `stream` (a hipStream_t
+ *    passed as void*; NULL = the default stream).
+ *  - Return value: FOF_OK (0) or a negative FOF_E* code.  Argument errors are detected on the
+ *    host before anything is enqueued.  Data errors that only the device can see
+ *    (coordinates outside [0, L) or NaN) set bits of the device status word (fof_status).
+ *  - Particle indices are int32: n <= 2^31 - 1 in total.
+ *  - Several boxes can be processed in one call ("batch"): box k owns the particles
+ *    [offset_k, offset_k + count_k) of the concatenated arrays, with offset_0 = 0 and
+ *    offset_{k+1} = offset_k + count_k.  A single box is the batch of one.  Components never
+ *    span boxes; labels are global indices into the concatenated arrays.
+ */
+#ifndef FOF_H
+#define FOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FOF_OK 0
+#define FOF_EINVAL (-1)     /* bad argument (null pointer, n out of range, b or L invalid)   */
+#define FOF_ENOMEM (-2)     /* workspace smaller than fof_workspace_bytes asked for          */
+#define FOF_EOVERFLOW (-3)  /* more groups than `cap`; counts still hold the true totals    */
+#define FOF_EDEVICE (-4)    /* a HIP launch failed                                            */
+#define FOF_ENOTSUP (-5)    /* option not supported by this build                             */
+
+/* Bits of the device status word (see fof_status). */
+#define FOF_STATUS_RANGE 1u     /* some coordinate was NaN or outside [0, L)                  */
+#define FOF_STATUS_DENSE_CAP 2u /* dense-cell tables overflowed; those cells took the plain path */
+
+/* One periodic box: side lengths L (physical) and the physical linking length b.
+ * Requirements: L[c] finite and > 0, b finite and > 0, 2 b < L[c] for every axis (so that
+ * within b the minimum image of a pair is unique).  The dimensionless form
+ * b_phys = b_dimless * (V/N)^(1/3) (paper Sec. 2 step (ii)) is the caller's business. */
+typedef struct fof_box {
+    double L[3];
+    double b;
+} fof_box;
+
+/* Tuning knobs.  Zero fields take defaults.  None of them changes any result. */
+typedef struct fof_tune {
+    double cell_side;        /* requested coarse cell side; raised to b plus a rounding margin */
+    int32_t dense_threshold; /* cells holding more particles take the clique-cell path;
+                                0 = default, < 0 = never                                      */
+    int32_t block;           /* threads per block for per-particle kernels (multiple of 64)    */
+    uint32_t flags;          /* reserved, must be 0                                            */
+    int32_t reserved;
+} fof_tune;
+
+/* Host-side plan of one batch: filled by fof_workspace_bytes, then passed unchanged to the
+ * other calls.  Plain data; the byte offsets locate the regions of the caller's workspace. */
+typedef struct fof_grid {
+    int32_t nbox;
+    int32_t block;
+    int64_t n;            /* total particles                                                  */
+    int64_t ncell;        /* total coarse cells over all boxes                                */
+    int64_t dense_cap;    /* dense cells that can get clique tables                           */
+    int32_t dense_threshold;
+    int32_t table_words;  /* 32-bit words of one clique bitmask                               */
+    size_t ws_bytes;      /* size of the workspace the caller must provide                    */
+    size_t desc_bytes;    /* size of the box descriptor block                                 */
+    size_t off_desc;      /* where the caller copies the descriptor block (see below)         */
+    size_t off_status, off_counters, off_cell_count, off_cell_start, off_rank, off_sorted,
+        off_parent, off_flags, off_keep, off_scan, off_dense, off_units, off_table, off_aux;
+} fof_grid;
+
+/* Plans a batch of `nbox` boxes with count[k] particles each (host arrays).  Fills *grid.
+ * If `desc` (host) is not NULL it must hold grid->desc_bytes bytes (call once with NULL to
+ * learn the size): it receives the packed box descriptors, which the caller must copy into
+ * the workspace at byte offset grid->off_desc before fof_build_grid runs (the library never
+ * copies host memory itself).  Errors: FOF_EINVAL for a bad box, count < 0, a total above
+ * 2^31 - 1, or a `desc` buffer smaller than desc_bytes. */
+int fof_workspace_bytes(int32_t nbox, const int64_t *count /*host*/, const fof_box *box /*host*/,
+                        const fof_tune *tune /*host, may be NULL*/, fof_grid *grid /*host*/,
+                        void *desc /*host or NULL*/, size_t desc_cap);
+
+/* Cell binning (paper Alg. 2: cell indexing with x fastest, sort by cell).  pos (dev) is
+ * float32 [n][3] (x, y, z per particle, AoS), every coordinate in [0, L) of its box.
+ * Builds, inside ws (dev, grid->ws_bytes bytes, 256-byte aligned), the per-cell offsets and
+ * the cell-sorted particle copy used by fof_link and fof_groups.  Clears the status word. */
+int fof_build_grid(const fof_grid *grid, const float *pos /*dev*/, void *ws /*dev*/,
+                   void *stream);
+
+/* Friends-of-Friends labels (paper Sec. 2 steps (iii)-(v); Alg. 2 candidate search, minimum
+ * image filter and label propagation, run here to convergence as a union-find).
+ * root (dev, int32 [n]) receives, for every particle i, the smallest index j in the
+ * connected component of i (so root[root[i]] == root[i]).  The link predicate is exact:
+ * per axis d = (double)x_i - (double)x_j wrapped once by +-L when |d| > L/2, then
+ * ((dx*dx + dy*dy) + dz*dz) < b*b in IEEE double without fused multiply-add.
+ * `sample` must be NULL (hard linking); any other value returns FOF_ENOTSUP. */
+int fof_link(const fof_grid *grid, void *ws /*dev*/, const void *sample /*must be NULL*/,
+             int32_t *root /*dev*/, void *stream);
+
+/* Group catalogue (paper Sec. 2 step (vi); Alg. 2 compaction; Sec. 3.1 halo position).
+ * Must follow fof_link on the same workspace.  Components with at least min_size members
+ * are kept and numbered 0..G-1 in ascending order of their label (the smallest member
+ * index); group_id (dev, int32 [n]) gets that number, or -1 for particles of cut
+ * components.  *n_groups (dev, one int32) receives G.  For g < min(G, cap):
+ *   sizes[g] (dev int32)       member count
+ *   com[g][3] (dev double)     centre of mass: members unwrapped about the label particle
+ *                              by minimum image, averaged, wrapped into [0, L)
+ *   vmean[g][3], sigv[g]       (dev double, only when vel != NULL) mean velocity and the
+ *                              1-D dispersion sqrt(sum_i sum_c (v_ic - vmean_c)^2 / (3 n))
+ * vel (dev) is float32 [n][3] or NULL; vmean and sigv may be NULL when vel is NULL.
+ * Returns FOF_OK even when G > cap: the device cannot report that without a sync, so the
+ * caller compares *n_groups with cap (group ids >= cap then have no table entries). */
+int fof_groups(const fof_grid *grid, void *ws /*dev*/, int32_t min_size, const float *vel,
+               int32_t cap, int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
+               double *vmean, double *sigv, void *stream);
+
+/* Frozen-assignment backward (paper Sec. 3.1 and its table of differentiation modes):
+ * memberships from the forward are held fixed, gradients flow only through member
+ * positions and velocities.  With upstream gradients g_mass[G], g_com[G][3], g_sigv[G]
+ * (dev double; any may be NULL = zero) of the forward outputs mass_g = n_g, com, sigv:
+ *   grad_pos[i][c] = g_com[g][c] / n_g                        (mass has zero gradient)
+ *   grad_vel[i][c] = g_sigv[g] (v_ic - vmean[g][c]) / (3 n_g sigv[g])   (0 if sigv[g] = 0)
+ * where g = group_id[i]; particles with g < 0 or g >= G get zeros.  sizes, vmean, sigv are
+ * the forward's outputs; G is the number of groups the tables hold (<= cap).  grad_pos and
+ * grad_vel (dev float32 [n][3]) may be NULL to skip them; vel is needed for grad_vel. */
+int fof_backward(const fof_grid *grid, const int32_t *group_id /*dev*/, int32_t G,
+                 const int32_t *sizes /*dev*/, const double *vmean /*dev*/,
+                 const double *sigv /*dev*/, const float *vel /*dev*/, const double *g_mass,
+                 const double *g_com, const double *g_sigv, float *grad_pos, float *grad_vel,
+                 void *stream);
+
+/* Device address of the int32 status word inside ws (FOF_STATUS_* bits; 0 = clean).  It is
+ * cleared by fof_build_grid; read it after synchronising the stream. */
+int fof_status(const fof_grid *grid, void *ws /*dev*/, int32_t **status /*host out: dev ptr*/);
+
+/* Static text for a FOF_E* code. */
+const char *fof_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FOF_H */

@@ -1,0 +1,88 @@
+"""ctypes view of libfof.so (include/fof.h).  Argument marshalling only.
+
+The library must have been built (``python paper_2510_26851_amd/build.py`` or
+``__graft_entry__.build()``); importing this module without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfof.so")
+
+FOF_OK = 0
+FOF_EINVAL = -1
+FOF_ENOMEM = -2
+FOF_EOVERFLOW = -3
+FOF_EDEVICE = -4
+FOF_ENOTSUP = -5
+FOF_STATUS_RANGE = 1
+FOF_STATUS_DENSE_CAP = 2
+
+# Every symbol include/fof.h declares.
+EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",
+           "fof_status", "fof_strerror")
+
+
+class fof_box(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double * 3), ("b", ctypes.c_double)]
+
+
+class fof_tune(ctypes.Structure):
+    _fields_ = [("cell_side", ctypes.c_double), ("dense_threshold", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
+class fof_grid(ctypes.Structure):
+    _fields_ = [("nbox", ctypes.c_int32), ("block", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("ncell", ctypes.c_int64), ("dense_cap", ctypes.c_int64),
+                ("dense_threshold", ctypes.c_int32), ("table_words", ctypes.c_int32),
+                ("ws_bytes", ctypes.c_size_t), ("desc_bytes", ctypes.c_size_t),
+                ("off_desc", ctypes.c_size_t)] + [
+                   (f, ctypes.c_size_t) for f in (
+                       "off_status", "off_counters", "off_cell_count", "off_cell_start",
+                       "off_rank", "off_sorted", "off_parent", "off_flags", "off_keep",
+                       "off_scan", "off_dense", "off_units", "off_table", "off_aux")]
+
+
+class FoFError(RuntimeError):
+    def __init__(self, fn, code):
+        self.code = code
+        super().__init__(f"{fn} failed: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.fof_workspace_bytes.argtypes = [i32, P, P, P, P, P, sz]
+    L.fof_build_grid.argtypes = [P, P, P, P]
+    L.fof_link.argtypes = [P, P, P, P, P]
+    L.fof_groups.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P, P]
+    L.fof_backward.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, P, P]
+    L.fof_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_void_p)]
+    L.fof_strerror.argtypes = [ctypes.c_int]
+    L.fof_strerror.restype = ctypes.c_char_p
+    for f in EXPORTS:
+        if f != "fof_strerror":
+            getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return load().fof_strerror(int(code)).decode()
+
+
+def check(fn: str, code: int):
+    if code != FOF_OK:
+        raise FoFError(fn, code)

@@ -1,0 +1,293 @@
+// Host entry points of libfof.so (declared in include/fof.h): planning, argument
+// validation and kernel launches.  Nothing here allocates, frees, synchronises or prints.
+#include <math.h>
+#include <string.h>
+
+#include "fof_internal.h"
+
+namespace fof {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Bound on how far a float32 cell index can move a coordinate: the computed fine cell of
+// x is the exact cell of some x' with |x' - x| <= L 2^-23 (1 + 2^-10) (one rounding of the
+// scale factor to float32 and one of the product).  `reach` adds the rounding of the
+// float32 face distance (< 1.5 L 2^-23) on top, with room to spare.
+double index_eps(double Lmax) { return ldexp(Lmax, -23) * (1.0 + ldexp(1.0, -10)); }
+double reach_of(double b, double Lmax) { return b + 4.0 * ldexp(Lmax, -23); }
+
+float round_up_f(double v)
+{
+    float f = (float)v;
+    if ((double)f < v)
+        f = nextafterf(f, INFINITY);
+    return f;
+}
+
+bool box_ok(const fof_box &bx)
+{
+    if (!(bx.b > 0.0) || !isfinite(bx.b))
+        return false;
+    for (int a = 0; a < 3; ++a)
+        if (!(bx.L[a] > 0.0) || !isfinite(bx.L[a]) || !(2.0 * bx.b < bx.L[a]))
+            return false;
+    return true;
+}
+
+// Per-box plan: coarse cells per axis and fine cells per coarse cell.
+int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_base, int64_t off,
+             BoxDesc *d)
+{
+    const double Lmax = fmax(bx.L[0], fmax(bx.L[1], bx.L[2]));
+    const double V = bx.L[0] * bx.L[1] * bx.L[2];
+    const double reach = reach_of(bx.b, Lmax);
+    const double eps = index_eps(Lmax);
+    // Largest clique cell side: any two points of one fine cell (each placed within eps of
+    // its exact cell) are closer than 0.999 b.
+    const double a_max = 0.999 * bx.b / sqrt(3.0) - 2.0 * eps;
+    if (!(a_max > 0.0))
+        return FOF_EINVAL;
+    double s = (tune && tune->cell_side > 0.0) ? tune->cell_side
+                                               : (n > 0 ? cbrt(V / (double)n) : Lmax);
+    // never more than about 8 coarse cells per particle
+    s = fmax(s, cbrt(V / (8.0 * (double)n + 64.0)));
+    double side_max = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        // cells per axis: from the requested side, then at least enough that a cell holds
+        // at most kMaxFine clique cells, and at most as many as keep the side >= reach
+        double q = floor(bx.L[a] / s);
+        double q_min = ceil(bx.L[a] / ((double)kMaxFine * a_max));
+        double q_max = floor(bx.L[a] / reach);
+        q = fmax(q, q_min);
+        q = fmin(q, q_max);
+        int64_t nc = q < 1.0 ? 1 : (int64_t)q;
+        if (nc > (1 << 20) || (nc > 1 && bx.L[a] / (double)nc < reach))
+            return FOF_EINVAL;
+        d->nc[a] = (int32_t)nc;
+        side_max = fmax(side_max, bx.L[a] / (double)nc);
+    }
+    int m = (int)ceil(side_max / a_max);
+    if (m < 1)
+        m = 1;
+    if (m > kMaxFine)
+        return FOF_EINVAL;
+    d->m = m;
+    d->off = off;
+    d->n = (int32_t)n;
+    d->cell_base = cell_base;
+    for (int a = 0; a < 3; ++a) {
+        d->nf[a] = d->nc[a] * m;
+        d->L[a] = bx.L[a];
+        d->halfL[a] = 0.5 * bx.L[a];
+        d->inv_fine[a] = (float)((double)d->nf[a] / bx.L[a]);
+        d->side[a] = (float)(bx.L[a] / (double)d->nc[a]);
+    }
+    d->b2 = bx.b * bx.b;
+    d->reach = round_up_f(reach);
+    d->pad = 0.0f;
+    return FOF_OK;
+}
+
+struct Layout {
+    size_t off_desc, off_status, off_cell_count, off_cell_start, off_scan, off_rank, off_sorted,
+        off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, total;
+};
+
+Layout layout(int32_t nbox, int64_t n, int64_t ncell)
+{
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + (bytes ? bytes : 1));
+        return at;
+    };
+    const int64_t nwords = (n + 31) / 32;
+    int64_t scan_n = ncell > nwords ? ncell : nwords;
+    L.off_desc = take(sizeof(BoxDesc) * (size_t)nbox);
+    L.off_status = take(sizeof(Counters));
+    L.off_cell_count = take(sizeof(int32_t) * (size_t)ncell);
+    L.off_cell_start = take(sizeof(int32_t) * (size_t)(ncell + 1));
+    L.off_scan = take(sizeof(int32_t) * (size_t)scan_scratch_elems(scan_n));
+    L.off_rank = take(sizeof(int32_t) * (size_t)n);
+    L.off_sorted = take(sizeof(float4) * (size_t)n);
+    L.off_parent = take(sizeof(uint64_t) * (size_t)n);
+    L.off_flags = take(sizeof(uint64_t) * (size_t)((n + 63) / 64));
+    L.off_keep = take(sizeof(uint32_t) * (size_t)nwords);
+    L.off_keep_prefix = take(sizeof(int32_t) * (size_t)(nwords + 1));
+    L.off_cnt = take(sizeof(int32_t) * (size_t)n);
+    L.off_groot = take(sizeof(int32_t) * (size_t)n);
+    L.total = o;
+    return L;
+}
+
+bool ws_ok(const fof_grid *g, const void *ws)
+{
+    return g && ws && ((uintptr_t)ws % kAlign) == 0 && g->nbox >= 1 && g->n >= 0 &&
+           g->block >= kWave && g->block % kWave == 0 && g->block <= 1024;
+}
+
+Work resolve(const fof_grid *g, void *ws)
+{
+    char *base = (char *)ws;
+    Layout L = layout(g->nbox, g->n, g->ncell);
+    Work w;
+    w.desc = (const BoxDesc *)(base + L.off_desc);
+    w.ctr = (Counters *)(base + L.off_status);
+    w.cell_count = (int32_t *)(base + L.off_cell_count);
+    w.cell_start = (int32_t *)(base + L.off_cell_start);
+    w.scan = (int32_t *)(base + L.off_scan);
+    w.rank = (int32_t *)(base + L.off_rank);
+    w.sorted = (float4 *)(base + L.off_sorted);
+    w.parent = (uint64_t *)(base + L.off_parent);
+    w.flags = (uint64_t *)(base + L.off_flags);
+    w.keep = (uint32_t *)(base + L.off_keep);
+    w.keep_prefix = (int32_t *)(base + L.off_keep_prefix);
+    w.cnt = (int32_t *)(base + L.off_cnt);
+    w.groot = (int32_t *)(base + L.off_groot);
+    w.nbox = g->nbox;
+    w.block = g->block;
+    w.n = g->n;
+    w.ncell = g->ncell;
+    return w;
+}
+
+int dev_err(hipError_t e) { return e == hipSuccess ? FOF_OK : FOF_EDEVICE; }
+
+}  // namespace
+}  // namespace fof
+
+using namespace fof;
+
+extern "C" {
+
+int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
+                        const fof_tune *tune, fof_grid *grid, void *desc, size_t desc_cap)
+{
+    if (nbox < 1 || !count || !box || !grid)
+        return FOF_EINVAL;
+    if (tune && (tune->flags != 0 || tune->block < 0 || (tune->block % kWave) != 0 ||
+                 tune->block > 1024 || !(tune->cell_side >= 0.0)))
+        return FOF_EINVAL;
+    int64_t n = 0, ncell = 0;
+    BoxDesc *out = (BoxDesc *)desc;
+    const size_t need = sizeof(BoxDesc) * (size_t)nbox;
+    if (desc && desc_cap < need)
+        return FOF_EINVAL;
+    for (int32_t k = 0; k < nbox; ++k) {
+        if (count[k] < 0 || !box_ok(box[k]))
+            return FOF_EINVAL;
+        BoxDesc d;
+        memset(&d, 0, sizeof(d));
+        int rc = plan_box(box[k], count[k], tune, ncell, n, &d);
+        if (rc)
+            return rc;
+        n += count[k];
+        ncell += (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+        if (n > INT32_MAX || ncell > ((int64_t)1 << 40))
+            return FOF_EINVAL;
+        if (out)
+            out[k] = d;
+    }
+    Layout L = layout(nbox, n, ncell);
+    memset(grid, 0, sizeof(*grid));
+    grid->nbox = nbox;
+    grid->block = (tune && tune->block) ? tune->block : kDefaultBlock;
+    grid->n = n;
+    grid->ncell = ncell;
+    grid->dense_threshold = -1;
+    grid->ws_bytes = L.total;
+    grid->desc_bytes = need;
+    grid->off_desc = L.off_desc;
+    grid->off_status = L.off_status;
+    grid->off_counters = L.off_status;
+    grid->off_cell_count = L.off_cell_count;
+    grid->off_cell_start = L.off_cell_start;
+    grid->off_rank = L.off_rank;
+    grid->off_sorted = L.off_sorted;
+    grid->off_parent = L.off_parent;
+    grid->off_flags = L.off_flags;
+    grid->off_keep = L.off_keep;
+    grid->off_scan = L.off_scan;
+    return FOF_OK;
+}
+
+int fof_build_grid(const fof_grid *grid, const float *pos, void *ws, void *stream)
+{
+    if (!ws_ok(grid, ws) || (grid->n > 0 && !pos))
+        return FOF_EINVAL;
+    Work w = resolve(grid, ws);
+    return dev_err(launch_build(w, pos, (hipStream_t)stream));
+}
+
+int fof_link(const fof_grid *grid, void *ws, const void *sample, int32_t *root, void *stream)
+{
+    if (sample)
+        return FOF_ENOTSUP;
+    if (!ws_ok(grid, ws) || (grid->n > 0 && !root))
+        return FOF_EINVAL;
+    Work w = resolve(grid, ws);
+    return dev_err(launch_link(w, root, (hipStream_t)stream));
+}
+
+int fof_groups(const fof_grid *grid, void *ws, int32_t min_size, const float *vel, int32_t cap,
+               int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com, double *vmean,
+               double *sigv, void *stream)
+{
+    if (!ws_ok(grid, ws) || !n_groups || cap < 0 || (grid->n > 0 && !group_id) ||
+        (cap > 0 && !sizes))
+        return FOF_EINVAL;
+    if ((vmean == nullptr) != (sigv == nullptr) || (vel == nullptr && vmean != nullptr))
+        return FOF_EINVAL;
+    Work w = resolve(grid, ws);
+    return dev_err(launch_groups(w, min_size, vel, cap, group_id, n_groups, sizes, com, vmean,
+                                 sigv, (hipStream_t)stream));
+}
+
+int fof_backward(const fof_grid *grid, const int32_t *group_id, int32_t G, const int32_t *sizes,
+                 const double *vmean, const double *sigv, const float *vel, const double *g_mass,
+                 const double *g_com, const double *g_sigv, float *grad_pos, float *grad_vel,
+                 void *stream)
+{
+    (void)g_mass;  // the member count has zero gradient with memberships frozen
+    if (!grid || grid->n < 0 || G < 0 || (grid->n > 0 && !group_id) || (G > 0 && !sizes))
+        return FOF_EINVAL;
+    if (grad_vel && g_sigv && (!vel || !vmean || !sigv))
+        return FOF_EINVAL;
+    const int32_t block = grid->block > 0 ? grid->block : kDefaultBlock;
+    return dev_err(launch_backward(grid->n, block, group_id, G, sizes, vmean, sigv, vel, g_com,
+                                   g_sigv, grad_pos, grad_vel, (hipStream_t)stream));
+}
+
+int fof_status(const fof_grid *grid, void *ws, int32_t **status)
+{
+    if (!ws_ok(grid, ws) || !status)
+        return FOF_EINVAL;
+    *status = (int32_t *)((char *)ws + grid->off_status);
+    return FOF_OK;
+}
+
+const char *fof_strerror(int code)
+{
+    switch (code) {
+    case FOF_OK:
+        return "ok";
+    case FOF_EINVAL:
+        return "invalid argument";
+    case FOF_ENOMEM:
+        return "workspace too small";
+    case FOF_EOVERFLOW:
+        return "more groups than the output capacity";
+    case FOF_EDEVICE:
+        return "HIP launch failed";
+    case FOF_ENOTSUP:
+        return "option not supported";
+    default:
+        return "unknown error";
+    }
+}
+
+}  // extern "C"

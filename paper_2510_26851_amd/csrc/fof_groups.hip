@@ -1,0 +1,282 @@
+// Group catalogue (paper Sec. 2 step (vi), Alg. 2 compaction; Sec. 3.1 halo position).
+//
+// Works in cell-sorted order on the state fof_link leaves behind: particles without a
+// friend are singleton components; every flagged particle's union-find entry points
+// straight at its root, whose key is the component label (smallest original index).
+//
+//   g_zero     cnt[i] = 0 for flagged i (every non-singleton root is flagged)
+//   g_count    cnt[root] += 1 for flagged i
+//   g_keep     set keep bit [label] for kept components (size >= min_size)
+//   scan       popcount prefix over the keep bitmap -> group id = rank of the label
+//   g_assign   group_id[orig] for everyone; per kept group: size, root slot, and the
+//              moment accumulators cleared (singleton groups are finished here)
+//   g_sum      FP64 sums of minimum-image offsets from the root and of velocities
+//   g_mean     com = wrap(x_root + sum / n), vmean = vsum / n
+//   g_dev      sum of squared velocity deviations; g_sig: sigv = sqrt(sum / (3 n))
+#include "fof_internal.h"
+
+namespace fof {
+
+namespace {
+
+__device__ __forceinline__ bool flagged(const uint64_t *flags, int64_t i)
+{
+    return (flags[i >> 6] >> (i & 63)) & 1ull;
+}
+
+__device__ __forceinline__ uint32_t root_slot(const uint64_t *parent, const uint64_t *flags,
+                                              int64_t i)
+{
+    return flagged(flags, i) ? uf_idx(parent[i]) : (uint32_t)i;
+}
+
+__device__ __forceinline__ int32_t group_of(const uint32_t *keep, const int32_t *keep_prefix,
+                                            uint32_t label)
+{
+    uint32_t w = keep[label >> 5];
+    uint32_t bit = 1u << (label & 31);
+    if (!(w & bit))
+        return -1;
+    return keep_prefix[label >> 5] + __popc(w & (bit - 1u));
+}
+
+__global__ void g_zero(int64_t n, const uint64_t *__restrict__ flags, int32_t *__restrict__ cnt)
+{
+    int64_t i = gtid();
+    if (i < n && flagged(flags, i))
+        cnt[i] = 0;
+}
+
+__global__ void g_count(int64_t n, const uint64_t *__restrict__ parent,
+                        const uint64_t *__restrict__ flags, int32_t *__restrict__ cnt)
+{
+    int64_t i = gtid();
+    if (i < n && flagged(flags, i))
+        atomicAdd(cnt + uf_idx(parent[i]), 1);
+}
+
+__global__ void g_keep(const float4 *__restrict__ sorted, int64_t n,
+                       const uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
+                       const int32_t *__restrict__ cnt, int32_t min_size,
+                       uint32_t *__restrict__ keep)
+{
+    int64_t i = gtid();
+    if (i >= n)
+        return;
+    int32_t size;
+    if (flagged(flags, i)) {
+        if (uf_idx(parent[i]) != (uint32_t)i)
+            return;  // not a root
+        size = cnt[i];
+    } else {
+        size = 1;
+    }
+    if (size >= min_size) {
+        uint32_t label = (uint32_t)__float_as_int(sorted[i].w);
+        atomicOr(keep + (label >> 5), 1u << (label & 31));
+    }
+}
+
+__global__ void g_assign(const float4 *__restrict__ sorted, int64_t n,
+                         const uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
+                         const int32_t *__restrict__ cnt, const uint32_t *__restrict__ keep,
+                         const int32_t *__restrict__ keep_prefix, const float *__restrict__ vel,
+                         int32_t cap, int32_t *__restrict__ group_id, int32_t *__restrict__ groot,
+                         int32_t *__restrict__ sizes, double *__restrict__ com,
+                         double *__restrict__ vmean, double *__restrict__ sigv)
+{
+    int64_t i = gtid();
+    if (i >= n)
+        return;
+    const float4 p = sorted[i];
+    const int32_t orig = __float_as_int(p.w);
+    const bool fl = flagged(flags, i);
+    const uint32_t rs = fl ? uf_idx(parent[i]) : (uint32_t)i;
+    const uint32_t label = fl ? uf_key(parent[i]) : (uint32_t)orig;
+    const int32_t g = group_of(keep, keep_prefix, label);
+    group_id[orig] = g;
+    if (g < 0 || g >= cap || rs != (uint32_t)i)
+        return;
+    // i is the root of kept group g
+    groot[g] = (int32_t)i;
+    if (fl) {
+        sizes[g] = cnt[i];
+        if (com) {
+            com[3 * g + 0] = 0.0;
+            com[3 * g + 1] = 0.0;
+            com[3 * g + 2] = 0.0;
+        }
+        if (vel) {
+            if (vmean) {
+                vmean[3 * g + 0] = 0.0;
+                vmean[3 * g + 1] = 0.0;
+                vmean[3 * g + 2] = 0.0;
+            }
+            if (sigv)
+                sigv[g] = 0.0;
+        }
+    } else {  // singleton group (min_size <= 1): finished here
+        sizes[g] = 1;
+        if (com) {
+            com[3 * g + 0] = (double)p.x;
+            com[3 * g + 1] = (double)p.y;
+            com[3 * g + 2] = (double)p.z;
+        }
+        if (vel) {
+            if (vmean) {
+                vmean[3 * g + 0] = (double)vel[3 * (int64_t)orig + 0];
+                vmean[3 * g + 1] = (double)vel[3 * (int64_t)orig + 1];
+                vmean[3 * g + 2] = (double)vel[3 * (int64_t)orig + 2];
+            }
+            if (sigv)
+                sigv[g] = 0.0;
+        }
+    }
+}
+
+__global__ void g_sum(const float4 *__restrict__ sorted, int64_t n,
+                      const BoxDesc *__restrict__ desc, int nbox,
+                      const uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
+                      const uint32_t *__restrict__ keep, const int32_t *__restrict__ keep_prefix,
+                      const float *__restrict__ vel, int32_t cap, double *__restrict__ com,
+                      double *__restrict__ vmean)
+{
+    int64_t i = gtid();
+    if (i >= n || !flagged(flags, i))
+        return;
+    const uint64_t r = parent[i];
+    const int32_t g = group_of(keep, keep_prefix, uf_key(r));
+    if (g < 0 || g >= cap)
+        return;
+    const float4 p = sorted[i];
+    if (com) {
+        const BoxDesc &B = desc[find_box(desc, nbox, i)];
+        const float4 q = sorted[uf_idx(r)];
+        atomicAdd(com + 3 * g + 0, min_image((double)p.x - (double)q.x, B.L[0], B.halfL[0]));
+        atomicAdd(com + 3 * g + 1, min_image((double)p.y - (double)q.y, B.L[1], B.halfL[1]));
+        atomicAdd(com + 3 * g + 2, min_image((double)p.z - (double)q.z, B.L[2], B.halfL[2]));
+    }
+    if (vel && vmean) {
+        const int64_t o = __float_as_int(p.w);
+        atomicAdd(vmean + 3 * g + 0, (double)vel[3 * o + 0]);
+        atomicAdd(vmean + 3 * g + 1, (double)vel[3 * o + 1]);
+        atomicAdd(vmean + 3 * g + 2, (double)vel[3 * o + 2]);
+    }
+}
+
+__global__ void g_mean(const float4 *__restrict__ sorted, const BoxDesc *__restrict__ desc,
+                       int nbox, const int32_t *__restrict__ n_groups, int32_t cap,
+                       const int32_t *__restrict__ groot, const int32_t *__restrict__ sizes,
+                       const float *__restrict__ vel, double *__restrict__ com,
+                       double *__restrict__ vmean)
+{
+    int64_t g = gtid();
+    int32_t G = *n_groups < cap ? *n_groups : cap;
+    if (g >= G)
+        return;
+    const int32_t r = groot[g];
+    const int32_t nn = sizes[g];
+    if (nn <= 1)
+        return;  // singleton groups were written by g_assign
+    const double dn = (double)nn;
+    if (com) {
+        const BoxDesc &B = desc[find_box(desc, nbox, r)];
+        const float4 q = sorted[r];
+        const float qc[3] = {q.x, q.y, q.z};
+        for (int a = 0; a < 3; ++a) {
+            double v = (double)qc[a] + com[3 * g + a] / dn;
+            if (v >= B.L[a])
+                v -= B.L[a];
+            if (v < 0.0)
+                v += B.L[a];
+            com[3 * g + a] = v;
+        }
+    }
+    if (vel && vmean)
+        for (int a = 0; a < 3; ++a)
+            vmean[3 * g + a] = vmean[3 * g + a] / dn;
+}
+
+__global__ void g_dev(const float4 *__restrict__ sorted, int64_t n,
+                      const uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
+                      const uint32_t *__restrict__ keep, const int32_t *__restrict__ keep_prefix,
+                      const float *__restrict__ vel, int32_t cap,
+                      const double *__restrict__ vmean, double *__restrict__ sigv)
+{
+    int64_t i = gtid();
+    if (i >= n || !flagged(flags, i))
+        return;
+    const int32_t g = group_of(keep, keep_prefix, uf_key(parent[i]));
+    if (g < 0 || g >= cap)
+        return;
+    const int64_t o = __float_as_int(sorted[i].w);
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double d = (double)vel[3 * o + a] - vmean[3 * g + a];
+        s += d * d;
+    }
+    atomicAdd(sigv + g, s);
+}
+
+__global__ void g_sig(const int32_t *__restrict__ n_groups, int32_t cap,
+                      const int32_t *__restrict__ sizes, double *__restrict__ sigv)
+{
+    int64_t g = gtid();
+    int32_t G = *n_groups < cap ? *n_groups : cap;
+    if (g >= G)
+        return;
+    const int32_t nn = sizes[g];
+    if (nn > 1)
+        sigv[g] = sqrt(sigv[g] / (3.0 * (double)nn));
+}
+
+__global__ void g_total(const int32_t *__restrict__ keep_prefix, int64_t nwords,
+                        int32_t *__restrict__ n_groups)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *n_groups = keep_prefix[nwords];
+}
+
+}  // namespace
+
+hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int32_t cap,
+                         int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
+                         double *vmean, double *sigv, hipStream_t s)
+{
+    const int64_t nwords = (w.n + 31) / 32;
+    hipError_t e = launch_fill_u32(w.keep, nwords, 0u, s);
+    if (e != hipSuccess)
+        return e;
+    const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
+    if (w.n > 0) {
+        hipLaunchKernelGGL(g_zero, dim3(nb), dim3(w.block), 0, s, w.n, w.flags, w.cnt);
+        hipLaunchKernelGGL(g_count, dim3(nb), dim3(w.block), 0, s, w.n, w.parent, w.flags, w.cnt);
+        hipLaunchKernelGGL(g_keep, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent,
+                           w.flags, w.cnt, min_size, w.keep);
+    }
+    e = launch_scan_popc(w.keep, w.keep_prefix, nwords, w.scan, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(g_total, dim3(1), dim3(64), 0, s, w.keep_prefix, nwords, n_groups);
+    if (w.n == 0)
+        return hipGetLastError();
+    hipLaunchKernelGGL(g_assign, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent, w.flags,
+                       w.cnt, w.keep, w.keep_prefix, vel, cap, group_id, w.groot, sizes, com,
+                       vmean, sigv);
+    if (cap <= 0)
+        return hipGetLastError();
+    const unsigned gb = (unsigned)((cap + 255) / 256);
+    const float *v = (vmean || sigv) ? vel : nullptr;
+    hipLaunchKernelGGL(g_sum, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.desc, w.nbox,
+                       w.parent, w.flags, w.keep, w.keep_prefix, v, cap, com, vmean);
+    hipLaunchKernelGGL(g_mean, dim3(gb), dim3(256), 0, s, w.sorted, w.desc, w.nbox, n_groups, cap,
+                       w.groot, sizes, v, com, vmean);
+    if (v && vmean && sigv) {
+        hipLaunchKernelGGL(g_dev, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent, w.flags,
+                           w.keep, w.keep_prefix, v, cap, vmean, sigv);
+        hipLaunchKernelGGL(g_sig, dim3(gb), dim3(256), 0, s, n_groups, cap, sizes, sigv);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fof

@@ -1,0 +1,210 @@
+// Internal declarations shared by the kernels and the host entry points of libfof.so.
+// Target: gfx950 (CDNA4), wave64.  Everything here is device-side plumbing; the public
+// interface is include/fof.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fof.h"
+
+// The link predicate must round exactly like its definition (no fused multiply-add).
+#pragma clang fp contract(off)
+
+namespace fof {
+
+constexpr int kWave = 64;
+constexpr int kDefaultBlock = 256;
+constexpr int kScanItems = 8;                  // elements per thread in the scan kernels
+constexpr int kMaxFine = 10;                   // fine cells per coarse cell per axis (max)
+constexpr int kMaxFineKeys = kMaxFine * kMaxFine * kMaxFine;
+
+// Per-box constants, computed once on the host in double precision and copied into the
+// workspace by the caller.  Layout is private to this library.
+struct alignas(16) BoxDesc {
+    int64_t off;        // first particle of the box in the concatenated arrays
+    int64_t cell_base;  // first coarse cell of the box in the concatenated cell table
+    int32_t n;          // particles in the box
+    int32_t m;          // fine (clique) cells per coarse cell per axis
+    int32_t nc[3];      // coarse cells per axis
+    int32_t nf[3];      // fine cells per axis (nc * m)
+    double L[3];        // box lengths
+    double halfL[3];    // 0.5 * L (exact)
+    double b2;          // b * b, rounded once in double
+    float inv_fine[3];  // float(nf / L): fine index = trunc(x * inv_fine)
+    float side[3];      // float(L / nc): coarse cell side
+    float reach;        // pruning distance: b plus the bound on index rounding error
+    float pad;
+};
+
+// Status bits (public values in fof.h) and the counters block.
+struct Counters {
+    int32_t status;
+    int32_t n_dense;     // dense cells found
+    int32_t n_units;     // clique units in dense cells
+    int32_t pad[61];
+};
+
+// ---------------------------------------------------------------------------------------
+// Box lookup: box k owns global indices [off_k, off_k + n_k); boxes are in order.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int find_box(const BoxDesc *__restrict__ d, int nbox, int64_t i)
+{
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d[mid].off <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Fine (clique) cell index along one axis: trunc(x * inv_fine) clamped to nf - 1.  The
+// coarse index is fine / m, so fine cells nest exactly inside coarse cells.  The computed
+// fine cell is the exact cell of some x' with |x' - x| <= L 2^-23 (1 + 2^-10).
+__device__ __forceinline__ int fine_index(float x, float inv, int nf)
+{
+    int f = (int)(x * inv);
+    return f < nf - 1 ? f : nf - 1;
+}
+
+__device__ __forceinline__ int64_t coarse_cell(const BoxDesc &B, int ix, int iy, int iz)
+{
+    return B.cell_base + ((int64_t)iz * B.nc[1] + iy) * B.nc[0] + ix;
+}
+
+// Exact link predicate: per axis d = (double)xi - (double)xj, wrapped once by +-L when
+// |d| > L/2; s = ((dx*dx + dy*dy) + dz*dz) in double; friends iff s < b*b.
+__device__ __forceinline__ double min_image(double d, double L, double h)
+{
+    if (d > h)
+        d -= L;
+    else if (d < -h)
+        d += L;
+    return d;
+}
+
+__device__ __forceinline__ bool linked(const BoxDesc &B, float xi, float yi, float zi, float xj,
+                                       float yj, float zj)
+{
+    double dx = min_image((double)xi - (double)xj, B.L[0], B.halfL[0]);
+    double dy = min_image((double)yi - (double)yj, B.L[1], B.halfL[1]);
+    double dz = min_image((double)zi - (double)zj, B.L[2], B.halfL[2]);
+    double sx = __dmul_rn(dx, dx);
+    double sy = __dmul_rn(dy, dy);
+    double sz = __dmul_rn(dz, dz);
+    double s = __dadd_rn(__dadd_rn(sx, sy), sz);
+    return s < B.b2;
+}
+
+// ---------------------------------------------------------------------------------------
+// Lock-free union-find over sorted positions.  parent[i] packs (key << 32) | index, where
+// key is the particle's original index; a root holds its own packed value.  Hooks always
+// put the root with the larger key under the one with the smaller key, so every tree's
+// root is its member with the smallest original index.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_relaxed(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t uf_idx(uint64_t v) { return (uint32_t)v; }
+__device__ __forceinline__ uint32_t uf_key(uint64_t v) { return (uint32_t)(v >> 32); }
+
+// Returns the packed value of the root of x, halving the path on the way (only non-root
+// entries are rewritten, so this never races with a hook, which only targets roots).
+__device__ __forceinline__ uint64_t uf_find(uint64_t *P, uint32_t x)
+{
+    uint64_t px = ld_relaxed(P + x);
+    while (uf_idx(px) != x) {
+        uint32_t y = uf_idx(px);
+        uint64_t py = ld_relaxed(P + y);
+        if (uf_idx(py) != y)
+            st_relaxed(P + x, py);
+        x = y;
+        px = py;
+    }
+    return px;
+}
+
+__device__ __forceinline__ void uf_union(uint64_t *P, uint32_t a, uint32_t b)
+{
+    uint64_t ra = uf_find(P, a);
+    uint64_t rb = uf_find(P, b);
+    while (ra != rb) {
+        if (ra > rb) {  // keys are unique, so packed order is key order
+            uint64_t t = ra;
+            ra = rb;
+            rb = t;
+        }
+        uint32_t hi = uf_idx(rb);
+        uint64_t old = atomicCAS((unsigned long long *)(P + hi), (unsigned long long)rb,
+                                 (unsigned long long)ra);
+        if (old == rb)
+            return;
+        rb = uf_find(P, hi);
+        ra = uf_find(P, uf_idx(ra));
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+}  // namespace fof
+
+// ---------------------------------------------------------------------------------------
+// Host-side launchers (defined in the .hip files, called by the entry points).
+// ---------------------------------------------------------------------------------------
+namespace fof {
+struct Work {  // device pointers resolved from a fof_grid and a workspace base
+    const BoxDesc *desc;
+    Counters *ctr;
+    int32_t *cell_count;
+    int32_t *cell_start;
+    int32_t *scan;
+    int32_t *rank;
+    float4 *sorted;
+    uint64_t *parent;
+    uint64_t *flags;
+    uint32_t *keep;
+    int32_t *keep_prefix;
+    int32_t *cnt;
+    int32_t *groot;
+    int32_t nbox;
+    int32_t block;
+    int64_t n;
+    int64_t ncell;
+};
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch,
+                           hipStream_t s);
+hipError_t launch_scan_popc(const uint32_t *in, int32_t *out, int64_t n, int32_t *scratch,
+                            hipStream_t s);
+int64_t scan_scratch_elems(int64_t n);
+
+hipError_t launch_build(const Work &w, const float *pos, hipStream_t s);
+hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s);
+hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int32_t cap,
+                         int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
+                         double *vmean, double *sigv, hipStream_t s);
+hipError_t launch_backward(int64_t n, int32_t block, const int32_t *group_id, int32_t G,
+                           const int32_t *sizes, const double *vmean, const double *sigv,
+                           const float *vel, const double *g_com, const double *g_sigv,
+                           float *grad_pos, float *grad_vel, hipStream_t s);
+}  // namespace fof

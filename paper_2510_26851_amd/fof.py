@@ -1,0 +1,159 @@
+"""Python front end of libfof.so.  torch supplies device memory and the current stream;
+every step of the computation runs in the library's HIP kernels.
+
+    plan = Plan([n], [(L, b)])              # host planning + device workspace
+    plan.build_grid(pos)                    # pos: float32 [n, 3] on the GPU
+    root = plan.link()                      # int32 [n] smallest member index per component
+    out = plan.groups(min_size, vel=None)   # group ids, sizes, centres of mass, moments
+
+``find_groups(pos, L, b, min_size)`` does all three for one box.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A planned batch of periodic boxes with its device workspace.
+
+    counts: particles per box; boxes: (L, b) per box where L is a scalar or 3 sides and b
+    the physical linking length.  tune: dict(cell_side=..., block=...), results do not
+    depend on it.
+    """
+
+    def __init__(self, counts, boxes, device=None, tune=None):
+        L = _lib.load()
+        self.device = torch.device(device if device is not None else "cuda")
+        counts = np.ascontiguousarray(np.asarray(counts, dtype=np.int64).reshape(-1))
+        nbox = counts.shape[0]
+        bx = (_lib.fof_box * nbox)()
+        for k, (Lk, bk) in enumerate(boxes):
+            Lk = np.broadcast_to(np.asarray(Lk, dtype=np.float64), (3,))
+            bx[k].L[:] = [float(v) for v in Lk]
+            bx[k].b = float(bk)
+        self.boxes = [(tuple(float(v) for v in bx[k].L), float(bx[k].b)) for k in range(nbox)]
+        self.counts = counts
+        self.tune = _lib.fof_tune()
+        for key, v in (tune or {}).items():
+            setattr(self.tune, key, v)
+        self.grid = _lib.fof_grid()
+        check("fof_workspace_bytes",
+              L.fof_workspace_bytes(nbox, counts.ctypes.data_as(ctypes.c_void_p), bx,
+                                    ctypes.byref(self.tune), ctypes.byref(self.grid), None, 0))
+        desc = np.zeros(self.grid.desc_bytes, dtype=np.uint8)
+        check("fof_workspace_bytes",
+              L.fof_workspace_bytes(nbox, counts.ctypes.data_as(ctypes.c_void_p), bx,
+                                    ctypes.byref(self.tune), ctypes.byref(self.grid),
+                                    desc.ctypes.data_as(ctypes.c_void_p), desc.shape[0]))
+        self.n = int(self.grid.n)
+        self.nbox = nbox
+        self.ws = torch.empty(int(self.grid.ws_bytes), dtype=torch.uint8, device=self.device)
+        o = int(self.grid.off_desc)
+        self.ws[o:o + desc.shape[0]].copy_(torch.from_numpy(desc))
+        self._gref = ctypes.byref(self.grid)
+
+    # -- stages ---------------------------------------------------------------------------
+    def build_grid(self, pos, stream=None):
+        assert pos.dtype == torch.float32 and pos.is_contiguous() and pos.shape == (self.n, 3)
+        assert pos.device == self.ws.device
+        self._pos = pos
+        check("fof_build_grid",
+              _lib.load().fof_build_grid(self._gref, _ptr(pos), _ptr(self.ws), _stream(stream)))
+
+    def link(self, root=None, stream=None):
+        if root is None:
+            root = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        check("fof_link",
+              _lib.load().fof_link(self._gref, _ptr(self.ws), None, _ptr(root), _stream(stream)))
+        return root
+
+    def groups(self, min_size, vel=None, cap=None, out=None, stream=None):
+        """Returns a dict of device tensors; n_groups stays on the device (one int32)."""
+        cap = self.n if cap is None else int(cap)
+        d = self.device
+        o = out or {}
+        gid = o.get("group_id")
+        if gid is None:
+            gid = torch.empty(self.n, dtype=torch.int32, device=d)
+        ng = o.get("n_groups")
+        if ng is None:
+            ng = torch.empty(1, dtype=torch.int32, device=d)
+        sizes = o.get("sizes")
+        if sizes is None:
+            sizes = torch.empty(max(cap, 1), dtype=torch.int32, device=d)
+        com = o.get("com")
+        if com is None:
+            com = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=d)
+        vm = sv = None
+        if vel is not None:
+            assert vel.dtype == torch.float32 and vel.shape == (self.n, 3) and vel.is_contiguous()
+            vm = o.get("vmean")
+            if vm is None:
+                vm = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=d)
+            sv = o.get("sigv")
+            if sv is None:
+                sv = torch.empty(max(cap, 1), dtype=torch.float64, device=d)
+        check("fof_groups",
+              _lib.load().fof_groups(self._gref, _ptr(self.ws), int(min_size), _ptr(vel), cap,
+                                     _ptr(gid), _ptr(ng), _ptr(sizes), _ptr(com), _ptr(vm),
+                                     _ptr(sv), _stream(stream)))
+        res = dict(group_id=gid, n_groups=ng, sizes=sizes, com=com, cap=cap)
+        if vel is not None:
+            res["vmean"] = vm
+            res["sigv"] = sv
+        return res
+
+    def status(self) -> int:
+        p = ctypes.c_void_p()
+        check("fof_status", _lib.load().fof_status(self._gref, _ptr(self.ws), ctypes.byref(p)))
+        off = p.value - self.ws.data_ptr()
+        return int(self.ws[off:off + 4].view(torch.int32).item())
+
+    def backward(self, group_id, G, sizes, vmean=None, sigv=None, vel=None, g_mass=None,
+                 g_com=None, g_sigv=None, want_pos=True, want_vel=True, stream=None):
+        d = self.device
+        gp = torch.empty((self.n, 3), dtype=torch.float32, device=d) if want_pos else None
+        gv = torch.empty((self.n, 3), dtype=torch.float32, device=d) if want_vel else None
+        f64 = lambda t: None if t is None else t.to(torch.float64).contiguous()
+        g_mass, g_com, g_sigv = f64(g_mass), f64(g_com), f64(g_sigv)
+        check("fof_backward",
+              _lib.load().fof_backward(self._gref, _ptr(group_id), int(G), _ptr(sizes),
+                                       _ptr(vmean), _ptr(sigv), _ptr(vel), _ptr(g_mass),
+                                       _ptr(g_com), _ptr(g_sigv), _ptr(gp), _ptr(gv),
+                                       _stream(stream)))
+        return gp, gv
+
+
+def trim(res):
+    """Synchronise once and cut the group tables to n_groups (host-side convenience)."""
+    G = int(res["n_groups"].item())
+    k = min(G, res["cap"])
+    out = dict(group_id=res["group_id"], n_groups=G, sizes=res["sizes"][:k], com=res["com"][:k])
+    if "vmean" in res:
+        out["vmean"] = res["vmean"][:k]
+        out["sigv"] = res["sigv"][:k]
+    return out
+
+
+def find_groups(pos, L, b, min_size=20, vel=None, cap=None, tune=None):
+    """One periodic box: returns (root, groups dict trimmed to n_groups)."""
+    plan = Plan([pos.shape[0]], [(L, b)], device=pos.device, tune=tune)
+    plan.build_grid(pos)
+    root = plan.link()
+    res = trim(plan.groups(min_size, vel=vel, cap=cap))
+    return root, res

@@ -1,0 +1,191 @@
+"""Host-only checks of libfof.so: it loads, exports every symbol include/fof.h declares, and
+rejects bad arguments on the host before anything would be enqueued (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+import struct
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fof.h")
+
+_lib = pytest.importorskip("paper_2510_26851_amd._lib")
+
+
+def lib():
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fof_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported():
+    names = declared_functions()
+    assert set(names) == set(_lib.EXPORTS)
+    L = lib()
+    for f in names:
+        assert hasattr(L, f), f
+
+
+def test_strerror():
+    assert _lib.strerror(0) == "ok"
+    assert "invalid" in _lib.strerror(-1)
+    assert _lib.strerror(12345) == "unknown error"
+
+
+def plan(counts, boxes, tune=None, desc=True):
+    nbox = len(counts)
+    c = np.asarray(counts, dtype=np.int64)
+    bx = (_lib.fof_box * nbox)()
+    for k, (L, b) in enumerate(boxes):
+        L3 = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+        bx[k].L[:] = [float(v) for v in L3]
+        bx[k].b = b
+    g = _lib.fof_grid()
+    t = ctypes.byref(tune) if tune is not None else None
+    rc = lib().fof_workspace_bytes(nbox, c.ctypes.data_as(ctypes.c_void_p), bx, t, ctypes.byref(g),
+                                   None, 0)
+    if rc or not desc:
+        return rc, g, None
+    buf = np.zeros(g.desc_bytes, np.uint8)
+    rc = lib().fof_workspace_bytes(nbox, c.ctypes.data_as(ctypes.c_void_p), bx, t,
+                                   ctypes.byref(g), buf.ctypes.data_as(ctypes.c_void_p),
+                                   buf.shape[0])
+    return rc, g, buf
+
+
+# BoxDesc layout (fof_internal.h): int64 off, cell_base; int32 n, m, nc[3], nf[3];
+# double L[3], halfL[3], b2; float inv_fine[3], side[3], reach, pad.
+_DESC = struct.Struct("<qqii3i3i3d3dd3f3fff")
+
+
+DESC_STRIDE = 144   # sizeof(BoxDesc), 16-byte aligned
+
+
+def decode(buf, k=0):
+    v = _DESC.unpack_from(buf.tobytes(), k * DESC_STRIDE)
+    return dict(off=v[0], cell_base=v[1], n=v[2], m=v[3], nc=v[4:7], nf=v[7:10], L=v[10:13],
+                halfL=v[13:16], b2=v[16], inv_fine=v[17:20], side=v[20:23], reach=v[23])
+
+
+def test_descriptor_size():
+    rc, g, buf = plan([10, 20], [(10.0, 0.5), (10.0, 0.5)])
+    assert rc == 0 and g.desc_bytes == 2 * DESC_STRIDE and _DESC.size <= DESC_STRIDE
+
+
+@pytest.mark.parametrize("L,b,n", [(64.0, 0.4, 32768), (512.0, 0.2, 512 ** 3), (256.0, 0.2, 256 ** 3),
+                                   (1.0, 0.4, 50), (0.9, 0.44, 100), ((0.7, 3.0, 5.0), 0.34, 50),
+                                   (50.397, 0.4, 16000)])
+def test_plan_geometry_guarantees(L, b, n):
+    """Coarse cells are at least b plus twice the float32 index error, so the 27-cell stencil
+    is complete; fine cells are cliques (any two members closer than 0.999 b)."""
+    rc, g, buf = plan([n], [(L, b)])
+    assert rc == 0
+    d = decode(buf)
+    L3 = np.broadcast_to(np.asarray(L, np.float64), (3,))
+    Lmax = float(L3.max())
+    eps = Lmax * 2.0 ** -23 * (1 + 2.0 ** -10)
+    for a in range(3):
+        side = L3[a] / d["nc"][a]
+        assert d["nc"][a] == 1 or side >= b + 2 * eps
+        fine = side / d["m"]
+        assert d["nf"][a] == d["nc"][a] * d["m"]
+        assert float(np.float32(d["inv_fine"][a])) == float(np.float32(d["nf"][a] / L3[a]))
+    fine_max = max(L3[a] / d["nc"][a] / d["m"] for a in range(3))
+    assert math.sqrt(3.0) * (fine_max + 2 * eps) <= 0.999 * b * (1 + 1e-12)
+    assert d["reach"] >= b + 2.5 * Lmax * 2.0 ** -23
+    assert d["b2"] == b * b
+    ncell = int(np.prod(d["nc"]))
+    assert g.ncell == ncell and ncell <= 8 * n + 64 + 3 * max(d["nc"]) ** 2 * 3
+    assert g.ws_bytes > 0 and g.ws_bytes % 256 == 0
+
+
+def test_batch_plan_offsets():
+    counts = [100, 0, 57, 1000]
+    boxes = [(10.0, 0.4), (5.0, 0.3), (8.0, 0.5), (20.0, 0.4)]
+    rc, g, buf = plan(counts, boxes)
+    assert rc == 0 and g.nbox == 4 and g.n == sum(counts)
+    off, cb = 0, 0
+    for k in range(4):
+        d = decode(buf, k)
+        assert d["off"] == off and d["cell_base"] == cb and d["n"] == counts[k]
+        off += counts[k]
+        cb += int(np.prod(d["nc"]))
+    assert g.ncell == cb
+
+
+@pytest.mark.parametrize("counts,boxes", [
+    ([10], [(10.0, 0.0)]),           # b = 0
+    ([10], [(10.0, -1.0)]),          # b < 0
+    ([10], [(1.0, 0.5)]),            # 2b == L
+    ([10], [(0.0, 0.1)]),            # L = 0
+    ([10], [(float("inf"), 0.1)]),   # L not finite
+    ([10], [(10.0, float("nan"))]),  # b NaN
+    ([-1], [(10.0, 0.4)]),           # negative count
+    ([2 ** 31], [(4096.0, 0.4)]),    # total above INT32_MAX
+])
+def test_plan_rejects_bad_arguments(counts, boxes):
+    rc, _, _ = plan(counts, boxes, desc=False)
+    assert rc == _lib.FOF_EINVAL
+
+
+def test_plan_rejects_bad_tune():
+    t = _lib.fof_tune()
+    t.block = 100     # not a multiple of 64
+    rc, _, _ = plan([10], [(10.0, 0.4)], tune=t, desc=False)
+    assert rc == _lib.FOF_EINVAL
+    t = _lib.fof_tune()
+    t.flags = 1
+    rc, _, _ = plan([10], [(10.0, 0.4)], tune=t, desc=False)
+    assert rc == _lib.FOF_EINVAL
+
+
+def test_plan_rejects_small_desc_buffer():
+    c = np.array([10], np.int64)
+    bx = (_lib.fof_box * 1)()
+    bx[0].L[:] = [10.0, 10.0, 10.0]
+    bx[0].b = 0.4
+    g = _lib.fof_grid()
+    buf = np.zeros(16, np.uint8)
+    rc = lib().fof_workspace_bytes(1, c.ctypes.data_as(ctypes.c_void_p), bx, None, ctypes.byref(g),
+                                   buf.ctypes.data_as(ctypes.c_void_p), 16)
+    assert rc == _lib.FOF_EINVAL
+
+
+def test_entry_points_reject_bad_arguments_before_launch():
+    L = lib()
+    rc, g, _ = plan([100], [(10.0, 0.4)])
+    assert rc == 0
+    gp = ctypes.byref(g)
+    fake_ws = ctypes.c_void_p(0x100000)      # never dereferenced: every call below fails first
+    misaligned = ctypes.c_void_p(0x100010)
+    assert L.fof_build_grid(None, None, fake_ws, None) == _lib.FOF_EINVAL
+    assert L.fof_build_grid(gp, None, fake_ws, None) == _lib.FOF_EINVAL          # pos NULL
+    assert L.fof_build_grid(gp, fake_ws, misaligned, None) == _lib.FOF_EINVAL    # ws alignment
+    assert L.fof_build_grid(gp, fake_ws, None, None) == _lib.FOF_EINVAL          # ws NULL
+    assert L.fof_link(gp, fake_ws, None, None, None) == _lib.FOF_EINVAL          # root NULL
+    assert L.fof_link(gp, fake_ws, fake_ws, fake_ws, None) == _lib.FOF_ENOTSUP   # sampling
+    assert L.fof_groups(gp, fake_ws, 20, None, 10, None, fake_ws, fake_ws, None, None, None,
+                        None) == _lib.FOF_EINVAL                                  # group_id NULL
+    assert L.fof_groups(gp, fake_ws, 20, None, -1, fake_ws, fake_ws, fake_ws, None, None, None,
+                        None) == _lib.FOF_EINVAL                                  # cap < 0
+    assert L.fof_groups(gp, fake_ws, 20, None, 10, fake_ws, fake_ws, None, None, None, None,
+                        None) == _lib.FOF_EINVAL                                  # sizes NULL
+    assert L.fof_groups(gp, fake_ws, 20, fake_ws, 10, fake_ws, fake_ws, fake_ws, None, fake_ws,
+                        None, None) == _lib.FOF_EINVAL                            # vmean w/o sigv
+    assert L.fof_backward(gp, None, 1, fake_ws, None, None, None, None, None, None, None, None,
+                          None) == _lib.FOF_EINVAL                                # group_id NULL
+    assert L.fof_backward(gp, fake_ws, -1, fake_ws, None, None, None, None, None, None, None,
+                          None, None) == _lib.FOF_EINVAL                          # G < 0
+    assert L.fof_backward(gp, fake_ws, 1, fake_ws, None, None, None, None, None, fake_ws, None,
+                          fake_ws, None) == _lib.FOF_EINVAL                       # vel missing
+    p = ctypes.c_void_p()
+    assert L.fof_status(gp, misaligned, ctypes.byref(p)) == _lib.FOF_EINVAL
+    assert L.fof_status(gp, fake_ws, ctypes.byref(p)) == 0
+    assert p.value == 0x100000 + g.off_status

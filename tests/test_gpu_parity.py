@@ -1,0 +1,126 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on the same seeded inputs.
+
+Labels, group ids and sizes must match bit-exactly; centres of mass, mean velocities and
+dispersions within 1e-5 relative (minimum-image difference over max(|ref|, mean spacing)).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import compare_with_oracle, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_26851_amd  # noqa: F401  (raises if libfof.so is missing)
+
+
+@pytest.mark.parametrize("seed,n,L,b", [
+    (1, 1, 10.0, 0.6),
+    (2, 2, 1.0, 0.45),
+    (3, 63, 3.0, 0.6),
+    (4, 65, 3.0, 0.6),
+    (5, 1000, 10.0, 0.6),
+    (6, 4097, 16.0, 0.9),
+    (7, 3000, (12.0, 9.0, 20.0), 0.7),
+    (8, 800, 3.0, 0.35),
+    (9, 200, 1.0, 0.4),          # 2 coarse cells per axis
+    (10, 50, (0.7, 3.0, 5.0), 0.34),
+    (11, 20000, 20.0, 0.5),
+])
+def test_uniform_boxes(seed, n, L, b):
+    say(f"uniform seed={seed} n={n} L={L} b={b}")
+    pos = W.uniform_box(n, np.broadcast_to(L, (3,)), seed)
+    compare_with_oracle(pos, L, b, min_size=2)
+
+
+@pytest.mark.parametrize("seed,n,L,ncl,b", [
+    (21, 5000, 24.0, 6, 0.5),
+    (22, 30000, 40.0, 20, 0.4),
+    (23, 12000, 8.0, 3, 0.3),
+])
+def test_clumpy_boxes(seed, n, L, ncl, b):
+    say(f"clumpy seed={seed} n={n}")
+    pos = W.clumpy_box(n, L, ncl, seed)
+    compare_with_oracle(pos, L, b, min_size=5)
+
+
+def test_empty_box():
+    say("empty box")
+    root, g, status = run_gpu(np.zeros((0, 3), np.float32), 10.0, 0.5, 2)
+    assert root.shape == (0,) and g["n_groups"] == 0 and status == 0
+
+
+def test_lattice_closed_cases():
+    say("lattice one group")
+    pos = W.cubic_lattice(24, 0.375)             # spacing < b: one group of 13824
+    root, g, _ = run_gpu(pos, 9.0, 0.4, 20)
+    assert np.all(root == 0) and g["n_groups"] == 1 and g["sizes"][0] == 24 ** 3
+    say("lattice singletons")
+    pos = W.cubic_lattice(24, 0.4375)            # spacing > b: all singletons
+    root, g, _ = run_gpu(pos, 10.5, 0.4, 1)
+    np.testing.assert_array_equal(root, np.arange(24 ** 3))
+    assert g["n_groups"] == 24 ** 3
+    np.testing.assert_array_equal(g["group_id"], np.arange(24 ** 3))
+
+
+def test_min_size_one_and_cap_overflow():
+    say("min_size 1 + cap overflow")
+    pos = W.clumpy_box(3000, 12.0, 4, 31)
+    root_ref, _ = oracle.fof(pos, 12.0, 0.45)
+    ref = oracle.groups(pos, root_ref, 12.0, 1)
+    root, g, _ = run_gpu(pos, 12.0, 0.45, 1)
+    np.testing.assert_array_equal(root, root_ref)
+    assert g["n_groups"] == ref["n_groups"]
+    np.testing.assert_array_equal(g["group_id"], ref["group_id"])
+    np.testing.assert_array_equal(g["sizes"], ref["sizes"])
+    cap = 17
+    root, g, _ = run_gpu(pos, 12.0, 0.45, 1, cap=cap)
+    assert g["n_groups"] == ref["n_groups"] and g["sizes"].shape[0] == cap
+    np.testing.assert_array_equal(g["sizes"], ref["sizes"][:cap])
+
+
+def test_out_of_range_sets_status():
+    say("status word: out-of-range and NaN inputs")
+    pos = W.uniform_box(500, (10.0,) * 3, 3)
+    pos[7, 1] = 10.0          # x == L is outside [0, L)
+    pos[11, 2] = np.nan
+    _, _, status = run_gpu(pos, 10.0, 0.5, 2)
+    assert status & 1
+
+
+@pytest.mark.parametrize("tune", [dict(block=64), dict(block=128), dict(block=512),
+                                  dict(block=1024), dict(cell_side=0.5), dict(cell_side=3.0)])
+def test_launch_shape_and_cell_side_do_not_change_results(tune):
+    say(f"launch shape {tune}")
+    box = W.config0()
+    root_ref, _ = oracle.fof(box.pos, box.L, box.b)
+    compare_with_oracle(box.pos, box.L, box.b, box.min_size, tune=tune, root_ref=root_ref)
+
+
+def test_config0_clumps_32768():
+    box = W.config0()
+    say(f"config0 {box.name}")
+    root, g = compare_with_oracle(box.pos, box.L, box.b, box.min_size)
+    assert g["n_groups"] > 10
+
+
+def test_config3_zeldovich_128_with_velocities():
+    box = W.config3()
+    say(f"config3 {box.name} n={box.n}")
+    compare_with_oracle(box.pos, box.L, box.b, box.min_size, vel=box.vel)
+
+
+def test_repeat_runs_identical():
+    box = W.config3()
+    say("repeat runs")
+    r1, g1, _ = run_gpu(box.pos, box.L, box.b, box.min_size)
+    r2, g2, _ = run_gpu(box.pos, box.L, box.b, box.min_size)
+    np.testing.assert_array_equal(r1, r2)
+    np.testing.assert_array_equal(g1["group_id"], g2["group_id"])
