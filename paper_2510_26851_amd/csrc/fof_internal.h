@@ -134,6 +134,18 @@ __device__ __forceinline__ uint64_t uf_find(uint64_t *P, uint32_t x)
     return px;
 }
 
+// Root lookup without writes.  Used once no hook can happen any more (the compress pass),
+// so that every thread is the only writer of its own entry there.
+__device__ __forceinline__ uint64_t uf_find_ro(const uint64_t *P, uint32_t x)
+{
+    uint64_t px = ld_relaxed(P + x);
+    while (uf_idx(px) != x) {
+        x = uf_idx(px);
+        px = ld_relaxed(P + x);
+    }
+    return px;
+}
+
 __device__ __forceinline__ void uf_union(uint64_t *P, uint32_t a, uint32_t b)
 {
     uint64_t ra = uf_find(P, a);

@@ -85,7 +85,9 @@ __global__ void k_link(const float4 *__restrict__ sorted, int64_t n,
 
 // Particles with a friend: follow the union-find to the root and write the root's key
 // (its original index, the smallest in the component) as the label.  Also leaves every
-// flagged entry pointing straight at its root for the group passes.
+// flagged entry pointing straight at its root for the group passes.  The lookup must not
+// halve paths: a halving write by one thread could replace the root another thread has
+// just stored in its own entry with a stale grandparent.
 __global__ void k_compress(const float4 *__restrict__ sorted, int64_t n,
                            uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
                            int32_t *__restrict__ root)
@@ -95,7 +97,7 @@ __global__ void k_compress(const float4 *__restrict__ sorted, int64_t n,
         return;
     if (!((flags[i >> 6] >> (i & 63)) & 1ull))
         return;
-    const uint64_t r = uf_find(parent, (uint32_t)i);
+    const uint64_t r = uf_find_ro(parent, (uint32_t)i);
     st_relaxed(parent + i, r);
     root[__float_as_int(sorted[i].w)] = (int32_t)uf_key(r);
 }
