@@ -545,3 +545,157 @@ int oracle_frozen_backward(int64_t n, const float *vel, const int32_t *group_id,
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* Topological mode (Sec. 3.2): stochastic linking sampled with a counter-based RNG       */
+/* ------------------------------------------------------------------------------------ */
+
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+ *   (hi0, lo0) = M0 * x0,  (hi1, lo1) = M1 * x2   (full 128-bit products)
+ *   x = (hi1 ^ x1 ^ k0, lo1, hi0 ^ x3 ^ k1, lo0)
+ * with the key advanced by the Weyl constants (W0, W1) between rounds. */
+void oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        unsigned __int128 p0 = (unsigned __int128)M0 * x0;
+        unsigned __int128 p1 = (unsigned __int128)M1 * x2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+/* Uniform in [0, 1) for edge {i, j} (original indices, i < j) in sample s:
+ * counter = (i | j << 32, s, 0, 0), key = (seed, 0); u = (first word >> 11) * 2^-53. */
+double oracle_uniform(uint64_t seed, uint32_t s, uint32_t i, uint32_t j)
+{
+    uint64_t ctr[4] = {(uint64_t)i | ((uint64_t)j << 32), (uint64_t)s, 0, 0};
+    uint64_t key[2] = {seed, 0};
+    uint64_t out[4];
+    oracle_philox4x64(ctr, key, out);
+    return (double)(out[0] >> 11) * ldexp(1.0, -53);
+}
+
+typedef struct {
+    const float *pos;
+    const double *L;
+    double r2;
+    int64_t cap, count;
+    int32_t *ei, *ej;
+    double *d2;
+} edge_ctx;
+
+static void edge_pair(void *vctx, int64_t i, int64_t j)
+{
+    edge_ctx *x = (edge_ctx *)vctx;
+    double s = oracle_dist2(x->pos + 3 * i, x->pos + 3 * j, x->L);
+    if (s < x->r2) {
+        if (x->count < x->cap) {
+            x->ei[x->count] = (int32_t)(i < j ? i : j);
+            x->ej[x->count] = (int32_t)(i < j ? j : i);
+            x->d2[x->count] = s;
+        }
+        x->count++;
+    }
+}
+
+typedef struct {
+    int32_t i, j;
+    double d2;
+} edge_rec;
+
+static int cmp_edge(const void *a, const void *b)
+{
+    const edge_rec *x = (const edge_rec *)a, *y = (const edge_rec *)b;
+    if (x->i != y->i)
+        return x->i < y->i ? -1 : 1;
+    return x->j < y->j ? -1 : (x->j > y->j);
+}
+
+/* Candidate edges: every unordered pair closer than r (same minimum-image squared distance
+ * as the link predicate, compared s < r*r), listed as (i < j) in ascending (i, j) order with
+ * the squared distance.  Returns the total count (which may exceed cap: then only the
+ * first cap edges of the enumeration are stored and the order is not sorted). */
+int64_t oracle_candidate_edges(int64_t n, const float *pos, const double *L, double r,
+                               int64_t cap, int32_t *ei, int32_t *ej, double *d2)
+{
+    int rc = check_args(n, pos, L, r);
+    if (rc)
+        return rc;
+    cell_list c;
+    rc = cells_build(&c, n, pos, L, r);
+    if (rc)
+        return rc;
+    edge_ctx ctx = {pos, L, r * r, cap, 0, ei, ej, d2};
+    cells_pairs(&c, edge_pair, &ctx);
+    cells_free(&c);
+    if (ctx.count <= cap && ctx.count > 1) {
+        edge_rec *e = (edge_rec *)malloc((size_t)ctx.count * sizeof(edge_rec));
+        if (!e)
+            return ORC_ENOMEM;
+        for (int64_t k = 0; k < ctx.count; ++k) {
+            e[k].i = ei[k];
+            e[k].j = ej[k];
+            e[k].d2 = d2[k];
+        }
+        qsort(e, (size_t)ctx.count, sizeof(edge_rec), cmp_edge);
+        for (int64_t k = 0; k < ctx.count; ++k) {
+            ei[k] = e[k].i;
+            ej[k] = e[k].j;
+            d2[k] = e[k].d2;
+        }
+        free(e);
+    }
+    return ctx.count;
+}
+
+/* Linking probability of an edge (Sec. 3.2 Bernoulli edges), logistic in
+ * z = (b - d) / tau with d = sqrt(d2): p = 1 / (1 + exp(-z)). */
+double oracle_edge_prob(double d2, double b, double tau)
+{
+    double z = (b - sqrt(d2)) / tau;
+    return 1.0 / (1.0 + exp(-z));
+}
+
+/* K sampled graphs: y_{e,s} = [u(seed, s, i_e, j_e) < p_e]; root[s][i] = smallest index in
+ * the component of i among the kept edges of sample s.  keep (optional, [K][ne] bytes)
+ * receives the sampled edge indicators. */
+int oracle_sample_labels(int64_t n, int64_t ne, const int32_t *ei, const int32_t *ej,
+                         const double *p, uint64_t seed, int32_t K, int32_t *root,
+                         uint8_t *keep)
+{
+    if (n < 0 || ne < 0 || K < 0)
+        return ORC_EINVAL;
+    for (int32_t s = 0; s < K; ++s) {
+        int32_t *par = root + (int64_t)s * n;
+        for (int64_t i = 0; i < n; ++i)
+            par[i] = (int32_t)i;
+        for (int64_t e = 0; e < ne; ++e) {
+            double u = oracle_uniform(seed, (uint32_t)s, (uint32_t)ei[e], (uint32_t)ej[e]);
+            int y = u < p[e];
+            if (keep)
+                keep[(int64_t)s * ne + e] = (uint8_t)y;
+            if (y)
+                uf_union(par, ei[e], ej[e]);
+        }
+        for (int64_t i = 0; i < n; ++i)
+            par[i] = uf_find(par, (int32_t)i);
+    }
+    return ORC_OK;
+}

@@ -9,6 +9,7 @@ namespace fof {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int32_t kDefaultDense = 32;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -87,16 +88,27 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
     }
     d->b2 = bx.b * bx.b;
     d->reach = round_up_f(reach);
-    d->pad = 0.0f;
+    // Fine cells: a friend lies at most R fine cells away per axis (its exact cell is within
+    // b + 2 eps); the fine side stored for gap pruning is a lower bound, less 2 eps.
+    double a_min = fmin(bx.L[0] / d->nf[0], fmin(bx.L[1] / d->nf[1], bx.L[2] / d->nf[2]));
+    d->R = (int32_t)floor((bx.b + 2.0 * eps) / a_min) + 1;
+    float fs = (float)(a_min - 2.0 * eps);
+    if ((double)fs > a_min - 2.0 * eps)
+        fs = nextafterf(fs, 0.0f);
+    d->fine_side = fs > 0.0f ? fs : 0.0f;
+    d->dense_ok = (d->nc[0] >= 3 && d->nc[1] >= 3 && d->nc[2] >= 3 && d->R <= 3) ? 1 : 0;
     return FOF_OK;
 }
 
 struct Layout {
     size_t off_desc, off_status, off_cell_count, off_cell_start, off_scan, off_rank, off_sorted,
-        off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, total;
+        off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, off_dense,
+        off_table, off_temp, total;
 };
 
-Layout layout(int32_t nbox, int64_t n, int64_t ncell)
+int32_t table_stride(int32_t words) { return kTableHeader + 2 * words; }
+
+Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t words)
 {
     Layout L;
     size_t o = 0;
@@ -120,6 +132,9 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell)
     L.off_keep_prefix = take(sizeof(int32_t) * (size_t)(nwords + 1));
     L.off_cnt = take(sizeof(int32_t) * (size_t)n);
     L.off_groot = take(sizeof(int32_t) * (size_t)n);
+    L.off_dense = take(sizeof(int32_t) * (size_t)dense_cap);
+    L.off_table = take(sizeof(int32_t) * (size_t)dense_cap * (size_t)table_stride(words));
+    L.off_temp = take(dense_cap > 0 ? sizeof(float4) * (size_t)n : 0);
     L.total = o;
     return L;
 }
@@ -133,7 +148,7 @@ bool ws_ok(const fof_grid *g, const void *ws)
 Work resolve(const fof_grid *g, void *ws)
 {
     char *base = (char *)ws;
-    Layout L = layout(g->nbox, g->n, g->ncell);
+    Layout L = layout(g->nbox, g->n, g->ncell, g->dense_cap, g->table_words);
     Work w;
     w.desc = (const BoxDesc *)(base + L.off_desc);
     w.ctr = (Counters *)(base + L.off_status);
@@ -148,6 +163,13 @@ Work resolve(const fof_grid *g, void *ws)
     w.keep_prefix = (int32_t *)(base + L.off_keep_prefix);
     w.cnt = (int32_t *)(base + L.off_cnt);
     w.groot = (int32_t *)(base + L.off_groot);
+    w.dense_list = (int32_t *)(base + L.off_dense);
+    w.table = (int32_t *)(base + L.off_table);
+    w.temp = (float4 *)(base + L.off_temp);
+    w.dense_threshold = g->dense_threshold;
+    w.dense_cap = (int32_t)g->dense_cap;
+    w.table_words = g->table_words;
+    w.table_stride = table_stride(g->table_words);
     w.nbox = g->nbox;
     w.block = g->block;
     w.n = g->n;
@@ -173,6 +195,7 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
                  tune->block > 1024 || !(tune->cell_side >= 0.0)))
         return FOF_EINVAL;
     int64_t n = 0, ncell = 0;
+    int32_t mmax = 1, any_dense = 0;
     BoxDesc *out = (BoxDesc *)desc;
     const size_t need = sizeof(BoxDesc) * (size_t)nbox;
     if (desc && desc_cap < need)
@@ -187,18 +210,39 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
             return rc;
         n += count[k];
         ncell += (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
-        if (n > INT32_MAX || ncell > ((int64_t)1 << 40))
+        if (n > INT32_MAX || ncell > INT32_MAX - 1)
             return FOF_EINVAL;
+        if (d.m > mmax)
+            mmax = d.m;
+        any_dense |= d.dense_ok;
         if (out)
             out[k] = d;
     }
-    Layout L = layout(nbox, n, ncell);
+    // Dense (clique-cell) path: cells holding more than `thr` particles.  The table count is
+    // the exact bound n / (thr + 1), limited to 2 GiB of tables; cells beyond the cap take
+    // the plain path and set FOF_STATUS_DENSE_CAP.
+    int32_t thr = (tune && tune->dense_threshold) ? tune->dense_threshold : kDefaultDense;
+    int32_t words = (mmax * mmax * mmax + 31) / 32;
+    int64_t dense_cap = 0;
+    if (thr > 0 && any_dense && n > thr) {
+        dense_cap = n / ((int64_t)thr + 1) + 1;
+        if (dense_cap > ncell)
+            dense_cap = ncell;
+        int64_t lim = ((int64_t)2 << 30) / (4 * (int64_t)table_stride(words));
+        if (dense_cap > lim)
+            dense_cap = lim;
+    }
+    if (thr <= 0)
+        thr = -1;
+    Layout L = layout(nbox, n, ncell, dense_cap, words);
     memset(grid, 0, sizeof(*grid));
     grid->nbox = nbox;
     grid->block = (tune && tune->block) ? tune->block : kDefaultBlock;
     grid->n = n;
     grid->ncell = ncell;
-    grid->dense_threshold = -1;
+    grid->dense_threshold = thr;
+    grid->dense_cap = dense_cap;
+    grid->table_words = words;
     grid->ws_bytes = L.total;
     grid->desc_bytes = need;
     grid->off_desc = L.off_desc;
@@ -212,6 +256,10 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
     grid->off_flags = L.off_flags;
     grid->off_keep = L.off_keep;
     grid->off_scan = L.off_scan;
+    grid->off_dense = L.off_dense;
+    grid->off_table = L.off_table;
+    grid->off_aux = L.off_rank;
+    grid->off_units = L.off_cnt;
     return FOF_OK;
 }
 

@@ -92,6 +92,10 @@ hipError_t launch_build(const Work &w, const float *pos, hipStream_t s)
         unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(w.block), 0, s, pos, w.n, w.desc, w.nbox,
                            w.cell_start, w.rank, w.sorted, w.parent);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        return launch_dense_build(w, s);
     }
     return hipGetLastError();
 }

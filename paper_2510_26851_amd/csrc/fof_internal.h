@@ -18,6 +18,8 @@ constexpr int kDefaultBlock = 256;
 constexpr int kScanItems = 8;                  // elements per thread in the scan kernels
 constexpr int kMaxFine = 10;                   // fine cells per coarse cell per axis (max)
 constexpr int kMaxFineKeys = kMaxFine * kMaxFine * kMaxFine;
+constexpr int kMaxTableWords = (kMaxFineKeys + 31) / 32;
+constexpr int kTableHeader = 4;  // dense-cell table: cell, ncomp, units, reserved
 
 // Per-box constants, computed once on the host in double precision and copied into the
 // workspace by the caller.  Layout is private to this library.
@@ -28,13 +30,15 @@ struct alignas(16) BoxDesc {
     int32_t m;          // fine (clique) cells per coarse cell per axis
     int32_t nc[3];      // coarse cells per axis
     int32_t nf[3];      // fine cells per axis (nc * m)
+    int32_t R;          // fine-cell reach: a friend lies at most R fine cells away per axis
+    int32_t dense_ok;   // 1 if this box may use the clique-cell path (>= 3 cells per axis)
     double L[3];        // box lengths
     double halfL[3];    // 0.5 * L (exact)
     double b2;          // b * b, rounded once in double
     float inv_fine[3];  // float(nf / L): fine index = trunc(x * inv_fine)
     float side[3];      // float(L / nc): coarse cell side
     float reach;        // pruning distance: b plus the bound on index rounding error
-    float pad;
+    float fine_side;    // largest fine cell side (float, rounded down)
 };
 
 // Status bits (public values in fof.h) and the counters block.
@@ -195,10 +199,17 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
     int32_t *keep_prefix;
     int32_t *cnt;
     int32_t *groot;
+    int32_t *dense_list;  // dense cell ids in discovery order
+    int32_t *table;       // per dense cell: header, key bitmask, popcount prefix
+    float4 *temp;         // staging for dense cells too large for LDS
     int32_t nbox;
     int32_t block;
     int64_t n;
     int64_t ncell;
+    int32_t dense_threshold;  // cells with more particles take the clique path (< 0: never)
+    int32_t dense_cap;        // dense cells with tables
+    int32_t table_words;      // words of one key bitmask
+    int32_t table_stride;     // int32 entries per dense-cell table
 };
 
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
@@ -212,6 +223,8 @@ int64_t scan_scratch_elems(int64_t n);
 
 hipError_t launch_build(const Work &w, const float *pos, hipStream_t s);
 hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s);
+hipError_t launch_dense_build(const Work &w, hipStream_t s);
+hipError_t launch_dense(const Work &w, hipStream_t s);
 hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int32_t cap,
                          int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
                          double *vmean, double *sigv, hipStream_t s);

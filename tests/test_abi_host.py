@@ -61,8 +61,8 @@ def plan(counts, boxes, tune=None, desc=True):
 
 
 # BoxDesc layout (fof_internal.h): int64 off, cell_base; int32 n, m, nc[3], nf[3];
-# double L[3], halfL[3], b2; float inv_fine[3], side[3], reach, pad.
-_DESC = struct.Struct("<qqii3i3i3d3dd3f3fff")
+# int32 R, dense_ok; double L[3], halfL[3], b2; float inv_fine[3], side[3], reach, fine_side.
+_DESC = struct.Struct("<qqii3i3iii3d3dd3f3fff")
 
 
 DESC_STRIDE = 144   # sizeof(BoxDesc), 16-byte aligned
@@ -70,8 +70,9 @@ DESC_STRIDE = 144   # sizeof(BoxDesc), 16-byte aligned
 
 def decode(buf, k=0):
     v = _DESC.unpack_from(buf.tobytes(), k * DESC_STRIDE)
-    return dict(off=v[0], cell_base=v[1], n=v[2], m=v[3], nc=v[4:7], nf=v[7:10], L=v[10:13],
-                halfL=v[13:16], b2=v[16], inv_fine=v[17:20], side=v[20:23], reach=v[23])
+    return dict(off=v[0], cell_base=v[1], n=v[2], m=v[3], nc=v[4:7], nf=v[7:10], R=v[10],
+                dense_ok=v[11], L=v[12:15], halfL=v[15:18], b2=v[18], inv_fine=v[19:22],
+                side=v[22:25], reach=v[25], fine_side=v[26])
 
 
 def test_descriptor_size():
@@ -101,6 +102,11 @@ def test_plan_geometry_guarantees(L, b, n):
     assert math.sqrt(3.0) * (fine_max + 2 * eps) <= 0.999 * b * (1 + 1e-12)
     assert d["reach"] >= b + 2.5 * Lmax * 2.0 ** -23
     assert d["b2"] == b * b
+    # a friend's fine cell is at most R away per axis; fine_side is a lower bound
+    a_min = min(L3[a] / d["nf"][a] for a in range(3))
+    assert d["R"] * a_min >= b + 2 * eps
+    assert d["fine_side"] <= a_min - 2 * eps
+    assert d["dense_ok"] == int(min(d["nc"]) >= 3 and d["R"] <= 3)
     ncell = int(np.prod(d["nc"]))
     assert g.ncell == ncell and ncell <= 8 * n + 64 + 3 * max(d["nc"]) ** 2 * 3
     assert g.ws_bytes > 0 and g.ws_bytes % 256 == 0

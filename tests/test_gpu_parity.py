@@ -124,3 +124,39 @@ def test_repeat_runs_identical():
     r2, g2, _ = run_gpu(box.pos, box.L, box.b, box.min_size)
     np.testing.assert_array_equal(r1, r2)
     np.testing.assert_array_equal(g1["group_id"], g2["group_id"])
+
+
+def very_dense_box(seed=41):
+    """20000 uniform particles plus 4 clumps of 10000 with sigma 0.12 in L = 24: several
+    coarse cells hold more than 2048 particles (the staging path of the clique sort)."""
+    rng = np.random.default_rng(seed)
+    L = 24.0
+    uni = rng.random((20000, 3)) * L
+    centres = rng.random((4, 3)) * L
+    mem = np.concatenate([c + 0.12 * rng.standard_normal((10000, 3)) for c in centres])
+    pos = W.wrap_to_f32(np.concatenate([uni, mem]), (L, L, L))
+    b = W.linking_length(0.2, L, pos.shape[0])
+    return pos, L, b
+
+
+@pytest.mark.parametrize("thr", [1, 4, 8, 32, 200, -1])
+def test_dense_threshold_does_not_change_results(thr):
+    say(f"dense threshold {thr}")
+    box = W.config0()
+    root_ref, _ = oracle.fof(box.pos, box.L, box.b)
+    compare_with_oracle(box.pos, box.L, box.b, box.min_size, tune=dict(dense_threshold=thr),
+                        root_ref=root_ref)
+
+
+@pytest.mark.parametrize("thr", [0, 1, 16, -1])
+def test_very_dense_clumps(thr):
+    pos, L, b = very_dense_box()
+    say(f"very dense clumps thr={thr} n={pos.shape[0]} b={b}")
+    compare_with_oracle(pos, L, b, 20, tune=dict(dense_threshold=thr))
+
+
+@pytest.mark.parametrize("cell_side", [0.0, 1.0, 2.5])
+def test_very_dense_clumps_cell_side(cell_side):
+    pos, L, b = very_dense_box(43)
+    say(f"very dense clumps cell_side={cell_side}")
+    compare_with_oracle(pos, L, b, 20, tune=dict(cell_side=cell_side))
