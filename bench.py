@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-zmax", type=float, default=32.0)
+    ap.add_argument("--cell-side", type=float, default=0.0, help="coarse cell side (0 = default)")
+    ap.add_argument("--dense-threshold", type=int, default=0, help="0 = default, <0 = off")
+    ap.add_argument("--block", type=int, default=0, help="threads per block (0 = default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -97,7 +100,8 @@ def main():
 
     pos = torch.from_numpy(box.pos).to(dev)
     vel = torch.from_numpy(box.vel).to(dev) if box.vel is not None else None
-    plan = Plan([box.n], [(box.L, box.b)], device=dev)
+    tune = dict(cell_side=args.cell_side, dense_threshold=args.dense_threshold, block=args.block)
+    plan = Plan([box.n], [(box.L, box.b)], device=dev, tune=tune)
     root = torch.empty(box.n, dtype=torch.int32, device=dev)
     cap = box.n
     out = dict(group_id=torch.empty(box.n, dtype=torch.int32, device=dev),
@@ -163,7 +167,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": box.name, "n": box.n, "L": box.L[0], "b": box.b,
-                   "min_size": box.min_size, "n_groups": ng},
+                   "min_size": box.min_size, "n_groups": ng, "tune": tune},
         "stages_ms": {"build_grid": round(build_ms, 4), "link": round(link_ms, 4),
                       "groups": round(groups_ms, 4)},
         "hbm_frac_end_to_end": round((BUILD_BYTES_PER_PARTICLE + LINK_BYTES_PER_PARTICLE +

@@ -69,6 +69,7 @@ typedef struct fof_grid {
     int64_t n;            /* total particles                                                  */
     int64_t ncell;        /* total coarse cells over all boxes                                */
     int64_t dense_cap;    /* dense cells that can get clique tables                           */
+    int64_t ntiles;       /* link tiles (blocks of the LDS-tiled link kernel)                 */
     int32_t dense_threshold;
     int32_t table_words;  /* 32-bit words of one clique bitmask                               */
     size_t ws_bytes;      /* size of the workspace the caller must provide                    */

@@ -33,6 +33,10 @@
  *   frozen backward  gradients of (mass, centre of mass, sigma_v) with memberships held
  *                    fixed (Sec. 3.1): d com / d x_i = 1/n, mass has zero gradient,
  *                    d sigma_v / d v_ic = (v_ic - vbar_c) / (3 n sigma_v).
+ *   stochastic links candidate edges closer than a cut radius, their logistic linking
+ *                    probability, and K sampled graphs (Sec. 3.2 Bernoulli edges), with the
+ *                    uniforms drawn from Philox4x64-10 keyed by a seed and counted by
+ *                    (edge, sample) so that any implementation can reproduce them.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no -ffast-math: IEEE round-to-nearest,
  * no contraction, denormals kept).

@@ -97,13 +97,18 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
         fs = nextafterf(fs, 0.0f);
     d->fine_side = fs > 0.0f ? fs : 0.0f;
     d->dense_ok = (d->nc[0] >= 3 && d->nc[1] >= 3 && d->nc[2] >= 3 && d->R <= 3) ? 1 : 0;
+    // the tiled link kernel needs distinct neighbour cells (>= 3 per axis)
+    d->tiled = (d->nc[0] >= 3 && d->nc[1] >= 3 && d->nc[2] >= 3) ? 1 : 0;
+    d->ntile[0] = (d->nc[0] + kTileX - 1) / kTileX;
+    d->ntile[1] = (d->nc[1] + kTileY - 1) / kTileY;
+    d->ntile[2] = (d->nc[2] + kTileZ - 1) / kTileZ;
     return FOF_OK;
 }
 
 struct Layout {
     size_t off_desc, off_status, off_cell_count, off_cell_start, off_scan, off_rank, off_sorted,
         off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, off_dense,
-        off_table, off_temp, total;
+        off_big, off_table, off_temp, total;
 };
 
 int32_t table_stride(int32_t words) { return kTableHeader + 2 * words; }
@@ -133,6 +138,7 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
     L.off_cnt = take(sizeof(int32_t) * (size_t)n);
     L.off_groot = take(sizeof(int32_t) * (size_t)n);
     L.off_dense = take(sizeof(int32_t) * (size_t)dense_cap);
+    L.off_big = take(sizeof(int32_t) * (size_t)dense_cap);
     L.off_table = take(sizeof(int32_t) * (size_t)dense_cap * (size_t)table_stride(words));
     L.off_temp = take(dense_cap > 0 ? sizeof(float4) * (size_t)n : 0);
     L.total = o;
@@ -164,6 +170,7 @@ Work resolve(const fof_grid *g, void *ws)
     w.cnt = (int32_t *)(base + L.off_cnt);
     w.groot = (int32_t *)(base + L.off_groot);
     w.dense_list = (int32_t *)(base + L.off_dense);
+    w.big_list = (int32_t *)(base + L.off_big);
     w.table = (int32_t *)(base + L.off_table);
     w.temp = (float4 *)(base + L.off_temp);
     w.dense_threshold = g->dense_threshold;
@@ -174,6 +181,7 @@ Work resolve(const fof_grid *g, void *ws)
     w.block = g->block;
     w.n = g->n;
     w.ncell = g->ncell;
+    w.ntiles = g->ntiles;
     return w;
 }
 
@@ -194,7 +202,7 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
     if (tune && (tune->flags != 0 || tune->block < 0 || (tune->block % kWave) != 0 ||
                  tune->block > 1024 || !(tune->cell_side >= 0.0)))
         return FOF_EINVAL;
-    int64_t n = 0, ncell = 0;
+    int64_t n = 0, ncell = 0, ntiles = 0;
     int32_t mmax = 1, any_dense = 0;
     BoxDesc *out = (BoxDesc *)desc;
     const size_t need = sizeof(BoxDesc) * (size_t)nbox;
@@ -208,6 +216,9 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
         int rc = plan_box(box[k], count[k], tune, ncell, n, &d);
         if (rc)
             return rc;
+        d.tile_base = ntiles;
+        if (d.tiled)
+            ntiles += (int64_t)d.ntile[0] * d.ntile[1] * d.ntile[2];
         n += count[k];
         ncell += (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
         if (n > INT32_MAX || ncell > INT32_MAX - 1)
@@ -241,6 +252,7 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
     grid->n = n;
     grid->ncell = ncell;
     grid->dense_threshold = thr;
+    grid->ntiles = ntiles;
     grid->dense_cap = dense_cap;
     grid->table_words = words;
     grid->ws_bytes = L.total;

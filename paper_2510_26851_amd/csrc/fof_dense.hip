@@ -26,7 +26,8 @@ namespace fof {
 namespace {
 
 constexpr int kDenseBlock = 256;
-constexpr int kLdsCap = 2048;  // particles a dense cell may hold to be handled in LDS
+constexpr int kLdsCap = 2048;     // particles a dense cell may hold to be sorted in LDS
+constexpr int kSmallCell = 512;   // dense cells up to this size are linked by one wave
 
 __device__ __forceinline__ int find_box_cell(const BoxDesc *d, int nbox, int64_t c)
 {
@@ -47,12 +48,12 @@ struct CellXYZ {
 
 __device__ __forceinline__ CellXYZ cell_xyz(const BoxDesc &B, int64_t c)
 {
-    int64_t l = c - B.cell_base;
+    int64_t l = c - B.cell_base;  // z fastest, see coarse_cell
     CellXYZ r;
-    r.x = (int)(l % B.nc[0]);
-    l /= B.nc[0];
+    r.z = (int)(l % B.nc[2]);
+    l /= B.nc[2];
     r.y = (int)(l % B.nc[1]);
-    r.z = (int)(l / B.nc[1]);
+    r.x = (int)(l / B.nc[1]);
     return r;
 }
 
@@ -140,29 +141,50 @@ __device__ __forceinline__ int dense_count(const Counters *ctr, int cap)
 // ---------------------------------------------------------------------------------------
 __global__ void k_dense_reset(Counters *ctr)
 {
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         ctr->n_dense = 0;
+        ctr->n_big = 0;
+    }
 }
 
+// Cells holding more than dense_threshold particles get a dense id (one atomic per wave)
+// and a table slot; the per-cell counters are dead after the scan and hold the tag
+// (dense id, or -1 when the cell takes the plain path).
 __global__ void k_classify(Work w)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t c = gtid(); c < w.ncell; c += stride) {
-        const int32_t cnt = w.cell_start[c + 1] - w.cell_start[c];
-        if (cnt <= w.dense_threshold)
-            continue;
-        const BoxDesc &B = w.desc[find_box_cell(w.desc, w.nbox, c)];
-        int32_t tag = -1;
-        if (B.dense_ok) {
-            int32_t d = atomicAdd(&w.ctr->n_dense, 1);
+    const int64_t nround = (w.ncell + stride - 1) / stride;
+    for (int64_t k = 0; k < nround; ++k) {
+        const int64_t c = gtid() + k * stride;
+        bool big = false, want = false;
+        if (c < w.ncell) {
+            big = w.cell_start[c + 1] - w.cell_start[c] > w.dense_threshold;
+            if (big)
+                want = w.desc[find_box_cell(w.desc, w.nbox, c)].dense_ok != 0;
+        }
+        const uint64_t mask = ballot(want);
+        const int lane = lane_id();
+        int32_t d = -1;
+        if (mask) {
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            int32_t base = 0;
+            if (lane == leader)
+                base = atomicAdd(&w.ctr->n_dense, __popcll(mask));
+            base = __shfl(base, leader, kWave);
+            d = base + __popcll(mask & ((1ull << lane) - 1ull));
+        }
+        if (want) {
             if (d < w.dense_cap) {
                 w.dense_list[d] = (int32_t)c;
-                tag = d;
+                if (w.cell_start[c + 1] - w.cell_start[c] > kSmallCell)
+                    w.big_list[atomicAdd(&w.ctr->n_big, 1)] = d;
             } else {
                 atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_DENSE_CAP);
+                d = -1;
             }
         }
-        w.cell_count[c] = tag;  // the counters are dead after the scan: reused as tags
+        if (big)
+            w.cell_count[c] = want ? d : -1;
     }
 }
 
@@ -291,93 +313,156 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_sort(Work w)
 }
 
 // ---------------------------------------------------------------------------------------
-// Union-find over the units of one dense cell, in LDS.
+// Link stage.  Cells of up to kSmallCell particles are handled by one wave each (four per
+// block, each with its own LDS slice); larger cells by a whole block.  The code is shared
+// through the group type G.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kDenseBlock) void k_dense_cc(Work w)
+constexpr int kMaxOffsets = (7 * 7 * 7 - 1) / 2;  // forward offsets for R <= 3
+
+template <int G>
+struct Grp;
+
+template <>
+struct Grp<kWave> {
+    static constexpr int per_block = kDenseBlock / kWave;
+    static __device__ int tid() { return lane_id(); }
+    static __device__ int slot() { return threadIdx.x / kWave; }
+    static __device__ void sync()
+    {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+};
+
+template <>
+struct Grp<kDenseBlock> {
+    static constexpr int per_block = 1;
+    static __device__ int tid() { return threadIdx.x; }
+    static __device__ int slot() { return 0; }
+    static __device__ void sync() { __syncthreads(); }
+};
+
+template <int UMAX>
+struct CellLds {
+    int uf[UMAX];                   // union-find over unit ranks
+    unsigned long long umin[UMAX];  // (original index << 32 | sorted index) minimum
+    int ustart[UMAX + 1];           // absolute sorted index of each unit's first member
+    short ukey[UMAX];               // fine key of each unit
+    short uxyz[UMAX];               // fine coordinates: x | y << 4 | z << 8
+    short ucomp[UMAX];              // component number of each unit
+    uint32_t bits[kMaxTableWords];  // key bitmask of the cell (or of a neighbour, in cross)
+    int pre[kMaxTableWords];
+    short offs[kMaxOffsets];        // forward fine offsets: (dx+R) | (dy+R) << 4 | (dz+R) << 8
+    uint32_t pairbits[32];
+    int noff, ncomp, nnb, done;
+    int nb[13];                     // neighbour dense ids handled by this cell
+    short nbo[13];                  // their offsets: (ox+1) | (oy+1) << 2 | (oz+1) << 4
+};
+
+__device__ __forceinline__ int rank_in(const uint32_t *bits, const int *pre, int k)
 {
-    __shared__ float4 pbuf[kLdsCap];
-    __shared__ int kuf[kMaxFineKeys];
-    __shared__ int ucomp[kMaxFineKeys];      // component number by root key
-    __shared__ unsigned long long kmin[kMaxFineKeys];
-    __shared__ short ulist[kMaxFineKeys];    // key of each unit, by unit rank
-    __shared__ int ustart[kMaxFineKeys + 1]; // unit start relative to the cell, by rank
-    __shared__ int sh_ncomp;
+    return pre[k >> 5] + __popc(bits[k >> 5] & ((1u << (k & 31)) - 1u));
+}
 
-    const int nd = dense_count(w.ctr, w.dense_cap);
-    for (int d = blockIdx.x; d < nd; d += gridDim.x) {
-        const int64_t c = w.dense_list[d];
-        const int32_t s = w.cell_start[c];
-        const int32_t n = w.cell_start[c + 1] - s;
-        const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
-        const int m = B.m, K = m * m * m, R = B.R;
-        const int W = w.table_words;
-        int32_t *T = w.table + (int64_t)d * w.table_stride;
-        const int u = T[2];
-        const bool lds = n <= kLdsCap;
-        const float4 *mem = lds ? pbuf : (w.sorted + s);
-
-        if (threadIdx.x == 0)
-            sh_ncomp = 0;
-        for (int k = threadIdx.x; k < K; k += kDenseBlock) {
-            kuf[k] = k;
-            kmin[k] = ~0ull;
+// Own units of dense cell d: keys, coordinates, member ranges, key bitmask.
+template <int G, int UMAX>
+__device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n, int m, int u,
+                           CellLds<UMAX> &L)
+{
+    const int W = w.table_words;
+    const int t = Grp<G>::tid();
+    for (int q = t; q < W; q += G) {
+        L.bits[q] = (uint32_t)T[kTableHeader + q];
+        L.pre[q] = T[kTableHeader + W + q];
+    }
+    for (int r = t; r < u; r += G)
+        L.ustart[r] = w.rank[s + r];
+    if (t == 0)
+        L.ustart[u] = s + n;
+    Grp<G>::sync();
+    for (int q = t; q < W; q += G) {
+        uint32_t bits = L.bits[q];
+        int r = L.pre[q];
+        while (bits) {
+            const int k = q * 32 + __ffs(bits) - 1;
+            bits &= bits - 1u;
+            L.ukey[r] = (short)k;
+            L.uxyz[r] = (short)((k % m) | (((k / m) % m) << 4) | ((k / (m * m)) << 8));
+            ++r;
         }
-        if (lds)
-            for (int t = threadIdx.x; t < n; t += kDenseBlock)
-                pbuf[t] = w.sorted[s + t];
-        for (int r = threadIdx.x; r < u; r += kDenseBlock)
-            ustart[r] = w.rank[s + r] - s;
-        if (threadIdx.x == 0)
-            ustart[u] = n;
-        for (int q = threadIdx.x; q < W; q += kDenseBlock) {
-            uint32_t bits = (uint32_t)T[kTableHeader + q];
-            int r = T[kTableHeader + W + q];
-            while (bits) {
-                int bpos = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                ulist[r++] = (short)(q * 32 + bpos);
-            }
-        }
-        __syncthreads();
+    }
+    Grp<G>::sync();
+}
 
-        // member with the smallest original index in each unit
-        for (int r = threadIdx.x; r < u; r += kDenseBlock) {
-            unsigned long long best = ~0ull;
-            for (int t = ustart[r]; t < ustart[r + 1]; ++t) {
-                unsigned long long v =
-                    ((unsigned long long)(uint32_t)__float_as_int(mem[t].w) << 32) | (uint32_t)t;
-                best = v < best ? v : best;
-            }
-            kmin[ulist[r]] = best;
-        }
+template <int G, int UMAX>
+__device__ void cc_cell(const Work &w, int d, CellLds<UMAX> &L)
+{
+    const int t = Grp<G>::tid();
+    const int64_t c = w.dense_list[d];
+    const int32_t s = w.cell_start[c];
+    const int32_t n = w.cell_start[c + 1] - s;
+    const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
+    const int m = B.m, R = B.R;
+    int32_t *T = w.table + (int64_t)d * w.table_stride;
+    const int u = T[2];
 
-        // join units of this cell: forward offsets within [-R, R]^3, first friend pair wins
-        const int side = 2 * R + 1, half = (side * side * side - 1) / 2;
-        const double fs = (double)B.fine_side;
-        for (int task = threadIdx.x; task < u * half; task += kDenseBlock) {
-            const int r = task / half;
-            const int q = half + 1 + task % half;  // forward offsets follow the centre
-            const int dx = q % side - R, dy = (q / side) % side - R, dz = q / (side * side) - R;
-            const int ka = ulist[r];
-            const int ax = ka % m + dx, ay = (ka / m) % m + dy, az = ka / (m * m) + dz;
-            if (ax < 0 || ay < 0 || az < 0 || ax >= m || ay >= m || az >= m)
+    if (t == 0) {
+        L.ncomp = 0;
+        L.noff = 0;
+    }
+    load_units<G>(w, T, s, n, m, u, L);
+
+    // forward offsets in [-R, R]^3 that survive gap pruning
+    const int side = 2 * R + 1, half = (side * side * side - 1) / 2;
+    for (int q0 = 0; q0 < half; q0 += G) {
+        const int q = half + 1 + q0 + t;
+        bool keep = false;
+        int packed = 0;
+        if (q0 + t < half) {
+            const int dx = q % side, dy = (q / side) % side, dz = q / (side * side);
+            const double gx = fmax(0.0, (double)(abs(dx - R) - 1)) * B.fine_side;
+            const double gy = fmax(0.0, (double)(abs(dy - R) - 1)) * B.fine_side;
+            const double gz = fmax(0.0, (double)(abs(dz - R) - 1)) * B.fine_side;
+            keep = gx * gx + gy * gy + gz * gz < B.b2;
+            packed = dx | (dy << 4) | (dz << 8);
+        }
+        if (keep)
+            L.offs[atomicAdd(&L.noff, 1)] = (short)packed;
+    }
+    // unit minima
+    for (int r = t; r < u; r += G) {
+        unsigned long long best = ~0ull;
+        for (int i = L.ustart[r]; i < L.ustart[r + 1]; ++i) {
+            const unsigned long long v =
+                ((unsigned long long)(uint32_t)__float_as_int(w.sorted[i].w) << 32) | (uint32_t)i;
+            best = v < best ? v : best;
+        }
+        L.umin[r] = best;
+        L.uf[r] = r;
+    }
+    Grp<G>::sync();
+
+    // join units of this cell: first friend pair wins
+    const int noff = L.noff;
+    for (int r = t; r < u; r += G) {
+        const int xyz = L.uxyz[r];
+        const int ax = xyz & 15, ay = (xyz >> 4) & 15, az = xyz >> 8;
+        for (int q = 0; q < noff; ++q) {
+            const int o = L.offs[q];
+            const int bx = ax + (o & 15) - R, by = ay + ((o >> 4) & 15) - R, bz = az + (o >> 8) - R;
+            if ((unsigned)bx >= (unsigned)m || (unsigned)by >= (unsigned)m || (unsigned)bz >= (unsigned)m)
                 continue;
-            const double gx = fmax(0.0, (double)(abs(dx) - 1)) * fs;
-            const double gy = fmax(0.0, (double)(abs(dy) - 1)) * fs;
-            const double gz = fmax(0.0, (double)(abs(dz) - 1)) * fs;
-            if (gx * gx + gy * gy + gz * gz >= B.b2)
+            const int kb = (bz * m + by) * m + bx;
+            if (!((L.bits[kb >> 5] >> (kb & 31)) & 1u))
                 continue;
-            const int kb = (az * m + ay) * m + ax;
-            if (!table_has(T, kb))
+            const int rb = rank_in(L.bits, L.pre, kb);
+            if (lfind(L.uf, r) == lfind(L.uf, rb))
                 continue;
-            if (lfind(kuf, ka) == lfind(kuf, kb))
-                continue;
-            const int rb = table_rank(T, W, kb);
             bool hit = false;
-            for (int i = ustart[r]; i < ustart[r + 1] && !hit; ++i) {
-                const float4 p = mem[i];
-                for (int j = ustart[rb]; j < ustart[rb + 1]; ++j) {
-                    const float4 q4 = mem[j];
+            for (int i = L.ustart[r]; i < L.ustart[r + 1] && !hit; ++i) {
+                const float4 p = w.sorted[i];
+                for (int j = L.ustart[rb]; j < L.ustart[rb + 1]; ++j) {
+                    const float4 q4 = w.sorted[j];
                     if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
                         hit = true;
                         break;
@@ -385,173 +470,206 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_cc(Work w)
                 }
             }
             if (hit)
-                lunion(kuf, ka, kb);
+                lunion(L.uf, r, rb);
         }
-        __syncthreads();
-
-        // flatten, component minimum, component numbers
-        int rootreg[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = threadIdx.x + j * kDenseBlock;
-            rootreg[j] = r < u ? lfind(kuf, ulist[r]) : 0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = threadIdx.x + j * kDenseBlock;
-            if (r < u)
-                kuf[ulist[r]] = rootreg[j];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = threadIdx.x + j * kDenseBlock;
-            if (r < u) {
-                const int k = ulist[r];
-                if (rootreg[j] != k)
-                    atomicMin(kmin + rootreg[j], kmin[k]);
-                else
-                    ucomp[k] = atomicAdd(&sh_ncomp, 1);
-            }
-        }
-        __syncthreads();
-
-        // every member points at its component's smallest original index
-        for (int r = threadIdx.x; r < u; r += kDenseBlock) {
-            const int root = kuf[ulist[r]];
-            const unsigned long long lead = kmin[root];
-            const uint64_t packed = (lead & 0xffffffff00000000ull) | (uint32_t)(s + (uint32_t)lead);
-            for (int t = ustart[r]; t < ustart[r + 1]; ++t)
-                w.parent[s + t] = packed;
-            w.cnt[s + r] = ucomp[root];
-        }
-        if (threadIdx.x == 0)
-            T[1] = sh_ncomp;
-        __syncthreads();
     }
+    Grp<G>::sync();
+
+    // flatten: component minimum and component numbers
+    for (int r = t; r < u; r += G) {
+        const int root = lfind(L.uf, r);
+        if (root != r)
+            atomicMin(L.umin + root, L.umin[r]);
+        else
+            L.ucomp[r] = (short)atomicAdd(&L.ncomp, 1);
+    }
+    Grp<G>::sync();
+
+    // every member points at its component's smallest original index
+    for (int r = t; r < u; r += G) {
+        const int root = lfind(L.uf, r);
+        const unsigned long long lead = L.umin[root];
+        for (int i = L.ustart[r]; i < L.ustart[r + 1]; ++i)
+            w.parent[i] = lead;
+        w.cnt[s + r] = L.ucomp[root];
+    }
+    // mark every particle of the cell for the compress pass
+    for (int64_t q = (s >> 6) + t; q <= ((int64_t)s + n - 1) >> 6; q += G) {
+        const int64_t lo = q << 6, hi = lo + 64;
+        const int64_t a = lo > s ? lo : s, b = hi < s + n ? hi : s + n;
+        const uint64_t mask = (b - a == 64) ? ~0ull : (((1ull << (b - a)) - 1ull) << (a - lo));
+        atomicOr((unsigned long long *)(w.flags + q), (unsigned long long)mask);
+    }
+    if (t == 0)
+        T[1] = L.ncomp;
+    Grp<G>::sync();
 }
 
-// ---------------------------------------------------------------------------------------
-// Units of neighbouring dense cells.
-// ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kDenseBlock) void k_dense_cross(Work w)
+template <int G, int UMAX>
+__device__ void cross_cell(const Work &w, int d, CellLds<UMAX> &L)
 {
-    __shared__ short ukey[kMaxFineKeys];
-    __shared__ int ubeg[kMaxFineKeys + 1];
-    __shared__ int ucmp[kMaxFineKeys];
-    __shared__ uint32_t pairbits[32];
-    __shared__ int done;
+    const int t = Grp<G>::tid();
+    const int64_t c = w.dense_list[d];
+    const int32_t s = w.cell_start[c];
+    const int32_t n = w.cell_start[c + 1] - s;
+    const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
+    const CellXYZ cc = cell_xyz(B, c);
+    const int m = B.m, R = B.R;
+    const int W = w.table_words;
+    const int32_t *T = w.table + (int64_t)d * w.table_stride;
+    const int u = T[2], ncomp = T[1];
 
-    const int nd = dense_count(w.ctr, w.dense_cap);
-    for (int d = blockIdx.x; d < nd; d += gridDim.x) {
-        const int64_t c = w.dense_list[d];
-        const int32_t s = w.cell_start[c];
-        const int32_t n = w.cell_start[c + 1] - s;
-        const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
-        const CellXYZ cc = cell_xyz(B, c);
-        const int m = B.m, R = B.R;
-        const int W = w.table_words;
-        const int32_t *T = w.table + (int64_t)d * w.table_stride;
-        const int u = T[2], ncomp = T[1];
-
-        for (int r = threadIdx.x; r < u; r += kDenseBlock) {
-            ubeg[r] = w.rank[s + r];
-            ucmp[r] = w.cnt[s + r];
-        }
-        if (threadIdx.x == 0)
-            ubeg[u] = s + n;
-        for (int q = threadIdx.x; q < W; q += kDenseBlock) {
-            uint32_t bits = (uint32_t)T[kTableHeader + q];
-            int r = T[kTableHeader + W + q];
-            while (bits) {
-                int bpos = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                ukey[r++] = (short)(q * 32 + bpos);
+    // neighbour dense cells with a higher index: this cell handles those pairs
+    if (t == 0)
+        L.nnb = 0;
+    Grp<G>::sync();
+    if (t < 27 && t != 13) {
+        const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = t / 9 - 1;
+        int nx = cc.x + ox, ny = cc.y + oy, nz = cc.z + oz;
+        nx += nx < 0 ? B.nc[0] : (nx >= B.nc[0] ? -B.nc[0] : 0);
+        ny += ny < 0 ? B.nc[1] : (ny >= B.nc[1] ? -B.nc[1] : 0);
+        nz += nz < 0 ? B.nc[2] : (nz >= B.nc[2] ? -B.nc[2] : 0);
+        const int64_t c2 = coarse_cell(B, nx, ny, nz);
+        if (c2 > c && w.cell_start[c2 + 1] - w.cell_start[c2] > w.dense_threshold) {
+            const int32_t d2 = w.cell_count[c2];
+            if (d2 >= 0) {
+                const int k = atomicAdd(&L.nnb, 1);
+                L.nb[k] = d2;
+                L.nbo[k] = (short)((ox + 1) | ((oy + 1) << 2) | ((oz + 1) << 4));
             }
         }
-        __syncthreads();
+    }
+    Grp<G>::sync();
+    const int nnb = L.nnb;
+    if (nnb == 0) {  // uniform: every thread read the same count
+        Grp<G>::sync();
+        return;
+    }
+    for (int r = t; r < u; r += G) {
+        L.ustart[r] = w.rank[s + r];
+        L.ucomp[r] = (short)w.cnt[s + r];
+    }
+    if (t == 0)
+        L.ustart[u] = s + n;
+    for (int q = t; q < W; q += G) {
+        uint32_t bits = (uint32_t)T[kTableHeader + q];
+        int r = T[kTableHeader + W + q];
+        while (bits) {
+            const int k = q * 32 + __ffs(bits) - 1;
+            bits &= bits - 1u;
+            L.uxyz[r] = (short)((k % m) | (((k / m) % m) << 4) | ((k / (m * m)) << 8));
+            ++r;
+        }
+    }
+    Grp<G>::sync();
 
-        for (int o = 0; o < 27; ++o) {
-            if (o == 13)
-                continue;
-            const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-            int nx = cc.x + ox, ny = cc.y + oy, nz = cc.z + oz;
-            nx += nx < 0 ? B.nc[0] : (nx >= B.nc[0] ? -B.nc[0] : 0);
-            ny += ny < 0 ? B.nc[1] : (ny >= B.nc[1] ? -B.nc[1] : 0);
-            nz += nz < 0 ? B.nc[2] : (nz >= B.nc[2] ? -B.nc[2] : 0);
-            const int64_t c2 = coarse_cell(B, nx, ny, nz);
-            if (c2 <= c)
-                continue;  // each pair of cells once, by the lower index
-            const int32_t s2 = w.cell_start[c2];
-            const int32_t n2 = w.cell_start[c2 + 1] - s2;
-            if (n2 <= w.dense_threshold)
-                continue;
-            const int32_t d2 = w.cell_count[c2];
-            if (d2 < 0)
-                continue;  // cell without tables: its particles search themselves
-            const int32_t *T2 = w.table + (int64_t)d2 * w.table_stride;
-            const int u2 = T2[2], ncomp2 = T2[1];
-            const bool dedupe = ncomp * ncomp2 <= 1024;
-            const bool single = ncomp == 1 && ncomp2 == 1;
-            if (threadIdx.x < 32)
-                pairbits[threadIdx.x] = 0u;
-            if (threadIdx.x == 0)
-                done = 0;
-            __syncthreads();
-            for (int r = threadIdx.x; r < u; r += kDenseBlock) {
-                if (__hip_atomic_load(&done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-                    break;
-                const int ka = ukey[r];
-                // unit A in the frame of the neighbour cell
-                const int rx = ka % m - ox * m, ry = (ka / m) % m - oy * m, rz = ka / (m * m) - oz * m;
-                const int x0 = max(0, rx - R), x1 = min(m - 1, rx + R);
-                const int y0 = max(0, ry - R), y1 = min(m - 1, ry + R);
-                const int z0 = max(0, rz - R), z1 = min(m - 1, rz + R);
-                bool stop = false;
-                for (int bz = z0; bz <= z1 && !stop; ++bz)
-                    for (int by = y0; by <= y1 && !stop; ++by)
-                        for (int bx = x0; bx <= x1 && !stop; ++bx) {
-                            const double gx = fmax(0.0, (double)(abs(bx - rx) - 1)) * B.fine_side;
-                            const double gy = fmax(0.0, (double)(abs(by - ry) - 1)) * B.fine_side;
-                            const double gz = fmax(0.0, (double)(abs(bz - rz) - 1)) * B.fine_side;
-                            if (gx * gx + gy * gy + gz * gz >= B.b2)
-                                continue;
-                            const int kb = (bz * m + by) * m + bx;
-                            if (!table_has(T2, kb))
-                                continue;
-                            const int rb = table_rank(T2, W, kb);
-                            const int cb = w.cnt[s2 + rb];
-                            const int bit = ucmp[r] * ncomp2 + cb;
-                            if (dedupe && ((pairbits[bit >> 5] >> (bit & 31)) & 1u))
-                                continue;
-                            const int32_t b0 = w.rank[s2 + rb];
-                            const int32_t b1 = rb + 1 < u2 ? w.rank[s2 + rb + 1] : s2 + n2;
-                            bool hit = false;
-                            for (int32_t i = ubeg[r]; i < ubeg[r + 1] && !hit; ++i) {
-                                const float4 p = w.sorted[i];
-                                for (int32_t j = b0; j < b1; ++j) {
-                                    const float4 q4 = w.sorted[j];
-                                    if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
-                                        uf_union(w.parent, (uint32_t)i, (uint32_t)j);
-                                        hit = true;
-                                        break;
-                                    }
-                                }
-                            }
-                            if (hit) {
-                                if (dedupe)
-                                    atomicOr(pairbits + (bit >> 5), 1u << (bit & 31));
-                                if (single) {
-                                    __hip_atomic_store(&done, 1, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                                    stop = true;
+    for (int k = 0; k < nnb; ++k) {
+        const int d2 = L.nb[k];
+        const int o = L.nbo[k];
+        const int ox = (o & 3) - 1, oy = ((o >> 2) & 3) - 1, oz = (o >> 4) - 1;
+        const int32_t *T2 = w.table + (int64_t)d2 * w.table_stride;
+        const int64_t c2 = T2[0];
+        const int32_t s2 = w.cell_start[c2];
+        const int32_t n2 = w.cell_start[c2 + 1] - s2;
+        const int u2 = T2[2], ncomp2 = T2[1];
+        const bool dedupe = ncomp * ncomp2 <= 1024;
+        const bool single = ncomp == 1 && ncomp2 == 1;
+        for (int q = t; q < W; q += G) {
+            L.bits[q] = (uint32_t)T2[kTableHeader + q];
+            L.pre[q] = T2[kTableHeader + W + q];
+        }
+        for (int q = t; q < 32; q += G)
+            L.pairbits[q] = 0u;
+        if (t == 0)
+            L.done = 0;
+        Grp<G>::sync();
+        for (int r = t; r < u; r += G) {
+            if (__hip_atomic_load(&L.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                break;
+            const int xyz = L.uxyz[r];
+            // unit r in the frame of the neighbour cell
+            const int rx = (xyz & 15) - ox * m, ry = ((xyz >> 4) & 15) - oy * m,
+                      rz = (xyz >> 8) - oz * m;
+            const int x0 = max(0, rx - R), x1 = min(m - 1, rx + R);
+            const int y0 = max(0, ry - R), y1 = min(m - 1, ry + R);
+            const int z0 = max(0, rz - R), z1 = min(m - 1, rz + R);
+            bool stop = false;
+            for (int bz = z0; bz <= z1 && !stop; ++bz)
+                for (int by = y0; by <= y1 && !stop; ++by)
+                    for (int bx = x0; bx <= x1 && !stop; ++bx) {
+                        const double gx = fmax(0.0, (double)(abs(bx - rx) - 1)) * B.fine_side;
+                        const double gy = fmax(0.0, (double)(abs(by - ry) - 1)) * B.fine_side;
+                        const double gz = fmax(0.0, (double)(abs(bz - rz) - 1)) * B.fine_side;
+                        if (gx * gx + gy * gy + gz * gz >= B.b2)
+                            continue;
+                        const int kb = (bz * m + by) * m + bx;
+                        if (!((L.bits[kb >> 5] >> (kb & 31)) & 1u))
+                            continue;
+                        const int rb = rank_in(L.bits, L.pre, kb);
+                        const int cb = w.cnt[s2 + rb];
+                        const int bit = L.ucomp[r] * ncomp2 + cb;
+                        if (dedupe && ((L.pairbits[bit >> 5] >> (bit & 31)) & 1u))
+                            continue;
+                        const int32_t b0 = w.rank[s2 + rb];
+                        const int32_t b1 = rb + 1 < u2 ? w.rank[s2 + rb + 1] : s2 + n2;
+                        bool hit = false;
+                        for (int32_t i = L.ustart[r]; i < L.ustart[r + 1] && !hit; ++i) {
+                            const float4 p = w.sorted[i];
+                            for (int32_t j = b0; j < b1; ++j) {
+                                const float4 q4 = w.sorted[j];
+                                if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
+                                    uf_union(w.parent, (uint32_t)i, (uint32_t)j);
+                                    hit = true;
+                                    break;
                                 }
                             }
                         }
-            }
-            __syncthreads();
+                        if (hit) {
+                            if (dedupe)
+                                atomicOr(L.pairbits + (bit >> 5), 1u << (bit & 31));
+                            if (single) {
+                                __hip_atomic_store(&L.done, 1, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                                stop = true;
+                            }
+                        }
+                    }
         }
+        Grp<G>::sync();
+    }
+}
+
+// Small cells: one wave per cell, iterating over every dense id and skipping big cells.
+template <bool kCross>
+__global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
+{
+    __shared__ CellLds<kSmallCell> lds[Grp<kWave>::per_block];
+    CellLds<kSmallCell> &L = lds[Grp<kWave>::slot()];
+    const int nd = dense_count(w.ctr, w.dense_cap);
+    const int stride = gridDim.x * Grp<kWave>::per_block;
+    for (int d = blockIdx.x * Grp<kWave>::per_block + Grp<kWave>::slot(); d < nd; d += stride) {
+        const int64_t c = w.dense_list[d];
+        if (w.cell_start[c + 1] - w.cell_start[c] > kSmallCell)
+            continue;
+        if (kCross)
+            cross_cell<kWave>(w, d, L);
+        else
+            cc_cell<kWave>(w, d, L);
+    }
+}
+
+// Big cells: one block per cell, over the list of big dense ids.
+template <bool kCross>
+__global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
+{
+    __shared__ CellLds<kMaxFineKeys> L;
+    const int nb = __hip_atomic_load(&w.ctr->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int k = blockIdx.x; k < nb; k += gridDim.x) {
+        const int d = w.big_list[k];
+        if (kCross)
+            cross_cell<kDenseBlock>(w, d, L);
+        else
+            cc_cell<kDenseBlock>(w, d, L);
     }
 }
 
@@ -581,10 +699,11 @@ hipError_t launch_dense(const Work &w, hipStream_t s)
 {
     if (w.dense_cap <= 0 || w.dense_threshold < 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_dense_cc, dim3(persistent_blocks(w.dense_cap)), dim3(kDenseBlock), 0, s,
-                       w);
-    hipLaunchKernelGGL(k_dense_cross, dim3(persistent_blocks(w.dense_cap)), dim3(kDenseBlock), 0,
-                       s, w);
+    const unsigned pb = persistent_blocks(w.dense_cap);
+    hipLaunchKernelGGL(k_dense_small<false>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_big<false>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_small<true>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_big<true>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     return hipGetLastError();
 }
 

@@ -19,6 +19,43 @@ namespace fof {
 
 namespace {
 
+// Runs of equal keys inside a wave (consecutive lanes): each lane learns the first lane of
+// its run; the last lane of a run performs the run's single atomic.  Members of one group
+// sit next to each other in cell-sorted order, so a large group costs one atomic per run
+// instead of one per member.
+struct Run {
+    int head;   // first lane of this lane's run
+    bool tail;  // last lane of its run
+};
+
+__device__ __forceinline__ Run wave_run(int64_t key)
+{
+    const int lane = lane_id();
+    const int64_t prev = __shfl_up(key, 1, kWave);
+    const int64_t next = __shfl_down(key, 1, kWave);
+    const bool head = lane == 0 || prev != key;
+    const uint64_t heads = ballot(head);
+    const uint64_t below = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+    Run r;
+    r.head = 63 - __clzll((long long)below);
+    r.tail = lane == kWave - 1 || next != key;
+    return r;
+}
+
+// Inclusive sum over the lane's run (segmented scan); exact: no cancellation.
+template <typename T>
+__device__ __forceinline__ T run_sum(T v, int head)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const T u = __shfl_up(v, o, kWave);
+        if (lane - o >= head)
+            v += u;
+    }
+    return v;
+}
+
 __device__ __forceinline__ bool flagged(const uint64_t *flags, int64_t i)
 {
     return (flags[i >> 6] >> (i & 63)) & 1ull;
@@ -50,9 +87,13 @@ __global__ void g_zero(int64_t n, const uint64_t *__restrict__ flags, int32_t *_
 __global__ void g_count(int64_t n, const uint64_t *__restrict__ parent,
                         const uint64_t *__restrict__ flags, int32_t *__restrict__ cnt)
 {
-    int64_t i = gtid();
-    if (i < n && flagged(flags, i))
-        atomicAdd(cnt + uf_idx(parent[i]), 1);
+    const int64_t i = gtid();
+    const bool in = i < n && flagged(flags, i);
+    const int64_t key = in ? (int64_t)uf_idx(parent[i]) : -1 - (int64_t)lane_id();
+    const Run r = wave_run(key);
+    const int c = run_sum(in ? 1 : 0, r.head);
+    if (in && r.tail)
+        atomicAdd(cnt + key, c);
 }
 
 __global__ void g_keep(const float4 *__restrict__ sorted, int64_t n,
@@ -141,26 +182,47 @@ __global__ void g_sum(const float4 *__restrict__ sorted, int64_t n,
                       const float *__restrict__ vel, int32_t cap, double *__restrict__ com,
                       double *__restrict__ vmean)
 {
-    int64_t i = gtid();
-    if (i >= n || !flagged(flags, i))
-        return;
-    const uint64_t r = parent[i];
-    const int32_t g = group_of(keep, keep_prefix, uf_key(r));
-    if (g < 0 || g >= cap)
-        return;
-    const float4 p = sorted[i];
+    const int64_t i = gtid();
+    int32_t g = -1;
+    uint64_t r = 0;
+    if (i < n && flagged(flags, i)) {
+        r = parent[i];
+        g = group_of(keep, keep_prefix, uf_key(r));
+        if (g >= cap)
+            g = -1;
+    }
+    const bool in = g >= 0;
+    const Run run = wave_run(in ? (int64_t)g : -1 - (int64_t)lane_id());
+    double d[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    if (in) {
+        const float4 p = sorted[i];
+        if (com) {
+            const BoxDesc &B = desc[find_box(desc, nbox, i)];
+            const float4 q = sorted[uf_idx(r)];
+            d[0] = min_image((double)p.x - (double)q.x, B.L[0], B.halfL[0]);
+            d[1] = min_image((double)p.y - (double)q.y, B.L[1], B.halfL[1]);
+            d[2] = min_image((double)p.z - (double)q.z, B.L[2], B.halfL[2]);
+        }
+        if (vel && vmean) {
+            const int64_t o = __float_as_int(p.w);
+            v[0] = (double)vel[3 * o + 0];
+            v[1] = (double)vel[3 * o + 1];
+            v[2] = (double)vel[3 * o + 2];
+        }
+    }
     if (com) {
-        const BoxDesc &B = desc[find_box(desc, nbox, i)];
-        const float4 q = sorted[uf_idx(r)];
-        atomicAdd(com + 3 * g + 0, min_image((double)p.x - (double)q.x, B.L[0], B.halfL[0]));
-        atomicAdd(com + 3 * g + 1, min_image((double)p.y - (double)q.y, B.L[1], B.halfL[1]));
-        atomicAdd(com + 3 * g + 2, min_image((double)p.z - (double)q.z, B.L[2], B.halfL[2]));
+        for (int a = 0; a < 3; ++a) {
+            const double sa = run_sum(d[a], run.head);
+            if (in && run.tail)
+                atomicAdd(com + 3 * g + a, sa);
+        }
     }
     if (vel && vmean) {
-        const int64_t o = __float_as_int(p.w);
-        atomicAdd(vmean + 3 * g + 0, (double)vel[3 * o + 0]);
-        atomicAdd(vmean + 3 * g + 1, (double)vel[3 * o + 1]);
-        atomicAdd(vmean + 3 * g + 2, (double)vel[3 * o + 2]);
+        for (int a = 0; a < 3; ++a) {
+            const double sa = run_sum(v[a], run.head);
+            if (in && run.tail)
+                atomicAdd(vmean + 3 * g + a, sa);
+        }
     }
 }
 
@@ -203,19 +265,26 @@ __global__ void g_dev(const float4 *__restrict__ sorted, int64_t n,
                       const float *__restrict__ vel, int32_t cap,
                       const double *__restrict__ vmean, double *__restrict__ sigv)
 {
-    int64_t i = gtid();
-    if (i >= n || !flagged(flags, i))
-        return;
-    const int32_t g = group_of(keep, keep_prefix, uf_key(parent[i]));
-    if (g < 0 || g >= cap)
-        return;
-    const int64_t o = __float_as_int(sorted[i].w);
-    double s = 0.0;
-    for (int a = 0; a < 3; ++a) {
-        double d = (double)vel[3 * o + a] - vmean[3 * g + a];
-        s += d * d;
+    const int64_t i = gtid();
+    int32_t g = -1;
+    if (i < n && flagged(flags, i)) {
+        g = group_of(keep, keep_prefix, uf_key(parent[i]));
+        if (g >= cap)
+            g = -1;
     }
-    atomicAdd(sigv + g, s);
+    const bool in = g >= 0;
+    const Run run = wave_run(in ? (int64_t)g : -1 - (int64_t)lane_id());
+    double s2 = 0.0;
+    if (in) {
+        const int64_t o = __float_as_int(sorted[i].w);
+        for (int a = 0; a < 3; ++a) {
+            const double dv = (double)vel[3 * o + a] - vmean[3 * g + a];
+            s2 += dv * dv;
+        }
+    }
+    s2 = run_sum(s2, run.head);
+    if (in && run.tail)
+        atomicAdd(sigv + g, s2);
 }
 
 __global__ void g_sig(const int32_t *__restrict__ n_groups, int32_t cap,

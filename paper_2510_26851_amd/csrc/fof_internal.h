@@ -20,18 +20,23 @@ constexpr int kMaxFine = 10;                   // fine cells per coarse cell per
 constexpr int kMaxFineKeys = kMaxFine * kMaxFine * kMaxFine;
 constexpr int kMaxTableWords = (kMaxFineKeys + 31) / 32;
 constexpr int kTableHeader = 4;  // dense-cell table: cell, ncomp, units, reserved
+// Link tiles: kTileX x kTileY x kTileZ coarse cells per block (z fastest, like the cells).
+constexpr int kTileX = 2, kTileY = 4, kTileZ = 32;
 
 // Per-box constants, computed once on the host in double precision and copied into the
 // workspace by the caller.  Layout is private to this library.
 struct alignas(16) BoxDesc {
     int64_t off;        // first particle of the box in the concatenated arrays
     int64_t cell_base;  // first coarse cell of the box in the concatenated cell table
+    int64_t tile_base;  // first link tile of the box (tiled boxes only)
     int32_t n;          // particles in the box
     int32_t m;          // fine (clique) cells per coarse cell per axis
     int32_t nc[3];      // coarse cells per axis
     int32_t nf[3];      // fine cells per axis (nc * m)
     int32_t R;          // fine-cell reach: a friend lies at most R fine cells away per axis
     int32_t dense_ok;   // 1 if this box may use the clique-cell path (>= 3 cells per axis)
+    int32_t tiled;      // 1 if the LDS-tiled link kernel handles this box
+    int32_t ntile[3];   // link tiles per axis
     double L[3];        // box lengths
     double halfL[3];    // 0.5 * L (exact)
     double b2;          // b * b, rounded once in double
@@ -45,7 +50,7 @@ struct alignas(16) BoxDesc {
 struct Counters {
     int32_t status;
     int32_t n_dense;     // dense cells found
-    int32_t n_units;     // clique units in dense cells
+    int32_t n_big;       // dense cells linked by a whole block
     int32_t pad[61];
 };
 
@@ -74,9 +79,23 @@ __device__ __forceinline__ int fine_index(float x, float inv, int nf)
     return f < nf - 1 ? f : nf - 1;
 }
 
+// Linear coarse cell id with z fastest (C order over (ix, iy, iz)).  The paper's grid uses
+// x fastest; z fastest makes the counting sort nearly sequential for particles stored in
+// C order of a Lagrangian lattice, the usual N-body layout.  No result depends on it.
 __device__ __forceinline__ int64_t coarse_cell(const BoxDesc &B, int ix, int iy, int iz)
 {
-    return B.cell_base + ((int64_t)iz * B.nc[1] + iy) * B.nc[0] + ix;
+    return B.cell_base + ((int64_t)ix * B.nc[1] + iy) * B.nc[2] + iz;
+}
+
+// Block index remapped so that the blocks the hardware hands to one XCD (blockIdx mod 8)
+// process one contiguous stretch of the cell-sorted particles, keeping neighbour cells in
+// that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int64_t g = gridDim.x, b = blockIdx.x;
+    const int64_t per = g / 8, rem = g % 8, x = b % 8, k = b / 8;
+    // XCD x owns per + (x < rem) consecutive logical blocks
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + k;
 }
 
 // Exact link predicate: per axis d = (double)xi - (double)xj, wrapped once by +-L when
@@ -174,6 +193,7 @@ __device__ __forceinline__ void uf_union(uint64_t *P, uint32_t a, uint32_t b)
 // Small helpers
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int64_t gtid_xcd() { return xcd_block() * blockDim.x + threadIdx.x; }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
@@ -200,12 +220,14 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
     int32_t *cnt;
     int32_t *groot;
     int32_t *dense_list;  // dense cell ids in discovery order
+    int32_t *big_list;    // dense ids of cells too large for one wave
     int32_t *table;       // per dense cell: header, key bitmask, popcount prefix
     float4 *temp;         // staging for dense cells too large for LDS
     int32_t nbox;
     int32_t block;
     int64_t n;
     int64_t ncell;
+    int64_t ntiles;           // link tiles over all tiled boxes
     int32_t dense_threshold;  // cells with more particles take the clique path (< 0: never)
     int32_t dense_cap;        // dense cells with tables
     int32_t table_words;      // words of one key bitmask
@@ -215,6 +237,7 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch,
                            hipStream_t s);
 hipError_t launch_scan_popc(const uint32_t *in, int32_t *out, int64_t n, int32_t *scratch,

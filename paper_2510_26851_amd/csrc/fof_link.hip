@@ -99,66 +99,290 @@ __device__ bool link_dense_neighbour(const Work &w, const BoxDesc &B, uint32_t i
     return any;
 }
 
-__global__ void k_link(Work w, int32_t *__restrict__ root)
+// Whether particle p (sorted index i) sits in a cell linked by the dense kernels.
+__device__ __forceinline__ bool in_dense_cell(const Work &w, const BoxDesc &B, int ix, int iy,
+                                              int iz)
 {
-    const int64_t i = gtid();
-    const bool dense_on = w.dense_cap > 0 && w.dense_threshold >= 0;
+    if (!(w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok))
+        return false;
+    const int64_t c0 = coarse_cell(B, ix, iy, iz);
+    return w.cell_start[c0 + 1] - w.cell_start[c0] > w.dense_threshold && w.cell_count[c0] >= 0;
+}
+
+// Candidate search of one particle straight from global memory.  Returns true if it has a
+// friend (its hooks are done).
+__device__ bool link_particle_global(const Work &w, const BoxDesc &B, int64_t i, float4 p,
+                                     int ix, int iy, int iz)
+{
+    const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
     bool has_friend = false;
-    if (i < w.n) {
-        const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, i)];
-        const float4 p = w.sorted[i];
-        const int ix = fine_index(p.x, B.inv_fine[0], B.nf[0]) / B.m;
-        const int iy = fine_index(p.y, B.inv_fine[1], B.nf[1]) / B.m;
-        const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
-        const bool box_dense = dense_on && B.dense_ok;
-        bool own_dense = false;
-        if (box_dense) {
-            const int64_t c0 = coarse_cell(B, ix, iy, iz);
-            own_dense = w.cell_start[c0 + 1] - w.cell_start[c0] > w.dense_threshold &&
-                        w.cell_count[c0] >= 0;
-        }
-        if (own_dense) {
-            has_friend = true;  // linked by the dense kernels, resolved by compress
-        } else {
-            const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
-            const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
-            const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
+    const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
+    const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
+    const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
+    for (int ox = sx.lo; ox <= sx.hi; ++ox) {
+        const int cx = wrap_cell(ix + ox, B.nc[0]);
+        for (int oy = sy.lo; oy <= sy.hi; ++oy) {
+            const int cy = wrap_cell(iy + oy, B.nc[1]);
             for (int oz = sz.lo; oz <= sz.hi; ++oz) {
                 const int cz = wrap_cell(iz + oz, B.nc[2]);
-                for (int oy = sy.lo; oy <= sy.hi; ++oy) {
-                    const int cy = wrap_cell(iy + oy, B.nc[1]);
-                    for (int ox = sx.lo; ox <= sx.hi; ++ox) {
-                        const int cx = wrap_cell(ix + ox, B.nc[0]);
-                        const int64_t c = coarse_cell(B, cx, cy, cz);
-                        const int32_t s = w.cell_start[c], e = w.cell_start[c + 1];
-                        if (box_dense && e - s > w.dense_threshold) {
-                            const int32_t d2 = w.cell_count[c];
-                            if (d2 >= 0) {
-                                has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy,
-                                                                   iz, ox, oy, oz, s, e - s, d2);
-                                continue;
-                            }
-                        }
-                        for (int32_t j = s; j < e; ++j) {
-                            if (j == i)
-                                continue;
-                            const float4 q = w.sorted[j];
-                            if (linked(B, p.x, p.y, p.z, q.x, q.y, q.z)) {
-                                has_friend = true;
-                                if (i < j)
-                                    uf_union(w.parent, (uint32_t)i, (uint32_t)j);
-                            }
-                        }
+                const int64_t c = coarse_cell(B, cx, cy, cz);
+                const int32_t s = w.cell_start[c], e = w.cell_start[c + 1];
+                if (box_dense && e - s > w.dense_threshold) {
+                    const int32_t d2 = w.cell_count[c];
+                    if (d2 >= 0) {
+                        has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz, ox,
+                                                           oy, oz, s, e - s, d2);
+                        continue;
+                    }
+                }
+                for (int32_t j = s; j < e; ++j) {
+                    if (j == i)
+                        continue;
+                    const float4 q = w.sorted[j];
+                    if (linked(B, p.x, p.y, p.z, q.x, q.y, q.z)) {
+                        has_friend = true;
+                        if (i < j)
+                            uf_union(w.parent, (uint32_t)i, (uint32_t)j);
                     }
                 }
             }
         }
-        if (!has_friend)
-            root[__float_as_int(p.w)] = __float_as_int(p.w);
     }
-    const uint64_t m = ballot(has_friend);
-    if (lane_id() == 0 && i < w.n)
-        w.flags[i >> 6] = m;
+    return has_friend;
+}
+
+__device__ __forceinline__ void finish_particle(const Work &w, int32_t *root, int64_t i,
+                                                int32_t orig, bool has_friend)
+{
+    if (has_friend)
+        atomicOr((unsigned long long *)(w.flags + (i >> 6)), 1ull << (i & 63));
+    else
+        root[orig] = orig;
+}
+
+// Per-particle kernel for boxes the tiled kernel does not take (fewer than 3 cells on an
+// axis).  Dense-cell particles were marked by the dense kernels.
+__global__ void k_link(Work w, int32_t *__restrict__ root)
+{
+    const int64_t i = gtid_xcd();
+    if (i >= w.n)
+        return;
+    const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, i)];
+    if (B.tiled)
+        return;
+    const float4 p = w.sorted[i];
+    const int ix = fine_index(p.x, B.inv_fine[0], B.nf[0]) / B.m;
+    const int iy = fine_index(p.y, B.inv_fine[1], B.nf[1]) / B.m;
+    const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
+    if (in_dense_cell(w, B, ix, iy, iz))
+        return;
+    finish_particle(w, root, i, __float_as_int(p.w), link_particle_global(w, B, i, p, ix, iy, iz));
+}
+
+// ---------------------------------------------------------------------------------------
+// LDS-tiled linking.  A block owns kTileX x kTileY x kTileZ coarse cells; it stages those
+// cells and a one-cell halo into LDS (each (x, y) row of the halo is a contiguous run of
+// cells and particles), then every own particle tests its candidates from LDS.  Cells
+// with clique tables are not staged: particles reach them through their unit tables.  A
+// tile whose staged particles do not fit falls back to the global search.
+// ---------------------------------------------------------------------------------------
+constexpr int kHX = kTileX + 2, kHY = kTileY + 2, kHZ = kTileZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;
+constexpr int kTileBlock = 256;
+constexpr int kTileCap = 2048;  // staged particles per tile
+constexpr int kRows = kTileX * kTileY;
+
+// Box owning tile t: the last box whose first tile is <= t.  Boxes without tiles share
+// their tile_base with the next box, which comes later, so they are never chosen.
+__device__ __forceinline__ int find_box_tile(const BoxDesc *d, int nbox, int64_t t)
+{
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile_base <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Periodic cell index for any offset (halo cells of a tile may lie several cells beyond the
+// box when the box has fewer cells than the tile).
+__device__ __forceinline__ int mod_cell(int c, int nc)
+{
+    int r = c % nc;
+    return r < 0 ? r + nc : r;
+}
+
+__global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__restrict__ root)
+{
+    __shared__ float4 part[kTileCap];
+    __shared__ int hoff[kHalo + 1];   // staged offset of each halo cell
+    __shared__ int gst[kHalo];        // global start of each halo cell
+    __shared__ int htag[kHalo];       // dense id (>= 0) or -1
+    __shared__ int rowoff[kRows + 1]; // own particles before each own row
+    __shared__ int scr[kTileBlock / kWave];
+    __shared__ int overflow;
+
+    const int64_t tile = xcd_block();
+    if (tile >= w.ntiles)
+        return;
+    const BoxDesc &B = w.desc[find_box_tile(w.desc, w.nbox, tile)];
+    int64_t tl = tile - B.tile_base;
+    const int tz = (int)(tl % B.ntile[2]);
+    tl /= B.ntile[2];
+    const int ty = (int)(tl % B.ntile[1]);
+    const int tx = (int)(tl / B.ntile[1]);
+    const int x0 = tx * kTileX, y0 = ty * kTileY, z0 = tz * kTileZ;
+    const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
+    const int t = threadIdx.x;
+
+    // halo cells: counts, global starts, dense tags
+    int cnt_local[(kHalo + kTileBlock - 1) / kTileBlock];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < (kHalo + kTileBlock - 1) / kTileBlock; ++k) {
+        const int h = t * ((kHalo + kTileBlock - 1) / kTileBlock) + k;
+        int cnt = 0;
+        if (h < kHalo) {
+            const int hz = h % kHZ, hy = (h / kHZ) % kHY, hx = h / (kHZ * kHY);
+            const int cx = mod_cell(x0 - 1 + hx, B.nc[0]);
+            const int cy = mod_cell(y0 - 1 + hy, B.nc[1]);
+            const int cz = mod_cell(z0 - 1 + hz, B.nc[2]);
+            const int64_t c = coarse_cell(B, cx, cy, cz);
+            const int32_t s = w.cell_start[c], e = w.cell_start[c + 1];
+            int tag = -1;
+            cnt = e - s;
+            if (box_dense && cnt > w.dense_threshold && w.cell_count[c] >= 0) {
+                tag = w.cell_count[c];
+                cnt = 0;
+            }
+            gst[h] = s;
+            htag[h] = tag;
+        }
+        cnt_local[k] = cnt;
+        sum += cnt;
+    }
+    // exclusive scan of the staged counts (each thread owns consecutive halo cells)
+    {
+        const int lane = lane_id(), wid = t / kWave;
+        int x = sum;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            int y = __shfl_up(x, o, kWave);
+            if (lane >= o)
+                x += y;
+        }
+        if (lane == kWave - 1)
+            scr[wid] = x;
+        __syncthreads();
+        int pre = 0, tot = 0;
+        for (int k = 0; k < kTileBlock / kWave; ++k) {
+            if (k < wid)
+                pre += scr[k];
+            tot += scr[k];
+        }
+        int run = pre + x - sum;
+#pragma unroll
+        for (int k = 0; k < (kHalo + kTileBlock - 1) / kTileBlock; ++k) {
+            const int h = t * ((kHalo + kTileBlock - 1) / kTileBlock) + k;
+            if (h < kHalo)
+                hoff[h] = run;
+            run += cnt_local[k];
+        }
+        if (t == 0) {
+            hoff[kHalo] = tot;
+            overflow = tot > kTileCap;
+        }
+    }
+    __syncthreads();
+
+    // own rows: (hx, hy) in [1, kTileX] x [1, kTileY] inside the box; own cells hz in [1, kTileZ]
+    if (t == 0) {
+        int acc = 0;
+        for (int r = 0; r < kRows; ++r) {
+            rowoff[r] = acc;
+            const int hx = 1 + r / kTileY, hy = 1 + r % kTileY;
+            const int zend = min(kTileZ, B.nc[2] - z0);
+            if (x0 + hx - 1 < B.nc[0] && y0 + hy - 1 < B.nc[1] && zend > 0) {
+                const int h0 = (hx * kHY + hy) * kHZ + 1;
+                acc += hoff[h0 + zend] - hoff[h0];
+            }
+        }
+        rowoff[kRows] = acc;
+    }
+    const bool staged = !overflow;
+    if (staged) {
+        const int total = hoff[kHalo];
+        for (int q = t; q < total; q += kTileBlock) {
+            int lo = 0, hi = kHalo - 1;  // last halo cell with hoff <= q
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (hoff[mid] <= q)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            part[q] = w.sorted[gst[lo] + (q - hoff[lo])];
+        }
+    }
+    __syncthreads();
+
+    const int nown = rowoff[kRows];
+    for (int k = t; k < nown; k += kTileBlock) {
+        int r = 0;
+        while (rowoff[r + 1] <= k)
+            ++r;
+        const int hx = 1 + r / kTileY, hy = 1 + r % kTileY;
+        const int h0 = (hx * kHY + hy) * kHZ + 1;
+        const int q = hoff[h0] + (k - rowoff[r]);  // staged slot
+        int hz = 1;                                // own cell holding slot q
+        while (hoff[h0 + hz] <= q)
+            ++hz;
+        const int h = (hx * kHY + hy) * kHZ + hz;
+        const int64_t i = gst[h] + (q - hoff[h]);
+        const float4 p = staged ? part[q] : w.sorted[i];
+        const int ix = x0 + hx - 1, iy = y0 + hy - 1, iz = z0 + hz - 1;
+        bool has_friend;
+        if (!staged) {
+            has_friend = link_particle_global(w, B, i, p, ix, iy, iz);
+        } else {
+            has_friend = false;
+            const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
+            const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
+            const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
+            for (int ox = sx.lo; ox <= sx.hi; ++ox)
+                for (int oy = sy.lo; oy <= sy.hi; ++oy)
+                    for (int oz = sz.lo; oz <= sz.hi; ++oz) {
+                        const int h2 = ((hx + ox) * kHY + hy + oy) * kHZ + hz + oz;
+                        const int tag = htag[h2];
+                        if (tag >= 0) {
+                            const int64_t c2 = coarse_cell(B, wrap_cell(ix + ox, B.nc[0]),
+                                                           wrap_cell(iy + oy, B.nc[1]),
+                                                           wrap_cell(iz + oz, B.nc[2]));
+                            const int32_t s2 = w.cell_start[c2];
+                            has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz,
+                                                               ox, oy, oz, s2,
+                                                               w.cell_start[c2 + 1] - s2, tag);
+                            continue;
+                        }
+                        const int a = hoff[h2], e = hoff[h2 + 1];
+                        for (int j = a; j < e; ++j) {
+                            const int64_t gj = gst[h2] + (j - a);
+                            if (gj == i)
+                                continue;
+                            const float4 q4 = part[j];
+                            if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
+                                has_friend = true;
+                                if (i < gj)
+                                    uf_union(w.parent, (uint32_t)i, (uint32_t)gj);
+                            }
+                        }
+                    }
+        }
+        finish_particle(w, root, i, __float_as_int(p.w), has_friend);
+    }
 }
 
 // Particles with a friend: follow the union-find to the root and write the root's key
@@ -170,7 +394,7 @@ __global__ void k_compress(const float4 *__restrict__ sorted, int64_t n,
                            uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
                            int32_t *__restrict__ root)
 {
-    const int64_t i = gtid();
+    const int64_t i = gtid_xcd();
     if (i >= n)
         return;
     if (!((flags[i >> 6] >> (i & 63)) & 1ull))
@@ -186,10 +410,16 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s)
 {
     if (w.n <= 0)
         return hipSuccess;
-    hipError_t e = launch_dense(w, s);
+    hipError_t e = launch_fill_u64(w.flags, (w.n + 63) / 64, 0ull, s);
+    if (e != hipSuccess)
+        return e;
+    e = launch_dense(w, s);
     if (e != hipSuccess)
         return e;
     const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
+    if (w.ntiles > 0)
+        hipLaunchKernelGGL(k_link_tiled, dim3((unsigned)w.ntiles), dim3(kTileBlock), 0, s, w,
+                           root);
     hipLaunchKernelGGL(k_link, dim3(nb), dim3(w.block), 0, s, w, root);
     hipLaunchKernelGGL(k_compress, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent,
                        w.flags, root);

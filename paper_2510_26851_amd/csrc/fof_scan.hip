@@ -176,6 +176,14 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fill<uint64_t>, dim3(fill_blocks(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
 {
     if (n <= 0)

@@ -60,24 +60,29 @@ def plan(counts, boxes, tune=None, desc=True):
     return rc, g, buf
 
 
-# BoxDesc layout (fof_internal.h): int64 off, cell_base; int32 n, m, nc[3], nf[3];
-# int32 R, dense_ok; double L[3], halfL[3], b2; float inv_fine[3], side[3], reach, fine_side.
-_DESC = struct.Struct("<qqii3i3iii3d3dd3f3fff")
+# BoxDesc layout (fof_internal.h): int64 off, cell_base, tile_base; int32 n, m, nc[3], nf[3],
+# R, dense_ok, tiled, ntile[3]; double L[3], halfL[3], b2; float inv_fine[3], side[3],
+# reach, fine_side.
+_DESC = struct.Struct("<qqqii3i3iiii3i3d3dd3f3fff")
 
 
-DESC_STRIDE = 144   # sizeof(BoxDesc), 16-byte aligned
+def desc_stride():
+    rc, g, _ = plan([1], [(10.0, 0.5)], desc=False)
+    return g.desc_bytes
 
 
 def decode(buf, k=0):
-    v = _DESC.unpack_from(buf.tobytes(), k * DESC_STRIDE)
-    return dict(off=v[0], cell_base=v[1], n=v[2], m=v[3], nc=v[4:7], nf=v[7:10], R=v[10],
-                dense_ok=v[11], L=v[12:15], halfL=v[15:18], b2=v[18], inv_fine=v[19:22],
-                side=v[22:25], reach=v[25], fine_side=v[26])
+    v = _DESC.unpack_from(buf.tobytes(), k * desc_stride())
+    return dict(off=v[0], cell_base=v[1], tile_base=v[2], n=v[3], m=v[4], nc=v[5:8],
+                nf=v[8:11], R=v[11], dense_ok=v[12], tiled=v[13], ntile=v[14:17], L=v[17:20],
+                halfL=v[20:23], b2=v[23], inv_fine=v[24:27], side=v[27:30], reach=v[30],
+                fine_side=v[31])
 
 
 def test_descriptor_size():
     rc, g, buf = plan([10, 20], [(10.0, 0.5), (10.0, 0.5)])
-    assert rc == 0 and g.desc_bytes == 2 * DESC_STRIDE and _DESC.size <= DESC_STRIDE
+    st = desc_stride()
+    assert rc == 0 and g.desc_bytes == 2 * st and _DESC.size <= st and st % 16 == 0
 
 
 @pytest.mark.parametrize("L,b,n", [(64.0, 0.4, 32768), (512.0, 0.2, 512 ** 3), (256.0, 0.2, 256 ** 3),
