@@ -97,8 +97,8 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
         fs = nextafterf(fs, 0.0f);
     d->fine_side = fs > 0.0f ? fs : 0.0f;
     d->dense_ok = (d->nc[0] >= 3 && d->nc[1] >= 3 && d->nc[2] >= 3 && d->R <= 3) ? 1 : 0;
-    // the tiled link kernel needs distinct neighbour cells (>= 3 per axis)
-    d->tiled = (d->nc[0] >= 3 && d->nc[1] >= 3 && d->nc[2] >= 3) ? 1 : 0;
+    // the tiled link kernel needs every halo cell of a tile to be a distinct cell
+    d->tiled = (d->nc[0] >= kTileX + 2 && d->nc[1] >= kTileY + 2 && d->nc[2] >= kTileZ + 2) ? 1 : 0;
     d->ntile[0] = (d->nc[0] + kTileX - 1) / kTileX;
     d->ntile[1] = (d->nc[1] + kTileY - 1) / kTileY;
     d->ntile[2] = (d->nc[2] + kTileZ - 1) / kTileZ;

@@ -21,7 +21,7 @@ constexpr int kMaxFineKeys = kMaxFine * kMaxFine * kMaxFine;
 constexpr int kMaxTableWords = (kMaxFineKeys + 31) / 32;
 constexpr int kTableHeader = 4;  // dense-cell table: cell, ncomp, units, reserved
 // Link tiles: kTileX x kTileY x kTileZ coarse cells per block (z fastest, like the cells).
-constexpr int kTileX = 2, kTileY = 4, kTileZ = 32;
+constexpr int kTileX = 4, kTileY = 4, kTileZ = 16;
 
 // Per-box constants, computed once on the host in double precision and copied into the
 // workspace by the caller.  Layout is private to this library.

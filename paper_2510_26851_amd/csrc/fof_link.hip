@@ -180,17 +180,20 @@ __global__ void k_link(Work w, int32_t *__restrict__ root)
 }
 
 // ---------------------------------------------------------------------------------------
-// LDS-tiled linking.  A block owns kTileX x kTileY x kTileZ coarse cells; it stages those
-// cells and a one-cell halo into LDS (each (x, y) row of the halo is a contiguous run of
-// cells and particles), then every own particle tests its candidates from LDS.  Cells
-// with clique tables are not staged: particles reach them through their unit tables.  A
-// tile whose staged particles do not fit falls back to the global search.
+// LDS-tiled linking.  A block owns kTileX x kTileY x kTileZ coarse cells and stages them
+// with a one-cell halo in LDS.  With cells z fastest, each (x, y) row of the halo is one
+// contiguous run of particles, copied with coalesced loads; then a particle's candidates
+// in one neighbour row (up to three consecutive cells) form one contiguous LDS range.
+// Cells with clique tables are not staged: particles reach them through their unit
+// tables.  A tile whose staged particles do not fit searches from global memory.
 // ---------------------------------------------------------------------------------------
 constexpr int kHX = kTileX + 2, kHY = kTileY + 2, kHZ = kTileZ + 2;
-constexpr int kHalo = kHX * kHY * kHZ;
+constexpr int kRowsH = kHX * kHY;
+constexpr int kHalo = kRowsH * kHZ;
+constexpr int kPerT = (kHalo + 255) / 256;  // halo cells per thread in the scan
 constexpr int kTileBlock = 256;
-constexpr int kTileCap = 2048;  // staged particles per tile
-constexpr int kRows = kTileX * kTileY;
+constexpr int kTileCap = 1024;  // staged particles per tile
+constexpr int kOwnRows = kTileX * kTileY;
 
 // Box owning tile t: the last box whose first tile is <= t.  Boxes without tiles share
 // their tile_base with the next box, which comes later, so they are never chosen.
@@ -207,8 +210,6 @@ __device__ __forceinline__ int find_box_tile(const BoxDesc *d, int nbox, int64_t
     return lo;
 }
 
-// Periodic cell index for any offset (halo cells of a tile may lie several cells beyond the
-// box when the box has fewer cells than the tile).
 __device__ __forceinline__ int mod_cell(int c, int nc)
 {
     int r = c % nc;
@@ -218,12 +219,13 @@ __device__ __forceinline__ int mod_cell(int c, int nc)
 __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__restrict__ root)
 {
     __shared__ float4 part[kTileCap];
+    __shared__ int pidx[kTileCap];    // sorted index of each staged particle
     __shared__ int hoff[kHalo + 1];   // staged offset of each halo cell
     __shared__ int gst[kHalo];        // global start of each halo cell
     __shared__ int htag[kHalo];       // dense id (>= 0) or -1
-    __shared__ int rowoff[kRows + 1]; // own particles before each own row
+    __shared__ int rowslow[kRowsH];   // row copied cell by cell (wraps or holds dense cells)
+    __shared__ int ownoff[kOwnRows + 1];
     __shared__ int scr[kTileBlock / kWave];
-    __shared__ int overflow;
 
     const int64_t tile = xcd_block();
     if (tile >= w.ntiles)
@@ -235,28 +237,38 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
     const int ty = (int)(tl % B.ntile[1]);
     const int tx = (int)(tl / B.ntile[1]);
     const int x0 = tx * kTileX, y0 = ty * kTileY, z0 = tz * kTileZ;
+    // last halo index (inclusive) in use per axis: own cells stop at the box edge
+    const int hxe = min(kTileX, B.nc[0] - x0) + 1;
+    const int hye = min(kTileY, B.nc[1] - y0) + 1;
+    const int hze = min(kTileZ, B.nc[2] - z0) + 1;
     const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
     const int t = threadIdx.x;
 
-    // halo cells: counts, global starts, dense tags
-    int cnt_local[(kHalo + kTileBlock - 1) / kTileBlock];
+    if (t < kRowsH)
+        rowslow[t] = 0;
+    __syncthreads();
+    int cnt_local[kPerT];
     int sum = 0;
 #pragma unroll
-    for (int k = 0; k < (kHalo + kTileBlock - 1) / kTileBlock; ++k) {
-        const int h = t * ((kHalo + kTileBlock - 1) / kTileBlock) + k;
+    for (int k = 0; k < kPerT; ++k) {
+        const int h = t * kPerT + k;
         int cnt = 0;
         if (h < kHalo) {
-            const int hz = h % kHZ, hy = (h / kHZ) % kHY, hx = h / (kHZ * kHY);
-            const int cx = mod_cell(x0 - 1 + hx, B.nc[0]);
-            const int cy = mod_cell(y0 - 1 + hy, B.nc[1]);
-            const int cz = mod_cell(z0 - 1 + hz, B.nc[2]);
-            const int64_t c = coarse_cell(B, cx, cy, cz);
-            const int32_t s = w.cell_start[c], e = w.cell_start[c + 1];
-            int tag = -1;
-            cnt = e - s;
-            if (box_dense && cnt > w.dense_threshold && w.cell_count[c] >= 0) {
-                tag = w.cell_count[c];
-                cnt = 0;
+            const int hz = h % kHZ, row = h / kHZ, hy = row % kHY, hx = row / kHY;
+            int tag = -1, s = 0;
+            if (hx <= hxe && hy <= hye && hz <= hze) {
+                const int gz = z0 - 1 + hz;
+                const int64_t c = coarse_cell(B, mod_cell(x0 - 1 + hx, B.nc[0]),
+                                              mod_cell(y0 - 1 + hy, B.nc[1]), mod_cell(gz, B.nc[2]));
+                s = w.cell_start[c];
+                cnt = w.cell_start[c + 1] - s;
+                if (box_dense && cnt > w.dense_threshold && w.cell_count[c] >= 0) {
+                    tag = w.cell_count[c];
+                    cnt = 0;
+                    rowslow[row] = 1;
+                }
+                if (gz < 0 || gz >= B.nc[2])
+                    rowslow[row] = 1;
             }
             gst[h] = s;
             htag[h] = tag;
@@ -264,8 +276,7 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
         cnt_local[k] = cnt;
         sum += cnt;
     }
-    // exclusive scan of the staged counts (each thread owns consecutive halo cells)
-    {
+    {  // exclusive scan of staged counts; each thread owns kPerT consecutive halo cells
         const int lane = lane_id(), wid = t / kWave;
         int x = sum;
 #pragma unroll
@@ -285,102 +296,117 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
         }
         int run = pre + x - sum;
 #pragma unroll
-        for (int k = 0; k < (kHalo + kTileBlock - 1) / kTileBlock; ++k) {
-            const int h = t * ((kHalo + kTileBlock - 1) / kTileBlock) + k;
+        for (int k = 0; k < kPerT; ++k) {
+            const int h = t * kPerT + k;
             if (h < kHalo)
                 hoff[h] = run;
             run += cnt_local[k];
         }
-        if (t == 0) {
+        if (t == 0)
             hoff[kHalo] = tot;
-            overflow = tot > kTileCap;
-        }
     }
     __syncthreads();
-
-    // own rows: (hx, hy) in [1, kTileX] x [1, kTileY] inside the box; own cells hz in [1, kTileZ]
-    if (t == 0) {
+    if (t <= kOwnRows) {  // own particles before each own row
         int acc = 0;
-        for (int r = 0; r < kRows; ++r) {
-            rowoff[r] = acc;
+        for (int r = 0; r < t; ++r) {
             const int hx = 1 + r / kTileY, hy = 1 + r % kTileY;
-            const int zend = min(kTileZ, B.nc[2] - z0);
-            if (x0 + hx - 1 < B.nc[0] && y0 + hy - 1 < B.nc[1] && zend > 0) {
-                const int h0 = (hx * kHY + hy) * kHZ + 1;
-                acc += hoff[h0 + zend] - hoff[h0];
-            }
+            const int rb = (hx * kHY + hy) * kHZ;
+            if (hx <= hxe - 1 && hy <= hye - 1)
+                acc += hoff[rb + hze] - hoff[rb + 1];
         }
-        rowoff[kRows] = acc;
+        ownoff[t] = acc;
     }
-    const bool staged = !overflow;
+    const bool staged = hoff[kHalo] <= kTileCap;
     if (staged) {
-        const int total = hoff[kHalo];
-        for (int q = t; q < total; q += kTileBlock) {
-            int lo = 0, hi = kHalo - 1;  // last halo cell with hoff <= q
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (hoff[mid] <= q)
-                    lo = mid;
-                else
-                    hi = mid - 1;
+        const int lane = lane_id();
+        for (int row = t / kWave; row < kRowsH; row += kTileBlock / kWave) {
+            const int rb = row * kHZ;
+            if (!rowslow[row]) {  // one contiguous run of particles
+                const int ls = hoff[rb], n = hoff[rb + kHZ] - ls;
+                const int gs = gst[rb];
+                for (int k = lane; k < n; k += kWave) {
+                    part[ls + k] = w.sorted[gs + k];
+                    pidx[ls + k] = gs + k;
+                }
+            } else {
+                for (int hz = 0; hz < kHZ; ++hz) {
+                    const int ls = hoff[rb + hz], n = hoff[rb + hz + 1] - ls;
+                    const int gs = gst[rb + hz];
+                    for (int k = lane; k < n; k += kWave) {
+                        part[ls + k] = w.sorted[gs + k];
+                        pidx[ls + k] = gs + k;
+                    }
+                }
             }
-            part[q] = w.sorted[gst[lo] + (q - hoff[lo])];
         }
     }
     __syncthreads();
 
-    const int nown = rowoff[kRows];
+    if (!staged) {  // global search, one thread per own cell
+        for (int q = t; q < kTileX * kTileY * kTileZ; q += kTileBlock) {
+            const int hz = 1 + q % kTileZ, hy = 1 + (q / kTileZ) % kTileY, hx = 1 + q / (kTileZ * kTileY);
+            if (hx >= hxe || hy >= hye || hz >= hze)
+                continue;
+            const int h = (hx * kHY + hy) * kHZ + hz;
+            if (htag[h] >= 0)
+                continue;  // dense cell: linked by the dense kernels
+            const int n = hoff[h + 1] - hoff[h];
+            for (int k = 0; k < n; ++k) {
+                const int64_t i = gst[h] + k;
+                const float4 p = w.sorted[i];
+                finish_particle(w, root, i, __float_as_int(p.w),
+                                link_particle_global(w, B, i, p, x0 + hx - 1, y0 + hy - 1,
+                                                     z0 + hz - 1));
+            }
+        }
+        return;
+    }
+
+    const int nown = ownoff[kOwnRows];
     for (int k = t; k < nown; k += kTileBlock) {
         int r = 0;
-        while (rowoff[r + 1] <= k)
+        while (ownoff[r + 1] <= k)
             ++r;
-        const int hx = 1 + r / kTileY, hy = 1 + r % kTileY;
-        const int h0 = (hx * kHY + hy) * kHZ + 1;
-        const int q = hoff[h0] + (k - rowoff[r]);  // staged slot
-        int hz = 1;                                // own cell holding slot q
-        while (hoff[h0 + hz] <= q)
-            ++hz;
-        const int h = (hx * kHY + hy) * kHZ + hz;
-        const int64_t i = gst[h] + (q - hoff[h]);
-        const float4 p = staged ? part[q] : w.sorted[i];
-        const int ix = x0 + hx - 1, iy = y0 + hy - 1, iz = z0 + hz - 1;
-        bool has_friend;
-        if (!staged) {
-            has_friend = link_particle_global(w, B, i, p, ix, iy, iz);
-        } else {
-            has_friend = false;
-            const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
-            const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
-            const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
-            for (int ox = sx.lo; ox <= sx.hi; ++ox)
-                for (int oy = sy.lo; oy <= sy.hi; ++oy)
-                    for (int oz = sz.lo; oz <= sz.hi; ++oz) {
-                        const int h2 = ((hx + ox) * kHY + hy + oy) * kHZ + hz + oz;
-                        const int tag = htag[h2];
-                        if (tag >= 0) {
-                            const int64_t c2 = coarse_cell(B, wrap_cell(ix + ox, B.nc[0]),
-                                                           wrap_cell(iy + oy, B.nc[1]),
-                                                           wrap_cell(iz + oz, B.nc[2]));
-                            const int32_t s2 = w.cell_start[c2];
-                            has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz,
-                                                               ox, oy, oz, s2,
-                                                               w.cell_start[c2 + 1] - s2, tag);
-                            continue;
-                        }
-                        const int a = hoff[h2], e = hoff[h2 + 1];
-                        for (int j = a; j < e; ++j) {
-                            const int64_t gj = gst[h2] + (j - a);
-                            if (gj == i)
-                                continue;
-                            const float4 q4 = part[j];
-                            if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
-                                has_friend = true;
-                                if (i < gj)
-                                    uf_union(w.parent, (uint32_t)i, (uint32_t)gj);
-                            }
-                        }
+        const int rhx = 1 + r / kTileY, rhy = 1 + r % kTileY;
+        const int slot = hoff[(rhx * kHY + rhy) * kHZ + 1] + (k - ownoff[r]);
+        const float4 p = part[slot];
+        const int64_t i = pidx[slot];
+        const int ix = fine_index(p.x, B.inv_fine[0], B.nf[0]) / B.m;
+        const int iy = fine_index(p.y, B.inv_fine[1], B.nf[1]) / B.m;
+        const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
+        const int hx = ix - x0 + 1, hy = iy - y0 + 1, hz = iz - z0 + 1;
+        bool has_friend = false;
+        const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
+        const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
+        const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
+        for (int ox = sx.lo; ox <= sx.hi; ++ox)
+            for (int oy = sy.lo; oy <= sy.hi; ++oy) {
+                const int rb = ((hx + ox) * kHY + hy + oy) * kHZ;
+                const int a = hoff[rb + hz + sz.lo], e = hoff[rb + hz + sz.hi + 1];
+                for (int j = a; j < e; ++j) {
+                    const int64_t gj = pidx[j];
+                    if (gj == i)
+                        continue;
+                    const float4 q4 = part[j];
+                    if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
+                        has_friend = true;
+                        if (i < gj)
+                            uf_union(w.parent, (uint32_t)i, (uint32_t)gj);
                     }
-        }
+                }
+                if (box_dense)
+                    for (int oz = sz.lo; oz <= sz.hi; ++oz) {
+                        const int tag = htag[rb + hz + oz];
+                        if (tag < 0)
+                            continue;
+                        const int64_t c2 = coarse_cell(B, wrap_cell(ix + ox, B.nc[0]),
+                                                       wrap_cell(iy + oy, B.nc[1]),
+                                                       wrap_cell(iz + oz, B.nc[2]));
+                        const int32_t s2 = w.cell_start[c2];
+                        has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz, ox, oy,
+                                                           oz, s2, w.cell_start[c2 + 1] - s2, tag);
+                    }
+            }
         finish_particle(w, root, i, __float_as_int(p.w), has_friend);
     }
 }
