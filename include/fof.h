@@ -41,6 +41,16 @@ extern "C" {
 /* Bits of the device status word (see fof_status). */
 #define FOF_STATUS_RANGE 1u     /* some coordinate was NaN or outside [0, L)                  */
 #define FOF_STATUS_DENSE_CAP 2u /* dense-cell tables overflowed; those cells took the plain path */
+#define FOF_STATUS_EDGE_CAP 4u  /* more candidate edges than fof_sample.edge_cap              */
+
+/* fof_backward modes */
+#define FOF_FROZEN 0 /* frozen assignment (paper Sec. 3.1)                                     */
+#define FOF_SCORE 1  /* score-function (REINFORCE) estimator over sampled edges (Sec. 3.2)    */
+
+/* Baselines of the score-function estimator */
+#define FOF_BASELINE_NONE 0
+#define FOF_BASELINE_MEAN 1 /* mean loss of the K samples                                       */
+#define FOF_BASELINE_LOO 2  /* mean loss of the other K-1 samples (exactly unbiased)            */
 
 /* One periodic box: side lengths L (physical) and the physical linking length b.
  * Requirements: L[c] finite and > 0, b finite and > 0, 2 b < L[c] for every axis (so that
@@ -60,6 +70,36 @@ typedef struct fof_tune {
     uint32_t flags;          /* reserved, must be 0                                            */
     int32_t reserved;
 } fof_tune;
+
+/* Stochastic linking (paper Sec. 3.2: every potential edge between nearby particles is a
+ * Bernoulli variable).  The candidate edges are the pairs closer than the plan's linking
+ * length (the cut radius r_c: plan the batch with fof_box.b = r_c); edge e = {i, j} is kept
+ * in sample s with probability p_e = 1 / (1 + exp(-(b - d_e) / tau)), d_e its
+ * minimum-image distance, when u(seed, s, i, j) < p_e, where u is the first word of
+ * Philox4x64-10 (Salmon et al. 2011) at counter (i | j << 32, s, 0, 0) and key (seed, 0),
+ * shifted right by 11 and scaled by 2^-53, on original indices i < j.  All pointers are
+ * device pointers owned by the caller. */
+typedef struct fof_sample {
+    double b;           /* linking length of the probability                                   */
+    double tau;         /* temperature, > 0                                                    */
+    uint64_t seed;
+    int32_t K;          /* sampled graphs, >= 1                                                */
+    int32_t edge_cap;   /* capacity of ei, ej, d2                                              */
+    int32_t *ei, *ej;   /* [edge_cap] candidate edges (original indices, ei < ej), any order   */
+    double *d2;         /* [edge_cap] squared minimum-image distances                          */
+    int32_t *n_edges;   /* [1] number of candidate edges (may exceed edge_cap: status bit)     */
+    void *scratch;      /* >= FOF_SAMPLE_SCRATCH_BYTES(n, K, edge_cap) bytes, 256-aligned      */
+    size_t scratch_bytes;
+} fof_sample;
+
+/* Scratch of the sampled labelling: a vertex map over all particles, the sorted ends of
+ * every edge, and one union-find per sample over the particles that touch a candidate edge
+ * (at most min(n, 2 edge_cap) of them). */
+#define FOF_SAMPLE_VCAP(n, edge_cap)                                                          \
+    (2 * (size_t)(edge_cap) < (size_t)(n) ? 2 * (size_t)(edge_cap) : (size_t)(n))
+#define FOF_SAMPLE_SCRATCH_BYTES(n, K, edge_cap)                                              \
+    (4096 + 8 * ((size_t)(n) + 1) + 4 * ((size_t)(n) / 2048 + 2) + 8 * (size_t)(edge_cap) +   \
+     8 * (size_t)(K) + 4 * ((size_t)(K) + 1) * FOF_SAMPLE_VCAP(n, edge_cap))
 
 /* Host-side plan of one batch: filled by fof_workspace_bytes, then passed unchanged to the
  * other calls.  Plain data; the byte offsets locate the regions of the caller's workspace. */
@@ -102,8 +142,10 @@ int fof_build_grid(const fof_grid *grid, const float *pos /*dev*/, void *ws /*de
  * connected component of i (so root[root[i]] == root[i]).  The link predicate is exact:
  * per axis d = (double)x_i - (double)x_j wrapped once by +-L when |d| > L/2, then
  * ((dx*dx + dy*dy) + dz*dz) < b*b in IEEE double without fused multiply-add.
- * `sample` must be NULL (hard linking); any other value returns FOF_ENOTSUP. */
-int fof_link(const fof_grid *grid, void *ws /*dev*/, const void *sample /*must be NULL*/,
+ * With sample != NULL (single-box plans only): writes the candidate edges into the sample
+ * buffers and, when root is not NULL, root (dev, int32 [K][n]) receives the smallest-index
+ * labels of each of the K sampled graphs. */
+int fof_link(const fof_grid *grid, void *ws /*dev*/, const fof_sample *sample /*host or NULL*/,
              int32_t *root /*dev*/, void *stream);
 
 /* Group catalogue (paper Sec. 2 step (vi); Alg. 2 compaction; Sec. 3.1 halo position).
@@ -123,20 +165,26 @@ int fof_groups(const fof_grid *grid, void *ws /*dev*/, int32_t min_size, const f
                int32_t cap, int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
                double *vmean, double *sigv, void *stream);
 
-/* Frozen-assignment backward (paper Sec. 3.1 and its table of differentiation modes):
- * memberships from the forward are held fixed, gradients flow only through member
- * positions and velocities.  With upstream gradients g_mass[G], g_com[G][3], g_sigv[G]
- * (dev double; any may be NULL = zero) of the forward outputs mass_g = n_g, com, sigv:
+/* Backward passes (paper Sec. 3: the forward is exact; gradients never differentiate the
+ * neighbour structure).  mode = FOF_FROZEN (Sec. 3.1 and its table of differentiation
+ * modes): memberships from the forward are held fixed.  With upstream gradients g_mass[G],
+ * g_com[G][3], g_sigv[G] (dev double; any may be NULL = zero) of mass_g = n_g, com, sigv:
  *   grad_pos[i][c] = g_com[g][c] / n_g                        (mass has zero gradient)
  *   grad_vel[i][c] = g_sigv[g] (v_ic - vmean[g][c]) / (3 n_g sigv[g])   (0 if sigv[g] = 0)
  * where g = group_id[i]; particles with g < 0 or g >= G get zeros.  sizes, vmean, sigv are
- * the forward's outputs; G is the number of groups the tables hold (<= cap).  grad_pos and
- * grad_vel (dev float32 [n][3]) may be NULL to skip them; vel is needed for grad_vel. */
-int fof_backward(const fof_grid *grid, const int32_t *group_id /*dev*/, int32_t G,
-                 const int32_t *sizes /*dev*/, const double *vmean /*dev*/,
-                 const double *sigv /*dev*/, const float *vel /*dev*/, const double *g_mass,
-                 const double *g_com, const double *g_sigv, float *grad_pos, float *grad_vel,
-                 void *stream);
+ * the forward's outputs; G is the number of groups the tables hold (<= cap).
+ * mode = FOF_SCORE (Sec. 3.2, REINFORCE): with the edges of the last fof_link(sample) and the
+ * sampled graphs' losses loss[K] (dev double),
+ *   grad_pos = (1/K) sum_s (loss_s - beta_s) sum_e (y_es - p_e) dz_e/dx,
+ *   z_e = (b - d_e)/tau,  dz_e/dx_i = -(x_i - x_j)/(tau d_e) = -dz_e/dx_j (minimum image),
+ * beta_s per `baseline` (FOF_BASELINE_*); the frozen-mode arguments are ignored and grad_vel
+ * is not written.  grad_pos and grad_vel (dev float32 [n][3]) may be NULL to skip them. */
+int fof_backward(const fof_grid *grid, void *ws /*dev*/, int32_t mode,
+                 const int32_t *group_id /*dev*/, int32_t G, const int32_t *sizes /*dev*/,
+                 const double *vmean /*dev*/, const double *sigv /*dev*/, const float *vel /*dev*/,
+                 const double *g_mass, const double *g_com, const double *g_sigv,
+                 const fof_sample *sample /*host*/, const double *loss /*dev [K]*/,
+                 int32_t baseline, float *grad_pos, float *grad_vel, void *stream);
 
 /* Device address of the int32 status word inside ws (FOF_STATUS_* bits; 0 = clean).  It is
  * cleared by fof_build_grid; read it after synchronising the stream. */

@@ -19,6 +19,19 @@ FOF_EDEVICE = -4
 FOF_ENOTSUP = -5
 FOF_STATUS_RANGE = 1
 FOF_STATUS_DENSE_CAP = 2
+FOF_STATUS_EDGE_CAP = 4
+FOF_FROZEN = 0
+FOF_SCORE = 1
+FOF_BASELINE_NONE = 0
+FOF_BASELINE_MEAN = 1
+FOF_BASELINE_LOO = 2
+
+
+def sample_scratch_bytes(n: int, K: int, edge_cap: int) -> int:
+    """FOF_SAMPLE_SCRATCH_BYTES of include/fof.h."""
+    vcap = min(2 * edge_cap, n)
+    return (4096 + 8 * (n + 1) + 4 * (n // 2048 + 2) + 8 * edge_cap + 8 * K +
+            4 * (K + 1) * vcap)
 
 # Every symbol include/fof.h declares.
 EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",
@@ -33,6 +46,13 @@ class fof_tune(ctypes.Structure):
     _fields_ = [("cell_side", ctypes.c_double), ("dense_threshold", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("reserved", ctypes.c_int32)]
+
+
+class fof_sample(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_double), ("tau", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("K", ctypes.c_int32), ("edge_cap", ctypes.c_int32), ("ei", ctypes.c_void_p),
+                ("ej", ctypes.c_void_p), ("d2", ctypes.c_void_p), ("n_edges", ctypes.c_void_p),
+                ("scratch", ctypes.c_void_p), ("scratch_bytes", ctypes.c_size_t)]
 
 
 class fof_grid(ctypes.Structure):
@@ -69,7 +89,7 @@ def load():
     L.fof_build_grid.argtypes = [P, P, P, P]
     L.fof_link.argtypes = [P, P, P, P, P]
     L.fof_groups.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P, P]
-    L.fof_backward.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, P, P]
+    L.fof_backward.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, i32, P, P, P]
     L.fof_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_void_p)]
     L.fof_strerror.argtypes = [ctypes.c_int]
     L.fof_strerror.restype = ctypes.c_char_p

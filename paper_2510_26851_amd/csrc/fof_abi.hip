@@ -283,13 +283,27 @@ int fof_build_grid(const fof_grid *grid, const float *pos, void *ws, void *strea
     return dev_err(launch_build(w, pos, (hipStream_t)stream));
 }
 
-int fof_link(const fof_grid *grid, void *ws, const void *sample, int32_t *root, void *stream)
+static bool sample_ok(const fof_grid *grid, const fof_sample *S)
 {
-    if (sample)
-        return FOF_ENOTSUP;
-    if (!ws_ok(grid, ws) || (grid->n > 0 && !root))
+    return grid->nbox == 1 && S->K >= 1 && S->edge_cap >= 0 && S->tau > 0.0 && isfinite(S->tau) &&
+           isfinite(S->b) && S->n_edges && S->scratch && ((uintptr_t)S->scratch % 256) == 0 &&
+           (S->edge_cap == 0 || (S->ei && S->ej && S->d2)) &&
+           S->scratch_bytes >= FOF_SAMPLE_SCRATCH_BYTES(grid->n, S->K, S->edge_cap) &&
+           sample_layout_ok(*S, grid->n);
+}
+
+int fof_link(const fof_grid *grid, void *ws, const fof_sample *sample, int32_t *root, void *stream)
+{
+    if (!ws_ok(grid, ws))
         return FOF_EINVAL;
     Work w = resolve(grid, ws);
+    if (sample) {
+        if (!sample_ok(grid, sample))
+            return FOF_EINVAL;
+        return dev_err(launch_sample(w, *sample, root, (hipStream_t)stream));
+    }
+    if (grid->n > 0 && !root)
+        return FOF_EINVAL;
     return dev_err(launch_link(w, root, (hipStream_t)stream));
 }
 
@@ -307,13 +321,25 @@ int fof_groups(const fof_grid *grid, void *ws, int32_t min_size, const float *ve
                                  sigv, (hipStream_t)stream));
 }
 
-int fof_backward(const fof_grid *grid, const int32_t *group_id, int32_t G, const int32_t *sizes,
-                 const double *vmean, const double *sigv, const float *vel, const double *g_mass,
-                 const double *g_com, const double *g_sigv, float *grad_pos, float *grad_vel,
-                 void *stream)
+int fof_backward(const fof_grid *grid, void *ws, int32_t mode, const int32_t *group_id, int32_t G,
+                 const int32_t *sizes, const double *vmean, const double *sigv, const float *vel,
+                 const double *g_mass, const double *g_com, const double *g_sigv,
+                 const fof_sample *sample, const double *loss, int32_t baseline, float *grad_pos,
+                 float *grad_vel, void *stream)
 {
     (void)g_mass;  // the member count has zero gradient with memberships frozen
-    if (!grid || grid->n < 0 || G < 0 || (grid->n > 0 && !group_id) || (G > 0 && !sizes))
+    if (!grid || grid->n < 0)
+        return FOF_EINVAL;
+    if (mode == FOF_SCORE) {
+        if (!ws_ok(grid, ws) || !sample || !sample_ok(grid, sample) || !loss ||
+            baseline < FOF_BASELINE_NONE || baseline > FOF_BASELINE_LOO)
+            return FOF_EINVAL;
+        Work w = resolve(grid, ws);
+        return dev_err(launch_score(w, *sample, loss, baseline, grad_pos, (hipStream_t)stream));
+    }
+    if (mode != FOF_FROZEN)
+        return FOF_EINVAL;
+    if (G < 0 || (grid->n > 0 && !group_id) || (G > 0 && !sizes))
         return FOF_EINVAL;
     if (grad_vel && g_sigv && (!vel || !vmean || !sigv))
         return FOF_EINVAL;

@@ -109,8 +109,8 @@ __device__ __forceinline__ double min_image(double d, double L, double h)
     return d;
 }
 
-__device__ __forceinline__ bool linked(const BoxDesc &B, float xi, float yi, float zi, float xj,
-                                       float yj, float zj)
+__device__ __forceinline__ double dist2(const BoxDesc &B, float xi, float yi, float zi, float xj,
+                                        float yj, float zj)
 {
     double dx = min_image((double)xi - (double)xj, B.L[0], B.halfL[0]);
     double dy = min_image((double)yi - (double)yj, B.L[1], B.halfL[1]);
@@ -118,8 +118,13 @@ __device__ __forceinline__ bool linked(const BoxDesc &B, float xi, float yi, flo
     double sx = __dmul_rn(dx, dx);
     double sy = __dmul_rn(dy, dy);
     double sz = __dmul_rn(dz, dz);
-    double s = __dadd_rn(__dadd_rn(sx, sy), sz);
-    return s < B.b2;
+    return __dadd_rn(__dadd_rn(sx, sy), sz);
+}
+
+__device__ __forceinline__ bool linked(const BoxDesc &B, float xi, float yi, float zi, float xj,
+                                       float yj, float zj)
+{
+    return dist2(B, xi, yi, zi, xj, yj, zj) < B.b2;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -251,6 +256,10 @@ hipError_t launch_dense(const Work &w, hipStream_t s);
 hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int32_t cap,
                          int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
                          double *vmean, double *sigv, hipStream_t s);
+int sample_layout_ok(const fof_sample &S, int64_t n);
+hipError_t launch_sample(const Work &w, const fof_sample &S, int32_t *root, hipStream_t s);
+hipError_t launch_score(const Work &w, const fof_sample &S, const double *loss, int32_t baseline,
+                        float *grad_pos, hipStream_t s);
 hipError_t launch_backward(int64_t n, int32_t block, const int32_t *group_id, int32_t G,
                            const int32_t *sizes, const double *vmean, const double *sigv,
                            const float *vel, const double *g_com, const double *g_sigv,

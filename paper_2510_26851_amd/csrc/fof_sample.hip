@@ -1,0 +1,365 @@
+// Stochastic linking and the score-function gradient (paper Sec. 3.2).
+//
+// Candidate edges are the pairs closer than the plan's linking length (the cut radius);
+// edge e = {i, j} is kept in sample s when u(seed, s, i, j) < p_e, p_e = 1/(1 + exp(-z_e)),
+// z_e = (b - d_e)/tau.  The neighbour structure is built once and reused by all K samples,
+// as the paper does ("we do not rebuild the neighbor list").
+//
+//   k_edges        candidate search (same grid and predicate form as the hard link, with
+//                  the cut radius), edges as original indices i < j, their squared distance
+//                  and sorted positions
+//   k_touch, scan  compact the particles that touch an edge: one union-find per sample over
+//                  those only, in original-index order
+//   k_sample_union one thread per (edge, sample): Philox uniform, keep, hook
+//   k_sample_label labels of every particle in every sample (smallest member index)
+//   k_score        per edge: w_e = (1/K) sum_s adv_s (y_es - p_e), scattered as
+//                  -+ w_e (x_i - x_j)/(tau d_e) into the position gradient
+#include "fof_internal.h"
+
+namespace fof {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 64x64->128-bit
+// products; the key advances by the Weyl increments between rounds.
+__device__ __forceinline__ uint64_t philox_first_word(uint64_t c0, uint64_t c1, uint64_t c2,
+                                                      uint64_t c3, uint64_t k0, uint64_t k1)
+{
+    const uint64_t mA = 0xD2E7470EE14C6C93ull, mB = 0xCA5A826395121157ull;
+    const uint64_t wA = 0x9E3779B97F4A7C15ull, wB = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round) {
+            k0 += wA;
+            k1 += wB;
+        }
+        const uint64_t h0 = __umul64hi(mA, c0), l0 = mA * c0;
+        const uint64_t h1 = __umul64hi(mB, c2), l1 = mB * c2;
+        const uint64_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = l1;
+        c2 = n2;
+        c3 = l0;
+    }
+    return c0;
+}
+
+__device__ __forceinline__ double edge_uniform(uint64_t seed, uint32_t s, uint32_t i, uint32_t j)
+{
+    const uint64_t w = philox_first_word((uint64_t)i | ((uint64_t)j << 32), (uint64_t)s, 0ull, 0ull,
+                                         seed, 0ull);
+    return (double)(w >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ double edge_prob(double d2, double b, double tau)
+{
+    const double z = (b - sqrt(d2)) / tau;
+    return 1.0 / (1.0 + exp(-z));
+}
+
+struct SampleArgs {
+    double b, tau;
+    uint64_t seed;
+    int32_t K, edge_cap;
+    int32_t *ei, *ej;
+    double *d2;
+    int32_t *n_edges;
+    // scratch
+    int32_t *vflag;  // [n] 1 if the particle touches an edge
+    int32_t *vmap;   // [n + 1] exclusive scan of vflag: local index
+    int32_t *scan;   // scan tile sums
+    int32_t *vlist;  // [vcap] local index -> original index
+    int32_t *si, *sj;  // [edge_cap] sorted indices of the edge ends
+    int32_t *forest;   // [K][vcap]
+    double *adv;       // [K] loss minus baseline
+    int64_t vcap;
+};
+
+__device__ __forceinline__ int32_t edge_count(const SampleArgs &a)
+{
+    const int32_t m = *a.n_edges;
+    return m < a.edge_cap ? m : a.edge_cap;
+}
+
+__device__ void edges_of(const Work &w, const SampleArgs &a, int64_t i)
+{
+    const BoxDesc &B = w.desc[0];
+    const float4 p = w.sorted[i];
+    const int32_t oi = __float_as_int(p.w);
+    const int ix = fine_index(p.x, B.inv_fine[0], B.nf[0]) / B.m;
+    const int iy = fine_index(p.y, B.inv_fine[1], B.nf[1]) / B.m;
+    const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
+    for (int ox = -1; ox <= 1; ++ox) {
+        if (B.nc[0] < 3 && ox != 0 && (B.nc[0] == 1 || ox < 0))
+            continue;  // distinct neighbour cells only
+        const int cx = (ix + ox + B.nc[0]) % B.nc[0];
+        for (int oy = -1; oy <= 1; ++oy) {
+            if (B.nc[1] < 3 && oy != 0 && (B.nc[1] == 1 || oy < 0))
+                continue;
+            const int cy = (iy + oy + B.nc[1]) % B.nc[1];
+            for (int oz = -1; oz <= 1; ++oz) {
+                if (B.nc[2] < 3 && oz != 0 && (B.nc[2] == 1 || oz < 0))
+                    continue;
+                const int cz = (iz + oz + B.nc[2]) % B.nc[2];
+                const int64_t c = coarse_cell(B, cx, cy, cz);
+                for (int32_t j = w.cell_start[c]; j < w.cell_start[c + 1]; ++j) {
+                    const float4 q = w.sorted[j];
+                    const int32_t oj = __float_as_int(q.w);
+                    if (oj <= oi)
+                        continue;  // each unordered pair once, from its lower index
+                    const double s2 = dist2(B, p.x, p.y, p.z, q.x, q.y, q.z);
+                    if (!(s2 < B.b2))
+                        continue;
+                    const int32_t k = atomicAdd(a.n_edges, 1);
+                    if (k < a.edge_cap) {
+                        a.ei[k] = oi;
+                        a.ej[k] = oj;
+                        a.d2[k] = s2;
+                        a.si[k] = (int32_t)i;
+                        a.sj[k] = j;
+                    } else {
+                        atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_EDGE_CAP);
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_edges(Work w, SampleArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gtid(); i < w.n; i += stride)
+        edges_of(w, a, i);
+}
+
+__global__ void k_touch(SampleArgs a)
+{
+    const int64_t m = edge_count(a), stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = gtid(); e < m; e += stride) {
+        a.vflag[a.ei[e]] = 1;
+        a.vflag[a.ej[e]] = 1;
+    }
+}
+
+__global__ void k_vlist(int64_t n, SampleArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gtid(); i < n; i += stride)
+        if (a.vflag[i])
+            a.vlist[a.vmap[i]] = (int32_t)i;
+}
+
+__global__ void k_forest_init(int64_t n, SampleArgs a)
+{
+    const int64_t nv = a.vmap[n];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = gtid(); t < (int64_t)a.K * nv; t += stride)
+        a.forest[(t / nv) * a.vcap + t % nv] = (int32_t)(t % nv);
+}
+
+__device__ __forceinline__ int32_t ffind(const int32_t *f, int32_t x)
+{
+    for (;;) {
+        const int32_t p = __hip_atomic_load(f + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == x)
+            return x;
+        x = p;
+    }
+}
+
+// Hook the larger root under the smaller: local order is original-index order, so each
+// tree's root is its member with the smallest original index.
+__device__ __forceinline__ void funion(int32_t *f, int32_t a, int32_t b)
+{
+    for (;;) {
+        a = ffind(f, a);
+        b = ffind(f, b);
+        if (a == b)
+            return;
+        if (a < b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(f + a, a, b) == a)
+            return;
+    }
+}
+
+__global__ void k_sample_union(SampleArgs a)
+{
+    const int64_t m = edge_count(a), stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = gtid(); t < m * a.K; t += stride) {
+        const int32_t e = (int32_t)(t % m), s = (int32_t)(t / m);
+        const int32_t i = a.ei[e], j = a.ej[e];
+        const double u = edge_uniform(a.seed, (uint32_t)s, (uint32_t)i, (uint32_t)j);
+        if (u < edge_prob(a.d2[e], a.b, a.tau))
+            funion(a.forest + (int64_t)s * a.vcap, a.vmap[i], a.vmap[j]);
+    }
+}
+
+__global__ void k_sample_label(int64_t n, SampleArgs a, int32_t *__restrict__ root)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = gtid(); t < n * a.K; t += stride) {
+        const int64_t s = t / n, i = t % n;
+        int32_t lab = (int32_t)i;
+        if (a.vflag[i])
+            lab = a.vlist[ffind(a.forest + s * a.vcap, a.vmap[i])];
+        root[t] = lab;
+    }
+}
+
+// Advantage of each sample: loss minus baseline.
+__global__ void k_advantage(const double *__restrict__ loss, int32_t K, int32_t baseline,
+                            double *__restrict__ adv)
+{
+    const int s = threadIdx.x + blockIdx.x * blockDim.x;
+    if (s >= K)
+        return;
+    double sum = 0.0;
+    for (int k = 0; k < K; ++k)
+        sum += loss[k];
+    double beta = 0.0;
+    if (baseline == FOF_BASELINE_MEAN)
+        beta = sum / (double)K;
+    else if (baseline == FOF_BASELINE_LOO && K > 1)
+        beta = (sum - loss[s]) / (double)(K - 1);
+    adv[s] = loss[s] - beta;
+}
+
+__device__ void score_edge(const Work &w, const SampleArgs &a, int64_t e, float *grad)
+{
+    const int32_t i = a.ei[e], j = a.ej[e];
+    const double p = edge_prob(a.d2[e], a.b, a.tau);
+    double wsum = 0.0;
+    for (int32_t s = 0; s < a.K; ++s) {
+        const double u = edge_uniform(a.seed, (uint32_t)s, (uint32_t)i, (uint32_t)j);
+        wsum += a.adv[s] * ((u < p ? 1.0 : 0.0) - p);
+    }
+    const double wgt = wsum / (double)a.K;
+    const BoxDesc &B = w.desc[0];
+    const float4 pi = w.sorted[a.si[e]], pj = w.sorted[a.sj[e]];
+    const double dx = min_image((double)pi.x - (double)pj.x, B.L[0], B.halfL[0]);
+    const double dy = min_image((double)pi.y - (double)pj.y, B.L[1], B.halfL[1]);
+    const double dz = min_image((double)pi.z - (double)pj.z, B.L[2], B.halfL[2]);
+    const double f = wgt / (a.tau * sqrt(a.d2[e]));
+    atomicAdd(grad + 3 * (int64_t)i + 0, (float)(-f * dx));
+    atomicAdd(grad + 3 * (int64_t)i + 1, (float)(-f * dy));
+    atomicAdd(grad + 3 * (int64_t)i + 2, (float)(-f * dz));
+    atomicAdd(grad + 3 * (int64_t)j + 0, (float)(f * dx));
+    atomicAdd(grad + 3 * (int64_t)j + 1, (float)(f * dy));
+    atomicAdd(grad + 3 * (int64_t)j + 2, (float)(f * dz));
+}
+
+
+__global__ void k_score(Work w, SampleArgs a, float *__restrict__ grad)
+{
+    const int64_t m = edge_count(a), stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = gtid(); e < m; e += stride)
+        score_edge(w, a, e, grad);
+}
+unsigned blocks_for(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b > (1 << 20))
+        b = 1 << 20;  // grid-stride kernels cover the rest
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+}  // namespace
+
+// Scratch layout (256-byte aligned): vflag [n], vmap [n + 1], scan [tiles], vlist [vcap],
+// si [cap], sj [cap], forest [K][vcap].  Fails when the scratch is too small.
+static bool carve(const fof_sample &S, int64_t n, SampleArgs &a)
+{
+    char *base = (char *)S.scratch;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base + o;
+        o = (o + bytes + 255) / 256 * 256;
+        return p;
+    };
+    a.vcap = 2 * (int64_t)S.edge_cap < n ? 2 * (int64_t)S.edge_cap : n;
+    a.vflag = (int32_t *)take(4 * (size_t)n);
+    a.vmap = (int32_t *)take(4 * ((size_t)n + 1));
+    a.scan = (int32_t *)take(4 * (size_t)scan_scratch_elems(n));
+    a.vlist = (int32_t *)take(4 * (size_t)(a.vcap > 0 ? a.vcap : 1));
+    a.si = (int32_t *)take(4 * (size_t)(S.edge_cap > 0 ? S.edge_cap : 1));
+    a.sj = (int32_t *)take(4 * (size_t)(S.edge_cap > 0 ? S.edge_cap : 1));
+    a.forest = (int32_t *)take(4 * (size_t)S.K * (size_t)(a.vcap > 0 ? a.vcap : 1));
+    a.adv = (double *)take(8 * (size_t)S.K);
+    return o <= S.scratch_bytes;
+}
+
+static void fill_args(const fof_sample &S, SampleArgs &a)
+{
+    a.b = S.b;
+    a.tau = S.tau;
+    a.seed = S.seed;
+    a.K = S.K;
+    a.edge_cap = S.edge_cap;
+    a.ei = S.ei;
+    a.ej = S.ej;
+    a.d2 = S.d2;
+    a.n_edges = S.n_edges;
+}
+
+int sample_layout_ok(const fof_sample &S, int64_t n)
+{
+    SampleArgs a;
+    return carve(S, n, a) ? 1 : 0;
+}
+
+hipError_t launch_sample(const Work &w, const fof_sample &S, int32_t *root, hipStream_t s)
+{
+    SampleArgs a;
+    fill_args(S, a);
+    carve(S, w.n, a);
+    hipError_t e = launch_fill_i32(a.n_edges, 1, 0, s);
+    if (e != hipSuccess)
+        return e;
+    e = launch_fill_i32(a.vflag, w.n, 0, s);
+    if (e != hipSuccess)
+        return e;
+    if (w.n > 0)
+        hipLaunchKernelGGL(k_edges, dim3(blocks_for(w.n)), dim3(kBlock), 0, s, w, a);
+    // edges at most edge_cap: the grid of the following kernels is sized for the cap
+    hipLaunchKernelGGL(k_touch, dim3(blocks_for(S.edge_cap)), dim3(kBlock), 0, s, a);
+    e = launch_scan_i32(a.vflag, a.vmap, w.n, a.scan, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_vlist, dim3(blocks_for(w.n)), dim3(kBlock), 0, s, w.n, a);
+    hipLaunchKernelGGL(k_forest_init, dim3(blocks_for((int64_t)S.K * a.vcap)), dim3(kBlock), 0, s,
+                       w.n, a);
+    hipLaunchKernelGGL(k_sample_union, dim3(blocks_for((int64_t)S.edge_cap * S.K)), dim3(kBlock), 0,
+                       s, a);
+    if (root)
+        hipLaunchKernelGGL(k_sample_label, dim3(blocks_for(w.n * S.K)), dim3(kBlock), 0, s, w.n,
+                           a, root);
+    return hipGetLastError();
+}
+
+hipError_t launch_score(const Work &w, const fof_sample &S, const double *loss, int32_t baseline,
+                        float *grad_pos, hipStream_t s)
+{
+    SampleArgs a;
+    fill_args(S, a);
+    carve(S, w.n, a);
+    hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(k_advantage, dim3((S.K + 255) / 256), dim3(256), 0, s, loss, S.K, baseline,
+                       a.adv);
+    if (grad_pos) {
+        e = launch_fill_u32((uint32_t *)grad_pos, 3 * w.n, 0u, s);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_score, dim3(blocks_for(S.edge_cap)), dim3(kBlock), 0, s, w, a,
+                           grad_pos);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fof

@@ -132,10 +132,10 @@ class Plan:
         f64 = lambda t: None if t is None else t.to(torch.float64).contiguous()
         g_mass, g_com, g_sigv = f64(g_mass), f64(g_com), f64(g_sigv)
         check("fof_backward",
-              _lib.load().fof_backward(self._gref, _ptr(group_id), int(G), _ptr(sizes),
-                                       _ptr(vmean), _ptr(sigv), _ptr(vel), _ptr(g_mass),
-                                       _ptr(g_com), _ptr(g_sigv), _ptr(gp), _ptr(gv),
-                                       _stream(stream)))
+              _lib.load().fof_backward(self._gref, _ptr(self.ws), _lib.FOF_FROZEN, _ptr(group_id),
+                                       int(G), _ptr(sizes), _ptr(vmean), _ptr(sigv), _ptr(vel),
+                                       _ptr(g_mass), _ptr(g_com), _ptr(g_sigv), None, None, 0,
+                                       _ptr(gp), _ptr(gv), _stream(stream)))
         return gp, gv
 
 

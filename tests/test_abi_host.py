@@ -181,7 +181,15 @@ def test_entry_points_reject_bad_arguments_before_launch():
     assert L.fof_build_grid(gp, fake_ws, misaligned, None) == _lib.FOF_EINVAL    # ws alignment
     assert L.fof_build_grid(gp, fake_ws, None, None) == _lib.FOF_EINVAL          # ws NULL
     assert L.fof_link(gp, fake_ws, None, None, None) == _lib.FOF_EINVAL          # root NULL
-    assert L.fof_link(gp, fake_ws, fake_ws, fake_ws, None) == _lib.FOF_ENOTSUP   # sampling
+    S = _lib.fof_sample()                                                        # K = 0
+    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    S.K, S.tau, S.b, S.edge_cap = 4, 0.01, 0.2, 100
+    S.n_edges, S.ei, S.ej, S.d2 = 0x100000, 0x100000, 0x100000, 0x100000
+    S.scratch, S.scratch_bytes = 0x100000, 10                                   # too small
+    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    S.scratch_bytes = _lib.sample_scratch_bytes(100, 4, 100)
+    S.tau = 0.0                                                                  # tau <= 0
+    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
     assert L.fof_groups(gp, fake_ws, 20, None, 10, None, fake_ws, fake_ws, None, None, None,
                         None) == _lib.FOF_EINVAL                                  # group_id NULL
     assert L.fof_groups(gp, fake_ws, 20, None, -1, fake_ws, fake_ws, fake_ws, None, None, None,
@@ -190,12 +198,18 @@ def test_entry_points_reject_bad_arguments_before_launch():
                         None) == _lib.FOF_EINVAL                                  # sizes NULL
     assert L.fof_groups(gp, fake_ws, 20, fake_ws, 10, fake_ws, fake_ws, fake_ws, None, fake_ws,
                         None, None) == _lib.FOF_EINVAL                            # vmean w/o sigv
-    assert L.fof_backward(gp, None, 1, fake_ws, None, None, None, None, None, None, None, None,
-                          None) == _lib.FOF_EINVAL                                # group_id NULL
-    assert L.fof_backward(gp, fake_ws, -1, fake_ws, None, None, None, None, None, None, None,
-                          None, None) == _lib.FOF_EINVAL                          # G < 0
-    assert L.fof_backward(gp, fake_ws, 1, fake_ws, None, None, None, None, None, fake_ws, None,
-                          fake_ws, None) == _lib.FOF_EINVAL                       # vel missing
+    F = _lib.FOF_FROZEN
+    nul = [None] * 3
+    assert L.fof_backward(gp, fake_ws, F, None, 1, fake_ws, *nul, None, None, None, None, None,
+                          0, None, None, None) == _lib.FOF_EINVAL                # group_id NULL
+    assert L.fof_backward(gp, fake_ws, F, fake_ws, -1, fake_ws, *nul, None, None, None, None,
+                          None, 0, None, None, None) == _lib.FOF_EINVAL          # G < 0
+    assert L.fof_backward(gp, fake_ws, F, fake_ws, 1, fake_ws, *nul, None, None, fake_ws, None,
+                          None, 0, None, fake_ws, None) == _lib.FOF_EINVAL       # vel missing
+    assert L.fof_backward(gp, fake_ws, 7, fake_ws, 1, fake_ws, *nul, None, None, None, None,
+                          None, 0, None, None, None) == _lib.FOF_EINVAL          # bad mode
+    assert L.fof_backward(gp, fake_ws, _lib.FOF_SCORE, None, 0, None, *nul, None, None, None,
+                          None, fake_ws, 2, fake_ws, None, None) == _lib.FOF_EINVAL  # no sample
     p = ctypes.c_void_p()
     assert L.fof_status(gp, misaligned, ctypes.byref(p)) == _lib.FOF_EINVAL
     assert L.fof_status(gp, fake_ws, ctypes.byref(p)) == 0

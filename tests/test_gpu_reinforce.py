@@ -1,0 +1,122 @@
+"""Stochastic linking and the REINFORCE gradient on the GPU (paper Sec. 3.2).
+
+* candidate edges: the same set as the oracle, squared distances bit-exact;
+* sampled labels of K graphs: bit-exact to the oracle, which draws the same Philox4x64-10
+  uniforms (a near-tie |u - p| of a few ulps, ~1e-9 expected per run, would be reported);
+* gradient: equal to the oracle's FP64 estimator on the same samples (1e-5 relative);
+* unbiasedness: the mean over many launches matches the exact gradient by enumeration.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import say
+from oracle import reinforce as RF
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def sampler(pos, L, b, tau, K, seed, edge_cap=None):
+    import torch
+    from paper_2510_26851_amd.reinforce import Sampler
+
+    return Sampler(torch.from_numpy(pos).cuda(), L, b, tau, K, seed, edge_cap=edge_cap)
+
+
+def edge_set(ei, ej, d2):
+    return {(int(a), int(c)): float(d) for a, c, d in zip(ei, ej, d2)}
+
+
+@pytest.mark.parametrize("which", ["config3", "clumpy"])
+def test_edges_labels_and_gradient_match_oracle(which):
+    import torch
+
+    if which == "config3":
+        box = W.config3()
+        pos, L, b = box.pos, box.L, box.b
+        K, seed = 64, W.REINFORCE_SEED
+    else:
+        pos = W.clumpy_box(8000, 16.0, 6, 77)
+        L, b = 16.0, 0.3
+        K, seed = 16, 1234
+    tau = W.CONFIG3_TAU_FRAC * b
+    r_c = b + 10 * tau
+    say(f"reinforce {which}: n={pos.shape[0]} K={K}")
+    smp = sampler(pos, L, b, tau, K, seed)
+    root = smp.sample()
+    ei, ej, d2, total = smp.edges()
+    torch.cuda.synchronize()
+    assert smp.plan.status() == 0 and total == ei.shape[0]
+    oei, oej, od2 = RF.candidate_edges(pos, L, r_c)
+    got = edge_set(ei.cpu().numpy(), ej.cpu().numpy(), d2.cpu().numpy())
+    assert got == edge_set(oei, oej, od2)
+    # sampled labels
+    p = RF.edge_prob(od2, b, tau)
+    oroot, keep = RF.sample_labels(pos.shape[0], oei, oej, p, seed, K)
+    mism = np.nonzero((root.cpu().numpy() != oroot).any(axis=1))[0]
+    if mism.size:
+        u = np.array([[RF.uniform(seed, s, a, c) for a, c in zip(oei, oej)] for s in mism])
+        near = np.abs(u - p[None, :]) <= 8 * 2.0 ** -53
+        pytest.fail(f"samples {mism.tolist()} differ; near ties there: {int(near.sum())}")
+    # gradient with a loss computed from the labels
+    from paper_2510_26851_amd.reinforce import sum_sq_sizes
+
+    losses = sum_sq_sizes(root, 2)
+    g = smp.grad(losses, baseline="loo").cpu().numpy()
+    delta, d = RF.edge_geometry(pos, L, oei, oej)
+    ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, tau, keep,
+                            losses.cpu().numpy(), "loo")
+    assert np.abs(g - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1e-30)
+    for bl in ("mean", "none"):
+        g = smp.grad(losses, baseline=bl).cpu().numpy()
+        ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, tau, keep,
+                                losses.cpu().numpy(), bl)
+        assert np.abs(g - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1e-30)
+
+
+def test_sample_zero_of_a_batch_equals_a_single_sample():
+    pos = W.clumpy_box(4000, 12.0, 4, 5)
+    say("K = 32 vs K = 1")
+    r32 = sampler(pos, 12.0, 0.3, 0.015, 32, 9).sample().cpu().numpy()
+    r1 = sampler(pos, 12.0, 0.3, 0.015, 1, 9).sample().cpu().numpy()
+    np.testing.assert_array_equal(r32[0], r1[0])
+
+
+def test_edge_capacity_overflow_sets_status():
+    pos = W.clumpy_box(3000, 8.0, 3, 6)
+    say("edge capacity overflow")
+    smp = sampler(pos, 8.0, 0.3, 0.015, 2, 1, edge_cap=10)
+    smp.sample()
+    _, _, _, total = smp.edges()
+    assert total > 10 and smp.plan.status() & 4
+
+
+def test_estimator_mean_matches_enumeration():
+    import torch
+    from paper_2510_26851_amd.reinforce import Sampler
+
+    rng = np.random.default_rng(4)
+    g = np.array([[i * 0.3, j * 0.3, 0.0] for i in range(2) for j in range(3)])
+    pos = (2.0 + g + rng.uniform(-0.02, 0.02, g.shape)).astype(np.float32)
+    L, b, tau = 8.0, 0.32, 0.02
+    lossf = lambda root: RF.loss_sum_sq(root, 2)
+    _, g_exact = RF.enumerate_gradient(pos, L, b, tau, b + 10 * tau, lossf)
+    say("REINFORCE unbiasedness on 11 edges")
+    K, reps = 16, 300
+    t = torch.from_numpy(pos).cuda()
+    ests = []
+    for rep in range(reps):
+        smp = Sampler(t, L, b, tau, K, 5000 + rep)
+        root = smp.sample()
+        losses = torch.tensor([lossf(r) for r in root.cpu().numpy()], dtype=torch.float64)
+        ests.append(smp.grad(losses, "loo").cpu().numpy().astype(np.float64))
+    ests = np.array(ests)
+    z = np.abs(ests.mean(0) - g_exact) / np.maximum(ests.std(0, ddof=1) / np.sqrt(reps), 1e-12)
+    assert np.all(z < 4.5), z.max()
