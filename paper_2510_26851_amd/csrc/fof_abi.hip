@@ -96,6 +96,11 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
     if ((double)fs > a_min - 2.0 * eps)
         fs = nextafterf(fs, 0.0f);
     d->fine_side = fs > 0.0f ? fs : 0.0f;
+    for (int a = 0; a < 3; ++a)
+        d->fine[a] = (float)(bx.L[a] / (double)d->nf[a]);
+    // a member lies within eps of its exact fine cell; float box bounds and differences add
+    // a few ulps of L: 8 L 2^-23 covers both with room to spare
+    d->slack = round_up_f(8.0 * ldexp(Lmax, -23));
     d->dense_ok = (d->nc[0] >= 3 && d->nc[1] >= 3 && d->nc[2] >= 3 && d->R <= 3) ? 1 : 0;
     // the tiled link kernel needs every halo cell of a tile to be a distinct cell
     d->tiled = (d->nc[0] >= kTileX + 2 && d->nc[1] >= kTileY + 2 && d->nc[2] >= kTileZ + 2) ? 1 : 0;

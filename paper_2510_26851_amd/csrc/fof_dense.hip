@@ -27,7 +27,7 @@ namespace {
 
 constexpr int kDenseBlock = 256;
 constexpr int kLdsCap = 2048;     // particles a dense cell may hold to be sorted in LDS
-constexpr int kSmallCell = 512;   // dense cells up to this size are linked by one wave
+constexpr int kSmallCell = 256;   // dense cells up to this size are linked by one wave
 
 __device__ __forceinline__ int find_box_cell(const BoxDesc *d, int nbox, int64_t c)
 {
@@ -342,8 +342,9 @@ struct Grp<kDenseBlock> {
     static __device__ void sync() { __syncthreads(); }
 };
 
-template <int UMAX>
+template <int UMAX, int CAP>
 struct CellLds {
+    float4 part[CAP];               // the cell's particles, when it has at most CAP
     int uf[UMAX];                   // union-find over unit ranks
     unsigned long long umin[UMAX];  // (original index << 32 | sorted index) minimum
     int ustart[UMAX + 1];           // absolute sorted index of each unit's first member
@@ -364,10 +365,60 @@ __device__ __forceinline__ int rank_in(const uint32_t *bits, const int *pre, int
     return pre[k >> 5] + __popc(bits[k >> 5] & ((1u << (k & 31)) - 1u));
 }
 
-// Own units of dense cell d: keys, coordinates, member ranges, key bitmask.
-template <int G, int UMAX>
+// Box of global fine cell (gx, gy, gz) (any periodic image), widened by the slack.
+struct FineBox {
+    float lo[3], hi[3];
+};
+
+__device__ __forceinline__ FineBox fine_box(const BoxDesc &B, int gx, int gy, int gz)
+{
+    FineBox f;
+    const int g[3] = {gx, gy, gz};
+    for (int a = 0; a < 3; ++a) {
+        f.lo[a] = (float)g[a] * B.fine[a] - B.slack;
+        f.hi[a] = (float)(g[a] + 1) * B.fine[a] + B.slack;
+    }
+    return f;
+}
+
+// True when every point of the unit lies at least b from p, so the pair tests of p against
+// the unit can be skipped.  The box is widened by the slack (>= 5 L 2^-23: float error of
+// its bounds, the members' index error and the rounding of the differences), so the
+// computed gaps never exceed the true ones; the float sum of three squares is within
+// 2e-7 relative, covered by the factor 1 + 1e-6 on b^2.
+__device__ __forceinline__ bool far_from(const BoxDesc &B, const FineBox &f, float4 p)
+{
+    const float c[3] = {p.x, p.y, p.z};
+    float s = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        const float g = fmaxf(0.0f, fmaxf(f.lo[a] - c[a], c[a] - f.hi[a]));
+        s += g * g;
+    }
+    return s >= (float)B.b2 * 1.000001f;
+}
+
+// Is some member of unit A (memA[a0, a1)) a friend of some member of unit B (memB[b0, b1))?
+// Members of A far from B's fine box are skipped.
+__device__ __forceinline__ bool units_meet(const BoxDesc &B, const float4 *memA, int a0, int a1,
+                                           const float4 *memB, int b0, int b1, const FineBox &fb)
+{
+    for (int i = a0; i < a1; ++i) {
+        const float4 p = memA[i];
+        if (far_from(B, fb, p))
+            continue;
+        for (int j = b0; j < b1; ++j) {
+            const float4 q = memB[j];
+            if (linked(B, p.x, p.y, p.z, q.x, q.y, q.z))
+                return true;
+        }
+    }
+    return false;
+}
+
+// Own units of dense cell d: keys, coordinates, member ranges; bitmask into L.bits.
+template <int G, int UMAX, int CAP>
 __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n, int m, int u,
-                           CellLds<UMAX> &L)
+                           CellLds<UMAX, CAP> &L)
 {
     const int W = w.table_words;
     const int t = Grp<G>::tid();
@@ -379,6 +430,9 @@ __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n
         L.ustart[r] = w.rank[s + r];
     if (t == 0)
         L.ustart[u] = s + n;
+    if (n <= CAP)
+        for (int k = t; k < n; k += G)
+            L.part[k] = w.sorted[s + k];
     Grp<G>::sync();
     for (int q = t; q < W; q += G) {
         uint32_t bits = L.bits[q];
@@ -394,17 +448,19 @@ __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n
     Grp<G>::sync();
 }
 
-template <int G, int UMAX>
-__device__ void cc_cell(const Work &w, int d, CellLds<UMAX> &L)
+template <int G, int UMAX, int CAP>
+__device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
 {
     const int t = Grp<G>::tid();
     const int64_t c = w.dense_list[d];
     const int32_t s = w.cell_start[c];
     const int32_t n = w.cell_start[c + 1] - s;
     const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
+    const CellXYZ cc = cell_xyz(B, c);
     const int m = B.m, R = B.R;
     int32_t *T = w.table + (int64_t)d * w.table_stride;
     const int u = T[2];
+    const float4 *mem = n <= CAP ? L.part : w.sorted + s;  // indexed by (sorted index - s)
 
     if (t == 0) {
         L.ncomp = 0;
@@ -412,29 +468,33 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX> &L)
     }
     load_units<G>(w, T, s, n, m, u, L);
 
-    // forward offsets in [-R, R]^3 that survive gap pruning
+    // forward offsets in [-R, R]^3 that survive gap pruning, nearest shell first
     const int side = 2 * R + 1, half = (side * side * side - 1) / 2;
-    for (int q0 = 0; q0 < half; q0 += G) {
-        const int q = half + 1 + q0 + t;
-        bool keep = false;
-        int packed = 0;
-        if (q0 + t < half) {
-            const int dx = q % side, dy = (q / side) % side, dz = q / (side * side);
-            const double gx = fmax(0.0, (double)(abs(dx - R) - 1)) * B.fine_side;
-            const double gy = fmax(0.0, (double)(abs(dy - R) - 1)) * B.fine_side;
-            const double gz = fmax(0.0, (double)(abs(dz - R) - 1)) * B.fine_side;
-            keep = gx * gx + gy * gy + gz * gz < B.b2;
-            packed = dx | (dy << 4) | (dz << 8);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int q0 = 0; q0 < half; q0 += G) {
+            const int q = half + 1 + q0 + t;
+            bool keep = false;
+            int packed = 0;
+            if (q0 + t < half) {
+                const int dx = q % side, dy = (q / side) % side, dz = q / (side * side);
+                const int cheb = max(abs(dx - R), max(abs(dy - R), abs(dz - R)));
+                const double gx = fmax(0.0, (double)(abs(dx - R) - 1)) * B.fine_side;
+                const double gy = fmax(0.0, (double)(abs(dy - R) - 1)) * B.fine_side;
+                const double gz = fmax(0.0, (double)(abs(dz - R) - 1)) * B.fine_side;
+                keep = gx * gx + gy * gy + gz * gz < B.b2 && ((cheb <= 1) == (pass == 0));
+                packed = dx | (dy << 4) | (dz << 8);
+            }
+            if (keep)
+                L.offs[atomicAdd(&L.noff, 1)] = (short)packed;
         }
-        if (keep)
-            L.offs[atomicAdd(&L.noff, 1)] = (short)packed;
+        Grp<G>::sync();
     }
     // unit minima
     for (int r = t; r < u; r += G) {
         unsigned long long best = ~0ull;
         for (int i = L.ustart[r]; i < L.ustart[r + 1]; ++i) {
             const unsigned long long v =
-                ((unsigned long long)(uint32_t)__float_as_int(w.sorted[i].w) << 32) | (uint32_t)i;
+                ((unsigned long long)(uint32_t)__float_as_int(mem[i - s].w) << 32) | (uint32_t)i;
             best = v < best ? v : best;
         }
         L.umin[r] = best;
@@ -458,18 +518,12 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX> &L)
             const int rb = rank_in(L.bits, L.pre, kb);
             if (lfind(L.uf, r) == lfind(L.uf, rb))
                 continue;
-            bool hit = false;
-            for (int i = L.ustart[r]; i < L.ustart[r + 1] && !hit; ++i) {
-                const float4 p = w.sorted[i];
-                for (int j = L.ustart[rb]; j < L.ustart[rb + 1]; ++j) {
-                    const float4 q4 = w.sorted[j];
-                    if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
-                        hit = true;
-                        break;
-                    }
-                }
-            }
-            if (hit)
+            const FineBox fb = fine_box(B, cc.x * m + bx, cc.y * m + by, cc.z * m + bz);
+            FOF_STAT(w.ctr, ST_CC_UNIT_PAIRS, 1);
+            FOF_STAT(w.ctr, ST_CC_MEMBER_TESTS,
+                     (L.ustart[r + 1] - L.ustart[r]) * (L.ustart[rb + 1] - L.ustart[rb]));
+            if (units_meet(B, mem, L.ustart[r] - s, L.ustart[r + 1] - s, mem, L.ustart[rb] - s,
+                           L.ustart[rb + 1] - s, fb))
                 lunion(L.uf, r, rb);
         }
     }
@@ -505,8 +559,8 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX> &L)
     Grp<G>::sync();
 }
 
-template <int G, int UMAX>
-__device__ void cross_cell(const Work &w, int d, CellLds<UMAX> &L)
+template <int G, int UMAX, int CAP>
+__device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
 {
     const int t = Grp<G>::tid();
     const int64_t c = w.dense_list[d];
@@ -545,12 +599,16 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX> &L)
         Grp<G>::sync();
         return;
     }
+    const float4 *mem = n <= CAP ? L.part : w.sorted + s;
     for (int r = t; r < u; r += G) {
         L.ustart[r] = w.rank[s + r];
         L.ucomp[r] = (short)w.cnt[s + r];
     }
     if (t == 0)
         L.ustart[u] = s + n;
+    if (n <= CAP)
+        for (int k = t; k < n; k += G)
+            L.part[k] = w.sorted[s + k];
     for (int q = t; q < W; q += G) {
         uint32_t bits = (uint32_t)T[kTableHeader + q];
         int r = T[kTableHeader + W + q];
@@ -574,6 +632,8 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX> &L)
         const int u2 = T2[2], ncomp2 = T2[1];
         const bool dedupe = ncomp * ncomp2 <= 1024;
         const bool single = ncomp == 1 && ncomp2 == 1;
+        if (t == 0)
+            FOF_STAT(w.ctr, ST_CROSS_CELLPAIRS, 1);
         for (int q = t; q < W; q += G) {
             L.bits[q] = (uint32_t)T2[kTableHeader + q];
             L.pre[q] = T2[kTableHeader + W + q];
@@ -612,19 +672,28 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX> &L)
                             continue;
                         const int32_t b0 = w.rank[s2 + rb];
                         const int32_t b1 = rb + 1 < u2 ? w.rank[s2 + rb + 1] : s2 + n2;
-                        bool hit = false;
-                        for (int32_t i = L.ustart[r]; i < L.ustart[r + 1] && !hit; ++i) {
-                            const float4 p = w.sorted[i];
+                        // unit B's box in the own cell's periodic frame
+                        const FineBox fb = fine_box(B, (cc.x + ox) * m + bx, (cc.y + oy) * m + by,
+                                                    (cc.z + oz) * m + bz);
+                        FOF_STAT(w.ctr, ST_CROSS_UNIT_PAIRS, 1);
+                        FOF_STAT(w.ctr, ST_CROSS_MEMBER_TESTS,
+                                 (L.ustart[r + 1] - L.ustart[r]) * (b1 - b0));
+                        int hit_i = -1, hit_j = -1;
+                        for (int i = L.ustart[r]; i < L.ustart[r + 1] && hit_i < 0; ++i) {
+                            const float4 p = mem[i - s];
+                            if (far_from(B, fb, p))
+                                continue;
                             for (int32_t j = b0; j < b1; ++j) {
                                 const float4 q4 = w.sorted[j];
                                 if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
-                                    uf_union(w.parent, (uint32_t)i, (uint32_t)j);
-                                    hit = true;
+                                    hit_i = i;
+                                    hit_j = j;
                                     break;
                                 }
                             }
                         }
-                        if (hit) {
+                        if (hit_i >= 0) {
+                            uf_union(w.parent, (uint32_t)hit_i, (uint32_t)hit_j);
                             if (dedupe)
                                 atomicOr(L.pairbits + (bit >> 5), 1u << (bit & 31));
                             if (single) {
@@ -643,8 +712,8 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX> &L)
 template <bool kCross>
 __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
 {
-    __shared__ CellLds<kSmallCell> lds[Grp<kWave>::per_block];
-    CellLds<kSmallCell> &L = lds[Grp<kWave>::slot()];
+    __shared__ CellLds<kSmallCell, kSmallCell> lds[Grp<kWave>::per_block];
+    CellLds<kSmallCell, kSmallCell> &L = lds[Grp<kWave>::slot()];
     const int nd = dense_count(w.ctr, w.dense_cap);
     const int stride = gridDim.x * Grp<kWave>::per_block;
     for (int d = blockIdx.x * Grp<kWave>::per_block + Grp<kWave>::slot(); d < nd; d += stride) {
@@ -662,7 +731,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
 template <bool kCross>
 __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
 {
-    __shared__ CellLds<kMaxFineKeys> L;
+    __shared__ CellLds<kMaxFineKeys, kLdsCap> L;
     const int nb = __hip_atomic_load(&w.ctr->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int k = blockIdx.x; k < nb; k += gridDim.x) {
         const int d = w.big_list[k];

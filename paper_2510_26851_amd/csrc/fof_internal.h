@@ -43,7 +43,9 @@ struct alignas(16) BoxDesc {
     float inv_fine[3];  // float(nf / L): fine index = trunc(x * inv_fine)
     float side[3];      // float(L / nc): coarse cell side
     float reach;        // pruning distance: b plus the bound on index rounding error
-    float fine_side;    // largest fine cell side (float, rounded down)
+    float fine_side;    // smallest fine cell side less the index error (float, rounded down)
+    float fine[3];      // fine cell side per axis, L / nf (float)
+    float slack;        // margin added to fine-cell boxes before a distance skip
 };
 
 // Status bits (public values in fof.h) and the counters block.
@@ -51,8 +53,21 @@ struct Counters {
     int32_t status;
     int32_t n_dense;     // dense cells found
     int32_t n_big;       // dense cells linked by a whole block
-    int32_t pad[61];
+    int32_t pad[29];
+    unsigned long long stats[16];  // event counts of diagnostic builds (-DFOF_STATS)
 };
+
+// Event counters for diagnostic builds; compiled out otherwise.
+enum Stat {
+    ST_TILES, ST_TILES_OVERFLOW, ST_OWN_STAGED, ST_OWN_GLOBAL, ST_PAIRS_TILED, ST_PAIRS_GLOBAL,
+    ST_DN_CALLS, ST_DN_UNITS, ST_DN_MEMBER_TESTS, ST_CC_UNIT_PAIRS, ST_CC_MEMBER_TESTS,
+    ST_CROSS_UNIT_PAIRS, ST_CROSS_MEMBER_TESTS, ST_UNIONS, ST_CROSS_CELLPAIRS, ST_SPARE
+};
+#ifdef FOF_STATS
+#define FOF_STAT(ctr, k, v) atomicAdd(&(ctr)->stats[k], (unsigned long long)(v))
+#else
+#define FOF_STAT(ctr, k, v) ((void)0)
+#endif
 
 // ---------------------------------------------------------------------------------------
 // Box lookup: box k owns global indices [off_k, off_k + n_k); boxes are in order.

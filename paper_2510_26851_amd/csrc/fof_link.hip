@@ -64,6 +64,7 @@ __device__ bool link_dense_neighbour(const Work &w, const BoxDesc &B, uint32_t i
     const int32_t *T = w.table + (int64_t)d2 * w.table_stride;
     const int u = T[2], ncomp = T[1];
     int x0, x1, y0, y1, z0, z1;
+    FOF_STAT(w.ctr, ST_DN_CALLS, 1);
     key_range(p.x * B.inv_fine[0] - (float)((ix + ox) * m), B.reach * B.inv_fine[0], m, x0, x1);
     key_range(p.y * B.inv_fine[1] - (float)((iy + oy) * m), B.reach * B.inv_fine[1], m, y0, y1);
     key_range(p.z * B.inv_fine[2] - (float)((iz + oz) * m), B.reach * B.inv_fine[2], m, z0, z1);
@@ -83,6 +84,8 @@ __device__ bool link_dense_neighbour(const Work &w, const BoxDesc &B, uint32_t i
                     continue;
                 const int32_t b0 = w.rank[s2 + rb];
                 const int32_t b1 = rb + 1 < u ? w.rank[s2 + rb + 1] : s2 + n2;
+                FOF_STAT(w.ctr, ST_DN_UNITS, 1);
+                FOF_STAT(w.ctr, ST_DN_MEMBER_TESTS, b1 - b0);
                 for (int32_t j = b0; j < b1; ++j) {
                     const float4 q = w.sorted[j];
                     if (linked(B, p.x, p.y, p.z, q.x, q.y, q.z)) {
@@ -135,6 +138,7 @@ __device__ bool link_particle_global(const Work &w, const BoxDesc &B, int64_t i,
                         continue;
                     }
                 }
+                FOF_STAT(w.ctr, ST_PAIRS_GLOBAL, e - s);
                 for (int32_t j = s; j < e; ++j) {
                     if (j == i)
                         continue;
@@ -317,6 +321,12 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
         ownoff[t] = acc;
     }
     const bool staged = hoff[kHalo] <= kTileCap;
+    if (t == 0) {
+        FOF_STAT(w.ctr, ST_TILES, 1);
+        FOF_STAT(w.ctr, staged ? ST_OWN_STAGED : ST_OWN_GLOBAL, ownoff[kOwnRows]);
+        if (!staged)
+            FOF_STAT(w.ctr, ST_TILES_OVERFLOW, 1);
+    }
     if (staged) {
         const int lane = lane_id();
         for (int row = t / kWave; row < kRowsH; row += kTileBlock / kWave) {
@@ -383,6 +393,7 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
             for (int oy = sy.lo; oy <= sy.hi; ++oy) {
                 const int rb = ((hx + ox) * kHY + hy + oy) * kHZ;
                 const int a = hoff[rb + hz + sz.lo], e = hoff[rb + hz + sz.hi + 1];
+                FOF_STAT(w.ctr, ST_PAIRS_TILED, e - a);
                 for (int j = a; j < e; ++j) {
                     const int64_t gj = pidx[j];
                     if (gj == i)

@@ -62,8 +62,8 @@ def plan(counts, boxes, tune=None, desc=True):
 
 # BoxDesc layout (fof_internal.h): int64 off, cell_base, tile_base; int32 n, m, nc[3], nf[3],
 # R, dense_ok, tiled, ntile[3]; double L[3], halfL[3], b2; float inv_fine[3], side[3],
-# reach, fine_side.
-_DESC = struct.Struct("<qqqii3i3iiii3i3d3dd3f3fff")
+# reach, fine_side, fine[3], slack.
+_DESC = struct.Struct("<qqqii3i3iiii3i3d3dd3f3fff3ff")
 
 
 def desc_stride():
@@ -76,7 +76,7 @@ def decode(buf, k=0):
     return dict(off=v[0], cell_base=v[1], tile_base=v[2], n=v[3], m=v[4], nc=v[5:8],
                 nf=v[8:11], R=v[11], dense_ok=v[12], tiled=v[13], ntile=v[14:17], L=v[17:20],
                 halfL=v[20:23], b2=v[23], inv_fine=v[24:27], side=v[27:30], reach=v[30],
-                fine_side=v[31])
+                fine_side=v[31], fine=v[32:35], slack=v[35])
 
 
 def test_descriptor_size():
@@ -112,6 +112,7 @@ def test_plan_geometry_guarantees(L, b, n):
     assert d["R"] * a_min >= b + 2 * eps
     assert d["fine_side"] <= a_min - 2 * eps
     assert d["dense_ok"] == int(min(d["nc"]) >= 3 and d["R"] <= 3)
+    assert d["slack"] >= 4 * eps
     ncell = int(np.prod(d["nc"]))
     assert g.ncell == ncell and ncell <= 8 * n + 64 + 3 * max(d["nc"]) ** 2 * 3
     assert g.ws_bytes > 0 and g.ws_bytes % 256 == 0

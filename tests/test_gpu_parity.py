@@ -160,3 +160,16 @@ def test_very_dense_clumps_cell_side(cell_side):
     pos, L, b = very_dense_box(43)
     say(f"very dense clumps cell_side={cell_side}")
     compare_with_oracle(pos, L, b, 20, tune=dict(cell_side=cell_side))
+
+
+def test_autotuner_choice_does_not_change_results(tmp_path):
+    import torch
+    from paper_2510_26851_amd.tune import autotune
+
+    box = W.config0()
+    say("autotuner on config 0")
+    pos = torch.from_numpy(box.pos).cuda()
+    tune = autotune(pos, box.L, box.b, box.min_size, cache=str(tmp_path / "tune.json"), reps=1)
+    assert autotune(pos, box.L, box.b, box.min_size, cache=str(tmp_path / "tune.json")) == tune
+    root_ref, _ = oracle.fof(box.pos, box.L, box.b)
+    compare_with_oracle(box.pos, box.L, box.b, box.min_size, tune=tune, root_ref=root_ref)
