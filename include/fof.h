@@ -193,6 +193,10 @@ int fof_status(const fof_grid *grid, void *ws /*dev*/, int32_t **status /*host o
 /* Static text for a FOF_E* code. */
 const char *fof_strerror(int code);
 
+/* The HIP error code (hipError_t) behind the calling thread's most recent FOF_EDEVICE, or 0.
+ * If `name` is not NULL it receives the runtime's static name of that code. */
+int fof_last_device_error(const char **name /*host out, may be NULL*/);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,7 +35,7 @@ def sample_scratch_bytes(n: int, K: int, edge_cap: int) -> int:
 
 # Every symbol include/fof.h declares.
 EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",
-           "fof_status", "fof_strerror")
+           "fof_status", "fof_strerror", "fof_last_device_error")
 
 
 class fof_box(ctypes.Structure):
@@ -71,7 +71,12 @@ class fof_grid(ctypes.Structure):
 class FoFError(RuntimeError):
     def __init__(self, fn, code):
         self.code = code
-        super().__init__(f"{fn} failed: {strerror(code)} ({code})")
+        msg = f"{fn} failed: {strerror(code)} ({code})"
+        if code == FOF_EDEVICE:
+            name = ctypes.c_char_p()
+            hip = load().fof_last_device_error(ctypes.byref(name))
+            msg += f": {name.value.decode() if name.value else '?'} ({hip})"
+        super().__init__(msg)
 
 
 _lib = None
@@ -83,6 +88,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime, which its libraries request as "libamdhip64.so".
+    # Loaded first, that copy also satisfies libfof.so's "libamdhip64.so.7", so the process
+    # holds one runtime.  The other order maps two, and the second sees no device.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     L.fof_workspace_bytes.argtypes = [i32, P, P, P, P, P, sz]
@@ -93,6 +102,7 @@ def load():
     L.fof_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_void_p)]
     L.fof_strerror.argtypes = [ctypes.c_int]
     L.fof_strerror.restype = ctypes.c_char_p
+    L.fof_last_device_error.argtypes = [ctypes.POINTER(ctypes.c_char_p)]
     for f in EXPORTS:
         if f != "fof_strerror":
             getattr(L, f).restype = ctypes.c_int

@@ -190,7 +190,20 @@ Work resolve(const fof_grid *g, void *ws)
     return w;
 }
 
-int dev_err(hipError_t e) { return e == hipSuccess ? FOF_OK : FOF_EDEVICE; }
+// HIP error behind the calling thread's last FOF_EDEVICE.
+thread_local hipError_t g_last_device_error = hipSuccess;
+
+int dev_err(hipError_t e)
+{
+    if (e == hipSuccess)
+        return FOF_OK;
+    g_last_device_error = e;
+    return FOF_EDEVICE;
+}
+
+// The runtime's last-error slot may hold an error of another caller's earlier API call;
+// clear it so that only this call's launches are reported.
+void clear_stale_error() { (void)hipGetLastError(); }
 
 }  // namespace
 }  // namespace fof
@@ -285,6 +298,7 @@ int fof_build_grid(const fof_grid *grid, const float *pos, void *ws, void *strea
     if (!ws_ok(grid, ws) || (grid->n > 0 && !pos))
         return FOF_EINVAL;
     Work w = resolve(grid, ws);
+    clear_stale_error();
     return dev_err(launch_build(w, pos, (hipStream_t)stream));
 }
 
@@ -302,6 +316,7 @@ int fof_link(const fof_grid *grid, void *ws, const fof_sample *sample, int32_t *
     if (!ws_ok(grid, ws))
         return FOF_EINVAL;
     Work w = resolve(grid, ws);
+    clear_stale_error();
     if (sample) {
         if (!sample_ok(grid, sample))
             return FOF_EINVAL;
@@ -322,6 +337,7 @@ int fof_groups(const fof_grid *grid, void *ws, int32_t min_size, const float *ve
     if ((vmean == nullptr) != (sigv == nullptr) || (vel == nullptr && vmean != nullptr))
         return FOF_EINVAL;
     Work w = resolve(grid, ws);
+    clear_stale_error();
     return dev_err(launch_groups(w, min_size, vel, cap, group_id, n_groups, sizes, com, vmean,
                                  sigv, (hipStream_t)stream));
 }
@@ -340,6 +356,7 @@ int fof_backward(const fof_grid *grid, void *ws, int32_t mode, const int32_t *gr
             baseline < FOF_BASELINE_NONE || baseline > FOF_BASELINE_LOO)
             return FOF_EINVAL;
         Work w = resolve(grid, ws);
+        clear_stale_error();
         return dev_err(launch_score(w, *sample, loss, baseline, grad_pos, (hipStream_t)stream));
     }
     if (mode != FOF_FROZEN)
@@ -349,6 +366,7 @@ int fof_backward(const fof_grid *grid, void *ws, int32_t mode, const int32_t *gr
     if (grad_vel && g_sigv && (!vel || !vmean || !sigv))
         return FOF_EINVAL;
     const int32_t block = grid->block > 0 ? grid->block : kDefaultBlock;
+    clear_stale_error();
     return dev_err(launch_backward(grid->n, block, group_id, G, sizes, vmean, sigv, vel, g_com,
                                    g_sigv, grad_pos, grad_vel, (hipStream_t)stream));
 }
@@ -359,6 +377,13 @@ int fof_status(const fof_grid *grid, void *ws, int32_t **status)
         return FOF_EINVAL;
     *status = (int32_t *)((char *)ws + grid->off_status);
     return FOF_OK;
+}
+
+int fof_last_device_error(const char **name)
+{
+    if (name)
+        *name = hipGetErrorName(g_last_device_error);
+    return (int)g_last_device_error;
 }
 
 const char *fof_strerror(int code)

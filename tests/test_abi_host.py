@@ -215,3 +215,17 @@ def test_entry_points_reject_bad_arguments_before_launch():
     assert L.fof_status(gp, misaligned, ctypes.byref(p)) == _lib.FOF_EINVAL
     assert L.fof_status(gp, fake_ws, ctypes.byref(p)) == 0
     assert p.value == 0x100000 + g.off_status
+
+
+def test_one_hip_runtime_per_process():
+    """Loading the library (even before anything imports torch) must leave one HIP runtime
+    mapped: two copies in one process give 'no device' on the second."""
+    import subprocess
+    import sys
+
+    code = ("import paper_2510_26851_amd, torch\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "1"
