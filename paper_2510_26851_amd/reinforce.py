@@ -22,6 +22,10 @@ _BASELINES = {"none": _lib.FOF_BASELINE_NONE, "mean": _lib.FOF_BASELINE_MEAN,
 
 
 class Sampler:
+    """Without an explicit edge_cap the capacity grows on demand: sample() reads the edge
+    count back (one synchronisation) and, if it exceeded the capacity, reallocates and runs
+    again.  With an explicit edge_cap an overflow only sets FOF_STATUS_EDGE_CAP."""
+
     def __init__(self, pos, L, b, tau, K, seed, r_cut=None, edge_cap=None, tune=None):
         self.n = pos.shape[0]
         self.device = pos.device
@@ -29,8 +33,13 @@ class Sampler:
         self.plan = Plan([self.n], [(L, self.r_cut)], device=pos.device, tune=tune)
         self.pos = pos
         self.K = int(K)
-        cap = int(edge_cap) if edge_cap is not None else max(1024, 4 * self.n)
-        d = pos.device
+        self.b, self.tau, self.seed = float(b), float(tau), int(seed)
+        self.auto_grow = edge_cap is None
+        self._alloc(int(edge_cap) if edge_cap is not None else max(1024, 4 * self.n))
+        self.plan.build_grid(pos)
+
+    def _alloc(self, cap):
+        d = self.device
         self.ei = torch.empty(cap, dtype=torch.int32, device=d)
         self.ej = torch.empty(cap, dtype=torch.int32, device=d)
         self.d2 = torch.empty(cap, dtype=torch.float64, device=d)
@@ -38,20 +47,27 @@ class Sampler:
         nb = _lib.sample_scratch_bytes(self.n, self.K, cap)
         self.scratch = torch.empty(nb, dtype=torch.uint8, device=d)
         S = _lib.fof_sample()
-        S.b, S.tau, S.seed, S.K, S.edge_cap = float(b), float(tau), int(seed), self.K, cap
+        S.b, S.tau, S.seed, S.K, S.edge_cap = self.b, self.tau, self.seed, self.K, cap
         S.ei, S.ej, S.d2 = self.ei.data_ptr(), self.ej.data_ptr(), self.d2.data_ptr()
         S.n_edges = self.n_edges.data_ptr()
         S.scratch, S.scratch_bytes = self.scratch.data_ptr(), nb
         self.S = S
-        self.plan.build_grid(pos)
+
+    def _launch(self, root, stream):
+        check("fof_link", _lib.load().fof_link(self.plan._gref, _ptr(self.plan.ws),
+                                               ctypes.byref(self.S), _ptr(root), _stream(stream)))
 
     def sample(self, root=None, want_labels=True, stream=None):
         if want_labels and root is None:
             root = torch.empty((self.K, self.n), dtype=torch.int32, device=self.device)
-        check("fof_link", _lib.load().fof_link(self.plan._gref, _ptr(self.plan.ws),
-                                               ctypes.byref(self.S),
-                                               _ptr(root) if want_labels else None,
-                                               _stream(stream)))
+        root = root if want_labels else None
+        self._launch(root, stream)
+        if self.auto_grow:
+            total = int(self.n_edges.item())
+            if total > self.S.edge_cap:
+                self._alloc(total + total // 8 + 1024)
+                self.plan.build_grid(self.pos, stream)  # clears the overflow status bit
+                self._launch(root, stream)
         return root
 
     def edges(self):
