@@ -12,6 +12,8 @@ link pass and the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import statistics
@@ -28,6 +30,39 @@ HBM_PEAK_GBS = 8000.0
 LINK_BYTES_PER_PARTICLE = 20
 BUILD_BYTES_PER_PARTICLE = 28
 GROUPS_BYTES_PER_PARTICLE = 20
+
+
+# The link stage (fof_link) as launched on the benchmark workload: its kernels, in order.
+LINK_STAGE = "fof_link: k_fill<u64>, k_dense_small/big<false>, k_dense_small/big<true>, " \
+             "k_link_tiled, k_link, k_compress"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "link_stage_traffic_zeldovich-nfw-512.txt")
+
+
+def kernel_digest():
+    """SHA-256 over the HIP sources and the ABI header: recorded HBM traffic is reported only
+    while the kernels it was measured on are unchanged."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2510_26851_amd", "csrc", "*"))) + \
+        [os.path.join(ROOT, "include", "fof.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload, tune):
+    """HBM bytes per link-stage launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE record, or
+    None when there is none for this workload and these kernels."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(l.strip().split("=", 1) for l in f if "=" in l and not l.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("workload") != workload or kv.get("kernel_digest") != kernel_digest() or \
+            kv.get("tune") != json.dumps(tune, sort_keys=True):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def log(*a):
@@ -70,6 +105,41 @@ def copy_bandwidth(torch, dev, nbytes=2 << 30):
     return 2 * nbytes / t / 1e9
 
 
+METRIC = "Mparticles/s end-to-end FoF at 512\u00b3 + % HBM peak; batched REINFORCE samples/s"
+
+
+def reinforce_rate(torch, dev, reps):
+    """Stochastic linking of the 128^3 velocity box: K = 64 sampled graphs in one launch plus
+    the score-function gradient.  The per-sample losses (the caller's function of the labels)
+    are computed once, outside the timed region."""
+    import workloads as W
+    from paper_2510_26851_amd.reinforce import Sampler, sum_sq_sizes
+
+    box = W.config3()
+    tau = W.CONFIG3_TAU_FRAC * box.b
+    pos = torch.from_numpy(box.pos).to(dev)
+    smp = Sampler(pos, box.L, box.b, tau, W.CONFIG3_K, W.REINFORCE_SEED)
+    root = smp.sample()              # sizes the edge buffers
+    smp.auto_grow = False
+    losses = sum_sq_sizes(root, 2)
+    smp.grad(losses)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        smp.sample(root)
+        smp.grad(losses)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    if smp.plan.status() != 0:
+        raise SystemExit(f"device status {smp.plan.status()} in the REINFORCE leg")
+    return {"workload": box.name, "n": box.n, "K": W.CONFIG3_K, "tau": tau,
+            "edges": int(smp.n_edges.item()), "ms_per_batch": round(ms, 4),
+            "samples_per_s": round(W.CONFIG3_K / (ms / 1e3), 1),
+            "timed": "fof_link(sample) + fof_backward(FOF_SCORE) per batch of K"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,10 +147,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-zmax", type=float, default=32.0)
+    ap.add_argument("--cpu-zmax", type=float, default=64.0)
     ap.add_argument("--cell-side", type=float, default=0.0, help="coarse cell side (0 = default)")
     ap.add_argument("--dense-threshold", type=int, default=0, help="0 = default, <0 = off")
     ap.add_argument("--block", type=int, default=0, help="threads per block (0 = default)")
+    ap.add_argument("--no-reinforce", action="store_true")
+    ap.add_argument("--reinforce-reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -152,9 +224,10 @@ def main():
     achieved = LINK_BYTES_PER_PARTICLE * box.n / (link_mean_ms / 1e3) / 1e9
     copy_gbs = copy_bandwidth(torch, dev)
     log(f"copy bandwidth {copy_gbs:.0f} GB/s")
+    traffic = recorded_traffic(box.name, tune)
 
     line = {
-        "metric": "Mparticles/s end-to-end FoF (build_grid + link + groups)",
+        "metric": METRIC,
         "value": round(value, 2),
         "unit": "Mparticles/s",
         "n_gpus": 1,
@@ -173,13 +246,21 @@ def main():
         "hbm_frac_end_to_end": round((BUILD_BYTES_PER_PARTICLE + LINK_BYTES_PER_PARTICLE +
                                       GROUPS_BYTES_PER_PARTICLE) * box.n /
                                      (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": {"kernel": "fof_link (k_link + k_compress)", "bound": "hbm",
+        "roofline": {"kernel": LINK_STAGE, "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / 1e9, 4),
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "scaled by a 2 GiB copy)",
+                     "algorithmic_GB_per_launch": round(LINK_BYTES_PER_PARTICLE * box.n / 1e9, 4),
                      "bytes_per_particle": LINK_BYTES_PER_PARTICLE,
                      "avg_ms": round(link_mean_ms, 4)},
+        "hbm_peak_frac_link": round(achieved / HBM_PEAK_GBS, 4),
         "copy_gbs": round(copy_gbs, 1),
     }
+    if not args.no_reinforce:
+        log("timing batched REINFORCE ...")
+        line["reinforce"] = reinforce_rate(torch, dev, args.reinforce_reps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(box, args.cpu_zmax)

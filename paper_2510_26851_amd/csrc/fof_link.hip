@@ -145,7 +145,9 @@ __device__ bool link_particle_global(const Work &w, const BoxDesc &B, int64_t i,
                     const float4 q = w.sorted[j];
                     if (linked(B, p.x, p.y, p.z, q.x, q.y, q.z)) {
                         has_friend = true;
-                        if (i < j)
+                        // each pair is hooked from the end with the smaller original index,
+                        // the rule every link path shares (the other end may be staged)
+                        if (__float_as_int(p.w) < __float_as_int(q.w))
                             uf_union(w.parent, (uint32_t)i, (uint32_t)j);
                     }
                 }
@@ -185,19 +187,22 @@ __global__ void k_link(Work w, int32_t *__restrict__ root)
 
 // ---------------------------------------------------------------------------------------
 // LDS-tiled linking.  A block owns kTileX x kTileY x kTileZ coarse cells and stages them
-// with a one-cell halo in LDS.  With cells z fastest, each (x, y) row of the halo is one
-// contiguous run of particles, copied with coalesced loads; then a particle's candidates
-// in one neighbour row (up to three consecutive cells) form one contiguous LDS range.
+// with a one-cell halo in LDS.  With cells z fastest, a particle's candidates in one
+// neighbour row (up to three consecutive cells) form one contiguous LDS range.  Staging is
+// flat: staged slot s belongs to the halo cell whose offset range holds s, found by a
+// fixed-length binary search, so each thread issues its few global loads back to back.
 // Cells with clique tables are not staged: particles reach them through their unit
 // tables.  A tile whose staged particles do not fit searches from global memory.
 // ---------------------------------------------------------------------------------------
 constexpr int kHX = kTileX + 2, kHY = kTileY + 2, kHZ = kTileZ + 2;
 constexpr int kRowsH = kHX * kHY;
 constexpr int kHalo = kRowsH * kHZ;
-constexpr int kPerT = (kHalo + 255) / 256;  // halo cells per thread in the scan
 constexpr int kTileBlock = 256;
-constexpr int kTileCap = 1024;  // staged particles per tile
+constexpr int kPerT = (kHalo + kTileBlock - 1) / kTileBlock;  // halo cells per thread
+constexpr int kTileCap = 1024;                                  // staged particles per tile
+constexpr int kStagePerT = kTileCap / kTileBlock;
 constexpr int kOwnRows = kTileX * kTileY;
+static_assert(kTileCap % kTileBlock == 0, "staging assumes whole rounds");
 
 // Box owning tile t: the last box whose first tile is <= t.  Boxes without tiles share
 // their tile_base with the next box, which comes later, so they are never chosen.
@@ -220,14 +225,25 @@ __device__ __forceinline__ int mod_cell(int c, int nc)
     return r < 0 ? r + nc : r;
 }
 
+// Halo cell holding staged slot s: the last h with hoff[h] <= s (hoff non-decreasing,
+// hoff[0] = 0 <= s < hoff[kHalo]).  Fixed trip count, so independent searches interleave.
+__device__ __forceinline__ int halo_cell_of(const int *hoff, int s)
+{
+    int pos = 0;
+#pragma unroll
+    for (int step = 512; step > 0; step >>= 1)
+        if (pos + step < kHalo && hoff[pos + step] <= s)
+            pos += step;
+    return pos;
+}
+static_assert(kHalo <= 1024, "halo_cell_of searches at most 1024 cells");
+
 __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__restrict__ root)
 {
     __shared__ float4 part[kTileCap];
-    __shared__ int pidx[kTileCap];    // sorted index of each staged particle
-    __shared__ int hoff[kHalo + 1];   // staged offset of each halo cell
-    __shared__ int gst[kHalo];        // global start of each halo cell
-    __shared__ int htag[kHalo];       // dense id (>= 0) or -1
-    __shared__ int rowslow[kRowsH];   // row copied cell by cell (wraps or holds dense cells)
+    __shared__ int hoff[kHalo + 1];  // staged offset of each halo cell
+    __shared__ int gst[kHalo];       // global (sorted) start of each halo cell
+    __shared__ int htag[kHalo];      // dense id (>= 0) or -1
     __shared__ int ownoff[kOwnRows + 1];
     __shared__ int scr[kTileBlock / kWave];
 
@@ -248,9 +264,6 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
     const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
     const int t = threadIdx.x;
 
-    if (t < kRowsH)
-        rowslow[t] = 0;
-    __syncthreads();
     int cnt_local[kPerT];
     int sum = 0;
 #pragma unroll
@@ -261,18 +274,15 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
             const int hz = h % kHZ, row = h / kHZ, hy = row % kHY, hx = row / kHY;
             int tag = -1, s = 0;
             if (hx <= hxe && hy <= hye && hz <= hze) {
-                const int gz = z0 - 1 + hz;
                 const int64_t c = coarse_cell(B, mod_cell(x0 - 1 + hx, B.nc[0]),
-                                              mod_cell(y0 - 1 + hy, B.nc[1]), mod_cell(gz, B.nc[2]));
+                                              mod_cell(y0 - 1 + hy, B.nc[1]),
+                                              mod_cell(z0 - 1 + hz, B.nc[2]));
                 s = w.cell_start[c];
                 cnt = w.cell_start[c + 1] - s;
                 if (box_dense && cnt > w.dense_threshold && w.cell_count[c] >= 0) {
                     tag = w.cell_count[c];
                     cnt = 0;
-                    rowslow[row] = 1;
                 }
-                if (gz < 0 || gz >= B.nc[2])
-                    rowslow[row] = 1;
             }
             gst[h] = s;
             htag[h] = tag;
@@ -320,70 +330,56 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
         }
         ownoff[t] = acc;
     }
-    const bool staged = hoff[kHalo] <= kTileCap;
+    const int total = hoff[kHalo];
+    const bool staged = total <= kTileCap;
     if (t == 0) {
         FOF_STAT(w.ctr, ST_TILES, 1);
-        FOF_STAT(w.ctr, staged ? ST_OWN_STAGED : ST_OWN_GLOBAL, ownoff[kOwnRows]);
         if (!staged)
             FOF_STAT(w.ctr, ST_TILES_OVERFLOW, 1);
     }
     if (staged) {
-        const int lane = lane_id();
-        for (int row = t / kWave; row < kRowsH; row += kTileBlock / kWave) {
-            const int rb = row * kHZ;
-            if (!rowslow[row]) {  // one contiguous run of particles
-                const int ls = hoff[rb], n = hoff[rb + kHZ] - ls;
-                const int gs = gst[rb];
-                for (int k = lane; k < n; k += kWave) {
-                    part[ls + k] = w.sorted[gs + k];
-                    pidx[ls + k] = gs + k;
-                }
-            } else {
-                for (int hz = 0; hz < kHZ; ++hz) {
-                    const int ls = hoff[rb + hz], n = hoff[rb + hz + 1] - ls;
-                    const int gs = gst[rb + hz];
-                    for (int k = lane; k < n; k += kWave) {
-                        part[ls + k] = w.sorted[gs + k];
-                        pidx[ls + k] = gs + k;
-                    }
-                }
+        int src[kStagePerT];
+#pragma unroll
+        for (int k = 0; k < kStagePerT; ++k) {
+            const int sl = t + k * kTileBlock;
+            src[k] = -1;
+            if (sl < total) {
+                const int h = halo_cell_of(hoff, sl);
+                src[k] = gst[h] + (sl - hoff[h]);
             }
         }
+        float4 v[kStagePerT];
+#pragma unroll
+        for (int k = 0; k < kStagePerT; ++k)
+            if (src[k] >= 0)
+                v[k] = w.sorted[src[k]];
+#pragma unroll
+        for (int k = 0; k < kStagePerT; ++k)
+            if (src[k] >= 0)
+                part[t + k * kTileBlock] = v[k];
     }
     __syncthreads();
 
-    if (!staged) {  // global search, one thread per own cell
-        for (int q = t; q < kTileX * kTileY * kTileZ; q += kTileBlock) {
-            const int hz = 1 + q % kTileZ, hy = 1 + (q / kTileZ) % kTileY, hx = 1 + q / (kTileZ * kTileY);
-            if (hx >= hxe || hy >= hye || hz >= hze)
-                continue;
-            const int h = (hx * kHY + hy) * kHZ + hz;
-            if (htag[h] >= 0)
-                continue;  // dense cell: linked by the dense kernels
-            const int n = hoff[h + 1] - hoff[h];
-            for (int k = 0; k < n; ++k) {
-                const int64_t i = gst[h] + k;
-                const float4 p = w.sorted[i];
-                finish_particle(w, root, i, __float_as_int(p.w),
-                                link_particle_global(w, B, i, p, x0 + hx - 1, y0 + hy - 1,
-                                                     z0 + hz - 1));
-            }
-        }
-        return;
-    }
-
     const int nown = ownoff[kOwnRows];
+    if (t == 0)
+        FOF_STAT(w.ctr, staged ? ST_OWN_STAGED : ST_OWN_GLOBAL, nown);
     for (int k = t; k < nown; k += kTileBlock) {
         int r = 0;
         while (ownoff[r + 1] <= k)
             ++r;
         const int rhx = 1 + r / kTileY, rhy = 1 + r % kTileY;
         const int slot = hoff[(rhx * kHY + rhy) * kHZ + 1] + (k - ownoff[r]);
-        const float4 p = part[slot];
-        const int64_t i = pidx[slot];
+        const int hs = halo_cell_of(hoff, slot);
+        const int64_t i = gst[hs] + (slot - hoff[hs]);
+        const float4 p = staged ? part[slot] : w.sorted[i];
+        const int32_t oi = __float_as_int(p.w);
         const int ix = fine_index(p.x, B.inv_fine[0], B.nf[0]) / B.m;
         const int iy = fine_index(p.y, B.inv_fine[1], B.nf[1]) / B.m;
         const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
+        if (!staged) {
+            finish_particle(w, root, i, oi, link_particle_global(w, B, i, p, ix, iy, iz));
+            continue;
+        }
         const int hx = ix - x0 + 1, hy = iy - y0 + 1, hz = iz - z0 + 1;
         bool has_friend = false;
         const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
@@ -395,14 +391,15 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
                 const int a = hoff[rb + hz + sz.lo], e = hoff[rb + hz + sz.hi + 1];
                 FOF_STAT(w.ctr, ST_PAIRS_TILED, e - a);
                 for (int j = a; j < e; ++j) {
-                    const int64_t gj = pidx[j];
-                    if (gj == i)
+                    if (j == slot)
                         continue;
                     const float4 q4 = part[j];
                     if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
                         has_friend = true;
-                        if (i < gj)
-                            uf_union(w.parent, (uint32_t)i, (uint32_t)gj);
+                        if (oi < __float_as_int(q4.w)) {  // each pair hooked from one end
+                            const int hj = halo_cell_of(hoff, j);
+                            uf_union(w.parent, (uint32_t)i, (uint32_t)(gst[hj] + (j - hoff[hj])));
+                        }
                     }
                 }
                 if (box_dense)
@@ -413,12 +410,12 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
                         const int64_t c2 = coarse_cell(B, wrap_cell(ix + ox, B.nc[0]),
                                                        wrap_cell(iy + oy, B.nc[1]),
                                                        wrap_cell(iz + oz, B.nc[2]));
-                        const int32_t s2 = w.cell_start[c2];
+                        const int32_t s2 = gst[rb + hz + oz];
                         has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz, ox, oy,
                                                            oz, s2, w.cell_start[c2 + 1] - s2, tag);
                     }
             }
-        finish_particle(w, root, i, __float_as_int(p.w), has_friend);
+        finish_particle(w, root, i, oi, has_friend);
     }
 }
 
