@@ -151,6 +151,7 @@ def main():
     ap.add_argument("--cell-side", type=float, default=0.0, help="coarse cell side (0 = default)")
     ap.add_argument("--dense-threshold", type=int, default=0, help="0 = default, <0 = off")
     ap.add_argument("--block", type=int, default=0, help="threads per block (0 = default)")
+    ap.add_argument("--no-tiles", action="store_true", help="link without LDS tiles")
     ap.add_argument("--no-reinforce", action="store_true")
     ap.add_argument("--reinforce-reps", type=int, default=20)
     args = ap.parse_args()
@@ -172,7 +173,8 @@ def main():
 
     pos = torch.from_numpy(box.pos).to(dev)
     vel = torch.from_numpy(box.vel).to(dev) if box.vel is not None else None
-    tune = dict(cell_side=args.cell_side, dense_threshold=args.dense_threshold, block=args.block)
+    tune = dict(cell_side=args.cell_side, dense_threshold=args.dense_threshold, block=args.block,
+                flags=1 if args.no_tiles else 0)
     plan = Plan([box.n], [(box.L, box.b)], device=dev, tune=tune)
     root = torch.empty(box.n, dtype=torch.int32, device=dev)
     cap = box.n

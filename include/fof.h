@@ -62,12 +62,13 @@ typedef struct fof_box {
 } fof_box;
 
 /* Tuning knobs.  Zero fields take defaults.  None of them changes any result. */
+#define FOF_TUNE_NO_TILES 1u /* link every particle from global memory, without LDS tiles    */
 typedef struct fof_tune {
     double cell_side;        /* requested coarse cell side; raised to b plus a rounding margin */
     int32_t dense_threshold; /* cells holding more particles take the clique-cell path;
                                 0 = default, < 0 = never                                      */
     int32_t block;           /* threads per block for per-particle kernels (multiple of 64)    */
-    uint32_t flags;          /* reserved, must be 0                                            */
+    uint32_t flags;          /* FOF_TUNE_* bits; other bits must be 0                          */
     int32_t reserved;
 } fof_tune;
 

@@ -18,6 +18,7 @@ FOF_EOVERFLOW = -3
 FOF_EDEVICE = -4
 FOF_ENOTSUP = -5
 FOF_STATUS_RANGE = 1
+FOF_TUNE_NO_TILES = 1
 FOF_STATUS_DENSE_CAP = 2
 FOF_STATUS_EDGE_CAP = 4
 FOF_FROZEN = 0

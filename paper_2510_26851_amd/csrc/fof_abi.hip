@@ -103,7 +103,10 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
     d->slack = round_up_f(8.0 * ldexp(Lmax, -23));
     d->dense_ok = (d->nc[0] >= 3 && d->nc[1] >= 3 && d->nc[2] >= 3 && d->R <= 3) ? 1 : 0;
     // the tiled link kernel needs every halo cell of a tile to be a distinct cell
-    d->tiled = (d->nc[0] >= kTileX + 2 && d->nc[1] >= kTileY + 2 && d->nc[2] >= kTileZ + 2) ? 1 : 0;
+    d->tiled = (d->nc[0] >= kTileX + 2 && d->nc[1] >= kTileY + 2 && d->nc[2] >= kTileZ + 2 &&
+                !(tune && (tune->flags & FOF_TUNE_NO_TILES)))
+                   ? 1
+                   : 0;
     d->ntile[0] = (d->nc[0] + kTileX - 1) / kTileX;
     d->ntile[1] = (d->nc[1] + kTileY - 1) / kTileY;
     d->ntile[2] = (d->nc[2] + kTileZ - 1) / kTileZ;
@@ -113,12 +116,23 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
 struct Layout {
     size_t off_desc, off_status, off_cell_count, off_cell_start, off_scan, off_rank, off_sorted,
         off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, off_dense,
-        off_big, off_table, off_temp, total;
+        off_big, off_table, off_temp, off_tiles, off_edges, total;
+    int64_t edge_cap;
 };
 
 int32_t table_stride(int32_t words) { return kTableHeader + 2 * words; }
 
-Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t words)
+// Deferred hooks of the tiled link kernel (pairs crossing a tile face, links into dense
+// cells): a fraction of a hook per particle in clustered boxes.  Tiles that overflow it are
+// redone with direct hooks, so the capacity only affects speed.
+int64_t link_edge_cap(int64_t n)
+{
+    int64_t c = n / 4 + 65536;
+    return c < INT32_MAX ? c : INT32_MAX;
+}
+
+Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t words,
+              int64_t ntiles)
 {
     Layout L;
     size_t o = 0;
@@ -146,6 +160,9 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
     L.off_big = take(sizeof(int32_t) * (size_t)dense_cap);
     L.off_table = take(sizeof(int32_t) * (size_t)dense_cap * (size_t)table_stride(words));
     L.off_temp = take(dense_cap > 0 ? sizeof(float4) * (size_t)n : 0);
+    L.off_tiles = take(sizeof(int32_t) * (size_t)ntiles);
+    L.edge_cap = ntiles > 0 ? link_edge_cap(n) : 0;
+    L.off_edges = take(sizeof(int2) * (size_t)L.edge_cap);
     L.total = o;
     return L;
 }
@@ -159,7 +176,7 @@ bool ws_ok(const fof_grid *g, const void *ws)
 Work resolve(const fof_grid *g, void *ws)
 {
     char *base = (char *)ws;
-    Layout L = layout(g->nbox, g->n, g->ncell, g->dense_cap, g->table_words);
+    Layout L = layout(g->nbox, g->n, g->ncell, g->dense_cap, g->table_words, g->ntiles);
     Work w;
     w.desc = (const BoxDesc *)(base + L.off_desc);
     w.ctr = (Counters *)(base + L.off_status);
@@ -178,6 +195,9 @@ Work resolve(const fof_grid *g, void *ws)
     w.big_list = (int32_t *)(base + L.off_big);
     w.table = (int32_t *)(base + L.off_table);
     w.temp = (float4 *)(base + L.off_temp);
+    w.tile_list = (int32_t *)(base + L.off_tiles);
+    w.edges = (int2 *)(base + L.off_edges);
+    w.edge_cap = (int32_t)L.edge_cap;
     w.dense_threshold = g->dense_threshold;
     w.dense_cap = (int32_t)g->dense_cap;
     w.table_words = g->table_words;
@@ -217,7 +237,7 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
 {
     if (nbox < 1 || !count || !box || !grid)
         return FOF_EINVAL;
-    if (tune && (tune->flags != 0 || tune->block < 0 || (tune->block % kWave) != 0 ||
+    if (tune && ((tune->flags & ~FOF_TUNE_NO_TILES) != 0 || tune->block < 0 || (tune->block % kWave) != 0 ||
                  tune->block > 1024 || !(tune->cell_side >= 0.0)))
         return FOF_EINVAL;
     int64_t n = 0, ncell = 0, ntiles = 0;
@@ -263,7 +283,7 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
     }
     if (thr <= 0)
         thr = -1;
-    Layout L = layout(nbox, n, ncell, dense_cap, words);
+    Layout L = layout(nbox, n, ncell, dense_cap, words, ntiles);
     memset(grid, 0, sizeof(*grid));
     grid->nbox = nbox;
     grid->block = (tune && tune->block) ? tune->block : kDefaultBlock;

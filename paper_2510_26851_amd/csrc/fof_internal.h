@@ -53,7 +53,9 @@ struct Counters {
     int32_t status;
     int32_t n_dense;     // dense cells found
     int32_t n_big;       // dense cells linked by a whole block
-    int32_t pad[29];
+    int32_t n_spill;       // link tiles queued in tile_list for the windowed kernel
+    int32_t n_link_edges;  // hooks the tiled kernel deferred to the edge list
+    int32_t pad[27];
     unsigned long long stats[16];  // event counts of diagnostic builds (-DFOF_STATS)
 };
 
@@ -97,6 +99,30 @@ __device__ __forceinline__ int fine_index(float x, float inv, int nf)
 // Linear coarse cell id with z fastest (C order over (ix, iy, iz)).  The paper's grid uses
 // x fastest; z fastest makes the counting sort nearly sequential for particles stored in
 // C order of a Lagrangian lattice, the usual N-body layout.  No result depends on it.
+// Offsets to visit along one axis, deduplicated when the grid has fewer than 3 cells:
+// a neighbour is needed only if the particle lies within `reach` of the shared face.
+struct AxisSpan {
+    int lo, hi;  // visit o in [lo, hi] (o = -1, 0, +1), skipping none in between
+};
+
+__device__ __forceinline__ AxisSpan axis_span(float x, int ix, float side, int nc, float reach)
+{
+    if (nc == 1)
+        return {0, 0};
+    float g_lo = x - (float)ix * side;          // distance to the lower face
+    float g_hi = (float)(ix + 1) * side - x;    // distance to the upper face
+    bool need_lo = g_lo < reach;
+    bool need_hi = g_hi < reach;
+    if (nc == 2)  // the single other cell is both the lower and the upper neighbour
+        return {0, (need_lo || need_hi) ? 1 : 0};
+    return {need_lo ? -1 : 0, need_hi ? 1 : 0};
+}
+
+__device__ __forceinline__ int wrap_cell(int c, int nc)
+{
+    return c < 0 ? c + nc : (c >= nc ? c - nc : c);
+}
+
 __device__ __forceinline__ int64_t coarse_cell(const BoxDesc &B, int ix, int iy, int iz)
 {
     return B.cell_base + ((int64_t)ix * B.nc[1] + iy) * B.nc[2] + iz;
@@ -243,6 +269,9 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
     int32_t *big_list;    // dense ids of cells too large for one wave
     int32_t *table;       // per dense cell: header, key bitmask, popcount prefix
     float4 *temp;         // staging for dense cells too large for LDS
+    int32_t *tile_list;   // link tiles left to the windowed kernel
+    int2 *edges;          // hooks deferred by the tiled kernel
+    int32_t edge_cap;
     int32_t nbox;
     int32_t block;
     int64_t n;

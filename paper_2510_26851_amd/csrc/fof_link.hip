@@ -20,29 +20,6 @@ namespace fof {
 
 namespace {
 
-// Offsets to visit along one axis, deduplicated when the grid has fewer than 3 cells.
-struct AxisSpan {
-    int lo, hi;  // visit o in [lo, hi] (o = -1, 0, +1), skipping none in between
-};
-
-__device__ __forceinline__ AxisSpan axis_span(float x, int ix, float side, int nc, float reach)
-{
-    if (nc == 1)
-        return {0, 0};
-    float g_lo = x - (float)ix * side;          // distance to the lower face
-    float g_hi = (float)(ix + 1) * side - x;    // distance to the upper face
-    bool need_lo = g_lo < reach;
-    bool need_hi = g_hi < reach;
-    if (nc == 2)  // the single other cell is both the lower and the upper neighbour
-        return {0, (need_lo || need_hi) ? 1 : 0};
-    return {need_lo ? -1 : 0, need_hi ? 1 : 0};
-}
-
-__device__ __forceinline__ int wrap_cell(int c, int nc)
-{
-    return c < 0 ? c + nc : (c >= nc ? c - nc : c);
-}
-
 // Fine-key range of a neighbour dense cell that a particle at fine coordinate f (relative
 // to that cell's origin, in the particle's periodic frame) can reach.
 __device__ __forceinline__ void key_range(float f, float rf, int m, int &lo, int &hi)
@@ -53,11 +30,45 @@ __device__ __forceinline__ void key_range(float f, float rf, int m, int &lo, int
     hi = hi > m - 1 ? m - 1 : hi;
 }
 
+// Where a hook goes.  DirectHook unions straight into the global forest.  DeferHook (the
+// tiled kernel, which publishes its local forests with plain stores and so must not touch
+// the global forest itself) appends the pair to a small LDS buffer, spilling to the global
+// edge list, which k_link_edges unions after the kernel.  A pair that finds the global list
+// full raises the block's overflow flag: the tile is then redone with direct hooks.
+struct DirectHook {
+    uint64_t *parent;
+    __device__ void operator()(uint32_t a, uint32_t b) const { uf_union(parent, a, b); }
+};
+
+constexpr int kLocalEdges = 96;  // LDS edge buffer of the tiled kernel
+
+struct DeferHook {
+    int2 *lbuf;
+    int *lcnt, *lover;
+    int2 *gbuf;
+    int *gcnt;
+    int gcap;
+    __device__ void operator()(uint32_t a, uint32_t b) const
+    {
+        const int k = atomicAdd(lcnt, 1);
+        if (k < kLocalEdges) {
+            lbuf[k] = make_int2((int)a, (int)b);
+            return;
+        }
+        const int gk = atomicAdd(gcnt, 1);
+        if (gk < gcap)
+            gbuf[gk] = make_int2((int)a, (int)b);
+        else
+            *lover = 1;
+    }
+};
+
 // Links particle i (position p) to the units of dense cell c2 at offset (ox, oy, oz) from
 // its own cell (ix, iy, iz).  Returns true if any friend was found.
+template <class Hook>
 __device__ bool link_dense_neighbour(const Work &w, const BoxDesc &B, uint32_t i, float4 p,
                                      int ix, int iy, int iz, int ox, int oy, int oz, int32_t s2,
-                                     int32_t n2, int32_t d2)
+                                     int32_t n2, int32_t d2, const Hook &hook)
 {
     const int m = B.m;
     const int W = w.table_words;
@@ -89,7 +100,7 @@ __device__ bool link_dense_neighbour(const Work &w, const BoxDesc &B, uint32_t i
                 for (int32_t j = b0; j < b1; ++j) {
                     const float4 q = w.sorted[j];
                     if (linked(B, p.x, p.y, p.z, q.x, q.y, q.z)) {
-                        uf_union(w.parent, i, (uint32_t)j);
+                        hook(i, (uint32_t)j);
                         any = true;
                         if (comp < 64)
                             seen |= 1ull << comp;
@@ -134,7 +145,8 @@ __device__ bool link_particle_global(const Work &w, const BoxDesc &B, int64_t i,
                     const int32_t d2 = w.cell_count[c];
                     if (d2 >= 0) {
                         has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz, ox,
-                                                           oy, oz, s, e - s, d2);
+                                                           oy, oz, s, e - s, d2,
+                                                           DirectHook{w.parent});
                         continue;
                     }
                 }
@@ -186,13 +198,18 @@ __global__ void k_link(Work w, int32_t *__restrict__ root)
 }
 
 // ---------------------------------------------------------------------------------------
-// LDS-tiled linking.  A block owns kTileX x kTileY x kTileZ coarse cells and stages them
-// with a one-cell halo in LDS.  With cells z fastest, a particle's candidates in one
-// neighbour row (up to three consecutive cells) form one contiguous LDS range.  Staging is
-// flat: staged slot s belongs to the halo cell whose offset range holds s, found by a
-// fixed-length binary search, so each thread issues its few global loads back to back.
-// Cells with clique tables are not staged: particles reach them through their unit
-// tables.  A tile whose staged particles do not fit searches from global memory.
+// LDS-tiled linking.  A block owns kTileX x kTileY x kTileZ coarse cells.  With cells z
+// fastest, every (x, y) row of the tile's one-cell halo is one contiguous run of particles
+// in cell order, so a particle's candidates in one neighbour row (up to three consecutive
+// cells) form one contiguous LDS range once the halo is staged.  Staging is flat: staged
+// slot s belongs to the halo cell whose offset range holds s, found by a fixed-length
+// binary search, so each thread issues its few global loads back to back.  Cells with
+// clique tables are not staged: particles reach them through their unit tables.
+//
+// k_link_tiled stages whole tiles.  A tile whose halo holds more than kTileCap particles is
+// queued for k_link_windows, which stages it in z-windows (the longest runs of z-layers
+// that fit) and searches a single z-layer too full to stage from global memory.  The
+// windowed kernel needs many more registers, so it is kept out of the common path.
 // ---------------------------------------------------------------------------------------
 constexpr int kHX = kTileX + 2, kHY = kTileY + 2, kHZ = kTileZ + 2;
 constexpr int kRowsH = kHX * kHY;
@@ -202,7 +219,11 @@ constexpr int kPerT = (kHalo + kTileBlock - 1) / kTileBlock;  // halo cells per 
 constexpr int kTileCap = 1024;                                  // staged particles per tile
 constexpr int kStagePerT = kTileCap / kTileBlock;
 constexpr int kOwnRows = kTileX * kTileY;
+constexpr int kWindowBlocks = 1024;  // grid of the windowed kernel (it loops over the queue)
 static_assert(kTileCap % kTileBlock == 0, "staging assumes whole rounds");
+static_assert(kRowsH <= kWave && kHZ <= kTileBlock, "row scans use one wave");
+
+constexpr int top_pow2(int n) { return n < 2 ? 1 : 2 * top_pow2(n / 2); }
 
 // Box owning tile t: the last box whose first tile is <= t.  Boxes without tiles share
 // their tile_base with the next box, which comes later, so they are never chosen.
@@ -219,51 +240,49 @@ __device__ __forceinline__ int find_box_tile(const BoxDesc *d, int nbox, int64_t
     return lo;
 }
 
-__device__ __forceinline__ int mod_cell(int c, int nc)
+// The last index h in [0, N) with off[h] <= s, for non-decreasing off with off[0] <= s.
+// Fixed trip count, so a thread's independent searches interleave.
+template <int N>
+__device__ __forceinline__ int last_le(const int *off, int s)
 {
-    int r = c % nc;
-    return r < 0 ? r + nc : r;
-}
-
-// Halo cell holding staged slot s: the last h with hoff[h] <= s (hoff non-decreasing,
-// hoff[0] = 0 <= s < hoff[kHalo]).  Fixed trip count, so independent searches interleave.
-__device__ __forceinline__ int halo_cell_of(const int *hoff, int s)
-{
+    constexpr int kTop = top_pow2(N - 1);  // evaluated at compile time
     int pos = 0;
 #pragma unroll
-    for (int step = 512; step > 0; step >>= 1)
-        if (pos + step < kHalo && hoff[pos + step] <= s)
+    for (int step = kTop; step > 0; step >>= 1)
+        if (pos + step < N && off[pos + step] <= s)
             pos += step;
     return pos;
 }
-static_assert(kHalo <= 1024, "halo_cell_of searches at most 1024 cells");
 
-__global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__restrict__ root)
+struct TileGeom {
+    int x0, y0, z0;     // first own cell
+    int hxe, hye, hze;  // last halo index in use per axis (own cells stop at the box edge)
+};
+
+__device__ __forceinline__ TileGeom tile_geom(const BoxDesc &B, int64_t tile)
 {
-    __shared__ float4 part[kTileCap];
-    __shared__ int hoff[kHalo + 1];  // staged offset of each halo cell
-    __shared__ int gst[kHalo];       // global (sorted) start of each halo cell
-    __shared__ int htag[kHalo];      // dense id (>= 0) or -1
-    __shared__ int ownoff[kOwnRows + 1];
-    __shared__ int scr[kTileBlock / kWave];
-
-    const int64_t tile = xcd_block();
-    if (tile >= w.ntiles)
-        return;
-    const BoxDesc &B = w.desc[find_box_tile(w.desc, w.nbox, tile)];
     int64_t tl = tile - B.tile_base;
     const int tz = (int)(tl % B.ntile[2]);
     tl /= B.ntile[2];
     const int ty = (int)(tl % B.ntile[1]);
     const int tx = (int)(tl / B.ntile[1]);
-    const int x0 = tx * kTileX, y0 = ty * kTileY, z0 = tz * kTileZ;
-    // last halo index (inclusive) in use per axis: own cells stop at the box edge
-    const int hxe = min(kTileX, B.nc[0] - x0) + 1;
-    const int hye = min(kTileY, B.nc[1] - y0) + 1;
-    const int hze = min(kTileZ, B.nc[2] - z0) + 1;
-    const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
-    const int t = threadIdx.x;
+    TileGeom g;
+    g.x0 = tx * kTileX;
+    g.y0 = ty * kTileY;
+    g.z0 = tz * kTileZ;
+    g.hxe = min(kTileX, B.nc[0] - g.x0) + 1;
+    g.hye = min(kTileY, B.nc[1] - g.y0) + 1;
+    g.hze = min(kTileZ, B.nc[2] - g.z0) + 1;
+    return g;
+}
 
+// Halo table of a tile: the staged count of every halo cell and its global start, or for a
+// cell with a clique table -1 - its dense id (halo coordinates lie in [-1, nc], so one wrap
+// suffices), then the running offsets.  Ends with a block barrier; returns the staged total.
+__device__ int build_halo(const Work &w, const BoxDesc &B, const TileGeom &g, bool box_dense,
+                          int *hoff, int *gst, int *scr)
+{
+    const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
     int cnt_local[kPerT];
     int sum = 0;
 #pragma unroll
@@ -273,10 +292,10 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
         if (h < kHalo) {
             const int hz = h % kHZ, row = h / kHZ, hy = row % kHY, hx = row / kHY;
             int tag = -1, s = 0;
-            if (hx <= hxe && hy <= hye && hz <= hze) {
-                const int64_t c = coarse_cell(B, mod_cell(x0 - 1 + hx, B.nc[0]),
-                                              mod_cell(y0 - 1 + hy, B.nc[1]),
-                                              mod_cell(z0 - 1 + hz, B.nc[2]));
+            if (hx <= g.hxe && hy <= g.hye && hz <= g.hze) {
+                const int64_t c = coarse_cell(B, wrap_cell(g.x0 - 1 + hx, B.nc[0]),
+                                              wrap_cell(g.y0 - 1 + hy, B.nc[1]),
+                                              wrap_cell(g.z0 - 1 + hz, B.nc[2]));
                 s = w.cell_start[c];
                 cnt = w.cell_start[c + 1] - s;
                 if (box_dense && cnt > w.dense_threshold && w.cell_count[c] >= 0) {
@@ -284,138 +303,410 @@ __global__ __launch_bounds__(kTileBlock) void k_link_tiled(Work w, int32_t *__re
                     cnt = 0;
                 }
             }
-            gst[h] = s;
-            htag[h] = tag;
+            gst[h] = tag >= 0 ? -1 - tag : s;
         }
         cnt_local[k] = cnt;
         sum += cnt;
     }
-    {  // exclusive scan of staged counts; each thread owns kPerT consecutive halo cells
-        const int lane = lane_id(), wid = t / kWave;
-        int x = sum;
+    // exclusive scan of staged counts; each thread owns kPerT consecutive halo cells
+    int x = sum;
 #pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            int y = __shfl_up(x, o, kWave);
-            if (lane >= o)
-                x += y;
-        }
-        if (lane == kWave - 1)
-            scr[wid] = x;
-        __syncthreads();
-        int pre = 0, tot = 0;
-        for (int k = 0; k < kTileBlock / kWave; ++k) {
-            if (k < wid)
-                pre += scr[k];
-            tot += scr[k];
-        }
-        int run = pre + x - sum;
-#pragma unroll
-        for (int k = 0; k < kPerT; ++k) {
-            const int h = t * kPerT + k;
-            if (h < kHalo)
-                hoff[h] = run;
-            run += cnt_local[k];
-        }
-        if (t == 0)
-            hoff[kHalo] = tot;
+    for (int o = 1; o < kWave; o <<= 1) {
+        int y = __shfl_up(x, o, kWave);
+        if (lane >= o)
+            x += y;
     }
+    if (lane == kWave - 1)
+        scr[wid] = x;
     __syncthreads();
+    int pre = 0, tot = 0;
+    for (int k = 0; k < kTileBlock / kWave; ++k) {
+        if (k < wid)
+            pre += scr[k];
+        tot += scr[k];
+    }
+    int run = pre + x - sum;
+#pragma unroll
+    for (int k = 0; k < kPerT; ++k) {
+        const int h = t * kPerT + k;
+        if (h < kHalo)
+            hoff[h] = run;
+        run += cnt_local[k];
+    }
+    if (t == 0)
+        hoff[kHalo] = tot;
+    __syncthreads();
+    return tot;
+}
+
+// Union-find over staged slots in LDS, keyed like the global one by original index (the w
+// field of the staged particle): a hook puts the root with the larger key under the other,
+// so a local root is its component's member with the smallest original index.
+__device__ __forceinline__ int lds_find(int *lpar, int x)
+{
+    int px = lpar[x];
+    while (px != x) {
+        const int gx = lpar[px];
+        if (gx != px)
+            lpar[x] = gx;  // halving: only non-root entries are rewritten
+        x = px;
+        px = gx;
+    }
+    return x;
+}
+
+__device__ __forceinline__ void lds_union(int *lpar, const float4 *part, int a, int b)
+{
+    a = lds_find(lpar, a);
+    b = lds_find(lpar, b);
+    while (a != b) {
+        if (__float_as_int(part[a].w) > __float_as_int(part[b].w)) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(lpar + b, b, a) == b)  // b, the larger key, goes under a
+            return;
+        a = lds_find(lpar, a);
+        b = lds_find(lpar, b);
+    }
+}
+
+__device__ __forceinline__ int lds_find_ro(const int *lpar, int x)
+{
+    int px = lpar[x];
+    while (px != x) {
+        x = px;
+        px = lpar[x];
+    }
+    return x;
+}
+
+// Sets the friend bit of sorted index i for every active lane with has_friend.  The lanes
+// of a wave hold increasing sorted indices, so lanes sharing a 64-bit word are adjacent:
+// their bits are OR-ed across the wave and the first lane of each word does one atomic.
+__device__ __forceinline__ void flag_friends_wave(uint64_t *flags, bool active, int64_t i,
+                                                  bool has_friend)
+{
+    const int lane = lane_id();
+    const int64_t word = active ? (i >> 6) : -1;
+    uint64_t v = (active && has_friend) ? (1ull << (i & 63)) : 0ull;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t w2 = __shfl_down(word, o, kWave);
+        const uint64_t v2 = __shfl_down(v, o, kWave);
+        if (lane + o < kWave && w2 == word)
+            v |= v2;
+    }
+    const int64_t wprev = __shfl_up(word, 1, kWave);
+    if (active && v && (lane == 0 || wprev != word))
+        atomicOr((unsigned long long *)(flags + word), (unsigned long long)v);
+}
+
+// Candidates of own particle p (sorted index i, own halo cell (hx, hy, hz)) in the staged
+// window: neighbour row r's halo cells [z_first, ...] sit at LDS wb[r] + slot - hoff[...].
+// Returns whether p has a friend; pairs are hooked from the smaller original index.
+template <class Hook>
+__device__ __forceinline__ bool link_staged(const Work &w, const BoxDesc &B, bool box_dense,
+                                            const float4 *part, const int *hoff, const int *gst,
+                                            int64_t i, float4 p, int ls,
+                                            int hx, int hy, int hz, int ix, int iy, int iz,
+                                            const int *wb, int z_first, int *lpar,
+                                            const TileGeom &g, const Hook &hook)
+{
+    const int32_t oi = __float_as_int(p.w);
+    bool has_friend = false;
+    const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
+    const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
+    const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
+    for (int ox = sx.lo; ox <= sx.hi; ++ox)
+        for (int oy = sy.lo; oy <= sy.hi; ++oy) {
+            const int row2 = (hx + ox) * kHY + hy + oy;
+            const int rb2 = row2 * kHZ;
+            const int shift = wb ? wb[row2] - hoff[rb2 + z_first] : 0;  // slot -> LDS
+            const int a = hoff[rb2 + hz + sz.lo] + shift;
+            const int e = hoff[rb2 + hz + sz.hi + 1] + shift;
+            // own particles of this row (LDS union-find), when the caller keeps one
+            int own_lo = 0, own_hi = 0;
+            if (lpar && hx + ox >= 1 && hx + ox < g.hxe && hy + oy >= 1 && hy + oy < g.hye) {
+                own_lo = hoff[rb2 + 1];
+                own_hi = hoff[rb2 + g.hze];
+            }
+            FOF_STAT(w.ctr, ST_PAIRS_TILED, e - a);
+            for (int j = a; j < e; ++j) {
+                if (j == ls)
+                    continue;
+                const float4 q4 = part[j];
+                if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
+                    has_friend = true;
+                    if (oi < __float_as_int(q4.w)) {  // each pair hooked from one end
+                        if (j >= own_lo && j < own_hi) {
+                            lds_union(lpar, part, ls, j);
+                        } else {
+                            const int sj = j - shift;
+                            const int hj = rb2 + last_le<kHZ>(hoff + rb2, sj);
+                            FOF_STAT(w.ctr, ST_UNIONS, 1);
+                            hook((uint32_t)i, (uint32_t)(gst[hj] + (sj - hoff[hj])));
+                        }
+                    }
+                }
+            }
+            if (box_dense)
+                for (int oz = sz.lo; oz <= sz.hi; ++oz) {
+                    const int code = gst[rb2 + hz + oz];
+                    if (code >= 0)
+                        continue;  // not a clique-table cell
+                    const int64_t c2 = coarse_cell(B, wrap_cell(ix + ox, B.nc[0]),
+                                                   wrap_cell(iy + oy, B.nc[1]),
+                                                   wrap_cell(iz + oz, B.nc[2]));
+                    const int32_t s2 = w.cell_start[c2];
+                    has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz, ox, oy,
+                                                       oz, s2, w.cell_start[c2 + 1] - s2, -1 - code,
+                                                       hook);
+                }
+        }
+    return has_friend;
+}
+
+__global__ __launch_bounds__(kTileBlock, 6) void k_link_tiled(Work w, int32_t *__restrict__ root)
+{
+    __shared__ float4 part[kTileCap];
+    __shared__ int hoff[kHalo + 1];  // staged offset of each halo cell
+    __shared__ int gst[kHalo];       // global (sorted) start, or -1 - dense id
+    __shared__ int ownoff[kOwnRows + 1];
+    __shared__ int scr[kTileBlock / kWave];
+    __shared__ int lpar[kTileCap];   // LDS union-find over staged slots
+    __shared__ int2 lbuf[kLocalEdges];  // deferred hooks of this tile
+    __shared__ int lcnt, lover, gbase;
+
+    const int64_t tile = xcd_block();
+    if (tile >= w.ntiles)
+        return;
+    const BoxDesc &B = w.desc[find_box_tile(w.desc, w.nbox, tile)];
+    const TileGeom g = tile_geom(B, tile);
+    const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
+    const int t = threadIdx.x;
+
+    const int total = build_halo(w, B, g, box_dense, hoff, gst, scr);
+    if (t == 0)
+        FOF_STAT(w.ctr, ST_TILES, 1);
+    if (total > kTileCap) {  // block-uniform: the windowed kernel takes this tile
+        if (t == 0) {
+            FOF_STAT(w.ctr, ST_TILES_OVERFLOW, 1);
+            w.tile_list[atomicAdd(&w.ctr->n_spill, 1)] = (int32_t)tile;
+        }
+        return;
+    }
     if (t <= kOwnRows) {  // own particles before each own row
         int acc = 0;
         for (int r = 0; r < t; ++r) {
             const int hx = 1 + r / kTileY, hy = 1 + r % kTileY;
             const int rb = (hx * kHY + hy) * kHZ;
-            if (hx <= hxe - 1 && hy <= hye - 1)
-                acc += hoff[rb + hze] - hoff[rb + 1];
+            if (hx < g.hxe && hy < g.hye)
+                acc += hoff[rb + g.hze] - hoff[rb + 1];
         }
         ownoff[t] = acc;
     }
-    const int total = hoff[kHalo];
-    const bool staged = total <= kTileCap;
     if (t == 0) {
-        FOF_STAT(w.ctr, ST_TILES, 1);
-        if (!staged)
-            FOF_STAT(w.ctr, ST_TILES_OVERFLOW, 1);
+        lcnt = 0;
+        lover = 0;
     }
-    if (staged) {
-        int src[kStagePerT];
 #pragma unroll
-        for (int k = 0; k < kStagePerT; ++k) {
-            const int sl = t + k * kTileBlock;
-            src[k] = -1;
-            if (sl < total) {
-                const int h = halo_cell_of(hoff, sl);
-                src[k] = gst[h] + (sl - hoff[h]);
-            }
+    for (int k = 0; k < kStagePerT; ++k) {  // LDS stores cannot alias the global loads
+        const int sl = t + k * kTileBlock;
+        if (sl < total) {
+            const int h = last_le<kHalo>(hoff, sl);
+            part[sl] = w.sorted[gst[h] + (sl - hoff[h])];
+            lpar[sl] = sl;
         }
-        float4 v[kStagePerT];
-#pragma unroll
-        for (int k = 0; k < kStagePerT; ++k)
-            if (src[k] >= 0)
-                v[k] = w.sorted[src[k]];
-#pragma unroll
-        for (int k = 0; k < kStagePerT; ++k)
-            if (src[k] >= 0)
-                part[t + k * kTileBlock] = v[k];
     }
     __syncthreads();
 
     const int nown = ownoff[kOwnRows];
     if (t == 0)
-        FOF_STAT(w.ctr, staged ? ST_OWN_STAGED : ST_OWN_GLOBAL, nown);
-    for (int k = t; k < nown; k += kTileBlock) {
+        FOF_STAT(w.ctr, ST_OWN_STAGED, nown);
+    // phase A: candidate search; pairs of own particles are joined in LDS, every other hook
+    // (halo particles of other tiles, dense cells) goes to the global forest
+    const DeferHook hook{lbuf, &lcnt, &lover, w.edges, &w.ctr->n_link_edges, w.edge_cap};
+    uint32_t fmask = 0;  // bit q: own particle t + q * kTileBlock has a friend
+    for (int k = t, q = 0; k < nown; k += kTileBlock, ++q) {
         int r = 0;
         while (ownoff[r + 1] <= k)
             ++r;
-        const int rhx = 1 + r / kTileY, rhy = 1 + r % kTileY;
-        const int slot = hoff[(rhx * kHY + rhy) * kHZ + 1] + (k - ownoff[r]);
-        const int hs = halo_cell_of(hoff, slot);
+        const int rb = ((1 + r / kTileY) * kHY + 1 + r % kTileY) * kHZ;
+        const int slot = hoff[rb + 1] + (k - ownoff[r]);
+        const int hs = rb + 1 + last_le<kTileZ>(hoff + rb + 1, slot);  // own halo cell
         const int64_t i = gst[hs] + (slot - hoff[hs]);
-        const float4 p = staged ? part[slot] : w.sorted[i];
-        const int32_t oi = __float_as_int(p.w);
-        const int ix = fine_index(p.x, B.inv_fine[0], B.nf[0]) / B.m;
-        const int iy = fine_index(p.y, B.inv_fine[1], B.nf[1]) / B.m;
-        const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
-        if (!staged) {
-            finish_particle(w, root, i, oi, link_particle_global(w, B, i, p, ix, iy, iz));
-            continue;
+        const float4 p = part[slot];
+        const int hz = hs % kHZ, hy = (hs / kHZ) % kHY, hx = hs / (kHZ * kHY);
+        if (link_staged(w, B, box_dense, part, hoff, gst, i, p, slot, hx, hy, hz, g.x0 - 1 + hx,
+                        g.y0 - 1 + hy, g.z0 - 1 + hz, nullptr, 0, lpar, g, hook))
+            fmask |= 1u << q;
+    }
+    __syncthreads();
+    {  // move the LDS edge buffer to the global list
+        const int nl = min(lcnt, kLocalEdges);
+        if (t == 0)
+            gbase = nl ? atomicAdd(&w.ctr->n_link_edges, nl) : 0;
+        __syncthreads();
+        if (t < nl) {
+            if (gbase + t < w.edge_cap)
+                w.edges[gbase + t] = lbuf[t];
+            else
+                lover = 1;
         }
-        const int hx = ix - x0 + 1, hy = iy - y0 + 1, hz = iz - z0 + 1;
-        bool has_friend = false;
-        const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
-        const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
-        const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
-        for (int ox = sx.lo; ox <= sx.hi; ++ox)
-            for (int oy = sy.lo; oy <= sy.hi; ++oy) {
-                const int rb = ((hx + ox) * kHY + hy + oy) * kHZ;
-                const int a = hoff[rb + hz + sz.lo], e = hoff[rb + hz + sz.hi + 1];
-                FOF_STAT(w.ctr, ST_PAIRS_TILED, e - a);
-                for (int j = a; j < e; ++j) {
-                    if (j == slot)
-                        continue;
-                    const float4 q4 = part[j];
-                    if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
-                        has_friend = true;
-                        if (oi < __float_as_int(q4.w)) {  // each pair hooked from one end
-                            const int hj = halo_cell_of(hoff, j);
-                            uf_union(w.parent, (uint32_t)i, (uint32_t)(gst[hj] + (j - hoff[hj])));
-                        }
-                    }
+    }
+    static_assert(kTileCap / kTileBlock <= 32, "friend bits of one thread fit one word");
+    __syncthreads();
+    // phase B: publish the local forest.  No thread of this kernel hooks in the global
+    // forest, so every own entry still holds itself and a plain store points it at its local
+    // root.  Particles with no friend write their final label.
+    for (int base = 0, q = 0; base < nown; base += kTileBlock, ++q) {
+        const int k = base + t;
+        const bool active = k < nown;
+        int64_t i = 0;
+        bool f = false;
+        if (active) {
+            int r = 0;
+            while (ownoff[r + 1] <= k)
+                ++r;
+            const int rb = ((1 + r / kTileY) * kHY + 1 + r % kTileY) * kHZ;
+            const int slot = hoff[rb + 1] + (k - ownoff[r]);
+            const int hs = rb + 1 + last_le<kTileZ>(hoff + rb + 1, slot);
+            i = gst[hs] + (slot - hoff[hs]);
+            const int32_t oi = __float_as_int(part[slot].w);
+            f = (fmask >> q) & 1u;
+            if (!f) {
+                root[oi] = oi;
+            } else {
+                FOF_STAT(w.ctr, ST_SPARE, 1);
+                const int lr = lds_find_ro(lpar, slot);
+                if (lr != slot) {
+                    const int hr = last_le<kHalo>(hoff, lr);
+                    const uint32_t ir = (uint32_t)(gst[hr] + (lr - hoff[hr]));
+                    w.parent[i] = ((uint64_t)(uint32_t)__float_as_int(part[lr].w) << 32) | ir;
                 }
-                if (box_dense)
-                    for (int oz = sz.lo; oz <= sz.hi; ++oz) {
-                        const int tag = htag[rb + hz + oz];
-                        if (tag < 0)
-                            continue;
-                        const int64_t c2 = coarse_cell(B, wrap_cell(ix + ox, B.nc[0]),
-                                                       wrap_cell(iy + oy, B.nc[1]),
-                                                       wrap_cell(iz + oz, B.nc[2]));
-                        const int32_t s2 = gst[rb + hz + oz];
-                        has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz, ox, oy,
-                                                           oz, s2, w.cell_start[c2 + 1] - s2, tag);
-                    }
             }
-        finish_particle(w, root, i, oi, has_friend);
+        }
+        flag_friends_wave(w.flags, active, i, f);
+    }
+    __syncthreads();
+    if (t == 0 && lover)  // some hooks were lost: the windowed kernel redoes the tile
+        w.tile_list[atomicAdd(&w.ctr->n_spill, 1)] = (int32_t)tile;
+}
+
+// The hooks the tiled kernel deferred, now that every local forest is published.
+__global__ void k_link_edges(Work w)
+{
+    const int64_t m = min(w.ctr->n_link_edges, w.edge_cap);
+    for (int64_t e = gtid(); e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int2 ab = w.edges[e];
+        uf_union(w.parent, (uint32_t)ab.x, (uint32_t)ab.y);
+    }
+}
+
+// Tiles queued by k_link_tiled, each staged in z-windows: own layers [za, zb) with halo
+// layers [za - 1, zb].  Window bounds come from LDS values every thread reads alike, so
+// all threads of a block take the same windows.
+__global__ __launch_bounds__(kTileBlock) void k_link_windows(Work w, int32_t *__restrict__ root)
+{
+    __shared__ float4 part[kTileCap];
+    __shared__ int hoff[kHalo + 1];
+    __shared__ int gst[kHalo];
+    __shared__ int colsum[kHZ];        // particles per halo z-layer
+    __shared__ int wbase[kRowsH + 1];  // LDS start of each halo row's part of the window
+    __shared__ int ownoff[kOwnRows + 1];
+    __shared__ int scr[kTileBlock / kWave];
+
+    const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
+    const int nq = w.ctr->n_spill;
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int64_t tile = w.tile_list[q];
+        const BoxDesc &B = w.desc[find_box_tile(w.desc, w.nbox, tile)];
+        const TileGeom g = tile_geom(B, tile);
+        const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
+        build_halo(w, B, g, box_dense, hoff, gst, scr);
+        if (t < kHZ) {
+            int c = 0;
+            for (int row = 0; row < kRowsH; ++row)
+                c += hoff[row * kHZ + t + 1] - hoff[row * kHZ + t];
+            colsum[t] = c;
+        }
+        __syncthreads();
+        int za = 1;
+        while (za < g.hze) {
+            int tot = colsum[za - 1] + colsum[za] + colsum[za + 1];
+            int zb = za + 1;
+            const bool fits = tot <= kTileCap;
+            if (fits)
+                while (zb < g.hze && tot + colsum[zb + 1] <= kTileCap)
+                    tot += colsum[++zb];
+            if (wid == 0) {  // row r's halo cells [za-1, zb] go to LDS [wbase[r], wbase[r+1])
+                const int n =
+                    lane < kRowsH ? hoff[lane * kHZ + zb + 1] - hoff[lane * kHZ + za - 1] : 0;
+                int x = n;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    int y = __shfl_up(x, o, kWave);
+                    if (lane >= o)
+                        x += y;
+                }
+                if (lane < kRowsH)
+                    wbase[lane] = x - n;
+                if (lane == kRowsH - 1)
+                    wbase[kRowsH] = x;
+            }
+            if (t <= kOwnRows) {  // own particles of the window before each own row
+                int acc = 0;
+                for (int r = 0; r < t; ++r) {
+                    const int hx = 1 + r / kTileY, hy = 1 + r % kTileY;
+                    const int rb = (hx * kHY + hy) * kHZ;
+                    if (hx < g.hxe && hy < g.hye)
+                        acc += hoff[rb + zb] - hoff[rb + za];
+                }
+                ownoff[t] = acc;
+            }
+            __syncthreads();
+            if (fits) {
+                for (int l = t; l < wbase[kRowsH]; l += kTileBlock) {
+                    const int row = last_le<kRowsH>(wbase, l);
+                    const int slot = hoff[row * kHZ + za - 1] + (l - wbase[row]);
+                    // search the row's own kHZ cells only (reads stay inside hoff)
+                    const int h = row * kHZ + last_le<kHZ>(hoff + row * kHZ, slot);
+                    part[l] = w.sorted[gst[h] + (slot - hoff[h])];
+                }
+            }
+            __syncthreads();
+            const int nown = ownoff[kOwnRows];
+            if (t == 0)
+                FOF_STAT(w.ctr, fits ? ST_OWN_STAGED : ST_OWN_GLOBAL, nown);
+            for (int k = t; k < nown; k += kTileBlock) {
+                int r = 0;
+                while (ownoff[r + 1] <= k)
+                    ++r;
+                const int row = (1 + r / kTileY) * kHY + 1 + r % kTileY;
+                const int rb = row * kHZ;
+                const int slot = hoff[rb + za] + (k - ownoff[r]);
+                const int hz = last_le<kHZ>(hoff + rb, slot);  // own cell, inside the row
+                const int64_t i = gst[rb + hz] + (slot - hoff[rb + hz]);
+                const int hx = row / kHY, hy = row % kHY;
+                const int ix = g.x0 - 1 + hx, iy = g.y0 - 1 + hy, iz = g.z0 - 1 + hz;
+                bool f;
+                float4 p;
+                if (fits) {
+                    const int ls = wbase[row] + slot - hoff[rb + za - 1];
+                    p = part[ls];
+                    f = link_staged(w, B, box_dense, part, hoff, gst, i, p, ls, hx, hy, hz, ix,
+                                    iy, iz, wbase, za - 1, nullptr, g, DirectHook{w.parent});
+                } else {
+                    p = w.sorted[i];
+                    f = link_particle_global(w, B, i, p, ix, iy, iz);
+                }
+                finish_particle(w, root, i, __float_as_int(p.w), f);
+            }
+            za = zb;
+            __syncthreads();  // the next window reuses part, wbase and ownoff
+        }
     }
 }
 
@@ -451,9 +742,16 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s)
     if (e != hipSuccess)
         return e;
     const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
-    if (w.ntiles > 0)
+    if (w.ntiles > 0) {
+        e = launch_fill_i32(&w.ctr->n_spill, 2, 0, s);  // n_spill, n_link_edges
+        if (e != hipSuccess)
+            return e;
         hipLaunchKernelGGL(k_link_tiled, dim3((unsigned)w.ntiles), dim3(kTileBlock), 0, s, w,
                            root);
+        hipLaunchKernelGGL(k_link_edges, dim3(1024), dim3(256), 0, s, w);
+        const unsigned wb = (unsigned)(w.ntiles < kWindowBlocks ? w.ntiles : kWindowBlocks);
+        hipLaunchKernelGGL(k_link_windows, dim3(wb), dim3(kTileBlock), 0, s, w, root);
+    }
     hipLaunchKernelGGL(k_link, dim3(nb), dim3(w.block), 0, s, w, root);
     hipLaunchKernelGGL(k_compress, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent,
                        w.flags, root);

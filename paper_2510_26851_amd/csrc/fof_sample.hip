@@ -91,18 +91,16 @@ __device__ void edges_of(const Work &w, const SampleArgs &a, int64_t i)
     const int ix = fine_index(p.x, B.inv_fine[0], B.nf[0]) / B.m;
     const int iy = fine_index(p.y, B.inv_fine[1], B.nf[1]) / B.m;
     const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
-    for (int ox = -1; ox <= 1; ++ox) {
-        if (B.nc[0] < 3 && ox != 0 && (B.nc[0] == 1 || ox < 0))
-            continue;  // distinct neighbour cells only
-        const int cx = (ix + ox + B.nc[0]) % B.nc[0];
-        for (int oy = -1; oy <= 1; ++oy) {
-            if (B.nc[1] < 3 && oy != 0 && (B.nc[1] == 1 || oy < 0))
-                continue;
-            const int cy = (iy + oy + B.nc[1]) % B.nc[1];
-            for (int oz = -1; oz <= 1; ++oz) {
-                if (B.nc[2] < 3 && oz != 0 && (B.nc[2] == 1 || oz < 0))
-                    continue;
-                const int cz = (iz + oz + B.nc[2]) % B.nc[2];
+    // neighbour cells within reach of the particle (the cut radius plus the index error)
+    const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
+    const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
+    const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
+    for (int ox = sx.lo; ox <= sx.hi; ++ox) {
+        const int cx = wrap_cell(ix + ox, B.nc[0]);
+        for (int oy = sy.lo; oy <= sy.hi; ++oy) {
+            const int cy = wrap_cell(iy + oy, B.nc[1]);
+            for (int oz = sz.lo; oz <= sz.hi; ++oz) {
+                const int cz = wrap_cell(iz + oz, B.nc[2]);
                 const int64_t c = coarse_cell(B, cx, cy, cz);
                 for (int32_t j = w.cell_start[c]; j < w.cell_start[c + 1]; ++j) {
                     const float4 q = w.sorted[j];

@@ -153,9 +153,18 @@ def test_plan_rejects_bad_tune():
     rc, _, _ = plan([10], [(10.0, 0.4)], tune=t, desc=False)
     assert rc == _lib.FOF_EINVAL
     t = _lib.fof_tune()
-    t.flags = 1
+    t.flags = 2       # unknown flag bit
     rc, _, _ = plan([10], [(10.0, 0.4)], tune=t, desc=False)
     assert rc == _lib.FOF_EINVAL
+
+
+def test_no_tiles_flag_clears_the_tiled_bit():
+    t = _lib.fof_tune()
+    rc, g, buf = plan([4000], [(40.0, 0.4)], tune=t)
+    assert rc == 0 and decode(buf, 0)["tiled"] == 1 and g.ntiles > 0
+    t.flags = _lib.FOF_TUNE_NO_TILES
+    rc, g, buf = plan([4000], [(40.0, 0.4)], tune=t)
+    assert rc == 0 and decode(buf, 0)["tiled"] == 0 and g.ntiles == 0
 
 
 def test_plan_rejects_small_desc_buffer():

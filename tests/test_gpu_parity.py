@@ -96,7 +96,8 @@ def test_out_of_range_sets_status():
 
 
 @pytest.mark.parametrize("tune", [dict(block=64), dict(block=128), dict(block=512),
-                                  dict(block=1024), dict(cell_side=0.5), dict(cell_side=3.0)])
+                                  dict(block=1024), dict(cell_side=0.5), dict(cell_side=3.0),
+                                  dict(flags=1)])
 def test_launch_shape_and_cell_side_do_not_change_results(tune):
     say(f"launch shape {tune}")
     box = W.config0()
