@@ -18,7 +18,9 @@
 //                smallest original index; units record their component number
 //   k_dense_cross units of neighbouring dense cells, each cell pair handled once (by the
 //                lower cell index), stopping as soon as two single-component cells meet
-// Particles of sparse cells reach dense neighbours through the unit tables (fof_link.hip).
+//   k_dense_sparse (after the sparse link kernels) the particles of ordinary cells around
+//                a dense cell: each one within reach is tested against the units its
+//                position can reach, one friend per component, straight from LDS
 #include "fof_internal.h"
 
 namespace fof {
@@ -356,8 +358,9 @@ struct CellLds {
     short offs[kMaxOffsets];        // forward fine offsets: (dx+R) | (dy+R) << 4 | (dz+R) << 8
     uint32_t pairbits[32];
     int noff, ncomp, nnb, done;
-    int nb[13];                     // neighbour dense ids handled by this cell
-    short nbo[13];                  // their offsets: (ox+1) | (oy+1) << 2 | (oz+1) << 4
+    int nb[26];                     // neighbour dense ids (cross), or sparse cell starts
+    short nbo[26];                  // their offsets: (ox+1) | (oy+1) << 2 | (oz+1) << 4
+    int nbp[27];                    // sparse neighbours: running particle count
 };
 
 __device__ __forceinline__ int rank_in(const uint32_t *bits, const int *pre, int k)
@@ -708,8 +711,129 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     }
 }
 
+// Ordinary (sparse) particles around dense cell d.  Runs after every sparse link kernel,
+// so hooks go straight into the global forest.  A particle q of a neighbouring cell
+// without a clique table is tested only if this cell lies within reach of q's position
+// (the face test of the sparse search, from q's side), then only against the fine cells
+// within reach of q, one friend per component of this cell.  q is then marked in the flag
+// bitmap, so the compress pass gives it its component's label.
+template <int G, int UMAX, int CAP>
+__device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
+{
+    const int t = Grp<G>::tid();
+    const int64_t c = w.dense_list[d];
+    const int32_t s = w.cell_start[c];
+    const int32_t n = w.cell_start[c + 1] - s;
+    const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
+    const CellXYZ cc = cell_xyz(B, c);
+    const int m = B.m;
+    const int W = w.table_words;
+    const int32_t *T = w.table + (int64_t)d * w.table_stride;
+    const int u = T[2], ncomp = T[1];
+
+    if (t == 0)
+        L.nnb = 0;
+    Grp<G>::sync();
+    if (t < 27 && t != 13) {  // dense_ok boxes have nc >= 3: the 26 neighbours are distinct
+        const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = t / 9 - 1;
+        const int64_t c2 = coarse_cell(B, wrap_cell(cc.x + ox, B.nc[0]),
+                                       wrap_cell(cc.y + oy, B.nc[1]), wrap_cell(cc.z + oz, B.nc[2]));
+        const int32_t s2 = w.cell_start[c2], n2 = w.cell_start[c2 + 1] - s2;
+        if (n2 > 0 && !(n2 > w.dense_threshold && w.cell_count[c2] >= 0)) {
+            const int k = atomicAdd(&L.nnb, 1);
+            L.nb[k] = s2;
+            L.nbp[k] = n2;
+            L.nbo[k] = (short)((ox + 1) | ((oy + 1) << 2) | ((oz + 1) << 4));
+        }
+    }
+    Grp<G>::sync();
+    const int nnb = L.nnb;
+    if (nnb == 0) {  // uniform: every thread read the same count
+        Grp<G>::sync();
+        return;
+    }
+    if (t == 0) {  // counts -> running offsets (at most 26 entries)
+        int acc = 0;
+        for (int k = 0; k < nnb; ++k) {
+            const int c2 = L.nbp[k];
+            L.nbp[k] = acc;
+            acc += c2;
+        }
+        L.nbp[nnb] = acc;
+    }
+    for (int q = t; q < W; q += G) {
+        L.bits[q] = (uint32_t)T[kTableHeader + q];
+        L.pre[q] = T[kTableHeader + W + q];
+    }
+    for (int r = t; r < u; r += G) {
+        L.ustart[r] = w.rank[s + r];
+        L.ucomp[r] = (short)w.cnt[s + r];
+    }
+    if (t == 0)
+        L.ustart[u] = s + n;
+    if (n <= CAP)
+        for (int k = t; k < n; k += G)
+            L.part[k] = w.sorted[s + k];
+    Grp<G>::sync();
+    const float4 *mem = n <= CAP ? L.part : w.sorted + s;
+    const int total = L.nbp[nnb];
+    for (int e = t; e < total; e += G) {
+        int k = 0;
+        while (L.nbp[k + 1] <= e)
+            ++k;
+        const int o = L.nbo[k];
+        const int ox = (o & 3) - 1, oy = ((o >> 2) & 3) - 1, oz = (o >> 4) - 1;
+        const int32_t j = L.nb[k] + (e - L.nbp[k]);
+        const float4 q = w.sorted[j];
+        // q's cell, and this cell's coordinate in q's periodic frame (q's cell minus o)
+        const int qx = wrap_cell(cc.x + ox, B.nc[0]), qy = wrap_cell(cc.y + oy, B.nc[1]),
+                  qz = wrap_cell(cc.z + oz, B.nc[2]);
+        const AxisSpan sx = axis_span(q.x, qx, B.side[0], B.nc[0], B.reach);
+        const AxisSpan sy = axis_span(q.y, qy, B.side[1], B.nc[1], B.reach);
+        const AxisSpan sz = axis_span(q.z, qz, B.side[2], B.nc[2], B.reach);
+        if (-ox < sx.lo || -ox > sx.hi || -oy < sy.lo || -oy > sy.hi || -oz < sz.lo || -oz > sz.hi)
+            continue;
+        int x0, x1, y0, y1, z0, z1;
+        key_range(q.x * B.inv_fine[0] - (float)((qx - ox) * m), B.reach * B.inv_fine[0], m, x0, x1);
+        key_range(q.y * B.inv_fine[1] - (float)((qy - oy) * m), B.reach * B.inv_fine[1], m, y0, y1);
+        key_range(q.z * B.inv_fine[2] - (float)((qz - oz) * m), B.reach * B.inv_fine[2], m, z0, z1);
+        FOF_STAT(w.ctr, ST_DN_CALLS, 1);
+        bool any = false;
+        uint64_t seen = 0;  // components (numbers < 64) already joined
+        for (int bz = z0; bz <= z1; ++bz)
+            for (int by = y0; by <= y1; ++by)
+                for (int bx = x0; bx <= x1; ++bx) {
+                    const int kb = (bz * m + by) * m + bx;
+                    if (!((L.bits[kb >> 5] >> (kb & 31)) & 1u))
+                        continue;
+                    const int rb = rank_in(L.bits, L.pre, kb);
+                    const int comp = L.ucomp[rb];
+                    if (comp < 64 && ((seen >> comp) & 1ull))
+                        continue;
+                    FOF_STAT(w.ctr, ST_DN_UNITS, 1);
+                    for (int i = L.ustart[rb]; i < L.ustart[rb + 1]; ++i) {
+                        const float4 p = mem[i - s];
+                        if (linked(B, q.x, q.y, q.z, p.x, p.y, p.z)) {
+                            uf_union(w.parent, (uint32_t)j, (uint32_t)i);
+                            any = true;
+                            if (comp < 64)
+                                seen |= 1ull << comp;
+                            break;
+                        }
+                    }
+                    if (any && ncomp == 1)
+                        goto done;
+                }
+    done:
+        if (any)
+            atomicOr((unsigned long long *)(w.flags + (j >> 6)), 1ull << (j & 63));
+    }
+    Grp<G>::sync();
+}
+
 // Small cells: one wave per cell, iterating over every dense id and skipping big cells.
-template <bool kCross>
+// kMode: 0 components inside the cell, 1 dense neighbours, 2 ordinary neighbours.
+template <int kMode>
 __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
 {
     __shared__ CellLds<kSmallCell, kSmallCell> lds[Grp<kWave>::per_block];
@@ -720,23 +844,27 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
         const int64_t c = w.dense_list[d];
         if (w.cell_start[c + 1] - w.cell_start[c] > kSmallCell)
             continue;
-        if (kCross)
+        if (kMode == 1)
             cross_cell<kWave>(w, d, L);
+        else if (kMode == 2)
+            sparse_cell<kWave>(w, d, L);
         else
             cc_cell<kWave>(w, d, L);
     }
 }
 
 // Big cells: one block per cell, over the list of big dense ids.
-template <bool kCross>
+template <int kMode>
 __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
 {
     __shared__ CellLds<kMaxFineKeys, kLdsCap> L;
     const int nb = __hip_atomic_load(&w.ctr->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int k = blockIdx.x; k < nb; k += gridDim.x) {
         const int d = w.big_list[k];
-        if (kCross)
+        if (kMode == 1)
             cross_cell<kDenseBlock>(w, d, L);
+        else if (kMode == 2)
+            sparse_cell<kDenseBlock>(w, d, L);
         else
             cc_cell<kDenseBlock>(w, d, L);
     }
@@ -769,10 +897,20 @@ hipError_t launch_dense(const Work &w, hipStream_t s)
     if (w.dense_cap <= 0 || w.dense_threshold < 0)
         return hipSuccess;
     const unsigned pb = persistent_blocks(w.dense_cap);
-    hipLaunchKernelGGL(k_dense_small<false>, dim3(pb), dim3(kDenseBlock), 0, s, w);
-    hipLaunchKernelGGL(k_dense_big<false>, dim3(pb), dim3(kDenseBlock), 0, s, w);
-    hipLaunchKernelGGL(k_dense_small<true>, dim3(pb), dim3(kDenseBlock), 0, s, w);
-    hipLaunchKernelGGL(k_dense_big<true>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_small<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_big<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_small<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_big<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_sparse(const Work &w, hipStream_t s)
+{
+    if (w.dense_cap <= 0 || w.dense_threshold < 0)
+        return hipSuccess;
+    const unsigned pb = persistent_blocks(w.dense_cap);
+    hipLaunchKernelGGL(k_dense_small<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_big<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     return hipGetLastError();
 }
 

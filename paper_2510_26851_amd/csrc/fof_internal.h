@@ -123,6 +123,16 @@ __device__ __forceinline__ int wrap_cell(int c, int nc)
     return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
 
+// Fine-key range of a neighbour dense cell that a particle at fine coordinate f (relative
+// to that cell's origin, in the particle's periodic frame) can reach.
+__device__ __forceinline__ void key_range(float f, float rf, int m, int &lo, int &hi)
+{
+    lo = (int)floorf(f - rf);
+    hi = (int)floorf(f + rf);
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > m - 1 ? m - 1 : hi;
+}
+
 __device__ __forceinline__ int64_t coarse_cell(const BoxDesc &B, int ix, int iy, int iz)
 {
     return B.cell_base + ((int64_t)ix * B.nc[1] + iy) * B.nc[2] + iz;
@@ -297,6 +307,7 @@ hipError_t launch_build(const Work &w, const float *pos, hipStream_t s);
 hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s);
 hipError_t launch_dense_build(const Work &w, hipStream_t s);
 hipError_t launch_dense(const Work &w, hipStream_t s);
+hipError_t launch_dense_sparse(const Work &w, hipStream_t s);
 hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int32_t cap,
                          int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
                          double *vmean, double *sigv, hipStream_t s);

@@ -2,33 +2,22 @@
 // the 27-cell stencil of the coarse grid, the exact minimum-image predicate, and connected
 // components by a lock-free union-find instead of a fixed number of label sweeps.
 //
-// One thread per particle in cell-sorted order.  Each thread tests every candidate in the
-// neighbour cells that its own position can reach (a neighbour cell is skipped when the
-// particle is farther than `reach` from the shared face), so every pair is tested from
-// both ends.  That lets a particle that finds no friend at all write its final label
-// (itself) at once; only particles with at least one friend are marked in the flag bitmap
-// and resolved by the compress pass.  Each friend pair is hooked once, by its lower
-// sorted index.
+// Each particle tests every candidate in the neighbour cells that its own position can
+// reach (a neighbour cell is skipped when the particle is farther than `reach` from the
+// shared face), so every pair is tested from both ends.  That lets a particle that finds
+// no friend write its final label (itself) at once; only particles with at least one
+// friend are marked in the flag bitmap and resolved by the compress pass.  Each friend
+// pair is hooked once, from its lower original index.
 //
-// Cells with clique tables (fof_dense.hip) are linked by the dense kernels; their
-// particles skip the search here and are only marked.  A particle of an ordinary cell
-// reaches a dense neighbour through its units: only the fine cells within reach are
-// visited, and one friend in a unit (a clique) joins the particle to all of it.
+// Cells with clique tables (fof_dense.hip) are skipped here: the dense kernels link their
+// own particles and, after these kernels, the ordinary particles around them
+// (k_dense_sparse), marking those that find a friend there; the compress pass then
+// replaces any label written here for them.
 #include "fof_internal.h"
 
 namespace fof {
 
 namespace {
-
-// Fine-key range of a neighbour dense cell that a particle at fine coordinate f (relative
-// to that cell's origin, in the particle's periodic frame) can reach.
-__device__ __forceinline__ void key_range(float f, float rf, int m, int &lo, int &hi)
-{
-    lo = (int)floorf(f - rf);
-    hi = (int)floorf(f + rf);
-    lo = lo < 0 ? 0 : lo;
-    hi = hi > m - 1 ? m - 1 : hi;
-}
 
 // Where a hook goes.  DirectHook unions straight into the global forest.  DeferHook (the
 // tiled kernel, which publishes its local forests with plain stores and so must not touch
@@ -63,56 +52,6 @@ struct DeferHook {
     }
 };
 
-// Links particle i (position p) to the units of dense cell c2 at offset (ox, oy, oz) from
-// its own cell (ix, iy, iz).  Returns true if any friend was found.
-template <class Hook>
-__device__ bool link_dense_neighbour(const Work &w, const BoxDesc &B, uint32_t i, float4 p,
-                                     int ix, int iy, int iz, int ox, int oy, int oz, int32_t s2,
-                                     int32_t n2, int32_t d2, const Hook &hook)
-{
-    const int m = B.m;
-    const int W = w.table_words;
-    const int32_t *T = w.table + (int64_t)d2 * w.table_stride;
-    const int u = T[2], ncomp = T[1];
-    int x0, x1, y0, y1, z0, z1;
-    FOF_STAT(w.ctr, ST_DN_CALLS, 1);
-    key_range(p.x * B.inv_fine[0] - (float)((ix + ox) * m), B.reach * B.inv_fine[0], m, x0, x1);
-    key_range(p.y * B.inv_fine[1] - (float)((iy + oy) * m), B.reach * B.inv_fine[1], m, y0, y1);
-    key_range(p.z * B.inv_fine[2] - (float)((iz + oz) * m), B.reach * B.inv_fine[2], m, z0, z1);
-    bool any = false;
-    uint64_t seen = 0;  // components (numbers < 64) already joined
-    for (int bz = z0; bz <= z1; ++bz)
-        for (int by = y0; by <= y1; ++by)
-            for (int bx = x0; bx <= x1; ++bx) {
-                const int kb = (bz * m + by) * m + bx;
-                const uint32_t word = (uint32_t)T[kTableHeader + (kb >> 5)];
-                if (!((word >> (kb & 31)) & 1u))
-                    continue;
-                const int rb = T[kTableHeader + W + (kb >> 5)] +
-                               __popc(word & ((1u << (kb & 31)) - 1u));
-                const int comp = w.cnt[s2 + rb];
-                if (comp < 64 && ((seen >> comp) & 1ull))
-                    continue;
-                const int32_t b0 = w.rank[s2 + rb];
-                const int32_t b1 = rb + 1 < u ? w.rank[s2 + rb + 1] : s2 + n2;
-                FOF_STAT(w.ctr, ST_DN_UNITS, 1);
-                FOF_STAT(w.ctr, ST_DN_MEMBER_TESTS, b1 - b0);
-                for (int32_t j = b0; j < b1; ++j) {
-                    const float4 q = w.sorted[j];
-                    if (linked(B, p.x, p.y, p.z, q.x, q.y, q.z)) {
-                        hook(i, (uint32_t)j);
-                        any = true;
-                        if (comp < 64)
-                            seen |= 1ull << comp;
-                        break;
-                    }
-                }
-                if (any && ncomp == 1)
-                    return true;
-            }
-    return any;
-}
-
 // Whether particle p (sorted index i) sits in a cell linked by the dense kernels.
 __device__ __forceinline__ bool in_dense_cell(const Work &w, const BoxDesc &B, int ix, int iy,
                                               int iz)
@@ -141,15 +80,8 @@ __device__ bool link_particle_global(const Work &w, const BoxDesc &B, int64_t i,
                 const int cz = wrap_cell(iz + oz, B.nc[2]);
                 const int64_t c = coarse_cell(B, cx, cy, cz);
                 const int32_t s = w.cell_start[c], e = w.cell_start[c + 1];
-                if (box_dense && e - s > w.dense_threshold) {
-                    const int32_t d2 = w.cell_count[c];
-                    if (d2 >= 0) {
-                        has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz, ox,
-                                                           oy, oz, s, e - s, d2,
-                                                           DirectHook{w.parent});
-                        continue;
-                    }
-                }
+                if (box_dense && e - s > w.dense_threshold && w.cell_count[c] >= 0)
+                    continue;  // clique-table cell: linked from its side (k_dense_sparse)
                 FOF_STAT(w.ctr, ST_PAIRS_GLOBAL, e - s);
                 for (int32_t j = s; j < e; ++j) {
                     if (j == i)
@@ -451,19 +383,7 @@ __device__ __forceinline__ bool link_staged(const Work &w, const BoxDesc &B, boo
                     }
                 }
             }
-            if (box_dense)
-                for (int oz = sz.lo; oz <= sz.hi; ++oz) {
-                    const int code = gst[rb2 + hz + oz];
-                    if (code >= 0)
-                        continue;  // not a clique-table cell
-                    const int64_t c2 = coarse_cell(B, wrap_cell(ix + ox, B.nc[0]),
-                                                   wrap_cell(iy + oy, B.nc[1]),
-                                                   wrap_cell(iz + oz, B.nc[2]));
-                    const int32_t s2 = w.cell_start[c2];
-                    has_friend |= link_dense_neighbour(w, B, (uint32_t)i, p, ix, iy, iz, ox, oy,
-                                                       oz, s2, w.cell_start[c2 + 1] - s2, -1 - code,
-                                                       hook);
-                }
+
         }
     return has_friend;
 }
@@ -753,6 +673,9 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s)
         hipLaunchKernelGGL(k_link_windows, dim3(wb), dim3(kTileBlock), 0, s, w, root);
     }
     hipLaunchKernelGGL(k_link, dim3(nb), dim3(w.block), 0, s, w, root);
+    e = launch_dense_sparse(w, s);  // after every plain store of the tiled kernel
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_compress, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent,
                        w.flags, root);
     return hipGetLastError();
