@@ -33,8 +33,9 @@ GROUPS_BYTES_PER_PARTICLE = 20
 
 
 # The link stage (fof_link) as launched on the benchmark workload: its kernels, in order.
-LINK_STAGE = "fof_link: k_fill<u64>, k_dense_small/big<false>, k_dense_small/big<true>, " \
-             "k_link_tiled, k_link, k_compress"
+LINK_STAGE = "fof_link: k_fill, k_dense_small/big<0> (components), k_dense_small/big<1> " \
+             "(dense pairs), k_link_tiled, k_link_edges, k_link_windows, k_link, " \
+             "k_dense_small/big<2> (sparse-dense), k_compress"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "link_stage_traffic_zeldovich-nfw-512.txt")
 
 

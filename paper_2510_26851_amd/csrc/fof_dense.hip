@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_sort(Work w)
         const int64_t c = w.dense_list[d];
         const int32_t s = w.cell_start[c];
         const int32_t n = w.cell_start[c + 1] - s;
-        const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
+        const BoxDesc &B = uniform_box(w.desc, find_box(w.desc, w.nbox, s));
         const CellXYZ cc = cell_xyz(B, c);
         const int K = B.m * B.m * B.m;
         const int W = w.table_words;
@@ -402,8 +402,9 @@ __device__ __forceinline__ bool far_from(const BoxDesc &B, const FineBox &f, flo
 
 // Is some member of unit A (memA[a0, a1)) a friend of some member of unit B (memB[b0, b1))?
 // Members of A far from B's fine box are skipped.
-__device__ __forceinline__ bool units_meet(const BoxDesc &B, const float4 *memA, int a0, int a1,
-                                           const float4 *memB, int b0, int b1, const FineBox &fb)
+__device__ __forceinline__ bool units_meet(const BoxDesc &B, const Pred &P, const float4 *memA,
+                                           int a0, int a1, const float4 *memB, int b0, int b1,
+                                           const FineBox &fb)
 {
     for (int i = a0; i < a1; ++i) {
         const float4 p = memA[i];
@@ -411,7 +412,7 @@ __device__ __forceinline__ bool units_meet(const BoxDesc &B, const float4 *memA,
             continue;
         for (int j = b0; j < b1; ++j) {
             const float4 q = memB[j];
-            if (linked(B, p.x, p.y, p.z, q.x, q.y, q.z))
+            if (linked(P, p.x, p.y, p.z, q.x, q.y, q.z))
                 return true;
         }
     }
@@ -458,8 +459,9 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     const int64_t c = w.dense_list[d];
     const int32_t s = w.cell_start[c];
     const int32_t n = w.cell_start[c + 1] - s;
-    const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
+    const BoxDesc &B = uniform_box(w.desc, find_box(w.desc, w.nbox, s));
     const CellXYZ cc = cell_xyz(B, c);
+    const Pred P = pred_of(B);
     const int m = B.m, R = B.R;
     int32_t *T = w.table + (int64_t)d * w.table_stride;
     const int u = T[2];
@@ -525,7 +527,7 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
             FOF_STAT(w.ctr, ST_CC_UNIT_PAIRS, 1);
             FOF_STAT(w.ctr, ST_CC_MEMBER_TESTS,
                      (L.ustart[r + 1] - L.ustart[r]) * (L.ustart[rb + 1] - L.ustart[rb]));
-            if (units_meet(B, mem, L.ustart[r] - s, L.ustart[r + 1] - s, mem, L.ustart[rb] - s,
+            if (units_meet(B, P, mem, L.ustart[r] - s, L.ustart[r + 1] - s, mem, L.ustart[rb] - s,
                            L.ustart[rb + 1] - s, fb))
                 lunion(L.uf, r, rb);
         }
@@ -569,8 +571,9 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     const int64_t c = w.dense_list[d];
     const int32_t s = w.cell_start[c];
     const int32_t n = w.cell_start[c + 1] - s;
-    const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
+    const BoxDesc &B = uniform_box(w.desc, find_box(w.desc, w.nbox, s));
     const CellXYZ cc = cell_xyz(B, c);
+    const Pred P = pred_of(B);
     const int m = B.m, R = B.R;
     const int W = w.table_words;
     const int32_t *T = w.table + (int64_t)d * w.table_stride;
@@ -688,7 +691,7 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
                                 continue;
                             for (int32_t j = b0; j < b1; ++j) {
                                 const float4 q4 = w.sorted[j];
-                                if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
+                                if (linked(P, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
                                     hit_i = i;
                                     hit_j = j;
                                     break;
@@ -724,8 +727,9 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     const int64_t c = w.dense_list[d];
     const int32_t s = w.cell_start[c];
     const int32_t n = w.cell_start[c + 1] - s;
-    const BoxDesc &B = w.desc[find_box(w.desc, w.nbox, s)];
+    const BoxDesc &B = uniform_box(w.desc, find_box(w.desc, w.nbox, s));
     const CellXYZ cc = cell_xyz(B, c);
+    const Pred P = pred_of(B);
     const int m = B.m;
     const int W = w.table_words;
     const int32_t *T = w.table + (int64_t)d * w.table_stride;
@@ -813,7 +817,7 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
                     FOF_STAT(w.ctr, ST_DN_UNITS, 1);
                     for (int i = L.ustart[rb]; i < L.ustart[rb + 1]; ++i) {
                         const float4 p = mem[i - s];
-                        if (linked(B, q.x, q.y, q.z, p.x, p.y, p.z)) {
+                        if (linked(P, q.x, q.y, q.z, p.x, p.y, p.z)) {
                             uf_union(w.parent, (uint32_t)j, (uint32_t)i);
                             any = true;
                             if (comp < 64)

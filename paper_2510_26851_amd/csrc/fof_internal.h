@@ -160,7 +160,33 @@ __device__ __forceinline__ double min_image(double d, double L, double h)
     return d;
 }
 
-__device__ __forceinline__ double dist2(const BoxDesc &B, float xi, float yi, float zi, float xj,
+// The predicate's box constants.  Kernels copy them out of the descriptor once (pred_of),
+// so they stay in registers across stores the compiler cannot prove disjoint from the
+// descriptor; dist2 and linked take either.
+struct Pred {
+    double L[3], halfL[3], b2;
+};
+
+__device__ __forceinline__ Pred pred_of(const BoxDesc &B)
+{
+    Pred P;
+    for (int a = 0; a < 3; ++a) {
+        P.L[a] = B.L[a];
+        P.halfL[a] = B.halfL[a];
+    }
+    P.b2 = B.b2;
+    return P;
+}
+
+// Descriptor of the box a whole wave works on: the index is made wave-uniform, so its
+// fields are read with scalar loads.
+__device__ __forceinline__ const BoxDesc &uniform_box(const BoxDesc *desc, int k)
+{
+    return desc[__builtin_amdgcn_readfirstlane(k)];
+}
+
+template <class Box>
+__device__ __forceinline__ double dist2(const Box &B, float xi, float yi, float zi, float xj,
                                         float yj, float zj)
 {
     double dx = min_image((double)xi - (double)xj, B.L[0], B.halfL[0]);
@@ -172,7 +198,8 @@ __device__ __forceinline__ double dist2(const BoxDesc &B, float xi, float yi, fl
     return __dadd_rn(__dadd_rn(sx, sy), sz);
 }
 
-__device__ __forceinline__ bool linked(const BoxDesc &B, float xi, float yi, float zi, float xj,
+template <class Box>
+__device__ __forceinline__ bool linked(const Box &B, float xi, float yi, float zi, float xj,
                                        float yj, float zj)
 {
     return dist2(B, xi, yi, zi, xj, yj, zj) < B.b2;

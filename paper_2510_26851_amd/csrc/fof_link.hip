@@ -339,7 +339,8 @@ __device__ __forceinline__ void flag_friends_wave(uint64_t *flags, bool active, 
 // window: neighbour row r's halo cells [z_first, ...] sit at LDS wb[r] + slot - hoff[...].
 // Returns whether p has a friend; pairs are hooked from the smaller original index.
 template <class Hook>
-__device__ __forceinline__ bool link_staged(const Work &w, const BoxDesc &B, bool box_dense,
+__device__ __forceinline__ bool link_staged(const Work &w, const BoxDesc &B, const Pred &P,
+                                            bool box_dense,
                                             const float4 *part, const int *hoff, const int *gst,
                                             int64_t i, float4 p, int ls,
                                             int hx, int hy, int hz, int ix, int iy, int iz,
@@ -369,7 +370,7 @@ __device__ __forceinline__ bool link_staged(const Work &w, const BoxDesc &B, boo
                 if (j == ls)
                     continue;
                 const float4 q4 = part[j];
-                if (linked(B, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
+                if (linked(P, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
                     has_friend = true;
                     if (oi < __float_as_int(q4.w)) {  // each pair hooked from one end
                         if (j >= own_lo && j < own_hi) {
@@ -402,7 +403,8 @@ __global__ __launch_bounds__(kTileBlock, 6) void k_link_tiled(Work w, int32_t *_
     const int64_t tile = xcd_block();
     if (tile >= w.ntiles)
         return;
-    const BoxDesc &B = w.desc[find_box_tile(w.desc, w.nbox, tile)];
+    const BoxDesc &B = uniform_box(w.desc, find_box_tile(w.desc, w.nbox, tile));
+    const Pred P = pred_of(B);
     const TileGeom g = tile_geom(B, tile);
     const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
     const int t = threadIdx.x;
@@ -459,7 +461,7 @@ __global__ __launch_bounds__(kTileBlock, 6) void k_link_tiled(Work w, int32_t *_
         const int64_t i = gst[hs] + (slot - hoff[hs]);
         const float4 p = part[slot];
         const int hz = hs % kHZ, hy = (hs / kHZ) % kHY, hx = hs / (kHZ * kHY);
-        if (link_staged(w, B, box_dense, part, hoff, gst, i, p, slot, hx, hy, hz, g.x0 - 1 + hx,
+        if (link_staged(w, B, P, box_dense, part, hoff, gst, i, p, slot, hx, hy, hz, g.x0 - 1 + hx,
                         g.y0 - 1 + hy, g.z0 - 1 + hz, nullptr, 0, lpar, g, hook))
             fmask |= 1u << q;
     }
@@ -542,7 +544,8 @@ __global__ __launch_bounds__(kTileBlock) void k_link_windows(Work w, int32_t *__
     const int nq = w.ctr->n_spill;
     for (int q = blockIdx.x; q < nq; q += gridDim.x) {
         const int64_t tile = w.tile_list[q];
-        const BoxDesc &B = w.desc[find_box_tile(w.desc, w.nbox, tile)];
+        const BoxDesc &B = uniform_box(w.desc, find_box_tile(w.desc, w.nbox, tile));
+        const Pred P = pred_of(B);
         const TileGeom g = tile_geom(B, tile);
         const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
         build_halo(w, B, g, box_dense, hoff, gst, scr);
@@ -616,7 +619,7 @@ __global__ __launch_bounds__(kTileBlock) void k_link_windows(Work w, int32_t *__
                 if (fits) {
                     const int ls = wbase[row] + slot - hoff[rb + za - 1];
                     p = part[ls];
-                    f = link_staged(w, B, box_dense, part, hoff, gst, i, p, ls, hx, hy, hz, ix,
+                    f = link_staged(w, B, P, box_dense, part, hoff, gst, i, p, ls, hx, hy, hz, ix,
                                     iy, iz, wbase, za - 1, nullptr, g, DirectHook{w.parent});
                 } else {
                     p = w.sorted[i];
