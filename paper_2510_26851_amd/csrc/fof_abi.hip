@@ -116,7 +116,7 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
 struct Layout {
     size_t off_desc, off_status, off_cell_count, off_cell_start, off_scan, off_rank, off_sorted,
         off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, off_dense,
-        off_big, off_table, off_temp, off_tiles, off_edges, total;
+        off_big, off_table, off_temp, off_tiles, off_edges, off_cursors, total;
     int64_t edge_cap;
 };
 
@@ -163,6 +163,7 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
     L.off_tiles = take(sizeof(int32_t) * (size_t)ntiles);
     L.edge_cap = ntiles > 0 ? link_edge_cap(n) : 0;
     L.off_edges = take(sizeof(int2) * (size_t)L.edge_cap);
+    L.off_cursors = take(dense_cap > 0 ? sizeof(int32_t) * (size_t)kCursorInts : 0);
     L.total = o;
     return L;
 }
@@ -197,6 +198,7 @@ Work resolve(const fof_grid *g, void *ws)
     w.temp = (float4 *)(base + L.off_temp);
     w.tile_list = (int32_t *)(base + L.off_tiles);
     w.edges = (int2 *)(base + L.off_edges);
+    w.cursors = (int32_t *)(base + L.off_cursors);
     w.edge_cap = (int32_t)L.edge_cap;
     w.dense_threshold = g->dense_threshold;
     w.dense_cap = (int32_t)g->dense_cap;

@@ -357,7 +357,7 @@ struct CellLds {
     int pre[kMaxTableWords];
     short offs[kMaxOffsets];        // forward fine offsets: (dx+R) | (dy+R) << 4 | (dz+R) << 8
     uint32_t pairbits[32];
-    int noff, ncomp, nnb, done;
+    int noff, nnear, ncomp, nnb, done;
     int nb[26];                     // neighbour dense ids (cross), or sparse cell starts
     short nbo[26];                  // their offsets: (ox+1) | (oy+1) << 2 | (oz+1) << 4
     int nbp[27];                    // sparse neighbours: running particle count
@@ -400,6 +400,29 @@ __device__ __forceinline__ bool far_from(const BoxDesc &B, const FineBox &f, flo
     return s >= (float)B.b2 * 1.000001f;
 }
 
+// Index of the first member of memB[b0, b1) that is a friend of p, or -1.  Members are
+// read four at a time so that their loads (LDS or global) overlap.
+__device__ __forceinline__ int first_friend(const Pred &P, float4 p, const float4 *memB, int b0,
+                                            int b1)
+{
+    int j = b0;
+    for (; j + 4 <= b1; j += 4) {
+        const float4 q0 = memB[j], q1 = memB[j + 1], q2 = memB[j + 2], q3 = memB[j + 3];
+        const bool h0 = linked(P, p.x, p.y, p.z, q0.x, q0.y, q0.z);
+        const bool h1 = linked(P, p.x, p.y, p.z, q1.x, q1.y, q1.z);
+        const bool h2 = linked(P, p.x, p.y, p.z, q2.x, q2.y, q2.z);
+        const bool h3 = linked(P, p.x, p.y, p.z, q3.x, q3.y, q3.z);
+        if (h0 | h1 | h2 | h3)
+            return h0 ? j : (h1 ? j + 1 : (h2 ? j + 2 : j + 3));
+    }
+    for (; j < b1; ++j) {
+        const float4 q = memB[j];
+        if (linked(P, p.x, p.y, p.z, q.x, q.y, q.z))
+            return j;
+    }
+    return -1;
+}
+
 // Is some member of unit A (memA[a0, a1)) a friend of some member of unit B (memB[b0, b1))?
 // Members of A far from B's fine box are skipped.
 __device__ __forceinline__ bool units_meet(const BoxDesc &B, const Pred &P, const float4 *memA,
@@ -410,11 +433,8 @@ __device__ __forceinline__ bool units_meet(const BoxDesc &B, const Pred &P, cons
         const float4 p = memA[i];
         if (far_from(B, fb, p))
             continue;
-        for (int j = b0; j < b1; ++j) {
-            const float4 q = memB[j];
-            if (linked(P, p.x, p.y, p.z, q.x, q.y, q.z))
-                return true;
-        }
+        if (first_friend(P, p, memB, b0, b1) >= 0)
+            return true;
     }
     return false;
 }
@@ -450,6 +470,36 @@ __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n
         }
     }
     Grp<G>::sync();
+}
+
+// Joins each unit r of the staged cell with the units at forward offsets [q0, q1): a pair
+// already in one component is skipped, otherwise its first friend pair (if any) joins it.
+template <int G, int UMAX, int CAP>
+__device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const CellXYZ &cc,
+                           int m, int R, int u, int32_t s, const float4 *mem,
+                           CellLds<UMAX, CAP> &L, int q0, int q1)
+{
+    for (int r = Grp<G>::tid(); r < u; r += G) {
+        const int xyz = L.uxyz[r];
+        const int ax = xyz & 15, ay = (xyz >> 4) & 15, az = xyz >> 8;
+        for (int q = q0; q < q1; ++q) {
+            const int o = L.offs[q];
+            const int bx = ax + (o & 15) - R, by = ay + ((o >> 4) & 15) - R, bz = az + (o >> 8) - R;
+            if ((unsigned)bx >= (unsigned)m || (unsigned)by >= (unsigned)m || (unsigned)bz >= (unsigned)m)
+                continue;
+            const int kb = (bz * m + by) * m + bx;
+            if (!((L.bits[kb >> 5] >> (kb & 31)) & 1u))
+                continue;
+            const int rb = rank_in(L.bits, L.pre, kb);
+            if (lfind(L.uf, r) == lfind(L.uf, rb))
+                continue;
+            const FineBox fb = fine_box(B, cc.x * m + bx, cc.y * m + by, cc.z * m + bz);
+            FOF_STAT(w.ctr, ST_CC_UNIT_PAIRS, 1);
+            if (units_meet(B, P, mem, L.ustart[r] - s, L.ustart[r + 1] - s, mem, L.ustart[rb] - s,
+                           L.ustart[rb + 1] - s, fb))
+                lunion(L.uf, r, rb);
+        }
+    }
 }
 
 template <int G, int UMAX, int CAP>
@@ -493,6 +543,8 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
                 L.offs[atomicAdd(&L.noff, 1)] = (short)packed;
         }
         Grp<G>::sync();
+        if (pass == 0 && t == 0)
+            L.nnear = L.noff;  // offsets [0, nnear) are the nearest shell
     }
     // unit minima
     for (int r = t; r < u; r += G) {
@@ -507,31 +559,25 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     }
     Grp<G>::sync();
 
-    // join units of this cell: first friend pair wins
-    const int noff = L.noff;
+    // join units of this cell: first friend pair wins.  The nearest shell goes first; when
+    // it already leaves one component (the usual case inside a clump) the rest is skipped.
+    const int noff = L.noff, nnear = L.nnear;
+    join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 0, nnear);
+    Grp<G>::sync();
+    if (t == 0)
+        L.ncomp = 0;
+    Grp<G>::sync();
     for (int r = t; r < u; r += G) {
-        const int xyz = L.uxyz[r];
-        const int ax = xyz & 15, ay = (xyz >> 4) & 15, az = xyz >> 8;
-        for (int q = 0; q < noff; ++q) {
-            const int o = L.offs[q];
-            const int bx = ax + (o & 15) - R, by = ay + ((o >> 4) & 15) - R, bz = az + (o >> 8) - R;
-            if ((unsigned)bx >= (unsigned)m || (unsigned)by >= (unsigned)m || (unsigned)bz >= (unsigned)m)
-                continue;
-            const int kb = (bz * m + by) * m + bx;
-            if (!((L.bits[kb >> 5] >> (kb & 31)) & 1u))
-                continue;
-            const int rb = rank_in(L.bits, L.pre, kb);
-            if (lfind(L.uf, r) == lfind(L.uf, rb))
-                continue;
-            const FineBox fb = fine_box(B, cc.x * m + bx, cc.y * m + by, cc.z * m + bz);
-            FOF_STAT(w.ctr, ST_CC_UNIT_PAIRS, 1);
-            FOF_STAT(w.ctr, ST_CC_MEMBER_TESTS,
-                     (L.ustart[r + 1] - L.ustart[r]) * (L.ustart[rb + 1] - L.ustart[rb]));
-            if (units_meet(B, P, mem, L.ustart[r] - s, L.ustart[r + 1] - s, mem, L.ustart[rb] - s,
-                           L.ustart[rb + 1] - s, fb))
-                lunion(L.uf, r, rb);
-        }
+        const int root = lfind(L.uf, r);
+        if (root == r)
+            atomicAdd(&L.ncomp, 1);
     }
+    Grp<G>::sync();
+    if (L.ncomp > 1)  // uniform: every thread reads the same count
+        join_units<G>(w, B, P, cc, m, R, u, s, mem, L, nnear, noff);
+    Grp<G>::sync();
+    if (t == 0)
+        L.ncomp = 0;
     Grp<G>::sync();
 
     // flatten: component minimum and component numbers
@@ -682,20 +728,15 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
                         const FineBox fb = fine_box(B, (cc.x + ox) * m + bx, (cc.y + oy) * m + by,
                                                     (cc.z + oz) * m + bz);
                         FOF_STAT(w.ctr, ST_CROSS_UNIT_PAIRS, 1);
-                        FOF_STAT(w.ctr, ST_CROSS_MEMBER_TESTS,
-                                 (L.ustart[r + 1] - L.ustart[r]) * (b1 - b0));
                         int hit_i = -1, hit_j = -1;
                         for (int i = L.ustart[r]; i < L.ustart[r + 1] && hit_i < 0; ++i) {
                             const float4 p = mem[i - s];
                             if (far_from(B, fb, p))
                                 continue;
-                            for (int32_t j = b0; j < b1; ++j) {
-                                const float4 q4 = w.sorted[j];
-                                if (linked(P, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
-                                    hit_i = i;
-                                    hit_j = j;
-                                    break;
-                                }
+                            const int j = first_friend(P, p, w.sorted, b0, b1);
+                            if (j >= 0) {
+                                hit_i = i;
+                                hit_j = j;
                             }
                         }
                         if (hit_i >= 0) {
@@ -815,15 +856,13 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
                     if (comp < 64 && ((seen >> comp) & 1ull))
                         continue;
                     FOF_STAT(w.ctr, ST_DN_UNITS, 1);
-                    for (int i = L.ustart[rb]; i < L.ustart[rb + 1]; ++i) {
-                        const float4 p = mem[i - s];
-                        if (linked(P, q.x, q.y, q.z, p.x, p.y, p.z)) {
-                            uf_union(w.parent, (uint32_t)j, (uint32_t)i);
-                            any = true;
-                            if (comp < 64)
-                                seen |= 1ull << comp;
-                            break;
-                        }
+                    const int hit =
+                        first_friend(P, q, mem, L.ustart[rb] - s, L.ustart[rb + 1] - s);
+                    if (hit >= 0) {
+                        uf_union(w.parent, (uint32_t)j, (uint32_t)(s + hit));
+                        any = true;
+                        if (comp < 64)
+                            seen |= 1ull << comp;
                     }
                     if (any && ncomp == 1)
                         goto done;
@@ -835,6 +874,42 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     Grp<G>::sync();
 }
 
+// Work distribution of a dense pass.  Items (dense ids) are dealt to kCursorGroups groups,
+// item d to group d % G; worker k (a wave or a block, of `nworkers`) serves group
+// k % G, first taking item g + G * (k / G) and then further items of its group from the
+// group's cursor.  Item costs differ widely, so the cursors balance the load; the groups
+// keep each cursor's atomics few and on its own line.  The cursor is read before it is
+// incremented, so that workers with nothing left do not queue on the atomic.
+struct Deal {
+    int32_t *cursor;
+    int g, per_group;  // this worker's group, workers per group
+};
+
+__device__ __forceinline__ Deal deal(int32_t *cursors, int pass, int worker, int nworkers)
+{
+    const int G = kCursorGroups;
+    const int g = worker % G;
+    Deal dl;
+    dl.cursor = cursors + (pass * G + g) * kCursorStride;
+    dl.g = g;
+    dl.per_group = (nworkers - g + G - 1) / G;  // workers k < nworkers with k % G == g
+    return dl;
+}
+
+__device__ __forceinline__ int deal_first(const Deal &dl, int worker)
+{
+    return dl.g + kCursorGroups * (worker / kCursorGroups);
+}
+
+__device__ __forceinline__ int deal_next(const Deal &dl, int n)
+{
+    const int G = kCursorGroups;
+    const int k0 = __hip_atomic_load(dl.cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (dl.g + G * (dl.per_group + k0) >= n)
+        return n;
+    return dl.g + G * (dl.per_group + atomicAdd(dl.cursor, 1));
+}
+
 // Small cells: one wave per cell, iterating over every dense id and skipping big cells.
 // kMode: 0 components inside the cell, 1 dense neighbours, 2 ordinary neighbours.
 template <int kMode>
@@ -843,17 +918,24 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
     __shared__ CellLds<kSmallCell, kSmallCell> lds[Grp<kWave>::per_block];
     CellLds<kSmallCell, kSmallCell> &L = lds[Grp<kWave>::slot()];
     const int nd = dense_count(w.ctr, w.dense_cap);
-    const int stride = gridDim.x * Grp<kWave>::per_block;
-    for (int d = blockIdx.x * Grp<kWave>::per_block + Grp<kWave>::slot(); d < nd; d += stride) {
+    const int nworkers = gridDim.x * Grp<kWave>::per_block;
+    const int worker = blockIdx.x * Grp<kWave>::per_block + Grp<kWave>::slot();
+    const Deal dl = deal(w.cursors, 2 * kMode, worker, nworkers);
+    int d = deal_first(dl, worker);
+    while (d < nd) {
         const int64_t c = w.dense_list[d];
-        if (w.cell_start[c + 1] - w.cell_start[c] > kSmallCell)
-            continue;
-        if (kMode == 1)
-            cross_cell<kWave>(w, d, L);
-        else if (kMode == 2)
-            sparse_cell<kWave>(w, d, L);
-        else
-            cc_cell<kWave>(w, d, L);
+        if (w.cell_start[c + 1] - w.cell_start[c] <= kSmallCell) {
+            if (kMode == 1)
+                cross_cell<kWave>(w, d, L);
+            else if (kMode == 2)
+                sparse_cell<kWave>(w, d, L);
+            else
+                cc_cell<kWave>(w, d, L);
+        }
+        int nx = 0;
+        if (lane_id() == 0)
+            nx = deal_next(dl, nd);
+        d = __shfl(nx, 0, kWave);
     }
 }
 
@@ -862,8 +944,10 @@ template <int kMode>
 __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
 {
     __shared__ CellLds<kMaxFineKeys, kLdsCap> L;
+    __shared__ int next;
     const int nb = __hip_atomic_load(&w.ctr->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int k = blockIdx.x; k < nb; k += gridDim.x) {
+    const Deal dl = deal(w.cursors, 2 * kMode + 1, blockIdx.x, gridDim.x);
+    for (int k = deal_first(dl, blockIdx.x); k < nb;) {
         const int d = w.big_list[k];
         if (kMode == 1)
             cross_cell<kDenseBlock>(w, d, L);
@@ -871,13 +955,20 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
             sparse_cell<kDenseBlock>(w, d, L);
         else
             cc_cell<kDenseBlock>(w, d, L);
+        if (threadIdx.x == 0)
+            next = deal_next(dl, nb);
+        __syncthreads();
+        k = next;
+        __syncthreads();  // every thread has read `next` before it is overwritten
     }
 }
 
+// Blocks of a dense pass: enough to fill the chip, at most one per possible item, and at
+// least one worker per cursor group (every group's items need a worker).
 unsigned persistent_blocks(int cap)
 {
     int b = cap < 4096 ? cap : 4096;
-    return (unsigned)(b > 0 ? b : 1);
+    return (unsigned)(b > kCursorGroups ? b : kCursorGroups);
 }
 
 }  // namespace
@@ -900,6 +991,9 @@ hipError_t launch_dense(const Work &w, hipStream_t s)
 {
     if (w.dense_cap <= 0 || w.dense_threshold < 0)
         return hipSuccess;
+    hipError_t e = launch_fill_i32(w.cursors, kCursorInts, 0, s);
+    if (e != hipSuccess)
+        return e;
     const unsigned pb = persistent_blocks(w.dense_cap);
     hipLaunchKernelGGL(k_dense_small<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     hipLaunchKernelGGL(k_dense_big<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);

@@ -19,6 +19,11 @@ constexpr int kScanItems = 8;                  // elements per thread in the sca
 constexpr int kMaxFine = 10;                   // fine cells per coarse cell per axis (max)
 constexpr int kMaxFineKeys = kMaxFine * kMaxFine * kMaxFine;
 constexpr int kMaxTableWords = (kMaxFineKeys + 31) / 32;
+// Dense-pass work cursors: per pass (3 modes x small/big cells) kCursorGroups counters, each
+// on its own 64-byte line so that groups do not contend.
+constexpr int kCursorGroups = 64;
+constexpr int kCursorStride = 16;
+constexpr int kCursorInts = 6 * kCursorGroups * kCursorStride;
 constexpr int kTableHeader = 4;  // dense-cell table: cell, ncomp, units, reserved
 // Link tiles: kTileX x kTileY x kTileZ coarse cells per block (z fastest, like the cells).
 constexpr int kTileX = 4, kTileY = 4, kTileZ = 16;
@@ -62,13 +67,15 @@ struct Counters {
 // Event counters for diagnostic builds; compiled out otherwise.
 enum Stat {
     ST_TILES, ST_TILES_OVERFLOW, ST_OWN_STAGED, ST_OWN_GLOBAL, ST_PAIRS_TILED, ST_PAIRS_GLOBAL,
-    ST_DN_CALLS, ST_DN_UNITS, ST_DN_MEMBER_TESTS, ST_CC_UNIT_PAIRS, ST_CC_MEMBER_TESTS,
-    ST_CROSS_UNIT_PAIRS, ST_CROSS_MEMBER_TESTS, ST_UNIONS, ST_CROSS_CELLPAIRS, ST_SPARE
+    ST_DN_CALLS, ST_DN_UNITS, ST_CELL_CYCLES, ST_CC_UNIT_PAIRS, ST_CELL_MAX_CYCLES,
+    ST_CROSS_UNIT_PAIRS, ST_CELLS_TIMED, ST_UNIONS, ST_CROSS_CELLPAIRS, ST_SPARE
 };
 #ifdef FOF_STATS
 #define FOF_STAT(ctr, k, v) atomicAdd(&(ctr)->stats[k], (unsigned long long)(v))
+#define FOF_STAT_MAX(ctr, k, v) atomicMax(&(ctr)->stats[k], (unsigned long long)(v))
 #else
 #define FOF_STAT(ctr, k, v) ((void)0)
+#define FOF_STAT_MAX(ctr, k, v) ((void)0)
 #endif
 
 // ---------------------------------------------------------------------------------------
@@ -165,6 +172,8 @@ __device__ __forceinline__ double min_image(double d, double L, double h)
 // descriptor; dist2 and linked take either.
 struct Pred {
     double L[3], halfL[3], b2;
+    float nowrap[3];   // |dx| below this (float) implies |dx| < L/2 exactly: no image shift
+    float b2lo, b2hi;  // float sums below b2lo are links, above b2hi are not (see linked)
 };
 
 __device__ __forceinline__ Pred pred_of(const BoxDesc &B)
@@ -173,8 +182,11 @@ __device__ __forceinline__ Pred pred_of(const BoxDesc &B)
     for (int a = 0; a < 3; ++a) {
         P.L[a] = B.L[a];
         P.halfL[a] = B.halfL[a];
+        P.nowrap[a] = (float)(B.halfL[a] * (1.0 - 0x1.0p-20));
     }
     P.b2 = B.b2;
+    P.b2lo = (float)(B.b2 * (1.0 - 0x1.0p-18));
+    P.b2hi = (float)(B.b2 * (1.0 + 0x1.0p-18));
     return P;
 }
 
@@ -198,11 +210,30 @@ __device__ __forceinline__ double dist2(const Box &B, float xi, float yi, float 
     return __dadd_rn(__dadd_rn(sx, sy), sz);
 }
 
-template <class Box>
-__device__ __forceinline__ bool linked(const Box &B, float xi, float yi, float zi, float xj,
+__device__ __forceinline__ bool linked(const BoxDesc &B, float xi, float yi, float zi, float xj,
                                        float yj, float zj)
 {
     return dist2(B, xi, yi, zi, xj, yj, zj) < B.b2;
+}
+
+// The same decision with a float prefilter.  Each float difference is within 2^-24 of the
+// exact one (relative), so the float sum of squares s is within 5 * 2^-24 of d^2; the double
+// path rounds d^2 by at most 3 * 2^-53.  With b2lo/b2hi 2^-18 below/above b^2 (rounded to
+// float: 2^-24 more), s < b2lo implies the double sum is below b^2 and s > b2hi that it is
+// not, so the result always equals the double predicate; sums in between, and pairs whose
+// float differences are near L/2 on some axis (where the image shift matters), take it.
+__device__ __forceinline__ bool linked(const Pred &P, float xi, float yi, float zi, float xj,
+                                       float yj, float zj)
+{
+    const float dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    if (fabsf(dx) < P.nowrap[0] && fabsf(dy) < P.nowrap[1] && fabsf(dz) < P.nowrap[2]) {
+        const float s = (dx * dx + dy * dy) + dz * dz;
+        if (s < P.b2lo)
+            return true;
+        if (s > P.b2hi)
+            return false;
+    }
+    return dist2(P, xi, yi, zi, xj, yj, zj) < P.b2;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -309,6 +340,7 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
     int32_t *tile_list;   // link tiles left to the windowed kernel
     int2 *edges;          // hooks deferred by the tiled kernel
     int32_t edge_cap;
+    int32_t *cursors;     // work cursors of the dense passes, kCursorStride ints apart
     int32_t nbox;
     int32_t block;
     int64_t n;
