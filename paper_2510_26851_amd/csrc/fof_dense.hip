@@ -84,10 +84,13 @@ __device__ __forceinline__ bool table_has(const int32_t *T, int k)
 __device__ __forceinline__ int lfind(int *uf, int x)
 {
     for (;;) {
-        int p = __hip_atomic_load(uf + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int p = __hip_atomic_load(uf + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (p == x)
             return x;
-        x = p;
+        const int g = __hip_atomic_load(uf + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (g != p)  // halving: only non-root entries are rewritten, never a root
+            __hip_atomic_store(uf + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = g;
     }
 }
 
@@ -350,14 +353,14 @@ struct CellLds {
     int uf[UMAX];                   // union-find over unit ranks
     unsigned long long umin[UMAX];  // (original index << 32 | sorted index) minimum
     int ustart[UMAX + 1];           // absolute sorted index of each unit's first member
-    short ukey[UMAX];               // fine key of each unit
+    int umark[UMAX];                // unit counts per root, then "outside the largest component"
     short uxyz[UMAX];               // fine coordinates: x | y << 4 | z << 8
     short ucomp[UMAX];              // component number of each unit
     uint32_t bits[kMaxTableWords];  // key bitmask of the cell (or of a neighbour, in cross)
     int pre[kMaxTableWords];
     short offs[kMaxOffsets];        // forward fine offsets: (dx+R) | (dy+R) << 4 | (dz+R) << 8
     uint32_t pairbits[32];
-    int noff, nnear, ncomp, nnb, done;
+    int noff, nnear, ncomp, nnb, done, giant;
     int nb[26];                     // neighbour dense ids (cross), or sparse cell starts
     short nbo[26];                  // their offsets: (ox+1) | (oy+1) << 2 | (oz+1) << 4
     int nbp[27];                    // sparse neighbours: running particle count
@@ -464,7 +467,6 @@ __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n
         while (bits) {
             const int k = q * 32 + __ffs(bits) - 1;
             bits &= bits - 1u;
-            L.ukey[r] = (short)k;
             L.uxyz[r] = (short)((k % m) | (((k / m) % m) << 4) | ((k / (m * m)) << 8));
             ++r;
         }
@@ -474,17 +476,24 @@ __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n
 
 // Joins each unit r of the staged cell with the units at forward offsets [q0, q1): a pair
 // already in one component is skipped, otherwise its first friend pair (if any) joins it.
+// With `marked_only`, only units with a nonzero mark take part, each with the offsets in
+// both directions (a pair with one unmarked end is then still examined from the other).
 template <int G, int UMAX, int CAP>
 __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const CellXYZ &cc,
                            int m, int R, int u, int32_t s, const float4 *mem,
-                           CellLds<UMAX, CAP> &L, int q0, int q1)
+                           CellLds<UMAX, CAP> &L, int q0, int q1, bool marked_only)
 {
+    const int nq = marked_only ? 2 * (q1 - q0) : q1 - q0;
     for (int r = Grp<G>::tid(); r < u; r += G) {
+        if (marked_only && !L.umark[r])
+            continue;
         const int xyz = L.uxyz[r];
         const int ax = xyz & 15, ay = (xyz >> 4) & 15, az = xyz >> 8;
-        for (int q = q0; q < q1; ++q) {
-            const int o = L.offs[q];
-            const int bx = ax + (o & 15) - R, by = ay + ((o >> 4) & 15) - R, bz = az + (o >> 8) - R;
+        for (int qq = 0; qq < nq; ++qq) {
+            const int o = L.offs[q0 + (qq >> (marked_only ? 1 : 0))];
+            const int sg = (marked_only && (qq & 1)) ? -1 : 1;  // odd: the opposite offset
+            const int bx = ax + sg * ((o & 15) - R), by = ay + sg * (((o >> 4) & 15) - R),
+                      bz = az + sg * ((o >> 8) - R);
             if ((unsigned)bx >= (unsigned)m || (unsigned)by >= (unsigned)m || (unsigned)bz >= (unsigned)m)
                 continue;
             const int kb = (bz * m + by) * m + bx;
@@ -562,19 +571,36 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     // join units of this cell: first friend pair wins.  The nearest shell goes first; when
     // it already leaves one component (the usual case inside a clump) the rest is skipped.
     const int noff = L.noff, nnear = L.nnear;
-    join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 0, nnear);
+    join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 0, nnear, false);
     Grp<G>::sync();
-    if (t == 0)
+    // components after the nearest shell: a far pair of two different components has at
+    // least one end outside the largest one, so only those units search the far offsets
+    if (t == 0) {
         L.ncomp = 0;
+        L.giant = 0;
+    }
+    for (int r = t; r < u; r += G)
+        L.umark[r] = 0;
     Grp<G>::sync();
     for (int r = t; r < u; r += G) {
         const int root = lfind(L.uf, r);
+        atomicAdd(&L.umark[root], 1);
         if (root == r)
             atomicAdd(&L.ncomp, 1);
     }
     Grp<G>::sync();
-    if (L.ncomp > 1)  // uniform: every thread reads the same count
-        join_units<G>(w, B, P, cc, m, R, u, s, mem, L, nnear, noff);
+    for (int r = t; r < u; r += G)
+        if (L.umark[r])
+            atomicMax(&L.giant, (L.umark[r] << 16) | r);  // unit count < 2^15, r < 2^16
+    Grp<G>::sync();
+    const bool far = L.ncomp > 1;  // uniform: every thread reads the same count
+    if (far) {
+        const int giant = L.giant & 0xFFFF;
+        for (int r = t; r < u; r += G)
+            L.umark[r] = lfind(L.uf, r) != giant;
+        Grp<G>::sync();
+        join_units<G>(w, B, P, cc, m, R, u, s, mem, L, nnear, noff, true);
+    }
     Grp<G>::sync();
     if (t == 0)
         L.ncomp = 0;
