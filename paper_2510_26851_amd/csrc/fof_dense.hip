@@ -322,7 +322,6 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_sort(Work w)
 // block, each with its own LDS slice); larger cells by a whole block.  The code is shared
 // through the group type G.
 // ---------------------------------------------------------------------------------------
-constexpr int kMaxOffsets = (7 * 7 * 7 - 1) / 2;  // forward offsets for R <= 3
 
 template <int G>
 struct Grp;
@@ -358,9 +357,8 @@ struct CellLds {
     short ucomp[UMAX];              // component number of each unit
     uint32_t bits[kMaxTableWords];  // key bitmask of the cell (or of a neighbour, in cross)
     int pre[kMaxTableWords];
-    short offs[kMaxOffsets];        // forward fine offsets: (dx+R) | (dy+R) << 4 | (dz+R) << 8
     uint32_t pairbits[32];
-    int noff, nnear, ncomp, nnb, done, giant;
+    int ncomp, nnb, done, giant;
     int nb[26];                     // neighbour dense ids (cross), or sparse cell starts
     short nbo[26];                  // their offsets: (ox+1) | (oy+1) << 2 | (oz+1) << 4
     int nbp[27];                    // sparse neighbours: running particle count
@@ -474,39 +472,71 @@ __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n
     Grp<G>::sync();
 }
 
-// Joins each unit r of the staged cell with the units at forward offsets [q0, q1): a pair
-// already in one component is skipped, otherwise its first friend pair (if any) joins it.
-// With `marked_only`, only units with a nonzero mark take part, each with the offsets in
-// both directions (a pair with one unmarked end is then still examined from the other).
+// Joins units of the staged cell with their neighbour units.  pass 0: every unit, the
+// forward half of the nearest shell (offsets in [-1, 1]^3).  pass 1: marked units only,
+// every offset in [-R, R]^3 outside the nearest shell, in both directions (a pair with an
+// unmarked end is then still examined from the other).  The occupied neighbours of one
+// fine row are read as a bit field of the key bitmask, so empty fine cells cost nothing.
+// A pair already in one component is skipped, otherwise its first friend pair joins it.
 template <int G, int UMAX, int CAP>
 __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const CellXYZ &cc,
                            int m, int R, int u, int32_t s, const float4 *mem,
-                           CellLds<UMAX, CAP> &L, int q0, int q1, bool marked_only)
+                           CellLds<UMAX, CAP> &L, int pass)
 {
-    const int nq = marked_only ? 2 * (q1 - q0) : q1 - q0;
+    const int W = w.table_words;
+    const int reach = pass == 0 ? 1 : R;
     for (int r = Grp<G>::tid(); r < u; r += G) {
-        if (marked_only && !L.umark[r])
+        if (pass == 1 && !L.umark[r])
             continue;
         const int xyz = L.uxyz[r];
         const int ax = xyz & 15, ay = (xyz >> 4) & 15, az = xyz >> 8;
-        for (int qq = 0; qq < nq; ++qq) {
-            const int o = L.offs[q0 + (qq >> (marked_only ? 1 : 0))];
-            const int sg = (marked_only && (qq & 1)) ? -1 : 1;  // odd: the opposite offset
-            const int bx = ax + sg * ((o & 15) - R), by = ay + sg * (((o >> 4) & 15) - R),
-                      bz = az + sg * ((o >> 8) - R);
-            if ((unsigned)bx >= (unsigned)m || (unsigned)by >= (unsigned)m || (unsigned)bz >= (unsigned)m)
+        for (int dz = -reach; dz <= reach; ++dz) {
+            const int bz = az + dz;
+            if (bz < 0 || bz >= m)
                 continue;
-            const int kb = (bz * m + by) * m + bx;
-            if (!((L.bits[kb >> 5] >> (kb & 31)) & 1u))
-                continue;
-            const int rb = rank_in(L.bits, L.pre, kb);
-            if (lfind(L.uf, r) == lfind(L.uf, rb))
-                continue;
-            const FineBox fb = fine_box(B, cc.x * m + bx, cc.y * m + by, cc.z * m + bz);
-            FOF_STAT(w.ctr, ST_CC_UNIT_PAIRS, 1);
-            if (units_meet(B, P, mem, L.ustart[r] - s, L.ustart[r + 1] - s, mem, L.ustart[rb] - s,
-                           L.ustart[rb + 1] - s, fb))
-                lunion(L.uf, r, rb);
+            for (int dy = -reach; dy <= reach; ++dy) {
+                const int by = ay + dy;
+                if (by < 0 || by >= m)
+                    continue;
+                int lo = -reach, hi = reach;  // dx range of this row
+                bool skip_core = false;       // drop dx in [-1, 1] (pass 1, near rows)
+                if (pass == 0) {
+                    if (dz < 0 || (dz == 0 && dy < 0))
+                        continue;  // backward rows
+                    if (dz == 0 && dy == 0)
+                        lo = 1;
+                } else {
+                    skip_core = dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+                }
+                lo = max(lo, -ax);
+                hi = min(hi, m - 1 - ax);
+                if (lo > hi)
+                    continue;
+                const int key0 = (bz * m + by) * m + ax + lo, nb = hi - lo + 1;
+                const int w0 = key0 >> 5, sh = key0 & 31;
+                uint64_t v = L.bits[w0];
+                if (sh + nb > 32 && w0 + 1 < W)
+                    v |= (uint64_t)L.bits[w0 + 1] << 32;
+                uint32_t row = (uint32_t)(v >> sh) & ((1u << nb) - 1u);
+                if (skip_core)  // positions of dx = -1, 0, 1 relative to lo
+                    for (int dx = -1; dx <= 1; ++dx)
+                        if (dx >= lo && dx <= hi)
+                            row &= ~(1u << (dx - lo));
+                while (row) {
+                    const int bpos = __ffs(row) - 1;
+                    row &= row - 1u;
+                    const int bx = ax + lo + bpos;
+                    const int kb = key0 + bpos;
+                    const int rb = rank_in(L.bits, L.pre, kb);
+                    if (lfind(L.uf, r) == lfind(L.uf, rb))
+                        continue;
+                    const FineBox fb = fine_box(B, cc.x * m + bx, cc.y * m + by, cc.z * m + bz);
+                    FOF_STAT(w.ctr, ST_CC_UNIT_PAIRS, 1);
+                    if (units_meet(B, P, mem, L.ustart[r] - s, L.ustart[r + 1] - s, mem,
+                                   L.ustart[rb] - s, L.ustart[rb + 1] - s, fb))
+                        lunion(L.uf, r, rb);
+                }
+            }
         }
     }
 }
@@ -526,35 +556,10 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     const int u = T[2];
     const float4 *mem = n <= CAP ? L.part : w.sorted + s;  // indexed by (sorted index - s)
 
-    if (t == 0) {
+    if (t == 0)
         L.ncomp = 0;
-        L.noff = 0;
-    }
     load_units<G>(w, T, s, n, m, u, L);
 
-    // forward offsets in [-R, R]^3 that survive gap pruning, nearest shell first
-    const int side = 2 * R + 1, half = (side * side * side - 1) / 2;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int q0 = 0; q0 < half; q0 += G) {
-            const int q = half + 1 + q0 + t;
-            bool keep = false;
-            int packed = 0;
-            if (q0 + t < half) {
-                const int dx = q % side, dy = (q / side) % side, dz = q / (side * side);
-                const int cheb = max(abs(dx - R), max(abs(dy - R), abs(dz - R)));
-                const double gx = fmax(0.0, (double)(abs(dx - R) - 1)) * B.fine_side;
-                const double gy = fmax(0.0, (double)(abs(dy - R) - 1)) * B.fine_side;
-                const double gz = fmax(0.0, (double)(abs(dz - R) - 1)) * B.fine_side;
-                keep = gx * gx + gy * gy + gz * gz < B.b2 && ((cheb <= 1) == (pass == 0));
-                packed = dx | (dy << 4) | (dz << 8);
-            }
-            if (keep)
-                L.offs[atomicAdd(&L.noff, 1)] = (short)packed;
-        }
-        Grp<G>::sync();
-        if (pass == 0 && t == 0)
-            L.nnear = L.noff;  // offsets [0, nnear) are the nearest shell
-    }
     // unit minima
     for (int r = t; r < u; r += G) {
         unsigned long long best = ~0ull;
@@ -570,8 +575,7 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
 
     // join units of this cell: first friend pair wins.  The nearest shell goes first; when
     // it already leaves one component (the usual case inside a clump) the rest is skipped.
-    const int noff = L.noff, nnear = L.nnear;
-    join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 0, nnear, false);
+    join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 0);
     Grp<G>::sync();
     // components after the nearest shell: a far pair of two different components has at
     // least one end outside the largest one, so only those units search the far offsets
@@ -599,7 +603,7 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
         for (int r = t; r < u; r += G)
             L.umark[r] = lfind(L.uf, r) != giant;
         Grp<G>::sync();
-        join_units<G>(w, B, P, cc, m, R, u, s, mem, L, nnear, noff, true);
+        join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 1);
     }
     Grp<G>::sync();
     if (t == 0)
