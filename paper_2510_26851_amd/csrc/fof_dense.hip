@@ -472,6 +472,30 @@ __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n
     Grp<G>::sync();
 }
 
+// Occupancy bits of fine keys [key0, key0 + nb) (nb <= 31) of a key bitmask in LDS
+// holding W words: bit i of the result is key key0 + i.
+__device__ __forceinline__ uint32_t row_bits(const uint32_t *bits, int W, int key0, int nb)
+{
+    const int w0 = key0 >> 5, sh = key0 & 31;
+    uint64_t v = bits[w0];
+    if (sh + nb > 32 && w0 + 1 < W)
+        v |= (uint64_t)bits[w0 + 1] << 32;
+    return (uint32_t)(v >> sh) & ((1u << nb) - 1u);
+}
+
+// Largest S with S fs^2 < b^2 (slightly below, so that pruning by it stays conservative):
+// fine cells whose squared gap, in whole fine cells per axis, exceeds S hold no friend.
+__device__ __forceinline__ int gap_budget(const BoxDesc &B)
+{
+    const double fs2 = (double)B.fine_side * (double)B.fine_side * (1.0 - 1e-12);
+    int K = (int)(B.b2 / fs2);
+    while (K > 0 && (double)K * fs2 >= B.b2)
+        --K;
+    while ((double)(K + 1) * fs2 < B.b2)
+        ++K;
+    return K;
+}
+
 // Joins units of the staged cell with their neighbour units.  pass 0: every unit, the
 // forward half of the nearest shell (offsets in [-1, 1]^3).  pass 1: marked units only,
 // every offset in [-R, R]^3 outside the nearest shell, in both directions (a pair with an
@@ -513,11 +537,7 @@ __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const
                 if (lo > hi)
                     continue;
                 const int key0 = (bz * m + by) * m + ax + lo, nb = hi - lo + 1;
-                const int w0 = key0 >> 5, sh = key0 & 31;
-                uint64_t v = L.bits[w0];
-                if (sh + nb > 32 && w0 + 1 < W)
-                    v |= (uint64_t)L.bits[w0 + 1] << 32;
-                uint32_t row = (uint32_t)(v >> sh) & ((1u << nb) - 1u);
+                uint32_t row = row_bits(L.bits, W, key0, nb);
                 if (skip_core)  // positions of dx = -1, 0, 1 relative to lo
                     for (int dx = -1; dx <= 1; ++dx)
                         if (dx >= lo && dx <= hi)
@@ -654,6 +674,7 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     const int W = w.table_words;
     const int32_t *T = w.table + (int64_t)d * w.table_stride;
     const int u = T[2], ncomp = T[1];
+    const int K = gap_budget(B);
 
     // neighbour dense cells with a higher index: this cell handles those pairs
     if (t == 0)
@@ -724,6 +745,18 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
             L.pairbits[q] = 0u;
         if (t == 0)
             L.done = 0;
+        // the neighbour's unit components and member starts, in LDS when they fit
+        const bool staged2 = u2 < UMAX;
+        int *ncomp_of = L.umark;
+        int *nstart = reinterpret_cast<int *>(L.umin);  // 2 * UMAX ints
+        if (staged2) {
+            for (int q = t; q < u2; q += G) {
+                ncomp_of[q] = w.cnt[s2 + q];
+                nstart[q] = w.rank[s2 + q];
+            }
+            if (t == 0)
+                nstart[u2] = s2 + n2;
+        }
         Grp<G>::sync();
         for (int r = t; r < u; r += G) {
             if (__hip_atomic_load(&L.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
@@ -732,28 +765,38 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
             // unit r in the frame of the neighbour cell
             const int rx = (xyz & 15) - ox * m, ry = ((xyz >> 4) & 15) - oy * m,
                       rz = (xyz >> 8) - oz * m;
-            const int x0 = max(0, rx - R), x1 = min(m - 1, rx + R);
-            const int y0 = max(0, ry - R), y1 = min(m - 1, ry + R);
-            const int z0 = max(0, rz - R), z1 = min(m - 1, rz + R);
             bool stop = false;
-            for (int bz = z0; bz <= z1 && !stop; ++bz)
-                for (int by = y0; by <= y1 && !stop; ++by)
-                    for (int bx = x0; bx <= x1 && !stop; ++bx) {
-                        const double gx = fmax(0.0, (double)(abs(bx - rx) - 1)) * B.fine_side;
-                        const double gy = fmax(0.0, (double)(abs(by - ry) - 1)) * B.fine_side;
-                        const double gz = fmax(0.0, (double)(abs(bz - rz) - 1)) * B.fine_side;
-                        if (gx * gx + gy * gy + gz * gz >= B.b2)
-                            continue;
-                        const int kb = (bz * m + by) * m + bx;
-                        if (!((L.bits[kb >> 5] >> (kb & 31)) & 1u))
-                            continue;
-                        const int rb = rank_in(L.bits, L.pre, kb);
-                        const int cb = w.cnt[s2 + rb];
+            for (int dz = -R; dz <= R && !stop; ++dz) {
+                const int bz = rz + dz;
+                if (bz < 0 || bz >= m)
+                    continue;
+                const int kz = max(0, abs(dz) - 1);
+                for (int dy = -R; dy <= R && !stop; ++dy) {
+                    const int by = ry + dy;
+                    if (by < 0 || by >= m)
+                        continue;
+                    const int ky = max(0, abs(dy) - 1);
+                    const int rem = K - kz * kz - ky * ky;
+                    if (rem < 0)
+                        continue;  // this row lies b or more from unit r
+                    const int span = min(R, (int)sqrtf((float)rem) + 1);
+                    const int lo = max(-span, -rx), hi = min(span, m - 1 - rx);
+                    if (lo > hi)
+                        continue;
+                    const int key0 = (bz * m + by) * m + rx + lo;
+                    uint32_t row = row_bits(L.bits, W, key0, hi - lo + 1);
+                    while (row && !stop) {
+                        const int bpos = __ffs(row) - 1;
+                        row &= row - 1u;
+                        const int bx = rx + lo + bpos;
+                        const int rb = rank_in(L.bits, L.pre, key0 + bpos);
+                        const int cb = staged2 ? ncomp_of[rb] : w.cnt[s2 + rb];
                         const int bit = L.ucomp[r] * ncomp2 + cb;
                         if (dedupe && ((L.pairbits[bit >> 5] >> (bit & 31)) & 1u))
                             continue;
-                        const int32_t b0 = w.rank[s2 + rb];
-                        const int32_t b1 = rb + 1 < u2 ? w.rank[s2 + rb + 1] : s2 + n2;
+                        const int32_t b0 = staged2 ? nstart[rb] : w.rank[s2 + rb];
+                        const int32_t b1 = staged2 ? nstart[rb + 1]
+                                                   : (rb + 1 < u2 ? w.rank[s2 + rb + 1] : s2 + n2);
                         // unit B's box in the own cell's periodic frame
                         const FineBox fb = fine_box(B, (cc.x + ox) * m + bx, (cc.y + oy) * m + by,
                                                     (cc.z + oz) * m + bz);
@@ -780,6 +823,8 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
                             }
                         }
                     }
+                }
+            }
         }
         Grp<G>::sync();
     }
@@ -876,12 +921,13 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
         bool any = false;
         uint64_t seen = 0;  // components (numbers < 64) already joined
         for (int bz = z0; bz <= z1; ++bz)
-            for (int by = y0; by <= y1; ++by)
-                for (int bx = x0; bx <= x1; ++bx) {
-                    const int kb = (bz * m + by) * m + bx;
-                    if (!((L.bits[kb >> 5] >> (kb & 31)) & 1u))
-                        continue;
-                    const int rb = rank_in(L.bits, L.pre, kb);
+            for (int by = y0; by <= y1 && x0 <= x1; ++by) {
+                const int key0 = (bz * m + by) * m + x0;
+                uint32_t row = row_bits(L.bits, W, key0, x1 - x0 + 1);
+                while (row) {
+                    const int bpos = __ffs(row) - 1;
+                    row &= row - 1u;
+                    const int rb = rank_in(L.bits, L.pre, key0 + bpos);
                     const int comp = L.ucomp[rb];
                     if (comp < 64 && ((seen >> comp) & 1ull))
                         continue;
@@ -897,6 +943,7 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
                     if (any && ncomp == 1)
                         goto done;
                 }
+            }
     done:
         if (any)
             atomicOr((unsigned long long *)(w.flags + (j >> 6)), 1ull << (j & 63));
