@@ -69,7 +69,9 @@ typedef struct fof_tune {
                                 0 = default, < 0 = never                                      */
     int32_t block;           /* threads per block for per-particle kernels (multiple of 64)    */
     uint32_t flags;          /* FOF_TUNE_* bits; other bits must be 0                          */
-    int32_t reserved;
+    int32_t link_edges;      /* capacity of the link pass's deferred cross-tile hooks (pairs);
+                                0 = n/4 + 65536.  Tiles that overflow it are relinked with
+                                direct hooks, so it trades memory for time only             */
 } fof_tune;
 
 /* Stochastic linking (paper Sec. 3.2: every potential edge between nearby particles is a
@@ -113,6 +115,7 @@ typedef struct fof_grid {
     int64_t ntiles;       /* link tiles (blocks of the LDS-tiled link kernel)                 */
     int32_t dense_threshold;
     int32_t table_words;  /* 32-bit words of one clique bitmask                               */
+    int64_t link_edges;   /* capacity of the deferred link hooks (pairs)                      */
     size_t ws_bytes;      /* size of the workspace the caller must provide                    */
     size_t desc_bytes;    /* size of the box descriptor block                                 */
     size_t off_desc;      /* where the caller copies the descriptor block (see below)         */

@@ -46,7 +46,7 @@ class fof_box(ctypes.Structure):
 class fof_tune(ctypes.Structure):
     _fields_ = [("cell_side", ctypes.c_double), ("dense_threshold", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32)]
+                ("link_edges", ctypes.c_int32)]
 
 
 class fof_sample(ctypes.Structure):
@@ -61,7 +61,7 @@ class fof_grid(ctypes.Structure):
                 ("ncell", ctypes.c_int64), ("dense_cap", ctypes.c_int64),
                 ("ntiles", ctypes.c_int64),
                 ("dense_threshold", ctypes.c_int32), ("table_words", ctypes.c_int32),
-                ("ws_bytes", ctypes.c_size_t), ("desc_bytes", ctypes.c_size_t),
+                ("link_edges", ctypes.c_int64), ("ws_bytes", ctypes.c_size_t), ("desc_bytes", ctypes.c_size_t),
                 ("off_desc", ctypes.c_size_t)] + [
                    (f, ctypes.c_size_t) for f in (
                        "off_status", "off_counters", "off_cell_count", "off_cell_start",

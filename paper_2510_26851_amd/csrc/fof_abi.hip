@@ -132,7 +132,7 @@ int64_t link_edge_cap(int64_t n)
 }
 
 Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t words,
-              int64_t ntiles)
+              int64_t ntiles, int64_t link_edges)
 {
     Layout L;
     size_t o = 0;
@@ -161,7 +161,7 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
     L.off_table = take(sizeof(int32_t) * (size_t)dense_cap * (size_t)table_stride(words));
     L.off_temp = take(dense_cap > 0 ? sizeof(float4) * (size_t)n : 0);
     L.off_tiles = take(sizeof(int32_t) * (size_t)ntiles);
-    L.edge_cap = ntiles > 0 ? link_edge_cap(n) : 0;
+    L.edge_cap = ntiles > 0 ? link_edges : 0;
     L.off_edges = take(sizeof(int2) * (size_t)L.edge_cap);
     L.off_cursors = take(dense_cap > 0 ? sizeof(int32_t) * (size_t)kCursorInts : 0);
     L.total = o;
@@ -171,13 +171,15 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
 bool ws_ok(const fof_grid *g, const void *ws)
 {
     return g && ws && ((uintptr_t)ws % kAlign) == 0 && g->nbox >= 1 && g->n >= 0 &&
+           g->link_edges >= 0 && g->link_edges <= INT32_MAX &&
            g->block >= kWave && g->block % kWave == 0 && g->block <= 1024;
 }
 
 Work resolve(const fof_grid *g, void *ws)
 {
     char *base = (char *)ws;
-    Layout L = layout(g->nbox, g->n, g->ncell, g->dense_cap, g->table_words, g->ntiles);
+    Layout L = layout(g->nbox, g->n, g->ncell, g->dense_cap, g->table_words, g->ntiles,
+                      g->link_edges);
     Work w;
     w.desc = (const BoxDesc *)(base + L.off_desc);
     w.ctr = (Counters *)(base + L.off_status);
@@ -239,7 +241,8 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
 {
     if (nbox < 1 || !count || !box || !grid)
         return FOF_EINVAL;
-    if (tune && ((tune->flags & ~FOF_TUNE_NO_TILES) != 0 || tune->block < 0 || (tune->block % kWave) != 0 ||
+    if (tune && ((tune->flags & ~FOF_TUNE_NO_TILES) != 0 || tune->link_edges < 0 ||
+                 tune->block < 0 || (tune->block % kWave) != 0 ||
                  tune->block > 1024 || !(tune->cell_side >= 0.0)))
         return FOF_EINVAL;
     int64_t n = 0, ncell = 0, ntiles = 0;
@@ -285,7 +288,9 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
     }
     if (thr <= 0)
         thr = -1;
-    Layout L = layout(nbox, n, ncell, dense_cap, words, ntiles);
+    const int64_t link_edges =
+        (tune && tune->link_edges > 0) ? (int64_t)tune->link_edges : link_edge_cap(n);
+    Layout L = layout(nbox, n, ncell, dense_cap, words, ntiles, link_edges);
     memset(grid, 0, sizeof(*grid));
     grid->nbox = nbox;
     grid->block = (tune && tune->block) ? tune->block : kDefaultBlock;
@@ -293,6 +298,7 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
     grid->ncell = ncell;
     grid->dense_threshold = thr;
     grid->ntiles = ntiles;
+    grid->link_edges = link_edges;
     grid->dense_cap = dense_cap;
     grid->table_words = words;
     grid->ws_bytes = L.total;

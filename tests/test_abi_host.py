@@ -156,6 +156,19 @@ def test_plan_rejects_bad_tune():
     t.flags = 2       # unknown flag bit
     rc, _, _ = plan([10], [(10.0, 0.4)], tune=t, desc=False)
     assert rc == _lib.FOF_EINVAL
+    t = _lib.fof_tune()
+    t.link_edges = -1
+    rc, _, _ = plan([10], [(10.0, 0.4)], tune=t, desc=False)
+    assert rc == _lib.FOF_EINVAL
+
+
+def test_link_edge_capacity_sets_the_workspace():
+    t = _lib.fof_tune()
+    rc, g0, _ = plan([40000], [(40.0, 0.4)], tune=t, desc=False)
+    assert rc == 0 and g0.link_edges == 40000 // 4 + 65536
+    t.link_edges = 5
+    rc, g1, _ = plan([40000], [(40.0, 0.4)], tune=t, desc=False)
+    assert rc == 0 and g1.link_edges == 5 and g1.ws_bytes < g0.ws_bytes
 
 
 def test_no_tiles_flag_clears_the_tiled_bit():

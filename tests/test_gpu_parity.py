@@ -174,3 +174,15 @@ def test_autotuner_choice_does_not_change_results(tmp_path):
     assert autotune(pos, box.L, box.b, box.min_size, cache=str(tmp_path / "tune.json")) == tune
     root_ref, _ = oracle.fof(box.pos, box.L, box.b)
     compare_with_oracle(box.pos, box.L, box.b, box.min_size, tune=tune, root_ref=root_ref)
+
+
+@pytest.mark.parametrize("tune", [
+    dict(dense_threshold=-1, cell_side=0.68),   # halos over the LDS cap, z-windows that fit
+    dict(dense_threshold=-1, cell_side=2.0),    # single z-layers too full: global search
+    dict(link_edges=1),                         # deferred hooks overflow: tiles relinked
+    dict(link_edges=1, dense_threshold=8),
+])
+def test_overflow_paths_of_the_tiled_link(tune):
+    say(f"overflow paths {tune}")
+    pos = W.clumpy_box(100000, 20.0, 30, 41)
+    compare_with_oracle(pos, 20.0, 0.3, 5, tune=tune)
