@@ -8,7 +8,8 @@
 //   g_count    cnt[root] += 1 for flagged i
 //   g_keep     set keep bit [label] for kept components (size >= min_size)
 //   scan       popcount prefix over the keep bitmap -> group id = rank of the label
-//   g_assign   group_id[orig] for everyone; per kept group: size, root slot, and the
+//   g_assign   group_id[orig] (with min_size > 1 only for particles with a friend, the
+//              rest is filled with -1 first); per kept group: size, root slot, and the
 //              moment accumulators cleared (singleton groups are finished here)
 //   g_sum      FP64 sums of minimum-image offsets from the root and of velocities
 //   g_mean     com = wrap(x_root + sum / n), vmean = vsum / n
@@ -104,8 +105,11 @@ __global__ void g_keep(const float4 *__restrict__ sorted, int64_t n,
     int64_t i = gtid();
     if (i >= n)
         return;
+    const bool fl = flagged(flags, i);
+    if (!fl && min_size > 1)
+        return;  // a particle without a friend is a group of one
     int32_t size;
-    if (flagged(flags, i)) {
+    if (fl) {
         if (uf_idx(parent[i]) != (uint32_t)i)
             return;  // not a root
         size = cnt[i];
@@ -118,20 +122,25 @@ __global__ void g_keep(const float4 *__restrict__ sorted, int64_t n,
     }
 }
 
+// With skip_lonely, group_id was filled with -1 beforehand (groups of one are cut) and
+// particles without a friend leave after reading their flag bit.
 __global__ void g_assign(const float4 *__restrict__ sorted, int64_t n,
                          const uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
                          const int32_t *__restrict__ cnt, const uint32_t *__restrict__ keep,
                          const int32_t *__restrict__ keep_prefix, const float *__restrict__ vel,
-                         int32_t cap, int32_t *__restrict__ group_id, int32_t *__restrict__ groot,
-                         int32_t *__restrict__ sizes, double *__restrict__ com,
-                         double *__restrict__ vmean, double *__restrict__ sigv)
+                         int32_t cap, bool skip_lonely, int32_t *__restrict__ group_id,
+                         int32_t *__restrict__ groot, int32_t *__restrict__ sizes,
+                         double *__restrict__ com, double *__restrict__ vmean,
+                         double *__restrict__ sigv)
 {
     int64_t i = gtid();
     if (i >= n)
         return;
+    const bool fl = flagged(flags, i);
+    if (!fl && skip_lonely)
+        return;
     const float4 p = sorted[i];
     const int32_t orig = __float_as_int(p.w);
-    const bool fl = flagged(flags, i);
     const uint32_t rs = fl ? uf_idx(parent[i]) : (uint32_t)i;
     const uint32_t label = fl ? uf_key(parent[i]) : (uint32_t)orig;
     const int32_t g = group_of(keep, keep_prefix, label);
@@ -329,9 +338,15 @@ hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int3
     hipLaunchKernelGGL(g_total, dim3(1), dim3(64), 0, s, w.keep_prefix, nwords, n_groups);
     if (w.n == 0)
         return hipGetLastError();
+    const bool skip_lonely = min_size > 1;
+    if (skip_lonely) {
+        e = launch_fill_i32(group_id, w.n, -1, s);
+        if (e != hipSuccess)
+            return e;
+    }
     hipLaunchKernelGGL(g_assign, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent, w.flags,
-                       w.cnt, w.keep, w.keep_prefix, vel, cap, group_id, w.groot, sizes, com,
-                       vmean, sigv);
+                       w.cnt, w.keep, w.keep_prefix, vel, cap, skip_lonely, group_id, w.groot,
+                       sizes, com, vmean, sigv);
     if (cap <= 0)
         return hipGetLastError();
     const unsigned gb = (unsigned)((cap + 255) / 256);
