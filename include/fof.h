@@ -86,7 +86,7 @@ typedef struct fof_sample {
     double b;           /* linking length of the probability                                   */
     double tau;         /* temperature, > 0                                                    */
     uint64_t seed;
-    int32_t K;          /* sampled graphs, >= 1                                                */
+    int32_t K;          /* sampled graphs, 1 <= K <= 65535                                     */
     int32_t edge_cap;   /* capacity of ei, ej, d2                                              */
     int32_t *ei, *ej;   /* [edge_cap] candidate edges (original indices, ei < ej), any order   */
     double *d2;         /* [edge_cap] squared minimum-image distances                          */

@@ -5,16 +5,18 @@
 // z_e = (b - d_e)/tau.  The neighbour structure is built once and reused by all K samples,
 // as the paper does ("we do not rebuild the neighbor list").
 //
-//   k_edges        candidate search (same grid and predicate form as the hard link, with
+//   k_edges(_tiled) candidate search (the hard link's grid, LDS tiles and predicate, with
 //                  the cut radius), edges as original indices i < j, their squared distance
 //                  and sorted positions
 //   k_touch, scan  compact the particles that touch an edge: one union-find per sample over
 //                  those only, in original-index order
 //   k_sample_union one thread per (edge, sample): Philox uniform, keep, hook
-//   k_sample_label labels of every particle in every sample (smallest member index)
+//   k_sample_label labels of every particle in every sample (smallest member index): a
+//                  stream of identity labels, then the particles that touch an edge
 //   k_score        per edge: w_e = (1/K) sum_s adv_s (y_es - p_e), scattered as
 //                  -+ w_e (x_i - x_j)/(tau d_e) into the position gradient
 #include "fof_internal.h"
+#include "fof_tile.h"
 
 namespace fof {
 
@@ -83,6 +85,23 @@ __device__ __forceinline__ int32_t edge_count(const SampleArgs &a)
     return m < a.edge_cap ? m : a.edge_cap;
 }
 
+constexpr int kBlockEdges = 128;  // edges a tile block collects before writing them out
+
+__device__ __forceinline__ void emit_edge(const Work &w, const SampleArgs &a, int32_t oi,
+                                          int32_t oj, double s2, int32_t si, int32_t sj)
+{
+    const int32_t k = atomicAdd(a.n_edges, 1);
+    if (k < a.edge_cap) {
+        a.ei[k] = oi;
+        a.ej[k] = oj;
+        a.d2[k] = s2;
+        a.si[k] = si;
+        a.sj[k] = sj;
+    } else {
+        atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_EDGE_CAP);
+    }
+}
+
 __device__ void edges_of(const Work &w, const SampleArgs &a, int64_t i)
 {
     const BoxDesc &B = w.desc[0];
@@ -110,18 +129,122 @@ __device__ void edges_of(const Work &w, const SampleArgs &a, int64_t i)
                     const double s2 = dist2(B, p.x, p.y, p.z, q.x, q.y, q.z);
                     if (!(s2 < B.b2))
                         continue;
-                    const int32_t k = atomicAdd(a.n_edges, 1);
-                    if (k < a.edge_cap) {
-                        a.ei[k] = oi;
-                        a.ej[k] = oj;
-                        a.d2[k] = s2;
-                        a.si[k] = (int32_t)i;
-                        a.sj[k] = j;
+                    emit_edge(w, a, oi, oj, s2, (int32_t)i, j);
+                }
+            }
+        }
+    }
+}
+
+// Candidate edges of one tile (box with LDS tiles): the tile and its halo are staged
+// (every cell, clique tables are not used here) and each own particle tests the LDS ranges
+// of the neighbour rows its position can reach.  The exact double squared distance is
+// computed for the pairs the (exact) predicate accepts.  A tile whose halo does not fit
+// searches its own particles from global memory.
+__global__ __launch_bounds__(kTileBlock) void k_edges_tiled(Work w, SampleArgs a)
+{
+    __shared__ float4 part[kTileCap];
+    __shared__ int hoff[kHalo + 1];
+    __shared__ int gst[kHalo];
+    __shared__ int ownoff[kOwnRows + 1];
+    __shared__ int scr[kTileBlock / kWave];
+    // edges of this block, written out with one counter update (one global counter bumped
+    // by every edge would serialize)
+    __shared__ int lei[kBlockEdges], lej[kBlockEdges], lsi[kBlockEdges], lsj[kBlockEdges];
+    __shared__ double ld2[kBlockEdges];
+    __shared__ int lcnt, lbase;
+
+    const int64_t tile = xcd_block();
+    if (tile >= w.ntiles)
+        return;
+    const BoxDesc &B = uniform_box(w.desc, 0);  // sampling plans hold one box
+    const Pred P = pred_of(B);
+    const TileGeom g = tile_geom(B, tile);
+    const int t = threadIdx.x;
+    const int total = build_halo(w, B, g, false, hoff, gst, scr);
+    if (t <= kOwnRows) {  // own particles before each own row
+        int acc = 0;
+        for (int r = 0; r < t; ++r) {
+            const int hx = 1 + r / kTileY, hy = 1 + r % kTileY;
+            const int rb = (hx * kHY + hy) * kHZ;
+            if (hx < g.hxe && hy < g.hye)
+                acc += hoff[rb + g.hze] - hoff[rb + 1];
+        }
+        ownoff[t] = acc;
+    }
+    const bool staged = total <= kTileCap;  // block-uniform
+    if (t == 0)
+        lcnt = 0;
+    if (staged) {
+#pragma unroll
+        for (int k = 0; k < kStagePerT; ++k) {
+            const int sl = t + k * kTileBlock;
+            if (sl < total) {
+                const int h = last_le<kHalo>(hoff, sl);
+                part[sl] = w.sorted[gst[h] + (sl - hoff[h])];
+            }
+        }
+    }
+    __syncthreads();
+    const int nown = ownoff[kOwnRows];
+    for (int k = t; k < nown; k += kTileBlock) {
+        int r = 0;
+        while (ownoff[r + 1] <= k)
+            ++r;
+        const int rb = ((1 + r / kTileY) * kHY + 1 + r % kTileY) * kHZ;
+        const int slot = hoff[rb + 1] + (k - ownoff[r]);
+        const int hs = rb + 1 + last_le<kTileZ>(hoff + rb + 1, slot);
+        const int64_t i = gst[hs] + (slot - hoff[hs]);
+        if (!staged) {
+            edges_of(w, a, i);
+            continue;
+        }
+        const float4 p = part[slot];
+        const int32_t oi = __float_as_int(p.w);
+        const int hz = hs % kHZ, hy = (hs / kHZ) % kHY, hx = hs / (kHZ * kHY);
+        const AxisSpan sx = axis_span(p.x, g.x0 - 1 + hx, B.side[0], B.nc[0], B.reach);
+        const AxisSpan sy = axis_span(p.y, g.y0 - 1 + hy, B.side[1], B.nc[1], B.reach);
+        const AxisSpan sz = axis_span(p.z, g.z0 - 1 + hz, B.side[2], B.nc[2], B.reach);
+        for (int ox = sx.lo; ox <= sx.hi; ++ox)
+            for (int oy = sy.lo; oy <= sy.hi; ++oy) {
+                const int rb2 = ((hx + ox) * kHY + hy + oy) * kHZ;
+                const int j0 = hoff[rb2 + hz + sz.lo], j1 = hoff[rb2 + hz + sz.hi + 1];
+                for (int j = j0; j < j1; ++j) {
+                    const float4 q = part[j];
+                    const int32_t oj = __float_as_int(q.w);
+                    if (oj <= oi || !linked(P, p.x, p.y, p.z, q.x, q.y, q.z))
+                        continue;  // each unordered pair once, from its lower index
+                    const double s2 = dist2(B, p.x, p.y, p.z, q.x, q.y, q.z);
+                    const int hj = rb2 + last_le<kHZ>(hoff + rb2, j);
+                    const int32_t sj = gst[hj] + (j - hoff[hj]);
+                    const int l = atomicAdd(&lcnt, 1);
+                    if (l < kBlockEdges) {
+                        lei[l] = oi;
+                        lej[l] = oj;
+                        ld2[l] = s2;
+                        lsi[l] = (int32_t)i;
+                        lsj[l] = sj;
                     } else {
-                        atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_EDGE_CAP);
+                        emit_edge(w, a, oi, oj, s2, (int32_t)i, sj);
                     }
                 }
             }
+    }
+    __syncthreads();
+    const int nl = min(lcnt, kBlockEdges);
+    if (t == 0)
+        lbase = nl ? atomicAdd(a.n_edges, nl) : 0;
+    __syncthreads();
+    for (int l = t; l < nl; l += kTileBlock) {
+        const int k2 = lbase + l;
+        if (k2 < a.edge_cap) {
+            a.ei[k2] = lei[l];
+            a.ej[k2] = lej[l];
+            a.d2[k2] = ld2[l];
+            a.si[k2] = lsi[l];
+            a.sj[k2] = lsj[l];
+        } else {
+            atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_EDGE_CAP);
         }
     }
 }
@@ -154,8 +277,9 @@ __global__ void k_forest_init(int64_t n, SampleArgs a)
 {
     const int64_t nv = a.vmap[n];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = gtid(); t < (int64_t)a.K * nv; t += stride)
-        a.forest[(t / nv) * a.vcap + t % nv] = (int32_t)(t % nv);
+    for (int64_t v = gtid(); v < nv; v += stride)
+        for (int32_t s = 0; s < a.K; ++s)
+            a.forest[(int64_t)s * a.vcap + v] = (int32_t)v;
 }
 
 __device__ __forceinline__ int32_t ffind(const int32_t *f, int32_t x)
@@ -187,28 +311,42 @@ __device__ __forceinline__ void funion(int32_t *f, int32_t a, int32_t b)
     }
 }
 
+// Samples [kSampleChunk * blockIdx.y, + kSampleChunk) of one item per thread: the item's
+// data is read once per chunk, and chunks keep enough threads for the union latencies.
+constexpr int kSampleChunk = 8;
+
 __global__ void k_sample_union(SampleArgs a)
 {
     const int64_t m = edge_count(a), stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = gtid(); t < m * a.K; t += stride) {
-        const int32_t e = (int32_t)(t % m), s = (int32_t)(t / m);
+    const int32_t s0 = (int32_t)blockIdx.y * kSampleChunk, s1 = min(s0 + kSampleChunk, a.K);
+    for (int64_t e = gtid(); e < m; e += stride) {
         const int32_t i = a.ei[e], j = a.ej[e];
-        const double u = edge_uniform(a.seed, (uint32_t)s, (uint32_t)i, (uint32_t)j);
-        if (u < edge_prob(a.d2[e], a.b, a.tau))
-            funion(a.forest + (int64_t)s * a.vcap, a.vmap[i], a.vmap[j]);
+        const int32_t vi = a.vmap[i], vj = a.vmap[j];
+        const double p = edge_prob(a.d2[e], a.b, a.tau);
+        for (int32_t s = s0; s < s1; ++s)
+            if (edge_uniform(a.seed, (uint32_t)s, (uint32_t)i, (uint32_t)j) < p)
+                funion(a.forest + (int64_t)s * a.vcap, vi, vj);
     }
+}
+
+// Labels of the K samples in two passes: every particle first gets itself (a coalesced
+// stream; sample blockIdx.y), then the particles that touch a candidate edge, one thread
+// per (particle, sample), get their tree's smallest original index.
+__global__ void k_sample_label_self(int64_t n, int32_t *__restrict__ root)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int32_t *row = root + (int64_t)blockIdx.y * n;
+    for (int64_t i = gtid(); i < n; i += stride)
+        row[i] = (int32_t)i;
 }
 
 __global__ void k_sample_label(int64_t n, SampleArgs a, int32_t *__restrict__ root)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = gtid(); t < n * a.K; t += stride) {
-        const int64_t s = t / n, i = t % n;
-        int32_t lab = (int32_t)i;
-        if (a.vflag[i])
-            lab = a.vlist[ffind(a.forest + s * a.vcap, a.vmap[i])];
-        root[t] = lab;
-    }
+    const int64_t nv = a.vmap[n], stride = (int64_t)gridDim.x * blockDim.x;
+    const int32_t s = (int32_t)blockIdx.y;
+    const int32_t *f = a.forest + (int64_t)s * a.vcap;
+    for (int64_t v = gtid(); v < nv; v += stride)
+        root[(int64_t)s * n + a.vlist[v]] = a.vlist[ffind(f, (int32_t)v)];
 }
 
 // Advantage of each sample: loss minus baseline.
@@ -268,6 +406,14 @@ unsigned blocks_for(int64_t n)
     return (unsigned)(b > 0 ? b : 1);
 }
 
+// Grid of a grid-stride pass over the candidate edges, whose count (at most the capacity)
+// is only known on the device: enough blocks to fill the chip, not one per possible edge.
+unsigned edge_blocks(int64_t cap)
+{
+    const unsigned b = blocks_for(cap);
+    return b < 2048u ? b : 2048u;
+}
+
 }  // namespace
 
 // Scratch layout (256-byte aligned): vflag [n], vmap [n + 1], scan [tiles], vlist [vcap],
@@ -324,20 +470,29 @@ hipError_t launch_sample(const Work &w, const fof_sample &S, int32_t *root, hipS
     if (e != hipSuccess)
         return e;
     if (w.n > 0)
-        hipLaunchKernelGGL(k_edges, dim3(blocks_for(w.n)), dim3(kBlock), 0, s, w, a);
+        if (w.ntiles > 0)
+            hipLaunchKernelGGL(k_edges_tiled, dim3((unsigned)w.ntiles), dim3(kTileBlock), 0, s,
+                               w, a);
+        else
+            hipLaunchKernelGGL(k_edges, dim3(blocks_for(w.n)), dim3(kBlock), 0, s, w, a);
     // edges at most edge_cap: the grid of the following kernels is sized for the cap
-    hipLaunchKernelGGL(k_touch, dim3(blocks_for(S.edge_cap)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_touch, dim3(edge_blocks(S.edge_cap)), dim3(kBlock), 0, s, a);
     e = launch_scan_i32(a.vflag, a.vmap, w.n, a.scan, s);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_vlist, dim3(blocks_for(w.n)), dim3(kBlock), 0, s, w.n, a);
-    hipLaunchKernelGGL(k_forest_init, dim3(blocks_for((int64_t)S.K * a.vcap)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(k_forest_init, dim3(blocks_for(a.vcap)), dim3(kBlock), 0, s,
                        w.n, a);
-    hipLaunchKernelGGL(k_sample_union, dim3(blocks_for((int64_t)S.edge_cap * S.K)), dim3(kBlock), 0,
+    const unsigned chunks = (unsigned)((S.K + kSampleChunk - 1) / kSampleChunk);
+    hipLaunchKernelGGL(k_sample_union, dim3(edge_blocks(S.edge_cap), chunks), dim3(kBlock), 0,
                        s, a);
-    if (root)
-        hipLaunchKernelGGL(k_sample_label, dim3(blocks_for(w.n * S.K)), dim3(kBlock), 0, s, w.n,
-                           a, root);
+    if (root) {
+        const unsigned rows = (unsigned)S.K, nb = blocks_for(w.n);
+        hipLaunchKernelGGL(k_sample_label_self, dim3(nb < 4096u ? nb : 4096u, rows), dim3(kBlock),
+                           0, s, w.n, root);
+        hipLaunchKernelGGL(k_sample_label, dim3(blocks_for(a.vcap), rows), dim3(kBlock), 0, s,
+                           w.n, a, root);
+    }
     return hipGetLastError();
 }
 
@@ -354,7 +509,7 @@ hipError_t launch_score(const Work &w, const fof_sample &S, const double *loss, 
         e = launch_fill_u32((uint32_t *)grad_pos, 3 * w.n, 0u, s);
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_score, dim3(blocks_for(S.edge_cap)), dim3(kBlock), 0, s, w, a,
+        hipLaunchKernelGGL(k_score, dim3(edge_blocks(S.edge_cap)), dim3(kBlock), 0, s, w, a,
                            grad_pos);
     }
     return hipGetLastError();

@@ -213,6 +213,10 @@ def test_entry_points_reject_bad_arguments_before_launch():
     S.scratch_bytes = _lib.sample_scratch_bytes(100, 4, 100)
     S.tau = 0.0                                                                  # tau <= 0
     assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    S.tau, S.K = 0.01, 65536                                                     # K too large
+    S.scratch_bytes = _lib.sample_scratch_bytes(100, 65536, 100)
+    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    S.K, S.tau = 4, 0.0
     assert L.fof_groups(gp, fake_ws, 20, None, 10, None, fake_ws, fake_ws, None, None, None,
                         None) == _lib.FOF_EINVAL                                  # group_id NULL
     assert L.fof_groups(gp, fake_ws, 20, None, -1, fake_ws, fake_ws, fake_ws, None, None, None,
