@@ -116,7 +116,7 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
 struct Layout {
     size_t off_desc, off_status, off_cell_count, off_cell_start, off_scan, off_rank, off_sorted,
         off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, off_dense,
-        off_big, off_table, off_temp, off_tiles, off_edges, off_cursors, total;
+        off_big, off_table, off_temp, off_tiles, off_edges, off_cursors, off_classify, total;
     int64_t edge_cap;
 };
 
@@ -164,6 +164,8 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
     L.edge_cap = ntiles > 0 ? link_edges : 0;
     L.off_edges = take(sizeof(int2) * (size_t)L.edge_cap);
     L.off_cursors = take(dense_cap > 0 ? sizeof(int32_t) * (size_t)kCursorInts : 0);
+    // dense-cell classification: counts and scans per chunk of 4096 cells (fof_dense.hip)
+    L.off_classify = take(dense_cap > 0 ? sizeof(int32_t) * 4 * (size_t)(ncell / 4096 + 2) : 0);
     L.total = o;
     return L;
 }
@@ -201,6 +203,7 @@ Work resolve(const fof_grid *g, void *ws)
     w.tile_list = (int32_t *)(base + L.off_tiles);
     w.edges = (int2 *)(base + L.off_edges);
     w.cursors = (int32_t *)(base + L.off_cursors);
+    w.classify = (int32_t *)(base + L.off_classify);
     w.edge_cap = (int32_t)L.edge_cap;
     w.dense_threshold = g->dense_threshold;
     w.dense_cap = (int32_t)g->dense_cap;

@@ -8,7 +8,8 @@
 // need one friend pair to be joined, so tests stop at the first hit.
 //
 // Build stage (index construction):
-//   k_classify   cells with more than `dense_threshold` particles get a dense id and a table
+//   k_classify_* cells with more than `dense_threshold` particles get a dense id (in cell
+//                order, by a count / scan / assign over chunks of cells) and a table
 //   k_dense_sort sort each dense cell by fine key (in LDS when it fits, else through a
 //                staging buffer) and write the key bitmask, its popcount prefix and the
 //                start of every unit
@@ -143,53 +144,122 @@ __device__ __forceinline__ int dense_count(const Counters *ctr, int cap)
     return nd < cap ? nd : cap;
 }
 
-// ---------------------------------------------------------------------------------------
-__global__ void k_dense_reset(Counters *ctr)
+// Cells holding more than dense_threshold particles (in boxes that allow clique tables)
+// get a dense id; those over kSmallCell also a place in the big list.  Ids follow cell
+// order and are assigned without atomics in two passes over chunks of kClassChunk cells:
+// k_classify_count counts per chunk, a scan gives each chunk its first ids, and
+// k_classify_assign ranks the cells inside the chunk.  A cell whose id would pass the
+// table capacity gets none (-1) and raises FOF_STATUS_DENSE_CAP.
+constexpr int kClassChunk = 4096;
+constexpr int kClassBlock = 256;
+constexpr int kClassPer = kClassChunk / kClassBlock;
+
+// 0: ordinary cell, 1: dense, 2: dense and big; -1: above the threshold, no table allowed.
+__device__ __forceinline__ int cell_class(const Work &w, int64_t c)
 {
-    if (threadIdx.x == 0) {
-        ctr->n_dense = 0;
-        ctr->n_big = 0;
+    const int32_t cnt = w.cell_start[c + 1] - w.cell_start[c];
+    if (cnt <= w.dense_threshold)
+        return 0;
+    if (!w.desc[find_box_cell(w.desc, w.nbox, c)].dense_ok)
+        return -1;
+    return cnt > kSmallCell ? 2 : 1;
+}
+
+// Block-wide exclusive scan of two small counts per thread (kClassBlock threads).
+__device__ __forceinline__ int2 block_scan2(int a, int b, int2 *total, int2 *scr)
+{
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    int xa = a, xb = b;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int ya = __shfl_up(xa, o, kWave), yb = __shfl_up(xb, o, kWave);
+        if (lane >= o) {
+            xa += ya;
+            xb += yb;
+        }
+    }
+    if (lane == kWave - 1)
+        scr[wid] = make_int2(xa, xb);
+    __syncthreads();
+    int2 pre = make_int2(0, 0), tot = make_int2(0, 0);
+    for (int k = 0; k < kClassBlock / kWave; ++k) {
+        if (k < wid) {
+            pre.x += scr[k].x;
+            pre.y += scr[k].y;
+        }
+        tot.x += scr[k].x;
+        tot.y += scr[k].y;
+    }
+    __syncthreads();  // scr is reused by the next call
+    *total = tot;
+    return make_int2(pre.x + xa - a, pre.y + xb - b);
+}
+
+__global__ __launch_bounds__(kClassBlock) void k_classify_count(Work w, int64_t nchunk,
+                                                                 int32_t *__restrict__ nd,
+                                                                 int32_t *__restrict__ nbig)
+{
+    __shared__ int2 scr[kClassBlock / kWave];
+    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        int a = 0, b = 0;
+        for (int k = 0; k < kClassPer; ++k) {
+            const int64_t c = ch * kClassChunk + k * kClassBlock + threadIdx.x;
+            if (c < w.ncell) {
+                const int cl = cell_class(w, c);
+                a += cl > 0;
+                b += cl == 2;
+            }
+        }
+        int2 tot;
+        block_scan2(a, b, &tot, scr);
+        if (threadIdx.x == 0) {
+            nd[ch] = tot.x;
+            nbig[ch] = tot.y;
+        }
     }
 }
 
-// Cells holding more than dense_threshold particles get a dense id (one atomic per wave)
-// and a table slot; the per-cell counters are dead after the scan and hold the tag
-// (dense id, or -1 when the cell takes the plain path).
-__global__ void k_classify(Work w)
+__global__ void k_classify_totals(Counters *ctr, int64_t nchunk, const int32_t *nd_pre,
+                                  const int32_t *nbig_pre)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t nround = (w.ncell + stride - 1) / stride;
-    for (int64_t k = 0; k < nround; ++k) {
-        const int64_t c = gtid() + k * stride;
-        bool big = false, want = false;
-        if (c < w.ncell) {
-            big = w.cell_start[c + 1] - w.cell_start[c] > w.dense_threshold;
-            if (big)
-                want = w.desc[find_box_cell(w.desc, w.nbox, c)].dense_ok != 0;
-        }
-        const uint64_t mask = ballot(want);
-        const int lane = lane_id();
-        int32_t d = -1;
-        if (mask) {
-            const int leader = __ffsll((unsigned long long)mask) - 1;
-            int32_t base = 0;
-            if (lane == leader)
-                base = atomicAdd(&w.ctr->n_dense, __popcll(mask));
-            base = __shfl(base, leader, kWave);
-            d = base + __popcll(mask & ((1ull << lane) - 1ull));
-        }
-        if (want) {
-            if (d < w.dense_cap) {
-                w.dense_list[d] = (int32_t)c;
-                if (w.cell_start[c + 1] - w.cell_start[c] > kSmallCell)
-                    w.big_list[atomicAdd(&w.ctr->n_big, 1)] = d;
-            } else {
-                atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_DENSE_CAP);
-                d = -1;
+    if (threadIdx.x == 0) {
+        ctr->n_dense = nd_pre[nchunk];
+        ctr->n_big = nbig_pre[nchunk];
+    }
+}
+
+__global__ __launch_bounds__(kClassBlock) void k_classify_assign(Work w, int64_t nchunk,
+                                                                  const int32_t *__restrict__ nd_pre,
+                                                                  const int32_t *__restrict__ nbig_pre)
+{
+    __shared__ int2 scr[kClassBlock / kWave];
+    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        int base_d = nd_pre[ch], base_b = nbig_pre[ch];
+        for (int k = 0; k < kClassPer; ++k) {  // cell order: k major, thread minor
+            const int64_t c = ch * kClassChunk + k * kClassBlock + threadIdx.x;
+            const int cl = c < w.ncell ? cell_class(w, c) : 0;
+            int2 tot;
+            const int2 r = block_scan2(cl > 0, cl == 2, &tot, scr);
+            if (cl != 0) {
+                int32_t d = -1;
+                if (cl > 0) {
+                    d = base_d + r.x;
+                    if (d < w.dense_cap) {
+                        w.dense_list[d] = (int32_t)c;
+                        if (cl == 2)
+                            w.big_list[base_b + r.y] = d;
+                    } else {
+                        atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_DENSE_CAP);
+                        if (cl == 2)  // big ids past this one have no table either
+                            atomicMin(&w.ctr->n_big, base_b + r.y);
+                        d = -1;
+                    }
+                }
+                w.cell_count[c] = d;
             }
+            base_d += tot.x;
+            base_b += tot.y;
         }
-        if (big)
-            w.cell_count[c] = want ? d : -1;
     }
 }
 
@@ -1054,11 +1124,21 @@ hipError_t launch_dense_build(const Work &w, hipStream_t s)
 {
     if (w.dense_cap <= 0 || w.dense_threshold < 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_dense_reset, dim3(1), dim3(64), 0, s, w.ctr);
-    int64_t nb = (w.ncell + 255) / 256;
-    if (nb > 65536)
-        nb = 65536;
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(256), 0, s, w);
+    const int64_t nchunk = (w.ncell + kClassChunk - 1) / kClassChunk;
+    int32_t *nd = w.classify, *nd_pre = nd + (nchunk + 1);
+    int32_t *nbig = nd_pre + (nchunk + 1), *nbig_pre = nbig + (nchunk + 1);
+    const unsigned cb = (unsigned)(nchunk < 65536 ? (nchunk > 0 ? nchunk : 1) : 65536);
+    hipLaunchKernelGGL(k_classify_count, dim3(cb), dim3(kClassBlock), 0, s, w, nchunk, nd, nbig);
+    hipError_t e = launch_scan_i32(nd, nd_pre, nchunk, w.scan, s);
+    if (e != hipSuccess)
+        return e;
+    e = launch_scan_i32(nbig, nbig_pre, nchunk, w.scan, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_classify_totals, dim3(1), dim3(64), 0, s, w.ctr, nchunk, nd_pre,
+                       nbig_pre);
+    hipLaunchKernelGGL(k_classify_assign, dim3(cb), dim3(kClassBlock), 0, s, w, nchunk, nd_pre,
+                       nbig_pre);
     hipLaunchKernelGGL(k_dense_sort, dim3(persistent_blocks(w.dense_cap)), dim3(kDenseBlock), 0, s,
                        w);
     return hipGetLastError();

@@ -341,6 +341,7 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
     int2 *edges;          // hooks deferred by the tiled kernel
     int32_t edge_cap;
     int32_t *cursors;     // work cursors of the dense passes, kCursorStride ints apart
+    int32_t *classify;    // per-chunk dense / big counts and their scans (binning)
     int32_t nbox;
     int32_t block;
     int64_t n;
