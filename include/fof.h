@@ -11,7 +11,8 @@
  *  - Pointers marked (dev) are device pointers on the device that owns `stream`; pointers
  *    marked (host) are host memory.  The caller owns every buffer.  No call allocates,
  *    frees, synchronises or prints: all device work is enqueued on `stream` (a hipStream_t
- *    passed as void*; NULL = the default stream).
+ *    passed as void*; NULL = the default stream), or, after fof_init, partly on a helper
+ *    stream that fof_link forks from and joins back to `stream`.
  *  - Return value: FOF_OK (0) or a negative FOF_E* code.  Argument errors are detected on the
  *    host before anything is enqueued.  Data errors that only the device can see
  *    (coordinates outside [0, L) or NaN) set bits of the device status word (fof_status).
@@ -193,6 +194,15 @@ int fof_backward(const fof_grid *grid, void *ws /*dev*/, int32_t mode,
 /* Device address of the int32 status word inside ws (FOF_STATUS_* bits; 0 = clean).  It is
  * cleared by fof_build_grid; read it after synchronising the stream. */
 int fof_status(const fof_grid *grid, void *ws /*dev*/, int32_t **status /*host out: dev ptr*/);
+
+/* Optional, once per device (the current one), before fof_link is called from a captured
+ * or performance-critical context: creates a helper stream (default priority) and two
+ * events, so that fof_link runs its dense-cell passes concurrently with the tiled pass
+ * (fork and join through the events; the call still orders everything after the caller's
+ * earlier work and before its later work).  Without it, every call runs on the caller's
+ * stream alone.  Allocates no device memory.  Errors: FOF_EDEVICE, FOF_ENOTSUP (device
+ * index 64 or above). */
+int fof_init(void);
 
 /* Static text for a FOF_E* code. */
 const char *fof_strerror(int code);

@@ -36,7 +36,7 @@ def sample_scratch_bytes(n: int, K: int, edge_cap: int) -> int:
 
 # Every symbol include/fof.h declares.
 EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",
-           "fof_status", "fof_strerror", "fof_last_device_error")
+           "fof_status", "fof_strerror", "fof_last_device_error", "fof_init")
 
 
 class fof_box(ctypes.Structure):
@@ -104,11 +104,17 @@ def load():
     L.fof_strerror.argtypes = [ctypes.c_int]
     L.fof_strerror.restype = ctypes.c_char_p
     L.fof_last_device_error.argtypes = [ctypes.POINTER(ctypes.c_char_p)]
+    L.fof_init.argtypes = []
     for f in EXPORTS:
         if f != "fof_strerror":
             getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
+
+
+def init():
+    """Creates the current device's helper stream (fof_init), once."""
+    check("fof_init", load().fof_init())
 
 
 def strerror(code: int) -> str:

@@ -3,6 +3,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "fof_internal.h"
 
 namespace fof {
@@ -228,6 +230,13 @@ int dev_err(hipError_t e)
     return FOF_EDEVICE;
 }
 
+// Helper streams made by fof_init, one per device; calls that use one hold the lock, so
+// that concurrent callers do not interleave their fork and join events.
+constexpr int kMaxDevices = 64;
+SideStream g_side[kMaxDevices];
+bool g_side_ok[kMaxDevices];
+std::mutex g_side_lock;
+
 // The runtime's last-error slot may hold an error of another caller's earlier API call;
 // clear it so that only this call's launches are reported.
 void clear_stale_error() { (void)hipGetLastError(); }
@@ -355,7 +364,12 @@ int fof_link(const fof_grid *grid, void *ws, const fof_sample *sample, int32_t *
     }
     if (grid->n > 0 && !root)
         return FOF_EINVAL;
-    return dev_err(launch_link(w, root, (hipStream_t)stream));
+    int dev = -1;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices && g_side_ok[dev]) {
+        std::lock_guard<std::mutex> hold(g_side_lock);
+        return dev_err(launch_link(w, root, (hipStream_t)stream, &g_side[dev]));
+    }
+    return dev_err(launch_link(w, root, (hipStream_t)stream, nullptr));
 }
 
 int fof_groups(const fof_grid *grid, void *ws, int32_t min_size, const float *vel, int32_t cap,
@@ -407,6 +421,28 @@ int fof_status(const fof_grid *grid, void *ws, int32_t **status)
     if (!ws_ok(grid, ws) || !status)
         return FOF_EINVAL;
     *status = (int32_t *)((char *)ws + grid->off_status);
+    return FOF_OK;
+}
+
+int fof_init(void)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+        return FOF_EDEVICE;
+    if (dev >= kMaxDevices)
+        return FOF_ENOTSUP;
+    std::lock_guard<std::mutex> hold(g_side_lock);
+    if (g_side_ok[dev])
+        return FOF_OK;
+    SideStream &sd = g_side[dev];
+    hipError_t e = hipStreamCreateWithFlags(&sd.stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming);
+    if (e != hipSuccess)
+        return dev_err(e);
+    g_side_ok[dev] = true;
     return FOF_OK;
 }
 

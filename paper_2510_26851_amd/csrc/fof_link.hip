@@ -529,14 +529,24 @@ __global__ void k_compress(const float4 *__restrict__ sorted, int64_t n,
 
 }  // namespace
 
-hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s)
+// The components and dense-pair passes touch only dense-cell particles (their parent
+// entries, and flag words through atomic ORs); the tiled pass only ordinary particles, with
+// plain stores to their own entries and no global hooks.  So the two run concurrently when
+// a helper stream is given: fork after the flag fill, join before the deferred hooks.
+hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideStream *side)
 {
     if (w.n <= 0)
         return hipSuccess;
     hipError_t e = launch_fill_u64(w.flags, (w.n + 63) / 64, 0ull, s);
     if (e != hipSuccess)
         return e;
-    e = launch_dense(w, s);
+    const bool fork = side && w.ntiles > 0 && w.dense_cap > 0 && w.dense_threshold >= 0;
+    if (fork) {
+        if ((e = hipEventRecord(side->fork, s)) != hipSuccess ||
+            (e = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess)
+            return e;
+    }
+    e = launch_dense(w, fork ? side->stream : s);
     if (e != hipSuccess)
         return e;
     const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
@@ -546,6 +556,11 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s)
             return e;
         hipLaunchKernelGGL(k_link_tiled, dim3((unsigned)w.ntiles), dim3(kTileBlock), 0, s, w,
                            root);
+        if (fork) {
+            if ((e = hipEventRecord(side->join, side->stream)) != hipSuccess ||
+                (e = hipStreamWaitEvent(s, side->join, 0)) != hipSuccess)
+                return e;
+        }
         hipLaunchKernelGGL(k_link_edges, dim3(1024), dim3(256), 0, s, w);
         const unsigned wb = (unsigned)(w.ntiles < kWindowBlocks ? w.ntiles : kWindowBlocks);
         hipLaunchKernelGGL(k_link_windows, dim3(wb), dim3(kTileBlock), 0, s, w, root);

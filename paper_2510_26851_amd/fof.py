@@ -39,6 +39,8 @@ class Plan:
     def __init__(self, counts, boxes, device=None, tune=None):
         L = _lib.load()
         self.device = torch.device(device if device is not None else "cuda")
+        with torch.cuda.device(self.device):
+            _lib.init()  # helper stream of this device (once per process)
         counts = np.ascontiguousarray(np.asarray(counts, dtype=np.int64).reshape(-1))
         nbox = counts.shape[0]
         bx = (_lib.fof_box * nbox)()
