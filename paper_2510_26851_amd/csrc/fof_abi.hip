@@ -117,7 +117,7 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
 
 struct Layout {
     size_t off_desc, off_status, off_cell_count, off_cell_start, off_scan, off_rank, off_sorted,
-        off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, off_dense,
+        off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, off_flist, off_dense,
         off_big, off_table, off_temp, off_tiles, off_edges, off_cursors, off_classify, total;
     int64_t edge_cap;
 };
@@ -158,6 +158,7 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
     L.off_keep_prefix = take(sizeof(int32_t) * (size_t)(nwords + 1));
     L.off_cnt = take(sizeof(int32_t) * (size_t)n);
     L.off_groot = take(sizeof(int32_t) * (size_t)n);
+    L.off_flist = take(sizeof(int32_t) * (size_t)n);
     L.off_dense = take(sizeof(int32_t) * (size_t)dense_cap);
     L.off_big = take(sizeof(int32_t) * (size_t)dense_cap);
     L.off_table = take(sizeof(int32_t) * (size_t)dense_cap * (size_t)table_stride(words));
@@ -198,6 +199,7 @@ Work resolve(const fof_grid *g, void *ws)
     w.keep_prefix = (int32_t *)(base + L.off_keep_prefix);
     w.cnt = (int32_t *)(base + L.off_cnt);
     w.groot = (int32_t *)(base + L.off_groot);
+    w.flist = (int32_t *)(base + L.off_flist);
     w.dense_list = (int32_t *)(base + L.off_dense);
     w.big_list = (int32_t *)(base + L.off_big);
     w.table = (int32_t *)(base + L.off_table);

@@ -4,16 +4,19 @@
 // friend are singleton components; every flagged particle's union-find entry points
 // straight at its root, whose key is the component label (smallest original index).
 //
-//   g_zero     cnt[i] = 0 for flagged i (every non-singleton root is flagged)
-//   g_count    cnt[root] += 1 for flagged i
-//   g_keep     set keep bit [label] for kept components (size >= min_size)
+//   g_compact  flist = sorted indices of the flagged particles, ascending (popcount scan
+//              of the flag bitmap); the passes marked (list) below walk only flist
+//   g_zero     cnt[i] = 0 for flagged i (every non-singleton root is flagged)   (list)
+//   g_count    cnt[root] += 1 for flagged i                                     (list)
+//   g_keep     set keep bit [label] for kept components (size >= min_size); with
+//              min_size > 1 only non-singleton roots qualify                  (list)
 //   scan       popcount prefix over the keep bitmap -> group id = rank of the label
-//   g_assign   group_id[orig] (with min_size > 1 only for particles with a friend, the
-//              rest is filled with -1 first); per kept group: size, root slot, and the
-//              moment accumulators cleared (singleton groups are finished here)
-//   g_sum      FP64 sums of minimum-image offsets from the root and of velocities
+//   g_assign   group_id[orig]; with min_size > 1 group_id is filled with -1 first and only
+//              flagged particles are visited (list); per kept group: size, root slot, and
+//              the moment accumulators cleared (singleton groups are finished here)
+//   g_sum      FP64 sums of minimum-image offsets from the root and of velocities (list)
 //   g_mean     com = wrap(x_root + sum / n), vmean = vsum / n
-//   g_dev      sum of squared velocity deviations; g_sig: sigv = sqrt(sum / (3 n))
+//   g_dev      sum of squared velocity deviations (list); g_sig: sigv = sqrt(sum / (3 n))
 #include "fof_internal.h"
 
 namespace fof {
@@ -62,12 +65,6 @@ __device__ __forceinline__ bool flagged(const uint64_t *flags, int64_t i)
     return (flags[i >> 6] >> (i & 63)) & 1ull;
 }
 
-__device__ __forceinline__ uint32_t root_slot(const uint64_t *parent, const uint64_t *flags,
-                                              int64_t i)
-{
-    return flagged(flags, i) ? uf_idx(parent[i]) : (uint32_t)i;
-}
-
 __device__ __forceinline__ int32_t group_of(const uint32_t *keep, const int32_t *keep_prefix,
                                             uint32_t label)
 {
@@ -78,23 +75,70 @@ __device__ __forceinline__ int32_t group_of(const uint32_t *keep, const int32_t 
     return keep_prefix[label >> 5] + __popc(w & (bit - 1u));
 }
 
-__global__ void g_zero(int64_t n, const uint64_t *__restrict__ flags, int32_t *__restrict__ cnt)
+// Flagged-list compaction: one wave per 64-bit flag word, lane l owning particle 64 q + l;
+// `prefix` is the exclusive popcount scan of the flag bitmap read as 32-bit words, so the
+// word's first slot is prefix[2 q].  The list comes out in ascending order.
+__global__ void g_compact(const uint64_t *__restrict__ flags, int64_t n,
+                          const int32_t *__restrict__ prefix, int64_t nwords32,
+                          int32_t *__restrict__ list, Counters *__restrict__ ctr)
 {
-    int64_t i = gtid();
-    if (i < n && flagged(flags, i))
-        cnt[i] = 0;
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int64_t nq = (n + 63) / 64;
+    for (int64_t q = wave; q < nq; q += nwaves) {
+        const uint64_t word = flags[q];
+        if ((word >> lane) & 1ull)
+            list[prefix[2 * q] + __popcll(word & ((1ull << lane) - 1ull))] =
+                (int32_t)(64 * q + lane);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        ctr->n_flagged = prefix[nwords32];
 }
 
-__global__ void g_count(int64_t n, const uint64_t *__restrict__ parent,
-                        const uint64_t *__restrict__ flags, int32_t *__restrict__ cnt)
+// The list-driven passes below walk flist in grid-sized rounds: lanes of a wave take
+// consecutive entries, so members of one group (adjacent in cell-sorted order) stay in
+// consecutive lanes for the run reductions.
+
+__global__ void g_zero(const int32_t *__restrict__ list, const Counters *__restrict__ ctr,
+                       int32_t *__restrict__ cnt)
 {
-    const int64_t i = gtid();
-    const bool in = i < n && flagged(flags, i);
-    const int64_t key = in ? (int64_t)uf_idx(parent[i]) : -1 - (int64_t)lane_id();
-    const Run r = wave_run(key);
-    const int c = run_sum(in ? 1 : 0, r.head);
-    if (in && r.tail)
-        atomicAdd(cnt + key, c);
+    const int64_t nf = ctr->n_flagged;
+    for (int64_t k = gtid(); k < nf; k += (int64_t)gridDim.x * blockDim.x)
+        cnt[list[k]] = 0;
+}
+
+__global__ void g_count(const int32_t *__restrict__ list, const Counters *__restrict__ ctr,
+                        const uint64_t *__restrict__ parent, int32_t *__restrict__ cnt)
+{
+    const int64_t nf = ctr->n_flagged;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nf; base += stride) {
+        const int64_t k = base + threadIdx.x;
+        const bool in = k < nf;
+        const int64_t key = in ? (int64_t)uf_idx(parent[list[k]]) : -1 - (int64_t)lane_id();
+        const Run r = wave_run(key);
+        const int c = run_sum(in ? 1 : 0, r.head);
+        if (in && r.tail)
+            atomicAdd(cnt + key, c);
+    }
+}
+
+// min_size > 1: only roots of non-singleton components can be kept; a root's key is its
+// own label.
+__global__ void g_keep_roots(const int32_t *__restrict__ list, const Counters *__restrict__ ctr,
+                             const uint64_t *__restrict__ parent, const int32_t *__restrict__ cnt,
+                             int32_t min_size, uint32_t *__restrict__ keep)
+{
+    const int64_t nf = ctr->n_flagged;
+    for (int64_t k = gtid(); k < nf; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = list[k];
+        const uint64_t e = parent[i];
+        if (uf_idx(e) == (uint32_t)i && cnt[i] >= min_size) {
+            const uint32_t label = uf_key(e);
+            atomicOr(keep + (label >> 5), 1u << (label & 31));
+        }
+    }
 }
 
 __global__ void g_keep(const float4 *__restrict__ sorted, int64_t n,
@@ -122,115 +166,136 @@ __global__ void g_keep(const float4 *__restrict__ sorted, int64_t n,
     }
 }
 
-// With skip_lonely, group_id was filled with -1 beforehand (groups of one are cut) and
-// particles without a friend leave after reading their flag bit.
-__global__ void g_assign(const float4 *__restrict__ sorted, int64_t n,
-                         const uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
-                         const int32_t *__restrict__ cnt, const uint32_t *__restrict__ keep,
-                         const int32_t *__restrict__ keep_prefix, const float *__restrict__ vel,
-                         int32_t cap, bool skip_lonely, int32_t *__restrict__ group_id,
-                         int32_t *__restrict__ groot, int32_t *__restrict__ sizes,
-                         double *__restrict__ com, double *__restrict__ vmean,
-                         double *__restrict__ sigv)
+struct GroupOut {
+    int32_t *group_id, *groot, *sizes;
+    double *com, *vmean, *sigv;
+    const float *vel;
+    int32_t cap;
+};
+
+// group_id of one particle; the root of a kept group also writes the group's size and root
+// slot and clears its moment accumulators (a singleton group is finished here).
+__device__ __forceinline__ void assign_one(const float4 *__restrict__ sorted,
+                                           const uint64_t *__restrict__ parent, bool fl,
+                                           uint32_t i, const int32_t *__restrict__ cnt,
+                                           const uint32_t *__restrict__ keep,
+                                           const int32_t *__restrict__ keep_prefix,
+                                           const GroupOut &o)
 {
-    int64_t i = gtid();
-    if (i >= n)
-        return;
-    const bool fl = flagged(flags, i);
-    if (!fl && skip_lonely)
-        return;
     const float4 p = sorted[i];
     const int32_t orig = __float_as_int(p.w);
-    const uint32_t rs = fl ? uf_idx(parent[i]) : (uint32_t)i;
-    const uint32_t label = fl ? uf_key(parent[i]) : (uint32_t)orig;
+    const uint64_t e = fl ? parent[i] : 0;
+    const uint32_t rs = fl ? uf_idx(e) : i;
+    const uint32_t label = fl ? uf_key(e) : (uint32_t)orig;
     const int32_t g = group_of(keep, keep_prefix, label);
-    group_id[orig] = g;
-    if (g < 0 || g >= cap || rs != (uint32_t)i)
+    o.group_id[orig] = g;
+    if (g < 0 || g >= o.cap || rs != i)
         return;
-    // i is the root of kept group g
-    groot[g] = (int32_t)i;
+    o.groot[g] = (int32_t)i;
+    const double c[3] = {(double)p.x, (double)p.y, (double)p.z};
     if (fl) {
-        sizes[g] = cnt[i];
-        if (com) {
-            com[3 * g + 0] = 0.0;
-            com[3 * g + 1] = 0.0;
-            com[3 * g + 2] = 0.0;
+        o.sizes[g] = cnt[i];
+        if (o.com)
+            for (int a = 0; a < 3; ++a)
+                o.com[3 * g + a] = 0.0;
+        if (o.vel) {
+            if (o.vmean)
+                for (int a = 0; a < 3; ++a)
+                    o.vmean[3 * g + a] = 0.0;
+            if (o.sigv)
+                o.sigv[g] = 0.0;
         }
-        if (vel) {
-            if (vmean) {
-                vmean[3 * g + 0] = 0.0;
-                vmean[3 * g + 1] = 0.0;
-                vmean[3 * g + 2] = 0.0;
-            }
-            if (sigv)
-                sigv[g] = 0.0;
-        }
-    } else {  // singleton group (min_size <= 1): finished here
-        sizes[g] = 1;
-        if (com) {
-            com[3 * g + 0] = (double)p.x;
-            com[3 * g + 1] = (double)p.y;
-            com[3 * g + 2] = (double)p.z;
-        }
-        if (vel) {
-            if (vmean) {
-                vmean[3 * g + 0] = (double)vel[3 * (int64_t)orig + 0];
-                vmean[3 * g + 1] = (double)vel[3 * (int64_t)orig + 1];
-                vmean[3 * g + 2] = (double)vel[3 * (int64_t)orig + 2];
-            }
-            if (sigv)
-                sigv[g] = 0.0;
+    } else {
+        o.sizes[g] = 1;
+        if (o.com)
+            for (int a = 0; a < 3; ++a)
+                o.com[3 * g + a] = c[a];
+        if (o.vel) {
+            if (o.vmean)
+                for (int a = 0; a < 3; ++a)
+                    o.vmean[3 * g + a] = (double)o.vel[3 * (int64_t)orig + a];
+            if (o.sigv)
+                o.sigv[g] = 0.0;
         }
     }
 }
 
-__global__ void g_sum(const float4 *__restrict__ sorted, int64_t n,
-                      const BoxDesc *__restrict__ desc, int nbox,
-                      const uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
+// Every particle (min_size <= 1: groups of one are kept).
+__global__ void g_assign(const float4 *__restrict__ sorted, int64_t n,
+                         const uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
+                         const int32_t *__restrict__ cnt, const uint32_t *__restrict__ keep,
+                         const int32_t *__restrict__ keep_prefix, GroupOut o)
+{
+    const int64_t i = gtid();
+    if (i < n)
+        assign_one(sorted, parent, flagged(flags, i), (uint32_t)i, cnt, keep, keep_prefix, o);
+}
+
+// Particles with a friend only (min_size > 1: group_id was filled with -1 beforehand).
+__global__ void g_assign_list(const float4 *__restrict__ sorted, const int32_t *__restrict__ list,
+                              const Counters *__restrict__ ctr,
+                              const uint64_t *__restrict__ parent, const int32_t *__restrict__ cnt,
+                              const uint32_t *__restrict__ keep,
+                              const int32_t *__restrict__ keep_prefix, GroupOut o)
+{
+    const int64_t nf = ctr->n_flagged;
+    for (int64_t k = gtid(); k < nf; k += (int64_t)gridDim.x * blockDim.x)
+        assign_one(sorted, parent, true, (uint32_t)list[k], cnt, keep, keep_prefix, o);
+}
+
+// Members of non-singleton groups only: singleton groups were finished by the assign pass.
+__global__ void g_sum(const float4 *__restrict__ sorted, const int32_t *__restrict__ list,
+                      const Counters *__restrict__ ctr, const BoxDesc *__restrict__ desc,
+                      int nbox, const uint64_t *__restrict__ parent,
                       const uint32_t *__restrict__ keep, const int32_t *__restrict__ keep_prefix,
                       const float *__restrict__ vel, int32_t cap, double *__restrict__ com,
                       double *__restrict__ vmean)
 {
-    const int64_t i = gtid();
-    int32_t g = -1;
-    uint64_t r = 0;
-    if (i < n && flagged(flags, i)) {
-        r = parent[i];
-        g = group_of(keep, keep_prefix, uf_key(r));
-        if (g >= cap)
-            g = -1;
-    }
-    const bool in = g >= 0;
-    const Run run = wave_run(in ? (int64_t)g : -1 - (int64_t)lane_id());
-    double d[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
-    if (in) {
-        const float4 p = sorted[i];
+    const int64_t nf = ctr->n_flagged;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nf; base += stride) {
+        const int64_t k = base + threadIdx.x;
+        int32_t g = -1, i = 0;
+        uint64_t r = 0;
+        if (k < nf) {
+            i = list[k];
+            r = parent[i];
+            g = group_of(keep, keep_prefix, uf_key(r));
+            if (g >= cap)
+                g = -1;
+        }
+        const bool in = g >= 0;
+        const Run run = wave_run(in ? (int64_t)g : -1 - (int64_t)lane_id());
+        double d[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+        if (in) {
+            const float4 p = sorted[i];
+            if (com) {
+                const BoxDesc &B = desc[find_box(desc, nbox, i)];
+                const float4 q = sorted[uf_idx(r)];
+                d[0] = min_image((double)p.x - (double)q.x, B.L[0], B.halfL[0]);
+                d[1] = min_image((double)p.y - (double)q.y, B.L[1], B.halfL[1]);
+                d[2] = min_image((double)p.z - (double)q.z, B.L[2], B.halfL[2]);
+            }
+            if (vel && vmean) {
+                const int64_t o = __float_as_int(p.w);
+                v[0] = (double)vel[3 * o + 0];
+                v[1] = (double)vel[3 * o + 1];
+                v[2] = (double)vel[3 * o + 2];
+            }
+        }
         if (com) {
-            const BoxDesc &B = desc[find_box(desc, nbox, i)];
-            const float4 q = sorted[uf_idx(r)];
-            d[0] = min_image((double)p.x - (double)q.x, B.L[0], B.halfL[0]);
-            d[1] = min_image((double)p.y - (double)q.y, B.L[1], B.halfL[1]);
-            d[2] = min_image((double)p.z - (double)q.z, B.L[2], B.halfL[2]);
+            for (int a = 0; a < 3; ++a) {
+                const double sa = run_sum(d[a], run.head);
+                if (in && run.tail)
+                    atomicAdd(com + 3 * g + a, sa);
+            }
         }
         if (vel && vmean) {
-            const int64_t o = __float_as_int(p.w);
-            v[0] = (double)vel[3 * o + 0];
-            v[1] = (double)vel[3 * o + 1];
-            v[2] = (double)vel[3 * o + 2];
-        }
-    }
-    if (com) {
-        for (int a = 0; a < 3; ++a) {
-            const double sa = run_sum(d[a], run.head);
-            if (in && run.tail)
-                atomicAdd(com + 3 * g + a, sa);
-        }
-    }
-    if (vel && vmean) {
-        for (int a = 0; a < 3; ++a) {
-            const double sa = run_sum(v[a], run.head);
-            if (in && run.tail)
-                atomicAdd(vmean + 3 * g + a, sa);
+            for (int a = 0; a < 3; ++a) {
+                const double sa = run_sum(v[a], run.head);
+                if (in && run.tail)
+                    atomicAdd(vmean + 3 * g + a, sa);
+            }
         }
     }
 }
@@ -268,32 +333,37 @@ __global__ void g_mean(const float4 *__restrict__ sorted, const BoxDesc *__restr
             vmean[3 * g + a] = vmean[3 * g + a] / dn;
 }
 
-__global__ void g_dev(const float4 *__restrict__ sorted, int64_t n,
-                      const uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
+__global__ void g_dev(const float4 *__restrict__ sorted, const int32_t *__restrict__ list,
+                      const Counters *__restrict__ ctr, const uint64_t *__restrict__ parent,
                       const uint32_t *__restrict__ keep, const int32_t *__restrict__ keep_prefix,
                       const float *__restrict__ vel, int32_t cap,
                       const double *__restrict__ vmean, double *__restrict__ sigv)
 {
-    const int64_t i = gtid();
-    int32_t g = -1;
-    if (i < n && flagged(flags, i)) {
-        g = group_of(keep, keep_prefix, uf_key(parent[i]));
-        if (g >= cap)
-            g = -1;
-    }
-    const bool in = g >= 0;
-    const Run run = wave_run(in ? (int64_t)g : -1 - (int64_t)lane_id());
-    double s2 = 0.0;
-    if (in) {
-        const int64_t o = __float_as_int(sorted[i].w);
-        for (int a = 0; a < 3; ++a) {
-            const double dv = (double)vel[3 * o + a] - vmean[3 * g + a];
-            s2 += dv * dv;
+    const int64_t nf = ctr->n_flagged;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nf; base += stride) {
+        const int64_t k = base + threadIdx.x;
+        int32_t g = -1, i = 0;
+        if (k < nf) {
+            i = list[k];
+            g = group_of(keep, keep_prefix, uf_key(parent[i]));
+            if (g >= cap)
+                g = -1;
         }
+        const bool in = g >= 0;
+        const Run run = wave_run(in ? (int64_t)g : -1 - (int64_t)lane_id());
+        double s2 = 0.0;
+        if (in) {
+            const int64_t o = __float_as_int(sorted[i].w);
+            for (int a = 0; a < 3; ++a) {
+                const double dv = (double)vel[3 * o + a] - vmean[3 * g + a];
+                s2 += dv * dv;
+            }
+        }
+        s2 = run_sum(s2, run.head);
+        if (in && run.tail)
+            atomicAdd(sigv + g, s2);
     }
-    s2 = run_sum(s2, run.head);
-    if (in && run.tail)
-        atomicAdd(sigv + g, s2);
 }
 
 __global__ void g_sig(const int32_t *__restrict__ n_groups, int32_t cap,
@@ -322,15 +392,32 @@ hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int3
                          double *vmean, double *sigv, hipStream_t s)
 {
     const int64_t nwords = (w.n + 31) / 32;
-    hipError_t e = launch_fill_u32(w.keep, nwords, 0u, s);
+    const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
+    // grid of the list-driven passes: a few rounds of a full chip
+    const unsigned lb = nb < 4096u ? (nb > 0 ? nb : 1u) : 4096u;
+    hipError_t e;
+    if (w.n > 0) {
+        // flagged list: popcount scan of the flag bitmap into keep_prefix, then compaction
+        e = launch_scan_popc((const uint32_t *)w.flags, w.keep_prefix, nwords, w.scan, s);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(g_compact, dim3(lb), dim3(w.block), 0, s, w.flags, w.n,
+                           w.keep_prefix, nwords, w.flist, w.ctr);
+    }
+    e = launch_fill_u32(w.keep, nwords, 0u, s);
     if (e != hipSuccess)
         return e;
-    const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
+    const bool lonely_cut = min_size > 1;
     if (w.n > 0) {
-        hipLaunchKernelGGL(g_zero, dim3(nb), dim3(w.block), 0, s, w.n, w.flags, w.cnt);
-        hipLaunchKernelGGL(g_count, dim3(nb), dim3(w.block), 0, s, w.n, w.parent, w.flags, w.cnt);
-        hipLaunchKernelGGL(g_keep, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent,
-                           w.flags, w.cnt, min_size, w.keep);
+        hipLaunchKernelGGL(g_zero, dim3(lb), dim3(w.block), 0, s, w.flist, w.ctr, w.cnt);
+        hipLaunchKernelGGL(g_count, dim3(lb), dim3(w.block), 0, s, w.flist, w.ctr, w.parent,
+                           w.cnt);
+        if (lonely_cut)
+            hipLaunchKernelGGL(g_keep_roots, dim3(lb), dim3(w.block), 0, s, w.flist, w.ctr,
+                               w.parent, w.cnt, min_size, w.keep);
+        else
+            hipLaunchKernelGGL(g_keep, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent,
+                               w.flags, w.cnt, min_size, w.keep);
     }
     e = launch_scan_popc(w.keep, w.keep_prefix, nwords, w.scan, s);
     if (e != hipSuccess)
@@ -338,26 +425,36 @@ hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int3
     hipLaunchKernelGGL(g_total, dim3(1), dim3(64), 0, s, w.keep_prefix, nwords, n_groups);
     if (w.n == 0)
         return hipGetLastError();
-    const bool skip_lonely = min_size > 1;
-    if (skip_lonely) {
+    GroupOut o;
+    o.group_id = group_id;
+    o.groot = w.groot;
+    o.sizes = sizes;
+    o.com = com;
+    o.vmean = vmean;
+    o.sigv = sigv;
+    o.vel = vel;
+    o.cap = cap;
+    if (lonely_cut) {
         e = launch_fill_i32(group_id, w.n, -1, s);
         if (e != hipSuccess)
             return e;
+        hipLaunchKernelGGL(g_assign_list, dim3(lb), dim3(w.block), 0, s, w.sorted, w.flist,
+                           w.ctr, w.parent, w.cnt, w.keep, w.keep_prefix, o);
+    } else {
+        hipLaunchKernelGGL(g_assign, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent,
+                           w.flags, w.cnt, w.keep, w.keep_prefix, o);
     }
-    hipLaunchKernelGGL(g_assign, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent, w.flags,
-                       w.cnt, w.keep, w.keep_prefix, vel, cap, skip_lonely, group_id, w.groot,
-                       sizes, com, vmean, sigv);
     if (cap <= 0)
         return hipGetLastError();
     const unsigned gb = (unsigned)((cap + 255) / 256);
     const float *v = (vmean || sigv) ? vel : nullptr;
-    hipLaunchKernelGGL(g_sum, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.desc, w.nbox,
-                       w.parent, w.flags, w.keep, w.keep_prefix, v, cap, com, vmean);
+    hipLaunchKernelGGL(g_sum, dim3(lb), dim3(w.block), 0, s, w.sorted, w.flist, w.ctr, w.desc,
+                       w.nbox, w.parent, w.keep, w.keep_prefix, v, cap, com, vmean);
     hipLaunchKernelGGL(g_mean, dim3(gb), dim3(256), 0, s, w.sorted, w.desc, w.nbox, n_groups, cap,
                        w.groot, sizes, v, com, vmean);
     if (v && vmean && sigv) {
-        hipLaunchKernelGGL(g_dev, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent, w.flags,
-                           w.keep, w.keep_prefix, v, cap, vmean, sigv);
+        hipLaunchKernelGGL(g_dev, dim3(lb), dim3(w.block), 0, s, w.sorted, w.flist, w.ctr,
+                           w.parent, w.keep, w.keep_prefix, v, cap, vmean, sigv);
         hipLaunchKernelGGL(g_sig, dim3(gb), dim3(256), 0, s, n_groups, cap, sizes, sigv);
     }
     return hipGetLastError();

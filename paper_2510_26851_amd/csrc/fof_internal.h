@@ -60,7 +60,8 @@ struct Counters {
     int32_t n_big;       // dense cells linked by a whole block
     int32_t n_spill;       // link tiles queued in tile_list for the windowed kernel
     int32_t n_link_edges;  // hooks the tiled kernel deferred to the edge list
-    int32_t pad[27];
+    int32_t n_flagged;     // particles with a friend (length of Work::flist)
+    int32_t pad[26];
     unsigned long long stats[16];  // event counts of diagnostic builds (-DFOF_STATS)
 };
 
@@ -333,6 +334,7 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
     int32_t *keep_prefix;
     int32_t *cnt;
     int32_t *groot;
+    int32_t *flist;       // sorted indices of the particles with a friend, ascending
     int32_t *dense_list;  // dense cell ids in discovery order
     int32_t *big_list;    // dense ids of cells too large for one wave
     int32_t *table;       // per dense cell: header, key bitmask, popcount prefix
