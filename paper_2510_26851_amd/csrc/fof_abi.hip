@@ -118,7 +118,7 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
 struct Layout {
     size_t off_desc, off_status, off_cell_count, off_cell_start, off_scan, off_rank, off_sorted,
         off_parent, off_flags, off_keep, off_keep_prefix, off_cnt, off_groot, off_flist, off_dense,
-        off_big, off_table, off_temp, off_tiles, off_edges, off_cursors, off_classify, total;
+        off_big, off_table, off_temp, off_tiles, off_edges, off_cursors, off_classify, off_bin, total;
     int64_t edge_cap;
 };
 
@@ -145,6 +145,10 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
     };
     const int64_t nwords = (n + 31) / 32;
     int64_t scan_n = ncell > nwords ? ncell : nwords;
+    const BinShape bs = bin_shape(n, ncell);
+    const int64_t bin_n = bs.ok ? bs.nbk * bs.G : 0;  // bucketed binning table
+    if (bin_n > scan_n)
+        scan_n = bin_n;
     L.off_desc = take(sizeof(BoxDesc) * (size_t)nbox);
     L.off_status = take(sizeof(Counters));
     L.off_cell_count = take(sizeof(int32_t) * (size_t)ncell);
@@ -162,13 +166,16 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
     L.off_dense = take(sizeof(int32_t) * (size_t)dense_cap);
     L.off_big = take(sizeof(int32_t) * (size_t)dense_cap);
     L.off_table = take(sizeof(int32_t) * (size_t)dense_cap * (size_t)table_stride(words));
-    L.off_temp = take(dense_cap > 0 ? sizeof(float4) * (size_t)n : 0);
+    // staging: the bucketed binning, then dense cells too large to sort in LDS
+    L.off_temp = take(dense_cap > 0 || bin_n > 0 ? sizeof(float4) * (size_t)n : 0);
     L.off_tiles = take(sizeof(int32_t) * (size_t)ntiles);
     L.edge_cap = ntiles > 0 ? link_edges : 0;
     L.off_edges = take(sizeof(int2) * (size_t)L.edge_cap);
     L.off_cursors = take(dense_cap > 0 ? sizeof(int32_t) * (size_t)kCursorInts : 0);
     // dense-cell classification: counts and scans per chunk of 4096 cells (fof_dense.hip)
     L.off_classify = take(dense_cap > 0 ? sizeof(int32_t) * 4 * (size_t)(ncell / 4096 + 2) : 0);
+    // counts per (bucket, block), then their exclusive scan (+ total) in place of a copy
+    L.off_bin = take(bin_n > 0 ? sizeof(int32_t) * (size_t)(2 * bin_n + 1) : 0);
     L.total = o;
     return L;
 }
@@ -208,6 +215,7 @@ Work resolve(const fof_grid *g, void *ws)
     w.edges = (int2 *)(base + L.off_edges);
     w.cursors = (int32_t *)(base + L.off_cursors);
     w.classify = (int32_t *)(base + L.off_classify);
+    w.bin_hist = (int32_t *)(base + L.off_bin);
     w.edge_cap = (int32_t)L.edge_cap;
     w.dense_threshold = g->dense_threshold;
     w.dense_cap = (int32_t)g->dense_cap;

@@ -1,10 +1,24 @@
-// Cell binning as a counting sort (paper Alg. 2: cell indexing with x fastest, then the
-// particles sorted by cell).  Three steps:
-//   count    validate the coordinate, compute the coarse cell, take a rank inside the cell
-//            with one atomic increment of the cell counter;
-//   scan     exclusive scan of the counters gives cell_start;
-//   scatter  sorted[cell_start[c] + rank] = (x, y, z, original index), and the union-find
-//            entry of that sorted slot is initialised to itself.
+// Cell binning as a counting sort (paper Alg. 2: cell indexing, then the particles sorted
+// by cell).
+//
+// Bucketed form (every grid of up to kBinMaxBuckets << kBinMaxShift cells).  Cells are
+// grouped into buckets of 2^shift consecutive ids; G blocks each own one contiguous chunk of
+// the input.  No global atomics:
+//   k_bin_count  per block, an LDS histogram of its particles over buckets (also validates
+//                the coordinates), written out as column g of a [bucket][block] table;
+//   scan         exclusive scan of the table: where each block's share of each bucket goes;
+//   k_bin_place  per block, LDS cursors from the scanned table; every particle goes, as
+//                (x, y, z, input index), to its bucket's slot of the staging array;
+//   k_bin_sort   one block per bucket: reads its particles (coalesced, into registers),
+//                counts them per cell in LDS, scans (cell_start of the bucket's cells), then
+//                writes sorted[dst] and the union-find entry of dst, all inside the bucket's
+//                own stretch of the output.
+// Particles stored in lattice order land in few buckets per block, so the staging writes and
+// the final scatter stay local, whatever the displacement of each particle from its cell.
+//
+// Per-particle form (larger grids): one atomic increment per particle gives its rank in the
+// cell, a scan gives cell_start, and a scatter writes the sorted copy.
+//
 // Within a cell the order is whatever the atomics produced; no result depends on it.
 #include "fof_internal.h"
 
@@ -66,6 +80,180 @@ __global__ void k_scatter(const float *__restrict__ pos, int64_t n,
     parent[dst] = ((uint64_t)(uint32_t)i << 32) | (uint32_t)dst;
 }
 
+constexpr int kBinBlock = 1024;  // k_bin_count / k_bin_place
+constexpr int kSortBlock = 1024;  // k_bin_sort
+constexpr int kSortPer = 16;     // particles per k_bin_sort thread held in registers
+
+__device__ __forceinline__ CellOf particle_cell(const float *__restrict__ pos,
+                                                const BoxDesc *__restrict__ desc, int nbox,
+                                                int64_t i, float &x, float &y, float &z)
+{
+    const BoxDesc &B = desc[find_box(desc, nbox, i)];
+    x = pos[3 * i + 0];
+    y = pos[3 * i + 1];
+    z = pos[3 * i + 2];
+    return cell_of(B, x, y, z);
+}
+
+__global__ __launch_bounds__(kBinBlock) void k_bin_count(const float *__restrict__ pos,
+                                                         const BoxDesc *__restrict__ desc,
+                                                         int nbox, int64_t n, BinShape bs,
+                                                         int32_t *__restrict__ hist,
+                                                         Counters *__restrict__ ctr)
+{
+    extern __shared__ int32_t lh[];  // bs.nbk counters
+    for (int64_t k = threadIdx.x; k < bs.nbk; k += kBinBlock)
+        lh[k] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * bs.chunk;
+    const int64_t i1 = i0 + bs.chunk < n ? i0 + bs.chunk : n;
+    bool bad = false;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBinBlock) {
+        float x, y, z;
+        const CellOf c = particle_cell(pos, desc, nbox, i, x, y, z);
+        bad |= !c.ok;
+        atomicAdd(lh + (c.cell >> bs.shift), 1);
+    }
+    if (bad)
+        atomicOr(&ctr->status, (int32_t)FOF_STATUS_RANGE);
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < bs.nbk; k += kBinBlock)
+        hist[k * bs.G + blockIdx.x] = lh[k];
+}
+
+__global__ __launch_bounds__(kBinBlock) void k_bin_place(const float *__restrict__ pos,
+                                                         const BoxDesc *__restrict__ desc,
+                                                         int nbox, int64_t n, BinShape bs,
+                                                         const int32_t *__restrict__ off,
+                                                         float4 *__restrict__ stage)
+{
+    extern __shared__ int32_t cur[];  // bs.nbk cursors
+    for (int64_t k = threadIdx.x; k < bs.nbk; k += kBinBlock)
+        cur[k] = off[k * bs.G + blockIdx.x];
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * bs.chunk;
+    const int64_t i1 = i0 + bs.chunk < n ? i0 + bs.chunk : n;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBinBlock) {
+        float x, y, z;
+        const CellOf c = particle_cell(pos, desc, nbox, i, x, y, z);
+        stage[atomicAdd(cur + (c.cell >> bs.shift), 1)] =
+            make_float4(x, y, z, __int_as_float((int32_t)i));
+    }
+}
+
+// Exclusive scan of one int per thread over a kSortBlock-thread block.
+__device__ __forceinline__ int32_t sort_block_scan(int32_t v, int32_t *wsum)
+{
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    int32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t y = __shfl_up(x, o, kWave);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == kWave - 1)
+        wsum[wid] = x;
+    __syncthreads();
+    int32_t pre = 0;
+    for (int k = 0; k < wid; ++k)
+        pre += wsum[k];
+    __syncthreads();
+    return pre + x - v;
+}
+
+// Cell of a staged particle relative to the bucket's first cell (coordinates were already
+// made valid by the placing pass, so this is the cell that pass used).
+__device__ __forceinline__ int staged_cell(const BoxDesc *__restrict__ desc, int nbox,
+                                           float4 p, int64_t c0)
+{
+    const BoxDesc &B = desc[find_box(desc, nbox, __float_as_int(p.w))];
+    return (int)(cell_of(B, p.x, p.y, p.z).cell - c0);
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_bin_sort(const BoxDesc *__restrict__ desc,
+                                                         int nbox, int64_t ncell, BinShape bs,
+                                                         const int32_t *__restrict__ off,
+                                                         const float4 *__restrict__ stage,
+                                                         int32_t *__restrict__ cell_start,
+                                                         float4 *__restrict__ sorted,
+                                                         uint64_t *__restrict__ parent)
+{
+    extern __shared__ int32_t lc[];  // 2^shift per-cell counters, then cursors
+    __shared__ int32_t wsum[kSortBlock / kWave];
+    constexpr int64_t kCap = (int64_t)kSortBlock * kSortPer;
+    const int64_t b = blockIdx.x;
+    const int64_t c0 = b << bs.shift;
+    const int nc = (int)((c0 + (1ll << bs.shift) < ncell ? (1ll << bs.shift) : ncell - c0));
+    const int64_t base = off[b * bs.G], end = off[(b + 1) * bs.G];
+    for (int k = threadIdx.x; k < nc; k += kSortBlock)
+        lc[k] = 0;
+    __syncthreads();
+    // Items k0 + threadIdx.x + r * kSortBlock (r < kSortPer) of a chunk live in registers; a
+    // bucket of at most kCap particles is read once, larger ones chunk by chunk, twice.
+    float4 it[kSortPer];
+    int cl[kSortPer];
+    for (int64_t k0 = base; k0 < end; k0 += kCap) {
+#pragma unroll
+        for (int r = 0; r < kSortPer; ++r) {
+            const int64_t k = k0 + threadIdx.x + (int64_t)r * kSortBlock;
+            if (k < end)
+                it[r] = stage[k];
+        }
+#pragma unroll
+        for (int r = 0; r < kSortPer; ++r) {
+            const int64_t k = k0 + threadIdx.x + (int64_t)r * kSortBlock;
+            if (k < end) {
+                cl[r] = staged_cell(desc, nbox, it[r], c0);
+                atomicAdd(lc + cl[r], 1);
+            }
+        }
+    }
+    __syncthreads();
+    // exclusive scan: thread t owns cells [t * per, (t + 1) * per)
+    const int per = (nc + kSortBlock - 1) / kSortBlock;
+    const int j0 = threadIdx.x * per;
+    const int j1 = j0 + per < nc ? j0 + per : nc;
+    int32_t sum = 0;
+    for (int j = j0; j < j1; ++j)
+        sum += lc[j];
+    int32_t run = (int32_t)base + sort_block_scan(sum, wsum);
+    for (int j = j0; j < j1; ++j) {
+        const int32_t v = lc[j];
+        lc[j] = run;
+        run += v;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nc; j += kSortBlock)
+        cell_start[c0 + j] = lc[j];
+    if (c0 + nc == ncell && threadIdx.x == 0)
+        cell_start[ncell] = (int32_t)end;
+    __syncthreads();
+    const bool one_chunk = end - base <= kCap;
+    for (int64_t k0 = base; k0 < end; k0 += kCap) {
+        if (!one_chunk) {
+#pragma unroll
+            for (int r = 0; r < kSortPer; ++r) {
+                const int64_t k = k0 + threadIdx.x + (int64_t)r * kSortBlock;
+                if (k < end) {
+                    it[r] = stage[k];
+                    cl[r] = staged_cell(desc, nbox, it[r], c0);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kSortPer; ++r) {
+            const int64_t k = k0 + threadIdx.x + (int64_t)r * kSortBlock;
+            if (k < end) {
+                const int32_t dst = atomicAdd(lc + cl[r], 1);
+                const uint32_t i = (uint32_t)__float_as_int(it[r].w);
+                sorted[dst] = it[r];
+                parent[dst] = ((uint64_t)i << 32) | (uint32_t)dst;
+            }
+        }
+    }
+}
+
 __global__ void k_clear_counters(Counters *ctr)
 {
     if (threadIdx.x < sizeof(Counters) / sizeof(int32_t))
@@ -77,27 +265,40 @@ __global__ void k_clear_counters(Counters *ctr)
 hipError_t launch_build(const Work &w, const float *pos, hipStream_t s)
 {
     hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, s, w.ctr);
-    hipError_t e = launch_fill_i32(w.cell_count, w.ncell, 0, s);
-    if (e != hipSuccess)
-        return e;
-    if (w.n > 0) {
-        unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
-        hipLaunchKernelGGL(k_count, dim3(nb), dim3(w.block), 0, s, pos, w.n, w.desc, w.nbox,
-                           w.cell_count, w.rank, w.ctr);
-    }
-    e = launch_scan_i32(w.cell_count, w.cell_start, w.ncell, w.scan, s);
-    if (e != hipSuccess)
-        return e;
-    if (w.n > 0) {
-        unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
-        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(w.block), 0, s, pos, w.n, w.desc, w.nbox,
-                           w.cell_start, w.rank, w.sorted, w.parent);
-        e = hipGetLastError();
+    hipError_t e;
+    if (w.n <= 0)  // every cell empty
+        return launch_fill_i32(w.cell_start, w.ncell + 1, 0, s);
+    const BinShape bs = bin_shape(w.n, w.ncell);
+    if (bs.ok) {
+        int32_t *hist = w.bin_hist, *off = w.bin_hist + bs.nbk * bs.G;
+        const size_t lds_b = sizeof(int32_t) * (size_t)bs.nbk;
+        hipLaunchKernelGGL(k_bin_count, dim3(bs.G), dim3(kBinBlock), lds_b, s, pos, w.desc,
+                           w.nbox, w.n, bs, hist, w.ctr);
+        e = launch_scan_i32(hist, off, bs.nbk * bs.G, w.scan, s);
         if (e != hipSuccess)
             return e;
-        return launch_dense_build(w, s);
+        hipLaunchKernelGGL(k_bin_place, dim3(bs.G), dim3(kBinBlock), lds_b, s, pos, w.desc,
+                           w.nbox, w.n, bs, off, w.temp);
+        hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)bs.nbk), dim3(kSortBlock),
+                           sizeof(int32_t) << bs.shift, s, w.desc, w.nbox, w.ncell, bs, off,
+                           w.temp, w.cell_start, w.sorted, w.parent);
+    } else {
+        e = launch_fill_i32(w.cell_count, w.ncell, 0, s);
+        if (e != hipSuccess)
+            return e;
+        const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
+        hipLaunchKernelGGL(k_count, dim3(nb), dim3(w.block), 0, s, pos, w.n, w.desc, w.nbox,
+                           w.cell_count, w.rank, w.ctr);
+        e = launch_scan_i32(w.cell_count, w.cell_start, w.ncell, w.scan, s);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(w.block), 0, s, pos, w.n, w.desc, w.nbox,
+                           w.cell_start, w.rank, w.sorted, w.parent);
     }
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return launch_dense_build(w, s);
 }
 
 }  // namespace fof

@@ -320,6 +320,37 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 // Host-side launchers (defined in the .hip files, called by the entry points).
 // ---------------------------------------------------------------------------------------
 namespace fof {
+// Shape of the bucketed cell binning (fof_build.hip): cells are grouped into buckets of
+// 2^shift consecutive cell ids (at most kBinMaxBuckets of them, each at most
+// 2^kBinMaxShift cells, so both per-block tables fit in LDS); G blocks each stream one
+// contiguous chunk of particles.  ok = false: too many cells, the per-particle counting
+// sort is used instead.
+constexpr int kBinMaxBuckets = 16384;
+constexpr int kBinMaxShift = 13;
+constexpr int kBinMaxBlocks = 512;
+
+struct BinShape {
+    int shift;
+    int G;
+    int64_t nbk;
+    int64_t chunk;
+    bool ok;
+};
+
+__host__ __device__ inline BinShape bin_shape(int64_t n, int64_t ncell)
+{
+    BinShape b;
+    b.shift = 6;
+    while (b.shift < kBinMaxShift && ((ncell + (1ll << b.shift) - 1) >> b.shift) > kBinMaxBuckets)
+        ++b.shift;
+    b.nbk = (ncell + (1ll << b.shift) - 1) >> b.shift;
+    b.ok = n > 0 && ncell > 0 && b.nbk <= kBinMaxBuckets;
+    int64_t g = (n + 65535) / 65536;
+    b.G = (int)(g < 1 ? 1 : (g > kBinMaxBlocks ? kBinMaxBlocks : g));
+    b.chunk = (n + b.G - 1) / b.G;
+    return b;
+}
+
 struct Work {  // device pointers resolved from a fof_grid and a workspace base
     const BoxDesc *desc;
     Counters *ctr;
@@ -344,6 +375,7 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
     int32_t edge_cap;
     int32_t *cursors;     // work cursors of the dense passes, kCursorStride ints apart
     int32_t *classify;    // per-chunk dense / big counts and their scans (binning)
+    int32_t *bin_hist;    // bucketed binning: per (bucket, block) counts, then their scan
     int32_t nbox;
     int32_t block;
     int64_t n;
