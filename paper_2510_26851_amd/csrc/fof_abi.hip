@@ -85,6 +85,7 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
         d->nf[a] = d->nc[a] * m;
         d->L[a] = bx.L[a];
         d->halfL[a] = 0.5 * bx.L[a];
+        d->Lup[a] = round_up_f(bx.L[a]);
         d->inv_fine[a] = (float)((double)d->nf[a] / bx.L[a]);
         d->side[a] = (float)(bx.L[a] / (double)d->nc[a]);
     }

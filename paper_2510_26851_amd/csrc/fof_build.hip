@@ -35,18 +35,35 @@ struct CellOf {
 // place, so every later kernel sees in-range positions; the status word reports them.
 __device__ __forceinline__ CellOf cell_of(const BoxDesc &B, float &x, float &y, float &z)
 {
-    // Valid coordinates are finite and 0 <= x < L, compared in double (NaN fails).
-    bool ok = ((double)x >= 0.0) & ((double)x < B.L[0]) & ((double)y >= 0.0) &
-              ((double)y < B.L[1]) & ((double)z >= 0.0) & ((double)z < B.L[2]);
-    if (!ok) {  // keep the index in range; the status word reports the bad input
-        x = (x >= 0.0f && x < (float)B.L[0]) ? x : 0.0f;
-        y = (y >= 0.0f && y < (float)B.L[1]) ? y : 0.0f;
-        z = (z >= 0.0f && z < (float)B.L[2]) ? z : 0.0f;
-    }
+    // Valid coordinates are 0 <= x < L (NaN fails).  For a float x, x < L holds exactly when
+    // x < Lup, the smallest float >= L, so the test needs no double arithmetic.
+    const bool okx = (x >= 0.0f) & (x < B.Lup[0]);
+    const bool oky = (y >= 0.0f) & (y < B.Lup[1]);
+    const bool okz = (z >= 0.0f) & (z < B.Lup[2]);
+    x = okx ? x : 0.0f;
+    y = oky ? y : 0.0f;
+    z = okz ? z : 0.0f;
     int ix = fine_index(x, B.inv_fine[0], B.nf[0]) / B.m;
     int iy = fine_index(y, B.inv_fine[1], B.nf[1]) / B.m;
     int iz = fine_index(z, B.inv_fine[2], B.nf[2]) / B.m;
-    return {coarse_cell(B, ix, iy, iz), ok};
+    return {coarse_cell(B, ix, iy, iz), okx && oky && okz};
+}
+
+// Calls f with the descriptor of particle i's box.  When every active lane of the wave lies
+// in the box of the wave's first active lane (the usual case), that descriptor is found and
+// read with scalar loads; otherwise each lane searches for its own.
+template <class F>
+__device__ __forceinline__ void with_box(const BoxDesc *__restrict__ desc, int nbox, int64_t i,
+                                         F &&f)
+{
+    const int64_t i0 =
+        (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(i >> 32)) << 32) |
+                  (uint32_t)__builtin_amdgcn_readfirstlane((int)i));
+    const BoxDesc &B0 = desc[find_box(desc, nbox, i0)];
+    if (ballot(i < B0.off || i >= B0.off + B0.n) == 0)
+        f(B0);
+    else
+        f(desc[find_box(desc, nbox, i)]);
 }
 
 __global__ void k_count(const float *__restrict__ pos, int64_t n, const BoxDesc *__restrict__ desc,
@@ -84,15 +101,28 @@ constexpr int kBinBlock = 1024;  // k_bin_count / k_bin_place
 constexpr int kSortBlock = 1024;  // k_bin_sort
 constexpr int kSortPer = 16;     // particles per k_bin_sort thread held in registers
 
-__device__ __forceinline__ CellOf particle_cell(const float *__restrict__ pos,
-                                                const BoxDesc *__restrict__ desc, int nbox,
-                                                int64_t i, float &x, float &y, float &z)
+constexpr int kBinUnroll = 4;  // particles per thread whose loads are issued together
+
+// Positions of particles r + threadIdx.x + u * kBinBlock (u < kBinUnroll) below i1, loaded
+// before any is used, so that each thread keeps several loads in flight.
+struct BinBatch {
+    float x[kBinUnroll], y[kBinUnroll], z[kBinUnroll];
+};
+
+__device__ __forceinline__ BinBatch load_batch(const float *__restrict__ pos, int64_t r,
+                                               int64_t i1)
 {
-    const BoxDesc &B = desc[find_box(desc, nbox, i)];
-    x = pos[3 * i + 0];
-    y = pos[3 * i + 1];
-    z = pos[3 * i + 2];
-    return cell_of(B, x, y, z);
+    BinBatch q;
+#pragma unroll
+    for (int u = 0; u < kBinUnroll; ++u) {
+        const int64_t i = r + threadIdx.x + (int64_t)u * kBinBlock;
+        if (i < i1) {
+            q.x[u] = pos[3 * i + 0];
+            q.y[u] = pos[3 * i + 1];
+            q.z[u] = pos[3 * i + 2];
+        }
+    }
+    return q;
 }
 
 __global__ __launch_bounds__(kBinBlock) void k_bin_count(const float *__restrict__ pos,
@@ -108,11 +138,18 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_count(const float *__restrict
     const int64_t i0 = (int64_t)blockIdx.x * bs.chunk;
     const int64_t i1 = i0 + bs.chunk < n ? i0 + bs.chunk : n;
     bool bad = false;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBinBlock) {
-        float x, y, z;
-        const CellOf c = particle_cell(pos, desc, nbox, i, x, y, z);
-        bad |= !c.ok;
-        atomicAdd(lh + (c.cell >> bs.shift), 1);
+    for (int64_t r = i0; r < i1; r += (int64_t)kBinBlock * kBinUnroll) {
+        BinBatch q = load_batch(pos, r, i1);
+#pragma unroll
+        for (int u = 0; u < kBinUnroll; ++u) {
+            const int64_t i = r + threadIdx.x + (int64_t)u * kBinBlock;
+            if (i < i1)
+                with_box(desc, nbox, i, [&](const BoxDesc &B) {
+                    const CellOf c = cell_of(B, q.x[u], q.y[u], q.z[u]);
+                    bad |= !c.ok;
+                    atomicAdd(lh + (c.cell >> bs.shift), 1);
+                });
+        }
     }
     if (bad)
         atomicOr(&ctr->status, (int32_t)FOF_STATUS_RANGE);
@@ -133,11 +170,18 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_place(const float *__restrict
     __syncthreads();
     const int64_t i0 = (int64_t)blockIdx.x * bs.chunk;
     const int64_t i1 = i0 + bs.chunk < n ? i0 + bs.chunk : n;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBinBlock) {
-        float x, y, z;
-        const CellOf c = particle_cell(pos, desc, nbox, i, x, y, z);
-        stage[atomicAdd(cur + (c.cell >> bs.shift), 1)] =
-            make_float4(x, y, z, __int_as_float((int32_t)i));
+    for (int64_t r = i0; r < i1; r += (int64_t)kBinBlock * kBinUnroll) {
+        BinBatch q = load_batch(pos, r, i1);
+#pragma unroll
+        for (int u = 0; u < kBinUnroll; ++u) {
+            const int64_t i = r + threadIdx.x + (int64_t)u * kBinBlock;
+            if (i < i1)
+                with_box(desc, nbox, i, [&](const BoxDesc &B) {
+                    const CellOf c = cell_of(B, q.x[u], q.y[u], q.z[u]);
+                    stage[atomicAdd(cur + (c.cell >> bs.shift), 1)] =
+                        make_float4(q.x[u], q.y[u], q.z[u], __int_as_float((int32_t)i));
+                });
+        }
     }
 }
 
@@ -167,8 +211,11 @@ __device__ __forceinline__ int32_t sort_block_scan(int32_t v, int32_t *wsum)
 __device__ __forceinline__ int staged_cell(const BoxDesc *__restrict__ desc, int nbox,
                                            float4 p, int64_t c0)
 {
-    const BoxDesc &B = desc[find_box(desc, nbox, __float_as_int(p.w))];
-    return (int)(cell_of(B, p.x, p.y, p.z).cell - c0);
+    int lc = 0;
+    with_box(desc, nbox, __float_as_int(p.w), [&](const BoxDesc &B) {
+        lc = (int)(cell_of(B, p.x, p.y, p.z).cell - c0);
+    });
+    return lc;
 }
 
 __global__ __launch_bounds__(kSortBlock) void k_bin_sort(const BoxDesc *__restrict__ desc,

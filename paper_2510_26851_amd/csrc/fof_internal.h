@@ -51,6 +51,7 @@ struct alignas(16) BoxDesc {
     float fine_side;    // smallest fine cell side less the index error (float, rounded down)
     float fine[3];      // fine cell side per axis, L / nf (float)
     float slack;        // margin added to fine-cell boxes before a distance skip
+    float Lup[3];       // smallest float >= L: a float x is below L exactly when x < Lup
 };
 
 // Status bits (public values in fof.h) and the counters block.

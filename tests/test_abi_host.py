@@ -63,7 +63,7 @@ def plan(counts, boxes, tune=None, desc=True):
 # BoxDesc layout (fof_internal.h): int64 off, cell_base, tile_base; int32 n, m, nc[3], nf[3],
 # R, dense_ok, tiled, ntile[3]; double L[3], halfL[3], b2; float inv_fine[3], side[3],
 # reach, fine_side, fine[3], slack.
-_DESC = struct.Struct("<qqqii3i3iiii3i3d3dd3f3fff3ff")
+_DESC = struct.Struct("<qqqii3i3iiii3i3d3dd3f3fff3ff3f")
 
 
 def desc_stride():
@@ -76,7 +76,17 @@ def decode(buf, k=0):
     return dict(off=v[0], cell_base=v[1], tile_base=v[2], n=v[3], m=v[4], nc=v[5:8],
                 nf=v[8:11], R=v[11], dense_ok=v[12], tiled=v[13], ntile=v[14:17], L=v[17:20],
                 halfL=v[20:23], b2=v[23], inv_fine=v[24:27], side=v[27:30], reach=v[30],
-                fine_side=v[31], fine=v[32:35], slack=v[35])
+                fine_side=v[31], fine=v[32:35], slack=v[35], Lup=v[36:39])
+
+
+@pytest.mark.parametrize("L", [512.0, 64.0, 0.7, 50.397, 1.0 / 3.0, 123456.789])
+def test_float_bound_of_the_box_length(L):
+    """Lup is the smallest float >= L, so the binning's float test x < Lup accepts exactly
+    the floats x with x < L in exact arithmetic."""
+    rc, g, buf = plan([10], [(L, L / 8)])
+    assert rc == 0
+    up = np.float32(decode(buf)["Lup"][0])
+    assert float(up) >= L and float(np.nextafter(up, np.float32(0))) < L
 
 
 def test_descriptor_size():

@@ -186,3 +186,37 @@ def test_overflow_paths_of_the_tiled_link(tune):
     say(f"overflow paths {tune}")
     pos = W.clumpy_box(100000, 20.0, 30, 41)
     compare_with_oracle(pos, 20.0, 0.3, 5, tune=tune)
+
+
+def test_grid_over_2_27_cells_takes_the_per_particle_binning():
+    """A grid of more than 2^27 cells is binned with one rank atomic per particle instead of
+    the bucketed counting sort.  Labels do not depend on the cell side, so a run with such a
+    grid must match, bit for bit, a run of the same particles at the default side (which is
+    binned through buckets and checked against the oracle above)."""
+    import torch
+    from paper_2510_26851_amd import Plan, trim
+
+    n, L = 17_000_000, 256.0
+    b = W.linking_length(0.2, L, n)
+    pos = W.clumpy_box(n, L, 4000, 51)
+    t = torch.from_numpy(pos).to("cuda:0")
+    runs = []
+    for side, over in [(0.25, True), (0.0, False)]:
+        say(f"per-particle binning check: n={n} cell_side={side}")
+        plan = Plan([n], [(L, b)], device=t.device, tune=dict(cell_side=side))
+        assert (plan.grid.ncell > (1 << 27)) == over, plan.grid.ncell
+        plan.build_grid(t)
+        root = plan.link()
+        res = trim(plan.groups(20))
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        runs.append((root.cpu().numpy(),
+                     {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}))
+        del plan, root, res
+    (r0, g0), (r1, g1) = runs
+    np.testing.assert_array_equal(r0, r1)
+    assert g0["n_groups"] == g1["n_groups"] > 0
+    np.testing.assert_array_equal(g0["group_id"], g1["group_id"])
+    np.testing.assert_array_equal(g0["sizes"], g1["sizes"])
+    from gpu_util import com_close
+    assert com_close(g0["com"], g1["com"], L, L / n ** (1 / 3))
