@@ -422,17 +422,49 @@ struct CellLds {
     int uf[UMAX];                   // union-find over unit ranks
     unsigned long long umin[UMAX];  // (original index << 32 | sorted index) minimum
     int ustart[UMAX + 1];           // absolute sorted index of each unit's first member
-    int umark[UMAX];                // unit counts per root, then "outside the largest component"
+    int umark[UMAX];                // unit counts per root, then the units outside the giant
     short uxyz[UMAX];               // fine coordinates: x | y << 4 | z << 8
     short ucomp[UMAX];              // component number of each unit
     uint32_t bits[kMaxTableWords];  // key bitmask of the cell (or of a neighbour, in cross)
     int pre[kMaxTableWords];
     uint32_t pairbits[32];
-    int ncomp, nnb, done, giant;
+    int ncomp, nnb, done, giant, nmark;
     int nb[26];                     // neighbour dense ids (cross), or sparse cell starts
     short nbo[26];                  // their offsets: (ox+1) | (oy+1) << 2 | (oz+1) << 4
     int nbp[27];                    // sparse neighbours: running particle count
+#ifdef FOF_TIMING
+    long long phase[8], tlast;      // diagnostic builds: clock ticks per phase of a pass
+#endif
 };
+
+#ifdef FOF_TIMING
+#define FOF_PHASE(L, lead, k)                                                                 \
+    do {                                                                                      \
+        if (lead) {                                                                           \
+            const long long now_ = clock64();                                                 \
+            (L).phase[k] += now_ - (L).tlast;                                                 \
+            (L).tlast = now_;                                                                 \
+        }                                                                                     \
+    } while (0)
+#define FOF_PHASE_START(L, lead)                                                              \
+    do {                                                                                      \
+        if (lead) {                                                                           \
+            for (int k_ = 0; k_ < 8; ++k_)                                                    \
+                (L).phase[k_] = 0;                                                            \
+            (L).tlast = clock64();                                                            \
+        }                                                                                     \
+    } while (0)
+#define FOF_PHASE_FLUSH(L, lead, ctr, base)                                                   \
+    do {                                                                                      \
+        if (lead)                                                                             \
+            for (int k_ = 0; k_ < 8; ++k_)                                                    \
+                atomicAdd(&(ctr)->stats[(base) + k_], (unsigned long long)(L).phase[k_]);     \
+    } while (0)
+#else
+#define FOF_PHASE(L, lead, k) ((void)0)
+#define FOF_PHASE_START(L, lead) ((void)0)
+#define FOF_PHASE_FLUSH(L, lead, ctr, base) ((void)0)
+#endif
 
 __device__ __forceinline__ int rank_in(const uint32_t *bits, const int *pre, int k)
 {
@@ -567,11 +599,13 @@ __device__ __forceinline__ int gap_budget(const BoxDesc &B)
 }
 
 // Joins units of the staged cell with their neighbour units.  pass 0: every unit, the
-// forward half of the nearest shell (offsets in [-1, 1]^3).  pass 1: marked units only,
-// every offset in [-R, R]^3 outside the nearest shell, in both directions (a pair with an
-// unmarked end is then still examined from the other).  The occupied neighbours of one
-// fine row are read as a bit field of the key bitmask, so empty fine cells cost nothing.
-// A pair already in one component is skipped, otherwise its first friend pair joins it.
+// forward half of the nearest shell (offsets in [-1, 1]^3).  pass 1: the units listed in
+// umark[0, nmark) (those outside the largest component), every offset in [-R, R]^3 outside
+// the nearest shell, in both directions (a pair with an unlisted end is then still examined
+// from the other).  The work items are (unit, fine row of offsets) pairs spread over all
+// threads; the occupied neighbours of one row are read as a bit field of the key bitmask,
+// so empty fine cells cost nothing.  A pair already in one component is skipped, otherwise
+// its first friend pair joins it.
 template <int G, int UMAX, int CAP>
 __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const CellXYZ &cc,
                            int m, int R, int u, int32_t s, const float4 *mem,
@@ -579,54 +613,54 @@ __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const
 {
     const int W = w.table_words;
     const int reach = pass == 0 ? 1 : R;
-    for (int r = Grp<G>::tid(); r < u; r += G) {
-        if (pass == 1 && !L.umark[r])
-            continue;
+    const int span = 2 * reach + 1;
+    const int rows = pass == 0 ? 5 : span * span;  // (dz, dy) rows per unit
+    const int nitems = (pass == 0 ? u : L.nmark) * rows;
+    for (int item = Grp<G>::tid(); item < nitems; item += G) {
+        const int r = pass == 0 ? item / rows : L.umark[item / rows];
+        const int q = item % rows;
+        int dz, dy;
+        if (pass == 0) {  // forward rows: (0, 0) with dx > 0, (0, 1), (1, -1), (1, 0), (1, 1)
+            dz = q < 2 ? 0 : 1;
+            dy = q < 2 ? q : q - 3;
+        } else {
+            dz = q / span - reach;
+            dy = q % span - reach;
+        }
         const int xyz = L.uxyz[r];
         const int ax = xyz & 15, ay = (xyz >> 4) & 15, az = xyz >> 8;
-        for (int dz = -reach; dz <= reach; ++dz) {
-            const int bz = az + dz;
-            if (bz < 0 || bz >= m)
+        const int bz = az + dz, by = ay + dy;
+        if (bz < 0 || bz >= m || by < 0 || by >= m)
+            continue;
+        int lo = -reach, hi = reach;  // dx range of this row
+        if (pass == 0 && q == 0)
+            lo = 1;
+        const bool skip_core = pass == 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+        lo = max(lo, -ax);
+        hi = min(hi, m - 1 - ax);
+        if (lo > hi)
+            continue;
+        const int key0 = (bz * m + by) * m + ax + lo, nb = hi - lo + 1;
+        uint32_t row = row_bits(L.bits, W, key0, nb);
+        if (skip_core)  // positions of dx = -1, 0, 1 relative to lo
+            for (int dx = -1; dx <= 1; ++dx)
+                if (dx >= lo && dx <= hi)
+                    row &= ~(1u << (dx - lo));
+        while (row) {
+            const int bpos = __ffs(row) - 1;
+            row &= row - 1u;
+            const int bx = ax + lo + bpos;
+            const int kb = key0 + bpos;
+            const int rb = rank_in(L.bits, L.pre, kb);
+            if (lfind(L.uf, r) == lfind(L.uf, rb)) {
+                FOF_STAT(w.ctr, ST_CC_SKIPS, 1);
                 continue;
-            for (int dy = -reach; dy <= reach; ++dy) {
-                const int by = ay + dy;
-                if (by < 0 || by >= m)
-                    continue;
-                int lo = -reach, hi = reach;  // dx range of this row
-                bool skip_core = false;       // drop dx in [-1, 1] (pass 1, near rows)
-                if (pass == 0) {
-                    if (dz < 0 || (dz == 0 && dy < 0))
-                        continue;  // backward rows
-                    if (dz == 0 && dy == 0)
-                        lo = 1;
-                } else {
-                    skip_core = dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
-                }
-                lo = max(lo, -ax);
-                hi = min(hi, m - 1 - ax);
-                if (lo > hi)
-                    continue;
-                const int key0 = (bz * m + by) * m + ax + lo, nb = hi - lo + 1;
-                uint32_t row = row_bits(L.bits, W, key0, nb);
-                if (skip_core)  // positions of dx = -1, 0, 1 relative to lo
-                    for (int dx = -1; dx <= 1; ++dx)
-                        if (dx >= lo && dx <= hi)
-                            row &= ~(1u << (dx - lo));
-                while (row) {
-                    const int bpos = __ffs(row) - 1;
-                    row &= row - 1u;
-                    const int bx = ax + lo + bpos;
-                    const int kb = key0 + bpos;
-                    const int rb = rank_in(L.bits, L.pre, kb);
-                    if (lfind(L.uf, r) == lfind(L.uf, rb))
-                        continue;
-                    const FineBox fb = fine_box(B, cc.x * m + bx, cc.y * m + by, cc.z * m + bz);
-                    FOF_STAT(w.ctr, ST_CC_UNIT_PAIRS, 1);
-                    if (units_meet(B, P, mem, L.ustart[r] - s, L.ustart[r + 1] - s, mem,
-                                   L.ustart[rb] - s, L.ustart[rb + 1] - s, fb))
-                        lunion(L.uf, r, rb);
-                }
             }
+            const FineBox fb = fine_box(B, cc.x * m + bx, cc.y * m + by, cc.z * m + bz);
+            FOF_STAT(w.ctr, ST_CC_UNIT_PAIRS, 1);
+            if (units_meet(B, P, mem, L.ustart[r] - s, L.ustart[r + 1] - s, mem,
+                           L.ustart[rb] - s, L.ustart[rb + 1] - s, fb))
+                lunion(L.uf, r, rb);
         }
     }
 }
@@ -649,6 +683,7 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     if (t == 0)
         L.ncomp = 0;
     load_units<G>(w, T, s, n, m, u, L);
+    FOF_PHASE(L, t == 0, 0);
 
     // unit minima
     for (int r = t; r < u; r += G) {
@@ -662,11 +697,13 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
         L.uf[r] = r;
     }
     Grp<G>::sync();
+    FOF_PHASE(L, t == 0, 1);
 
     // join units of this cell: first friend pair wins.  The nearest shell goes first; when
     // it already leaves one component (the usual case inside a clump) the rest is skipped.
     join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 0);
     Grp<G>::sync();
+    FOF_PHASE(L, t == 0, 2);
     // components after the nearest shell: a far pair of two different components has at
     // least one end outside the largest one, so only those units search the far offsets
     if (t == 0) {
@@ -688,14 +725,22 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
             atomicMax(&L.giant, (L.umark[r] << 16) | r);  // unit count < 2^15, r < 2^16
     Grp<G>::sync();
     const bool far = L.ncomp > 1;  // uniform: every thread reads the same count
+    FOF_PHASE(L, t == 0, 3);
+    if (far && t == 0)
+        FOF_STAT(w.ctr, ST_CC_FAR_CELLS, 1);
     if (far) {
         const int giant = L.giant & 0xFFFF;
-        for (int r = t; r < u; r += G)
-            L.umark[r] = lfind(L.uf, r) != giant;
+        if (t == 0)
+            L.nmark = 0;
+        Grp<G>::sync();
+        for (int r = t; r < u; r += G)  // umark becomes the list of units outside the giant
+            if (lfind(L.uf, r) != giant)
+                L.umark[atomicAdd(&L.nmark, 1)] = r;
         Grp<G>::sync();
         join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 1);
     }
     Grp<G>::sync();
+    FOF_PHASE(L, t == 0, 4);
     if (t == 0)
         L.ncomp = 0;
     Grp<G>::sync();
@@ -709,6 +754,7 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
             L.ucomp[r] = (short)atomicAdd(&L.ncomp, 1);
     }
     Grp<G>::sync();
+    FOF_PHASE(L, t == 0, 5);
 
     // every member points at its component's smallest original index
     for (int r = t; r < u; r += G) {
@@ -728,6 +774,7 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     if (t == 0)
         T[1] = L.ncomp;
     Grp<G>::sync();
+    FOF_PHASE(L, t == 0, 6);
 }
 
 template <int G, int UMAX, int CAP>
@@ -1068,6 +1115,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
     const int nworkers = gridDim.x * Grp<kWave>::per_block;
     const int worker = blockIdx.x * Grp<kWave>::per_block + Grp<kWave>::slot();
     const Deal dl = deal(w.cursors, 2 * kMode, worker, nworkers);
+    FOF_PHASE_START(L, lane_id() == 0);
     int d = deal_first(dl, worker);
     while (d < nd) {
         const int64_t c = w.dense_list[d];
@@ -1083,7 +1131,14 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
         if (lane_id() == 0)
             nx = deal_next(dl, nd);
         d = __shfl(nx, 0, kWave);
+        FOF_PHASE(L, lane_id() == 0, 7);
     }
+    FOF_PHASE(L, lane_id() == 0, 7);
+    FOF_PHASE_FLUSH(L, lane_id() == 0 && kMode == 0, w.ctr, 0);
+#ifdef FOF_TIMING
+    if (lane_id() == 0 && kMode != 0)
+        atomicAdd(&w.ctr->stats[16 + 2 * (kMode - 1)], (unsigned long long)L.phase[7]);
+#endif
 }
 
 // Big cells: one block per cell, over the list of big dense ids.
@@ -1094,6 +1149,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
     __shared__ int next;
     const int nb = __hip_atomic_load(&w.ctr->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const Deal dl = deal(w.cursors, 2 * kMode + 1, blockIdx.x, gridDim.x);
+    FOF_PHASE_START(L, threadIdx.x == 0);
     for (int k = deal_first(dl, blockIdx.x); k < nb;) {
         const int d = w.big_list[k];
         if (kMode == 1)
@@ -1107,7 +1163,14 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
         __syncthreads();
         k = next;
         __syncthreads();  // every thread has read `next` before it is overwritten
+        FOF_PHASE(L, threadIdx.x == 0, 7);
     }
+    FOF_PHASE(L, threadIdx.x == 0, 7);
+    FOF_PHASE_FLUSH(L, threadIdx.x == 0 && kMode == 0, w.ctr, 8);
+#ifdef FOF_TIMING
+    if (threadIdx.x == 0 && kMode != 0)
+        atomicAdd(&w.ctr->stats[17 + 2 * (kMode - 1)], (unsigned long long)L.phase[7]);
+#endif
 }
 
 // Blocks of a dense pass: enough to fill the chip, at most one per possible item, and at

@@ -62,17 +62,19 @@ struct Counters {
     int32_t n_spill;       // link tiles queued in tile_list for the windowed kernel
     int32_t n_link_edges;  // hooks the tiled kernel deferred to the edge list
     int32_t n_flagged;     // particles with a friend (length of Work::flist)
-    int32_t pad[26];
-    unsigned long long stats[16];  // event counts of diagnostic builds (-DFOF_STATS)
+    int32_t pad[10];
+    unsigned long long stats[24];  // event counts of diagnostic builds (-DFOF_STATS)
 };
 
 // Event counters for diagnostic builds; compiled out otherwise.
 enum Stat {
     ST_TILES, ST_TILES_OVERFLOW, ST_OWN_STAGED, ST_OWN_GLOBAL, ST_PAIRS_TILED, ST_PAIRS_GLOBAL,
     ST_DN_CALLS, ST_DN_UNITS, ST_CELL_CYCLES, ST_CC_UNIT_PAIRS, ST_CELL_MAX_CYCLES,
-    ST_CROSS_UNIT_PAIRS, ST_CELLS_TIMED, ST_UNIONS, ST_CROSS_CELLPAIRS, ST_SPARE
+    ST_CROSS_UNIT_PAIRS, ST_CELLS_TIMED, ST_UNIONS, ST_CROSS_CELLPAIRS, ST_SPARE,
+    ST_CC_SMALL_CYCLES, ST_CC_SMALL_CELLS, ST_CC_BIG_CYCLES, ST_CC_BIG_CELLS, ST_CC_UNITS,
+    ST_CC_MEMBER_TESTS, ST_CC_SKIPS, ST_CC_FAR_CELLS
 };
-#ifdef FOF_STATS
+#if defined(FOF_STATS) && !defined(FOF_TIMING)
 #define FOF_STAT(ctr, k, v) atomicAdd(&(ctr)->stats[k], (unsigned long long)(v))
 #define FOF_STAT_MAX(ctr, k, v) atomicMax(&(ctr)->stats[k], (unsigned long long)(v))
 #else
