@@ -815,6 +815,7 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     }
     Grp<G>::sync();
     const int nnb = L.nnb;
+    FOF_PHASE(L, t == 0, 0);
     if (nnb == 0) {  // uniform: every thread read the same count
         Grp<G>::sync();
         return;
@@ -840,6 +841,7 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
         }
     }
     Grp<G>::sync();
+    FOF_PHASE(L, t == 0, 1);
 
     for (int k = 0; k < nnb; ++k) {
         const int d2 = L.nb[k];
@@ -874,76 +876,88 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
             if (t == 0)
                 nstart[u2] = s2 + n2;
         }
+        // units of this cell within R fine cells of the shared face, edge or corner: only
+        // they can reach the neighbour's units
+        if (t == 0)
+            L.nmark = 0;
         Grp<G>::sync();
         for (int r = t; r < u; r += G) {
+            const int xyz = L.uxyz[r];
+            const int ax = xyz & 15, ay = (xyz >> 4) & 15, az = xyz >> 8;
+            const bool near = (ox == 0 || (ox > 0 ? ax >= m - R : ax < R)) &&
+                              (oy == 0 || (oy > 0 ? ay >= m - R : ay < R)) &&
+                              (oz == 0 || (oz > 0 ? az >= m - R : az < R));
+            if (near)
+                L.uf[atomicAdd(&L.nmark, 1)] = r;
+        }
+        Grp<G>::sync();
+        FOF_PHASE(L, t == 0, 2);
+        // items: (candidate unit, (dz, dy) row of the neighbour) spread over every thread
+        const int span = 2 * R + 1;
+        const int nitems = L.nmark * span * span;
+        for (int item = t; item < nitems; item += G) {
             if (__hip_atomic_load(&L.done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
                 break;
+            const int r = L.uf[item / (span * span)];
+            const int dz = (item % (span * span)) / span - R, dy = item % span - R;
             const int xyz = L.uxyz[r];
             // unit r in the frame of the neighbour cell
             const int rx = (xyz & 15) - ox * m, ry = ((xyz >> 4) & 15) - oy * m,
                       rz = (xyz >> 8) - oz * m;
-            bool stop = false;
-            for (int dz = -R; dz <= R && !stop; ++dz) {
-                const int bz = rz + dz;
-                if (bz < 0 || bz >= m)
+            const int bz = rz + dz, by = ry + dy;
+            if (bz < 0 || bz >= m || by < 0 || by >= m)
+                continue;
+            const int kz = max(0, abs(dz) - 1), ky = max(0, abs(dy) - 1);
+            const int rem = K - kz * kz - ky * ky;
+            if (rem < 0)
+                continue;  // this row lies b or more from unit r
+            const int sp = min(R, (int)sqrtf((float)rem) + 1);
+            const int lo = max(-sp, -rx), hi = min(sp, m - 1 - rx);
+            if (lo > hi)
+                continue;
+            const int key0 = (bz * m + by) * m + rx + lo;
+            uint32_t row = row_bits(L.bits, W, key0, hi - lo + 1);
+            while (row) {
+                const int bpos = __ffs(row) - 1;
+                row &= row - 1u;
+                const int bx = rx + lo + bpos;
+                const int rb = rank_in(L.bits, L.pre, key0 + bpos);
+                const int cb = staged2 ? ncomp_of[rb] : w.cnt[s2 + rb];
+                const int bit = L.ucomp[r] * ncomp2 + cb;
+                if (dedupe && ((L.pairbits[bit >> 5] >> (bit & 31)) & 1u))
                     continue;
-                const int kz = max(0, abs(dz) - 1);
-                for (int dy = -R; dy <= R && !stop; ++dy) {
-                    const int by = ry + dy;
-                    if (by < 0 || by >= m)
+                const int32_t b0 = staged2 ? nstart[rb] : w.rank[s2 + rb];
+                const int32_t b1 = staged2 ? nstart[rb + 1]
+                                           : (rb + 1 < u2 ? w.rank[s2 + rb + 1] : s2 + n2);
+                // unit B's box in the own cell's periodic frame
+                const FineBox fb = fine_box(B, (cc.x + ox) * m + bx, (cc.y + oy) * m + by,
+                                            (cc.z + oz) * m + bz);
+                FOF_STAT(w.ctr, ST_CROSS_UNIT_PAIRS, 1);
+                int hit_i = -1, hit_j = -1;
+                for (int i = L.ustart[r]; i < L.ustart[r + 1] && hit_i < 0; ++i) {
+                    const float4 p = mem[i - s];
+                    if (far_from(B, fb, p))
                         continue;
-                    const int ky = max(0, abs(dy) - 1);
-                    const int rem = K - kz * kz - ky * ky;
-                    if (rem < 0)
-                        continue;  // this row lies b or more from unit r
-                    const int span = min(R, (int)sqrtf((float)rem) + 1);
-                    const int lo = max(-span, -rx), hi = min(span, m - 1 - rx);
-                    if (lo > hi)
-                        continue;
-                    const int key0 = (bz * m + by) * m + rx + lo;
-                    uint32_t row = row_bits(L.bits, W, key0, hi - lo + 1);
-                    while (row && !stop) {
-                        const int bpos = __ffs(row) - 1;
-                        row &= row - 1u;
-                        const int bx = rx + lo + bpos;
-                        const int rb = rank_in(L.bits, L.pre, key0 + bpos);
-                        const int cb = staged2 ? ncomp_of[rb] : w.cnt[s2 + rb];
-                        const int bit = L.ucomp[r] * ncomp2 + cb;
-                        if (dedupe && ((L.pairbits[bit >> 5] >> (bit & 31)) & 1u))
-                            continue;
-                        const int32_t b0 = staged2 ? nstart[rb] : w.rank[s2 + rb];
-                        const int32_t b1 = staged2 ? nstart[rb + 1]
-                                                   : (rb + 1 < u2 ? w.rank[s2 + rb + 1] : s2 + n2);
-                        // unit B's box in the own cell's periodic frame
-                        const FineBox fb = fine_box(B, (cc.x + ox) * m + bx, (cc.y + oy) * m + by,
-                                                    (cc.z + oz) * m + bz);
-                        FOF_STAT(w.ctr, ST_CROSS_UNIT_PAIRS, 1);
-                        int hit_i = -1, hit_j = -1;
-                        for (int i = L.ustart[r]; i < L.ustart[r + 1] && hit_i < 0; ++i) {
-                            const float4 p = mem[i - s];
-                            if (far_from(B, fb, p))
-                                continue;
-                            const int j = first_friend(P, p, w.sorted, b0, b1);
-                            if (j >= 0) {
-                                hit_i = i;
-                                hit_j = j;
-                            }
-                        }
-                        if (hit_i >= 0) {
-                            uf_union(w.parent, (uint32_t)hit_i, (uint32_t)hit_j);
-                            if (dedupe)
-                                atomicOr(L.pairbits + (bit >> 5), 1u << (bit & 31));
-                            if (single) {
-                                __hip_atomic_store(&L.done, 1, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                                stop = true;
-                            }
-                        }
+                    const int j = first_friend(P, p, w.sorted, b0, b1);
+                    if (j >= 0) {
+                        hit_i = i;
+                        hit_j = j;
+                    }
+                }
+                if (hit_i >= 0) {
+                    uf_union(w.parent, (uint32_t)hit_i, (uint32_t)hit_j);
+                    if (dedupe)
+                        atomicOr(L.pairbits + (bit >> 5), 1u << (bit & 31));
+                    if (single) {
+                        __hip_atomic_store(&L.done, 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                        break;
                     }
                 }
             }
         }
         Grp<G>::sync();
+        FOF_PHASE(L, t == 0, 3);
     }
 }
 
@@ -985,6 +999,7 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     }
     Grp<G>::sync();
     const int nnb = L.nnb;
+    FOF_PHASE(L, t == 0, 0);
     if (nnb == 0) {  // uniform: every thread read the same count
         Grp<G>::sync();
         return;
@@ -1014,6 +1029,7 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     Grp<G>::sync();
     const float4 *mem = n <= CAP ? L.part : w.sorted + s;
     const int total = L.nbp[nnb];
+    FOF_PHASE(L, t == 0, 1);
     for (int e = t; e < total; e += G) {
         int k = 0;
         while (L.nbp[k + 1] <= e)
@@ -1066,6 +1082,7 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
             atomicOr((unsigned long long *)(w.flags + (j >> 6)), 1ull << (j & 63));
     }
     Grp<G>::sync();
+    FOF_PHASE(L, t == 0, 2);
 }
 
 // Work distribution of a dense pass.  Items (dense ids) are dealt to kCursorGroups groups,
@@ -1137,7 +1154,8 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
     FOF_PHASE_FLUSH(L, lane_id() == 0 && kMode == 0, w.ctr, 0);
 #ifdef FOF_TIMING
     if (lane_id() == 0 && kMode != 0)
-        atomicAdd(&w.ctr->stats[16 + 2 * (kMode - 1)], (unsigned long long)L.phase[7]);
+        for (int k = 0; k < 4; ++k)
+            atomicAdd(&w.ctr->stats[16 + 4 * (kMode - 1) + k], (unsigned long long)L.phase[k]);
 #endif
 }
 
@@ -1167,10 +1185,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
     }
     FOF_PHASE(L, threadIdx.x == 0, 7);
     FOF_PHASE_FLUSH(L, threadIdx.x == 0 && kMode == 0, w.ctr, 8);
-#ifdef FOF_TIMING
-    if (threadIdx.x == 0 && kMode != 0)
-        atomicAdd(&w.ctr->stats[17 + 2 * (kMode - 1)], (unsigned long long)L.phase[7]);
-#endif
+
 }
 
 // Blocks of a dense pass: enough to fill the chip, at most one per possible item, and at
