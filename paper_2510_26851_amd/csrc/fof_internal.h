@@ -343,12 +343,16 @@ struct BinShape {
 __host__ __device__ inline BinShape bin_shape(int64_t n, int64_t ncell)
 {
     BinShape b;
+    // buckets of about 8192 particles (what one sorting block holds in registers), then
+    // larger ones if there would be too many buckets
     b.shift = 6;
+    while (b.shift < kBinMaxShift && (ncell >> b.shift) * 8192 > n)
+        ++b.shift;
     while (b.shift < kBinMaxShift && ((ncell + (1ll << b.shift) - 1) >> b.shift) > kBinMaxBuckets)
         ++b.shift;
     b.nbk = (ncell + (1ll << b.shift) - 1) >> b.shift;
     b.ok = n > 0 && ncell > 0 && b.nbk <= kBinMaxBuckets;
-    int64_t g = (n + 65535) / 65536;
+    int64_t g = (n + 32767) / 32768;
     b.G = (int)(g < 1 ? 1 : (g > kBinMaxBlocks ? kBinMaxBlocks : g));
     b.chunk = (n + b.G - 1) / b.G;
     return b;
