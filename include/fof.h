@@ -196,10 +196,10 @@ int fof_backward(const fof_grid *grid, void *ws /*dev*/, int32_t mode,
 int fof_status(const fof_grid *grid, void *ws /*dev*/, int32_t **status /*host out: dev ptr*/);
 
 /* Optional, once per device (the current one), before fof_link is called from a captured
- * or performance-critical context: creates a helper stream (default priority) and two
- * events, so that fof_link runs its dense-cell passes concurrently with the tiled pass
- * (fork and join through the events; the call still orders everything after the caller's
- * earlier work and before its later work).  Without it, every call runs on the caller's
+ * or performance-critical context: creates a helper stream (default priority) and three
+ * events, so that fof_link runs its dense-cell passes concurrently with the sparse passes
+ * (fork, components-done and join through the events; the call still orders everything
+ * after the caller's earlier work and before its later work).  Without it, every call runs on the caller's
  * stream alone.  Allocates no device memory.  Errors: FOF_EDEVICE, FOF_ENOTSUP (device
  * index 64 or above). */
 int fof_init(void);

@@ -450,6 +450,8 @@ int fof_init(void)
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming);
     if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&sd.cc, hipEventDisableTiming);
+    if (e == hipSuccess)
         e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming);
     if (e != hipSuccess)
         return dev_err(e);

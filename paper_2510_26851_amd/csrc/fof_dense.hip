@@ -1222,7 +1222,8 @@ hipError_t launch_dense_build(const Work &w, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_dense(const Work &w, hipStream_t s)
+// Components, then pairs of dense cells; `cc_done` (optional) is recorded between the two.
+hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t cc_done)
 {
     if (w.dense_cap <= 0 || w.dense_threshold < 0)
         return hipSuccess;
@@ -1232,6 +1233,8 @@ hipError_t launch_dense(const Work &w, hipStream_t s)
     const unsigned pb = persistent_blocks(w.dense_cap);
     hipLaunchKernelGGL(k_dense_small<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     hipLaunchKernelGGL(k_dense_big<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    if (cc_done && (e = hipEventRecord(cc_done, s)) != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_dense_small<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     hipLaunchKernelGGL(k_dense_big<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     return hipGetLastError();

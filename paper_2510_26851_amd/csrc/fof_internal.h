@@ -405,16 +405,16 @@ hipError_t launch_scan_popc(const uint32_t *in, int32_t *out, int64_t n, int32_t
 int64_t scan_scratch_elems(int64_t n);
 
 hipError_t launch_build(const Work &w, const float *pos, hipStream_t s);
-// A helper stream and two events of one device: fof_link runs its dense-cell passes on
-// the helper stream, concurrently with the tiled sparse pass on the caller's stream.
+// A helper stream and three events of one device: fof_link runs its dense-cell passes on
+// the helper stream, concurrently with the sparse passes on the caller's stream.
 struct SideStream {
     hipStream_t stream;
-    hipEvent_t fork, join;
+    hipEvent_t fork, cc, join;  // flags cleared; dense components done; dense pairs done
 };
 
 hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideStream *side);
 hipError_t launch_dense_build(const Work &w, hipStream_t s);
-hipError_t launch_dense(const Work &w, hipStream_t s);
+hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t cc_done);
 hipError_t launch_dense_sparse(const Work &w, hipStream_t s);
 hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int32_t cap,
                          int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,

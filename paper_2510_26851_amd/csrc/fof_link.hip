@@ -531,8 +531,12 @@ __global__ void k_compress(const float4 *__restrict__ sorted, int64_t n,
 
 // The components and dense-pair passes touch only dense-cell particles (their parent
 // entries, and flag words through atomic ORs); the tiled pass only ordinary particles, with
-// plain stores to their own entries and no global hooks.  So the two run concurrently when
-// a helper stream is given: fork after the flag fill, join before the deferred hooks.
+// plain stores to their own entries and no global hooks; the deferred, windowed and global
+// sparse kernels hook ordinary particles only.  So with a helper stream the dense passes
+// run concurrently with all of those: fork after the flag fill.  The sparse-dense pass
+// needs the components (unit components, component counts, dense parents) and every plain
+// store of the tiled kernel, but not the dense pairs: it waits for the components only and
+// runs beside the pair pass (both hook through the lock-free forest).  Join before compress.
 hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideStream *side)
 {
     if (w.n <= 0)
@@ -546,7 +550,7 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideSt
             (e = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess)
             return e;
     }
-    e = launch_dense(w, fork ? side->stream : s);
+    e = launch_dense(w, fork ? side->stream : s, fork ? side->cc : nullptr);
     if (e != hipSuccess)
         return e;
     const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
@@ -556,19 +560,21 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideSt
             return e;
         hipLaunchKernelGGL(k_link_tiled, dim3((unsigned)w.ntiles), dim3(kTileBlock), 0, s, w,
                            root);
-        if (fork) {
-            if ((e = hipEventRecord(side->join, side->stream)) != hipSuccess ||
-                (e = hipStreamWaitEvent(s, side->join, 0)) != hipSuccess)
-                return e;
-        }
         hipLaunchKernelGGL(k_link_edges, dim3(1024), dim3(256), 0, s, w);
         const unsigned wb = (unsigned)(w.ntiles < kWindowBlocks ? w.ntiles : kWindowBlocks);
         hipLaunchKernelGGL(k_link_windows, dim3(wb), dim3(kTileBlock), 0, s, w, root);
     }
     hipLaunchKernelGGL(k_link, dim3(nb), dim3(w.block), 0, s, w, root);
+    if (fork && (e = hipStreamWaitEvent(s, side->cc, 0)) != hipSuccess)
+        return e;
     e = launch_dense_sparse(w, s);  // after every plain store of the tiled kernel
     if (e != hipSuccess)
         return e;
+    if (fork) {
+        if ((e = hipEventRecord(side->join, side->stream)) != hipSuccess ||
+            (e = hipStreamWaitEvent(s, side->join, 0)) != hipSuccess)
+            return e;
+    }
     hipLaunchKernelGGL(k_compress, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent,
                        w.flags, root);
     return hipGetLastError();
