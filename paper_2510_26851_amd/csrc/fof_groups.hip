@@ -5,7 +5,8 @@
 // straight at its root, whose key is the component label (smallest original index).
 //
 //   g_compact  flist = sorted indices of the flagged particles, ascending (popcount scan
-//              of the flag bitmap); the passes marked (list) below walk only flist
+//              of the flag bitmap); built at the end of fof_link (launch_flag_list), which
+//              also walks it; the passes marked (list) below walk only flist
 //   g_zero     cnt[i] = 0 for flagged i (every non-singleton root is flagged)   (list)
 //   g_count    cnt[root] += 1 for flagged i                                     (list)
 //   g_keep     set keep bit [label] for kept components (size >= min_size); with
@@ -387,6 +388,21 @@ __global__ void g_total(const int32_t *__restrict__ keep_prefix, int64_t nwords,
 
 }  // namespace
 
+hipError_t launch_flag_list(const Work &w, hipStream_t s)
+{
+    if (w.n <= 0)
+        return hipSuccess;
+    const int64_t nwords = (w.n + 31) / 32;
+    const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
+    const unsigned lb = nb < 4096u ? nb : 4096u;
+    hipError_t e = launch_scan_popc((const uint32_t *)w.flags, w.keep_prefix, nwords, w.scan, s);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(g_compact, dim3(lb), dim3(w.block), 0, s, w.flags, w.n, w.keep_prefix,
+                       nwords, w.flist, w.ctr);
+    return hipGetLastError();
+}
+
 hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int32_t cap,
                          int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
                          double *vmean, double *sigv, hipStream_t s)
@@ -395,16 +411,8 @@ hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int3
     const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
     // grid of the list-driven passes: a few rounds of a full chip
     const unsigned lb = nb < 4096u ? (nb > 0 ? nb : 1u) : 4096u;
-    hipError_t e;
-    if (w.n > 0) {
-        // flagged list: popcount scan of the flag bitmap into keep_prefix, then compaction
-        e = launch_scan_popc((const uint32_t *)w.flags, w.keep_prefix, nwords, w.scan, s);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(g_compact, dim3(lb), dim3(w.block), 0, s, w.flags, w.n,
-                           w.keep_prefix, nwords, w.flist, w.ctr);
-    }
-    e = launch_fill_u32(w.keep, nwords, 0u, s);
+    // flist and n_flagged were left by fof_link (launch_flag_list)
+    hipError_t e = launch_fill_u32(w.keep, nwords, 0u, s);
     if (e != hipSuccess)
         return e;
     const bool lonely_cut = min_size > 1;

@@ -416,6 +416,7 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideSt
 hipError_t launch_dense_build(const Work &w, hipStream_t s);
 hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t cc_done);
 hipError_t launch_dense_sparse(const Work &w, hipStream_t s);
+hipError_t launch_flag_list(const Work &w, hipStream_t s);
 hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int32_t cap,
                          int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
                          double *vmean, double *sigv, hipStream_t s);

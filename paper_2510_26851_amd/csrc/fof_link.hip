@@ -508,23 +508,22 @@ __global__ __launch_bounds__(kTileBlock) void k_link_windows(Work w, int32_t *__
     }
 }
 
-// Particles with a friend: follow the union-find to the root and write the root's key
-// (its original index, the smallest in the component) as the label.  Also leaves every
-// flagged entry pointing straight at its root for the group passes.  The lookup must not
+// Particles with a friend (the flagged list): follow the union-find to the root and write
+// the root's key (its original index, the smallest in the component) as the label.  Also
+// leaves every flagged entry pointing straight at its root for the group passes.  The lookup must not
 // halve paths: a halving write by one thread could replace the root another thread has
 // just stored in its own entry with a stale grandparent.
-__global__ void k_compress(const float4 *__restrict__ sorted, int64_t n,
-                           uint64_t *__restrict__ parent, const uint64_t *__restrict__ flags,
+__global__ void k_compress(const float4 *__restrict__ sorted, const int32_t *__restrict__ list,
+                           const Counters *__restrict__ ctr, uint64_t *__restrict__ parent,
                            int32_t *__restrict__ root)
 {
-    const int64_t i = gtid_xcd();
-    if (i >= n)
-        return;
-    if (!((flags[i >> 6] >> (i & 63)) & 1ull))
-        return;
-    const uint64_t r = uf_find_ro(parent, (uint32_t)i);
-    st_relaxed(parent + i, r);
-    root[__float_as_int(sorted[i].w)] = (int32_t)uf_key(r);
+    const int64_t nf = ctr->n_flagged;
+    for (int64_t k = gtid(); k < nf; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)list[k];
+        const uint64_t r = uf_find_ro(parent, i);
+        st_relaxed(parent + i, r);
+        root[__float_as_int(sorted[i].w)] = (int32_t)uf_key(r);
+    }
 }
 
 }  // namespace
@@ -575,8 +574,13 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideSt
             (e = hipStreamWaitEvent(s, side->join, 0)) != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(k_compress, dim3(nb), dim3(w.block), 0, s, w.sorted, w.n, w.parent,
-                       w.flags, root);
+    // the flagged particles, listed once for compress and the group passes
+    e = launch_flag_list(w, s);
+    if (e != hipSuccess)
+        return e;
+    const unsigned lb = nb < 4096u ? nb : 4096u;
+    hipLaunchKernelGGL(k_compress, dim3(lb), dim3(w.block), 0, s, w.sorted, w.flist, w.ctr,
+                       w.parent, root);
     return hipGetLastError();
 }
 
