@@ -685,16 +685,18 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     load_units<G>(w, T, s, n, m, u, L);
     FOF_PHASE(L, t == 0, 0);
 
-    // unit minima
+    // unit minima, one thread per member (a unit of a clump core can hold thousands); a
+    // member's unit is the rank of its fine key, the key the cell was sorted by
     for (int r = t; r < u; r += G) {
-        unsigned long long best = ~0ull;
-        for (int i = L.ustart[r]; i < L.ustart[r + 1]; ++i) {
-            const unsigned long long v =
-                ((unsigned long long)(uint32_t)__float_as_int(mem[i - s].w) << 32) | (uint32_t)i;
-            best = v < best ? v : best;
-        }
-        L.umin[r] = best;
+        L.umin[r] = ~0ull;
         L.uf[r] = r;
+    }
+    Grp<G>::sync();
+    for (int k = t; k < n; k += G) {
+        const float4 p = mem[k];
+        const unsigned long long v =
+            ((unsigned long long)(uint32_t)__float_as_int(p.w) << 32) | (uint32_t)(s + k);
+        atomicMin(L.umin + rank_in(L.bits, L.pre, fine_key(B, cc, p)), v);
     }
     Grp<G>::sync();
     FOF_PHASE(L, t == 0, 1);
@@ -756,13 +758,24 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     Grp<G>::sync();
     FOF_PHASE(L, t == 0, 5);
 
-    // every member points at its component's smallest original index
-    for (int r = t; r < u; r += G) {
-        const int root = lfind(L.uf, r);
-        const unsigned long long lead = L.umin[root];
-        for (int i = L.ustart[r]; i < L.ustart[r + 1]; ++i)
-            w.parent[i] = lead;
-        w.cnt[s + r] = L.ucomp[root];
+    // every member points at its component's smallest original index; every unit records
+    // its component number.  Cells of one wave hold few members per unit: one lane per
+    // unit; in a block's cell a unit can hold thousands: one thread per member.
+    if (G == kWave) {
+        for (int r = t; r < u; r += G) {
+            const int root = lfind(L.uf, r);
+            const unsigned long long lead = L.umin[root];
+            for (int i = L.ustart[r]; i < L.ustart[r + 1]; ++i)
+                w.parent[i] = lead;
+            w.cnt[s + r] = L.ucomp[root];
+        }
+    } else {
+        for (int r = t; r < u; r += G)
+            w.cnt[s + r] = L.ucomp[lfind(L.uf, r)];
+        for (int k = t; k < n; k += G) {
+            const int r = rank_in(L.bits, L.pre, fine_key(B, cc, mem[k]));
+            w.parent[s + k] = L.umin[lfind(L.uf, r)];
+        }
     }
     // mark every particle of the cell for the compress pass
     for (int64_t q = (s >> 6) + t; q <= ((int64_t)s + n - 1) >> 6; q += G) {
