@@ -228,37 +228,49 @@ __global__ void k_classify_totals(Counters *ctr, int64_t nchunk, const int32_t *
     }
 }
 
+// Thread t of chunk ch owns cells ch * kClassChunk + t * kClassPer + [0, kClassPer): one
+// scan per chunk numbers the dense cells in cell order.
 __global__ __launch_bounds__(kClassBlock) void k_classify_assign(Work w, int64_t nchunk,
                                                                   const int32_t *__restrict__ nd_pre,
                                                                   const int32_t *__restrict__ nbig_pre)
 {
     __shared__ int2 scr[kClassBlock / kWave];
     for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        int base_d = nd_pre[ch], base_b = nbig_pre[ch];
-        for (int k = 0; k < kClassPer; ++k) {  // cell order: k major, thread minor
-            const int64_t c = ch * kClassChunk + k * kClassBlock + threadIdx.x;
+        const int64_t c0 = ch * kClassChunk + (int64_t)threadIdx.x * kClassPer;
+        int a = 0, b = 0;
+        bool any = false;
+        for (int k = 0; k < kClassPer; ++k) {
+            const int cl = c0 + k < w.ncell ? cell_class(w, c0 + k) : 0;
+            a += cl > 0;
+            b += cl == 2;
+            any |= cl != 0;
+        }
+        int2 tot;
+        const int2 r = block_scan2(a, b, &tot, scr);
+        if (!any)
+            continue;
+        int next_d = nd_pre[ch] + r.x, next_b = nbig_pre[ch] + r.y;
+        for (int k = 0; k < kClassPer; ++k) {
+            const int64_t c = c0 + k;
             const int cl = c < w.ncell ? cell_class(w, c) : 0;
-            int2 tot;
-            const int2 r = block_scan2(cl > 0, cl == 2, &tot, scr);
-            if (cl != 0) {
-                int32_t d = -1;
-                if (cl > 0) {
-                    d = base_d + r.x;
-                    if (d < w.dense_cap) {
-                        w.dense_list[d] = (int32_t)c;
-                        if (cl == 2)
-                            w.big_list[base_b + r.y] = d;
-                    } else {
-                        atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_DENSE_CAP);
-                        if (cl == 2)  // big ids past this one have no table either
-                            atomicMin(&w.ctr->n_big, base_b + r.y);
-                        d = -1;
-                    }
+            if (cl == 0)
+                continue;
+            int32_t d = -1;
+            if (cl > 0) {
+                d = next_d++;
+                const int bg = cl == 2 ? next_b++ : -1;
+                if (d < w.dense_cap) {
+                    w.dense_list[d] = (int32_t)c;
+                    if (cl == 2)
+                        w.big_list[bg] = d;
+                } else {
+                    atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_DENSE_CAP);
+                    if (cl == 2)  // big ids past this one have no table either
+                        atomicMin(&w.ctr->n_big, bg);
+                    d = -1;
                 }
-                w.cell_count[c] = d;
             }
-            base_d += tot.x;
-            base_b += tot.y;
+            w.cell_count[c] = d;
         }
     }
 }
