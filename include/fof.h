@@ -191,6 +191,27 @@ int fof_backward(const fof_grid *grid, void *ws /*dev*/, int32_t mode,
                  const fof_sample *sample /*host*/, const double *loss /*dev [K]*/,
                  int32_t baseline, float *grad_pos, float *grad_vel, void *stream);
 
+/* Position dispersion of each group, the halo "decoration" of the decorated frozen
+ * assignment (paper Sec. 3.1, its inverse mass proxy: the particle standard deviation):
+ *   sigx[g] = sqrt(sum_{i in g} |mi(x_i - com[g])|^2 / (3 n_g)),  mi the per-axis minimum
+ * image, FP64, the same 1-D reading as sigv; groups of one get 0.  Must follow fof_groups on
+ * the same workspace with the same cap, and reads that call's n_groups, sizes and com (dev);
+ * sigx (dev double [cap]) receives min(G, cap) values and zeros beyond. */
+int fof_group_dispersion(const fof_grid *grid, void *ws /*dev*/, int32_t cap,
+                         const int32_t *n_groups, const int32_t *sizes, const double *com,
+                         double *sigx, void *stream);
+
+/* Gradient of the decoration with memberships frozen (paper Sec. 3.1, decorated frozen
+ * assignment): for every particle i with 0 <= g = group_id[i] < G and sigx[g] > 0,
+ *   grad_pos[i][c] += g_sigx[g] * mi(pos[i][c] - com[g][c]) / (3 n_g sigx[g])
+ * (the terms through com cancel).  ADDS to grad_pos (dev float32 [n][3]), so it composes with
+ * fof_backward(FOF_FROZEN).  pos (dev float32 [n][3]) is the forward's input; group_id,
+ * sizes, com and sigx are the forward's outputs (dev); g_sigx (dev double [G]). */
+int fof_backward_dispersion(const fof_grid *grid, void *ws /*dev*/, const float *pos,
+                            const int32_t *group_id, int32_t G, const int32_t *sizes,
+                            const double *com, const double *sigx, const double *g_sigx,
+                            float *grad_pos, void *stream);
+
 /* Device address of the int32 status word inside ws (FOF_STATUS_* bits; 0 = clean).  It is
  * cleared by fof_build_grid; read it after synchronising the stream. */
 int fof_status(const fof_grid *grid, void *ws /*dev*/, int32_t **status /*host out: dev ptr*/);

@@ -9,6 +9,9 @@ Functions and the passages they follow (paper section / algorithm):
   fof                    Sec. 2 steps (i)-(v); Alg. 2 (cell list, labels = min index)
   groups                 Sec. 2 step (vi) / Alg. 2 compaction; Sec. 3.1 halo position
   frozen_backward        Sec. 3.1 frozen assignment (gradients with memberships fixed)
+  group_dispersion,
+  dispersion_backward    Sec. 3.1 decorated frozen assignment: the particle standard
+                         deviation of each halo as the decoration, and its gradient
   component              BFS closure of one particle under the same predicate (sampled checks)
   philox4x64, uniforms,
   candidate_edges,
@@ -187,3 +190,50 @@ def frozen_backward(group_id, sizes, vmean=None, sigv=None, vel=None, g_mass=Non
     if rc:
         raise OracleError(f"oracle_frozen_backward failed ({rc})")
     return gp, gv
+
+
+def _min_image(d, L3):
+    """Per-axis minimum image of differences in (-L, L): wrapped once by +-L when |d| > L/2."""
+    half = 0.5 * L3
+    return np.where(d > half, d - L3, np.where(d < -half, d + L3, d))
+
+
+def group_dispersion(pos, group_id, sizes, com, L):
+    """Decoration of the decorated frozen assignment (Sec. 3.1): the particle standard
+    deviation of each group about its centre of mass, read as the 1-D population value
+        sigx_g = sqrt( sum_{i in g} sum_c mi(x_ic - com_gc)^2 / (3 n_g) ),
+    mi the minimum image, FP64; 0 for groups of one.  Plain numpy definition."""
+    pos = np.asarray(pos, dtype=np.float64)
+    gid = np.asarray(group_id)
+    sizes = np.asarray(sizes, dtype=np.int64)
+    com = np.asarray(com, dtype=np.float64)
+    G = sizes.shape[0]
+    m = (gid >= 0) & (gid < G)
+    d = _min_image(pos[m] - com[gid[m]], _L(L))
+    s2 = np.zeros(G, dtype=np.float64)
+    np.add.at(s2, gid[m], np.sum(d * d, axis=1))
+    out = np.zeros(G, dtype=np.float64)
+    many = sizes > 1
+    out[many] = np.sqrt(s2[many] / (3.0 * sizes[many]))
+    return out
+
+
+def dispersion_backward(pos, group_id, sizes, com, sigx, g_sigx, L):
+    """d(sum_g g_sigx_g sigx_g)/d x with memberships frozen (Sec. 3.1): the derivative of the
+    definition above, mi(x_i - com_g) / (3 n_g sigx_g) per member (the terms through com_g
+    vanish because the deviations of a group sum to zero); 0 where sigx_g = 0."""
+    pos = np.asarray(pos, dtype=np.float64)
+    gid = np.asarray(group_id)
+    sizes = np.asarray(sizes, dtype=np.float64)
+    com = np.asarray(com, dtype=np.float64)
+    sigx = np.asarray(sigx, dtype=np.float64)
+    g_sigx = np.asarray(g_sigx, dtype=np.float64)
+    G = sizes.shape[0]
+    grad = np.zeros_like(pos)
+    m = (gid >= 0) & (gid < G)
+    m[m] &= sigx[gid[m]] > 0.0
+    g = gid[m]
+    d = _min_image(pos[m] - com[g], _L(L))
+    grad[m] = (g_sigx[g] / (3.0 * sizes[g] * sigx[g]))[:, None] * d
+    return grad
+

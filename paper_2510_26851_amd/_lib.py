@@ -36,7 +36,8 @@ def sample_scratch_bytes(n: int, K: int, edge_cap: int) -> int:
 
 # Every symbol include/fof.h declares.
 EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",
-           "fof_status", "fof_strerror", "fof_last_device_error", "fof_init")
+           "fof_group_dispersion", "fof_backward_dispersion", "fof_status", "fof_strerror",
+           "fof_last_device_error", "fof_init")
 
 
 class fof_box(ctypes.Structure):
@@ -100,6 +101,8 @@ def load():
     L.fof_link.argtypes = [P, P, P, P, P]
     L.fof_groups.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P, P]
     L.fof_backward.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, i32, P, P, P]
+    L.fof_group_dispersion.argtypes = [P, P, i32, P, P, P, P, P]
+    L.fof_backward_dispersion.argtypes = [P, P, P, P, i32, P, P, P, P, P, P]
     L.fof_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_void_p)]
     L.fof_strerror.argtypes = [ctypes.c_int]
     L.fof_strerror.restype = ctypes.c_char_p

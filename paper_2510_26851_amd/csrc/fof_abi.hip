@@ -427,6 +427,33 @@ int fof_backward(const fof_grid *grid, void *ws, int32_t mode, const int32_t *gr
                                    g_sigv, grad_pos, grad_vel, (hipStream_t)stream));
 }
 
+int fof_group_dispersion(const fof_grid *grid, void *ws, int32_t cap, const int32_t *n_groups,
+                         const int32_t *sizes, const double *com, double *sigx, void *stream)
+{
+    if (!ws_ok(grid, ws) || cap < 0 || !n_groups || (cap > 0 && (!sizes || !com || !sigx)))
+        return FOF_EINVAL;
+    Work w = resolve(grid, ws);
+    clear_stale_error();
+    return dev_err(launch_group_dispersion(w, cap, n_groups, sizes, com, sigx,
+                                           (hipStream_t)stream));
+}
+
+int fof_backward_dispersion(const fof_grid *grid, void *ws, const float *pos,
+                            const int32_t *group_id, int32_t G, const int32_t *sizes,
+                            const double *com, const double *sigx, const double *g_sigx,
+                            float *grad_pos, void *stream)
+{
+    if (!ws_ok(grid, ws) || G < 0)
+        return FOF_EINVAL;
+    if (grid->n > 0 && G > 0 && (!pos || !group_id || !sizes || !com || !sigx || !g_sigx ||
+                                 !grad_pos))
+        return FOF_EINVAL;
+    Work w = resolve(grid, ws);
+    clear_stale_error();
+    return dev_err(launch_backward_dispersion(w, pos, group_id, G, sizes, com, sigx, g_sigx,
+                                              grad_pos, (hipStream_t)stream));
+}
+
 int fof_status(const fof_grid *grid, void *ws, int32_t **status)
 {
     if (!ws_ok(grid, ws) || !status)

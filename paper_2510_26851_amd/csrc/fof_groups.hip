@@ -367,6 +367,43 @@ __global__ void g_dev(const float4 *__restrict__ sorted, const int32_t *__restri
     }
 }
 
+// Position dispersion (the decoration of Sec. 3.1's decorated frozen assignment): sum over
+// the members of group g of |mi(x_i - com_g)|^2, mi the per-axis minimum image, FP64.
+__global__ void g_sigx(const float4 *__restrict__ sorted, const int32_t *__restrict__ list,
+                       const Counters *__restrict__ ctr, const BoxDesc *__restrict__ desc,
+                       int nbox, const uint64_t *__restrict__ parent,
+                       const uint32_t *__restrict__ keep, const int32_t *__restrict__ keep_prefix,
+                       int32_t cap, const double *__restrict__ com, double *__restrict__ sigx)
+{
+    const int64_t nf = ctr->n_flagged;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nf; base += stride) {
+        const int64_t k = base + threadIdx.x;
+        int32_t g = -1, i = 0;
+        if (k < nf) {
+            i = list[k];
+            g = group_of(keep, keep_prefix, uf_key(parent[i]));
+            if (g >= cap)
+                g = -1;
+        }
+        const bool in = g >= 0;
+        const Run run = wave_run(in ? (int64_t)g : -1 - (int64_t)lane_id());
+        double s2 = 0.0;
+        if (in) {
+            const float4 p = sorted[i];
+            const BoxDesc &B = desc[find_box(desc, nbox, i)];
+            const double c[3] = {(double)p.x, (double)p.y, (double)p.z};
+            for (int a = 0; a < 3; ++a) {
+                const double d = min_image(c[a] - com[3 * g + a], B.L[a], B.halfL[a]);
+                s2 += d * d;
+            }
+        }
+        s2 = run_sum(s2, run.head);
+        if (in && run.tail)
+            atomicAdd(sigx + g, s2);
+    }
+}
+
 __global__ void g_sig(const int32_t *__restrict__ n_groups, int32_t cap,
                       const int32_t *__restrict__ sizes, double *__restrict__ sigv)
 {
@@ -387,6 +424,28 @@ __global__ void g_total(const int32_t *__restrict__ keep_prefix, int64_t nwords,
 }
 
 }  // namespace
+
+// sigx[g] = sqrt(sum_i |mi(x_i - com_g)|^2 / (3 n_g)) for g < min(n_groups, cap); groups of
+// one get 0.  Uses the flagged list and the keep tables of the last fof_groups call.
+hipError_t launch_group_dispersion(const Work &w, int32_t cap, const int32_t *n_groups,
+                                   const int32_t *sizes, const double *com, double *sigx,
+                                   hipStream_t s)
+{
+    if (cap <= 0)
+        return hipSuccess;
+    hipError_t e = launch_fill_f64(sigx, cap, 0.0, s);
+    if (e != hipSuccess)
+        return e;
+    if (w.n > 0) {
+        const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
+        const unsigned lb = nb < 4096u ? nb : 4096u;
+        hipLaunchKernelGGL(g_sigx, dim3(lb), dim3(w.block), 0, s, w.sorted, w.flist, w.ctr,
+                           w.desc, w.nbox, w.parent, w.keep, w.keep_prefix, cap, com, sigx);
+    }
+    const unsigned gb = (unsigned)((cap + 255) / 256);
+    hipLaunchKernelGGL(g_sig, dim3(gb), dim3(256), 0, s, n_groups, cap, sizes, sigx);
+    return hipGetLastError();
+}
 
 hipError_t launch_flag_list(const Work &w, hipStream_t s)
 {

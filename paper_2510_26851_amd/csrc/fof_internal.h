@@ -417,6 +417,13 @@ hipError_t launch_dense_build(const Work &w, hipStream_t s);
 hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t cc_done);
 hipError_t launch_dense_sparse(const Work &w, hipStream_t s);
 hipError_t launch_flag_list(const Work &w, hipStream_t s);
+hipError_t launch_group_dispersion(const Work &w, int32_t cap, const int32_t *n_groups,
+                                   const int32_t *sizes, const double *com, double *sigx,
+                                   hipStream_t s);
+hipError_t launch_backward_dispersion(const Work &w, const float *pos, const int32_t *group_id,
+                                      int32_t G, const int32_t *sizes, const double *com,
+                                      const double *sigx, const double *g_sigx, float *grad_pos,
+                                      hipStream_t s);
 hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int32_t cap,
                          int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
                          double *vmean, double *sigv, hipStream_t s);

@@ -120,6 +120,29 @@ class Plan:
             res["sigv"] = sv
         return res
 
+    def dispersion(self, res, sigx=None, stream=None):
+        """Position dispersion per group (device float64 [cap]) for the result `res` of the
+        last groups() call; groups of one get 0."""
+        cap = res["cap"]
+        if sigx is None:
+            sigx = torch.empty(max(cap, 1), dtype=torch.float64, device=self.device)
+        check("fof_group_dispersion",
+              _lib.load().fof_group_dispersion(self._gref, _ptr(self.ws), cap,
+                                               _ptr(res["n_groups"]), _ptr(res["sizes"]),
+                                               _ptr(res["com"]), _ptr(sigx), _stream(stream)))
+        return sigx
+
+    def backward_dispersion(self, pos, group_id, G, sizes, com, sigx, g_sigx, grad_pos,
+                            stream=None):
+        """Adds the frozen-assignment gradient of the dispersion to grad_pos (in place)."""
+        g_sigx = g_sigx.to(torch.float64).contiguous()
+        check("fof_backward_dispersion",
+              _lib.load().fof_backward_dispersion(self._gref, _ptr(self.ws), _ptr(pos),
+                                                  _ptr(group_id), int(G), _ptr(sizes),
+                                                  _ptr(com), _ptr(sigx), _ptr(g_sigx),
+                                                  _ptr(grad_pos), _stream(stream)))
+        return grad_pos
+
     def status(self) -> int:
         p = ctypes.c_void_p()
         check("fof_status", _lib.load().fof_status(self._gref, _ptr(self.ws), ctypes.byref(p)))
