@@ -141,6 +141,39 @@ def reinforce_rate(torch, dev, reps):
             "timed": "fof_link(sample) + fof_backward(FOF_SCORE) per batch of K"}
 
 
+def decorated_rate(torch, plan, pos, out, cap, ng, stream, workload, reps=10):
+    """Decorated frozen assignment on the groups of the last step: per-call time of the
+    position dispersion (fof_group_dispersion) and of its gradient (fof_backward_dispersion,
+    which adds into grad_pos), HIP events on the launch stream."""
+    res = dict(out, cap=cap)
+    sig = torch.empty(cap, dtype=torch.float64, device=pos.device)
+    grad = torch.zeros_like(pos)
+    gen = torch.Generator(device=pos.device).manual_seed(1)
+    g_sigx = torch.randn(max(ng, 1), dtype=torch.float64, device=pos.device, generator=gen)
+    G = min(ng, cap)
+
+    def fwd():
+        plan.dispersion(res, sigx=sig)
+
+    def bwd():
+        plan.backward_dispersion(pos, out["group_id"], G, out["sizes"], out["com"], sig, g_sigx,
+                                 grad)
+
+    times = {}
+    for name, fn in (("dispersion_ms", fwd), ("backward_ms", bwd)):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        times[name] = round(a.elapsed_time(b) / reps, 4)
+    return dict(workload=workload, groups=G, **times,
+                timed="fof_group_dispersion; fof_backward_dispersion (adds into grad_pos)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +294,7 @@ def main():
         "hbm_peak_frac_link": round(achieved / HBM_PEAK_GBS, 4),
         "copy_gbs": round(copy_gbs, 1),
     }
+    line["decorated"] = decorated_rate(torch, plan, pos, out, cap, ng, stream, box.name)
     if not args.no_reinforce:
         log("timing batched REINFORCE ...")
         line["reinforce"] = reinforce_rate(torch, dev, args.reinforce_reps)
