@@ -78,8 +78,11 @@ typedef struct fof_tune {
 /* Stochastic linking (paper Sec. 3.2: every potential edge between nearby particles is a
  * Bernoulli variable).  The candidate edges are the pairs closer than the plan's linking
  * length (the cut radius r_c: plan the batch with fof_box.b = r_c); edge e = {i, j} is kept
- * in sample s with probability p_e = 1 / (1 + exp(-(b - d_e) / tau)), d_e its
- * minimum-image distance, when u(seed, s, i, j) < p_e, where u is the first word of
+ * in sample s with probability p_e = 1 / (1 + exp(-z_e)), d_e its minimum-image distance,
+ *   form FOF_PROB_DISTANCE:  z_e = (b - d_e) / tau,
+ *   form FOF_PROB_QUADRATIC: z_e = (alpha * (b*b - d_e^2)) / (b*b)  (the paper's Bernoulli
+ *                            form, evaluated in this order in FP64),
+ * when u(seed, s, i, j) < p_e, where u is the first word of
  * Philox4x64-10 (Salmon et al. 2011) at counter (i | j << 32, s, 0, 0) and key (seed, 0),
  * shifted right by 11 and scaled by 2^-53, on original indices i < j.  All pointers are
  * device pointers owned by the caller. */
@@ -94,7 +97,12 @@ typedef struct fof_sample {
     int32_t *n_edges;   /* [1] number of candidate edges (may exceed edge_cap: status bit)     */
     void *scratch;      /* >= FOF_SAMPLE_SCRATCH_BYTES(n, K, edge_cap) bytes, 256-aligned      */
     size_t scratch_bytes;
+    int32_t form;       /* FOF_PROB_DISTANCE (0) or FOF_PROB_QUADRATIC (1)                     */
+    double alpha;       /* relaxation of FOF_PROB_QUADRATIC, > 0 (tau is then unused)          */
 } fof_sample;
+
+#define FOF_PROB_DISTANCE 0
+#define FOF_PROB_QUADRATIC 1
 
 /* Scratch of the sampled labelling: a vertex map over all particles, the sorted ends of
  * every edge, and one union-find per sample over the particles that touch a candidate edge
@@ -181,7 +189,8 @@ int fof_groups(const fof_grid *grid, void *ws /*dev*/, int32_t min_size, const f
  * mode = FOF_SCORE (Sec. 3.2, REINFORCE): with the edges of the last fof_link(sample) and the
  * sampled graphs' losses loss[K] (dev double),
  *   grad_pos = (1/K) sum_s (loss_s - beta_s) sum_e (y_es - p_e) dz_e/dx,
- *   z_e = (b - d_e)/tau,  dz_e/dx_i = -(x_i - x_j)/(tau d_e) = -dz_e/dx_j (minimum image),
+ *   z_e as in fof_sample, dz_e/dx_i = -dz_e/dx_j = -(x_i - x_j)/(tau d_e) (FOF_PROB_DISTANCE)
+ *   or -2 alpha (x_i - x_j)/b^2 (FOF_PROB_QUADRATIC), x_i - x_j the minimum image,
  * beta_s per `baseline` (FOF_BASELINE_*); the frozen-mode arguments are ignored and grad_vel
  * is not written.  grad_pos and grad_vel (dev float32 [n][3]) may be NULL to skip them. */
 int fof_backward(const fof_grid *grid, void *ws /*dev*/, int32_t mode,

@@ -7,6 +7,8 @@ Readings fixed for this build (the paper is silent or uses other symbols):
   * edge probability p_e = sigmoid(z_e), z_e = (b - d_e) / tau, d_e the minimum-image
     distance (the paper's own form sigmoid(alpha (b^2 - d^2) / b^2) agrees near d = b with
     alpha = b / (2 tau));
+  * the paper's own form is available too: z_e = (alpha (b^2 - d_e^2)) / b^2, evaluated in
+    that order (edge_prob_quadratic), with dz_e/dx_i = -2 alpha (x_i - x_j) / b^2;
   * candidate edges: unordered pairs with d < r_c = b + 10 tau (p >= sigmoid(-10));
   * samples: y_{e,s} = [u(seed, s, i, j) < p_e] with u from Philox4x64-10 keyed by the
     seed, counter (i | j << 32, s, 0, 0) on original indices i < j;
@@ -83,6 +85,23 @@ def edge_prob(d2, b, tau):
     return np.array([L.oracle_edge_prob(float(v), float(b), float(tau)) for v in np.asarray(d2)])
 
 
+def edge_prob_quadratic(d2, b, alpha):
+    """The paper's Bernoulli form (Sec. 3.2): p = sigmoid(alpha (b^2 - d^2) / b^2), FP64."""
+    d2 = np.asarray(d2, np.float64)
+    b2 = float(b) * float(b)
+    z = (float(alpha) * (b2 - d2)) / b2
+    return 1.0 / (1.0 + np.exp(-z))
+
+
+def dz_factor(d, b, tau=None, alpha=None):
+    """c_e with dz_e/dx_j = c_e (x_i - x_j) = -dz_e/dx_i: 1/(tau d_e), or 2 alpha / b^2 for
+    the quadratic form."""
+    d = np.asarray(d, np.float64)
+    if alpha is None:
+        return 1.0 / (tau * d)
+    return np.full(d.shape, 2.0 * float(alpha) / (float(b) * float(b)))
+
+
 def sample_labels(n, ei, ej, p, seed, K):
     """root[K, n] (smallest index per component of each sampled graph) and keep[K, m]."""
     ei = np.ascontiguousarray(ei, np.int32)
@@ -111,8 +130,9 @@ def edge_geometry(pos, L, ei, ej):
     return delta, np.sqrt(d2)
 
 
-def score_gradient(n, ei, ej, delta, d, p, tau, keep, losses, baseline="loo"):
-    """(1/K) sum_s (L_s - beta_s) sum_e (y_es - p_e) dz_e/dx  ->  float64 [n, 3]."""
+def score_gradient(n, ei, ej, delta, d, p, tau, keep, losses, baseline="loo", c=None):
+    """(1/K) sum_s (L_s - beta_s) sum_e (y_es - p_e) dz_e/dx  ->  float64 [n, 3]; c is the
+    per-edge dz factor (dz_factor), by default that of the distance form with tau."""
     K = keep.shape[0]
     Ls = np.asarray(losses, np.float64)
     if baseline == "loo":
@@ -125,7 +145,9 @@ def score_gradient(n, ei, ej, delta, d, p, tau, keep, losses, baseline="loo"):
         raise ValueError(baseline)
     adv = Ls - beta
     w = (adv[:, None] * (keep.astype(np.float64) - p[None, :])).sum(axis=0) / K   # [m]
-    dz = delta / (tau * d)[:, None]                                             # dz/dx_j
+    if c is None:
+        c = dz_factor(d, None, tau=tau)
+    dz = delta * np.asarray(c, np.float64)[:, None]                             # dz/dx_j
     g = np.zeros((n, 3))
     np.add.at(g, ei, -w[:, None] * dz)
     np.add.at(g, ej, w[:, None] * dz)
@@ -166,25 +188,30 @@ def enumerate_expectation(n, ei, ej, p, loss_fn):
     return EL, gz
 
 
-def enumerate_gradient(pos, L, b, tau, r_c, loss_fn):
-    """Exact d E[L] / d x (float64 [n, 3]) on a small configuration by enumeration."""
+def _probs(d2, b, tau, alpha):
+    return edge_prob(d2, b, tau) if alpha is None else edge_prob_quadratic(d2, b, alpha)
+
+
+def enumerate_gradient(pos, L, b, tau, r_c, loss_fn, alpha=None):
+    """Exact d E[L] / d x (float64 [n, 3]) on a small configuration by enumeration (the
+    quadratic form when alpha is given)."""
     pos = _pos(pos)
     n = pos.shape[0]
     ei, ej, d2 = candidate_edges(pos, L, r_c)
     delta, d = edge_geometry(pos, L, ei, ej)
-    p = edge_prob(d2, b, tau)
+    p = _probs(d2, b, tau, alpha)
     EL, gz = enumerate_expectation(n, ei, ej, p, loss_fn)
-    dz = delta / (tau * d)[:, None]
+    dz = delta * dz_factor(d, b, tau=tau, alpha=alpha)[:, None]
     g = np.zeros((n, 3))
     np.add.at(g, ei, -gz[:, None] * dz)
     np.add.at(g, ej, gz[:, None] * dz)
     return EL, g
 
 
-def expected_loss(pos, L, b, tau, r_c, loss_fn):
+def expected_loss(pos, L, b, tau, r_c, loss_fn, alpha=None):
     pos = _pos(pos)
     ei, ej, d2 = candidate_edges(pos, L, r_c)
-    p = edge_prob(d2, b, tau)
+    p = _probs(d2, b, tau, alpha)
     return enumerate_expectation(pos.shape[0], ei, ej, p, loss_fn)[0]
 
 

@@ -18,6 +18,8 @@ FOF_EOVERFLOW = -3
 FOF_EDEVICE = -4
 FOF_ENOTSUP = -5
 FOF_STATUS_RANGE = 1
+FOF_PROB_DISTANCE = 0
+FOF_PROB_QUADRATIC = 1
 FOF_TUNE_NO_TILES = 1
 FOF_STATUS_DENSE_CAP = 2
 FOF_STATUS_EDGE_CAP = 4
@@ -54,7 +56,8 @@ class fof_sample(ctypes.Structure):
     _fields_ = [("b", ctypes.c_double), ("tau", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("K", ctypes.c_int32), ("edge_cap", ctypes.c_int32), ("ei", ctypes.c_void_p),
                 ("ej", ctypes.c_void_p), ("d2", ctypes.c_void_p), ("n_edges", ctypes.c_void_p),
-                ("scratch", ctypes.c_void_p), ("scratch_bytes", ctypes.c_size_t)]
+                ("scratch", ctypes.c_void_p), ("scratch_bytes", ctypes.c_size_t),
+                ("form", ctypes.c_int32), ("alpha", ctypes.c_double)]
 
 
 class fof_grid(ctypes.Structure):

@@ -355,8 +355,13 @@ int fof_build_grid(const fof_grid *grid, const float *pos, void *ws, void *strea
 
 static bool sample_ok(const fof_grid *grid, const fof_sample *S)
 {
-    return grid->nbox == 1 && S->K >= 1 && S->K <= 65535 && S->edge_cap >= 0 && S->tau > 0.0 && isfinite(S->tau) &&
-           isfinite(S->b) && S->n_edges && S->scratch && ((uintptr_t)S->scratch % 256) == 0 &&
+    const bool prob_ok =
+        S->form == FOF_PROB_DISTANCE
+            ? S->tau > 0.0 && isfinite(S->tau) && isfinite(S->b)
+            : S->form == FOF_PROB_QUADRATIC && S->alpha > 0.0 && isfinite(S->alpha) &&
+                  S->b > 0.0 && isfinite(S->b);
+    return grid->nbox == 1 && S->K >= 1 && S->K <= 65535 && S->edge_cap >= 0 && prob_ok &&
+           S->n_edges && S->scratch && ((uintptr_t)S->scratch % 256) == 0 &&
            (S->edge_cap == 0 || (S->ei && S->ej && S->d2)) &&
            S->scratch_bytes >= FOF_SAMPLE_SCRATCH_BYTES(grid->n, S->K, S->edge_cap) &&
            sample_layout_ok(*S, grid->n);

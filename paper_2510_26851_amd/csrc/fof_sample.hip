@@ -2,7 +2,7 @@
 //
 // Candidate edges are the pairs closer than the plan's linking length (the cut radius);
 // edge e = {i, j} is kept in sample s when u(seed, s, i, j) < p_e, p_e = 1/(1 + exp(-z_e)),
-// z_e = (b - d_e)/tau.  The neighbour structure is built once and reused by all K samples,
+// z_e = (b - d_e)/tau, or the paper's z_e = alpha (b^2 - d_e^2)/b^2.  The neighbour structure is built once and reused by all K samples,
 // as the paper does ("we do not rebuild the neighbor list").
 //
 //   k_edges(_tiled) candidate search (the hard link's grid, LDS tiles and predicate, with
@@ -14,7 +14,8 @@
 //   k_sample_label labels of every particle in every sample (smallest member index): a
 //                  stream of identity labels, then the particles that touch an edge
 //   k_score        per edge: w_e = (1/K) sum_s adv_s (y_es - p_e), scattered as
-//                  -+ w_e (x_i - x_j)/(tau d_e) into the position gradient
+//                  -+ w_e (x_i - x_j) c_e into the position gradient, c_e = 1/(tau d_e)
+//                  or 2 alpha / b^2
 #include "fof_internal.h"
 #include "fof_tile.h"
 
@@ -55,14 +56,9 @@ __device__ __forceinline__ double edge_uniform(uint64_t seed, uint32_t s, uint32
     return (double)(w >> 11) * 0x1.0p-53;
 }
 
-__device__ __forceinline__ double edge_prob(double d2, double b, double tau)
-{
-    const double z = (b - sqrt(d2)) / tau;
-    return 1.0 / (1.0 + exp(-z));
-}
-
 struct SampleArgs {
-    double b, tau;
+    double b, tau, alpha;
+    int32_t form;  // FOF_PROB_DISTANCE or FOF_PROB_QUADRATIC
     uint64_t seed;
     int32_t K, edge_cap;
     int32_t *ei, *ej;
@@ -78,6 +74,14 @@ struct SampleArgs {
     double *adv;       // [K] loss minus baseline
     int64_t vcap;
 };
+
+// Keep probability of an edge with squared distance d2 (Sec. 3.2).
+__device__ __forceinline__ double edge_prob(double d2, const SampleArgs &a)
+{
+    const double z = a.form == FOF_PROB_QUADRATIC ? (a.alpha * (a.b * a.b - d2)) / (a.b * a.b)
+                                                  : (a.b - sqrt(d2)) / a.tau;
+    return 1.0 / (1.0 + exp(-z));
+}
 
 __device__ __forceinline__ int32_t edge_count(const SampleArgs &a)
 {
@@ -322,7 +326,7 @@ __global__ void k_sample_union(SampleArgs a)
     for (int64_t e = gtid(); e < m; e += stride) {
         const int32_t i = a.ei[e], j = a.ej[e];
         const int32_t vi = a.vmap[i], vj = a.vmap[j];
-        const double p = edge_prob(a.d2[e], a.b, a.tau);
+        const double p = edge_prob(a.d2[e], a);
         for (int32_t s = s0; s < s1; ++s)
             if (edge_uniform(a.seed, (uint32_t)s, (uint32_t)i, (uint32_t)j) < p)
                 funion(a.forest + (int64_t)s * a.vcap, vi, vj);
@@ -370,7 +374,7 @@ __global__ void k_advantage(const double *__restrict__ loss, int32_t K, int32_t 
 __device__ void score_edge(const Work &w, const SampleArgs &a, int64_t e, float *grad)
 {
     const int32_t i = a.ei[e], j = a.ej[e];
-    const double p = edge_prob(a.d2[e], a.b, a.tau);
+    const double p = edge_prob(a.d2[e], a);
     double wsum = 0.0;
     for (int32_t s = 0; s < a.K; ++s) {
         const double u = edge_uniform(a.seed, (uint32_t)s, (uint32_t)i, (uint32_t)j);
@@ -382,7 +386,8 @@ __device__ void score_edge(const Work &w, const SampleArgs &a, int64_t e, float 
     const double dx = min_image((double)pi.x - (double)pj.x, B.L[0], B.halfL[0]);
     const double dy = min_image((double)pi.y - (double)pj.y, B.L[1], B.halfL[1]);
     const double dz = min_image((double)pi.z - (double)pj.z, B.L[2], B.halfL[2]);
-    const double f = wgt / (a.tau * sqrt(a.d2[e]));
+    const double f = a.form == FOF_PROB_QUADRATIC ? wgt * (2.0 * a.alpha / (a.b * a.b))
+                                                  : wgt / (a.tau * sqrt(a.d2[e]));
     atomicAdd(grad + 3 * (int64_t)i + 0, (float)(-f * dx));
     atomicAdd(grad + 3 * (int64_t)i + 1, (float)(-f * dy));
     atomicAdd(grad + 3 * (int64_t)i + 2, (float)(-f * dz));
@@ -443,6 +448,8 @@ static void fill_args(const fof_sample &S, SampleArgs &a)
 {
     a.b = S.b;
     a.tau = S.tau;
+    a.alpha = S.alpha;
+    a.form = S.form;
     a.seed = S.seed;
     a.K = S.K;
     a.edge_cap = S.edge_cap;

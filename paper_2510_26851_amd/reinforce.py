@@ -26,10 +26,20 @@ class Sampler:
     count back (one synchronisation) and, if it exceeded the capacity, reallocates and runs
     again.  With an explicit edge_cap an overflow only sets FOF_STATUS_EDGE_CAP."""
 
-    def __init__(self, pos, L, b, tau, K, seed, r_cut=None, edge_cap=None, tune=None):
+    def __init__(self, pos, L, b, tau, K, seed, r_cut=None, edge_cap=None, tune=None,
+                 alpha=None):
+        # alpha given: the paper's form z = alpha (b^2 - d^2) / b^2 (tau unused); otherwise
+        # z = (b - d) / tau.  Default cut: the distance where z = -10 (p = sigmoid(-10)).
         self.n = pos.shape[0]
         self.device = pos.device
-        self.r_cut = float(b + 10.0 * tau) if r_cut is None else float(r_cut)
+        self.form = _lib.FOF_PROB_DISTANCE if alpha is None else _lib.FOF_PROB_QUADRATIC
+        self.alpha = 0.0 if alpha is None else float(alpha)
+        if tau is None:
+            tau = 0.0
+        if r_cut is None:
+            r_cut = (b + 10.0 * tau if alpha is None
+                     else b * (1.0 + 10.0 / float(alpha)) ** 0.5)
+        self.r_cut = float(r_cut)
         self.plan = Plan([self.n], [(L, self.r_cut)], device=pos.device, tune=tune)
         self.pos = pos
         self.K = int(K)
@@ -51,6 +61,7 @@ class Sampler:
         S.ei, S.ej, S.d2 = self.ei.data_ptr(), self.ej.data_ptr(), self.d2.data_ptr()
         S.n_edges = self.n_edges.data_ptr()
         S.scratch, S.scratch_bytes = self.scratch.data_ptr(), nb
+        S.form, S.alpha = self.form, self.alpha
         self.S = S
 
     def _launch(self, root, stream):

@@ -226,7 +226,23 @@ def test_entry_points_reject_bad_arguments_before_launch():
     S.tau, S.K = 0.01, 65536                                                     # K too large
     S.scratch_bytes = _lib.sample_scratch_bytes(100, 65536, 100)
     assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
-    S.K, S.tau = 4, 0.0
+    S.K, S.tau = 4, 0.01
+    S.scratch_bytes = _lib.sample_scratch_bytes(100, 4, 100)
+    S.form, S.alpha = _lib.FOF_PROB_QUADRATIC, 0.0                              # alpha <= 0
+    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    S.form, S.alpha = 2, 1.0                                                     # unknown form
+    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    S.form, S.tau = _lib.FOF_PROB_DISTANCE, 0.0
+    assert L.fof_group_dispersion(gp, fake_ws, -1, fake_ws, fake_ws, fake_ws, fake_ws,
+                                  None) == _lib.FOF_EINVAL                        # cap < 0
+    assert L.fof_group_dispersion(gp, fake_ws, 10, None, fake_ws, fake_ws, fake_ws,
+                                  None) == _lib.FOF_EINVAL                        # n_groups NULL
+    assert L.fof_group_dispersion(gp, fake_ws, 10, fake_ws, fake_ws, None, fake_ws,
+                                  None) == _lib.FOF_EINVAL                        # com NULL
+    assert L.fof_backward_dispersion(gp, fake_ws, fake_ws, fake_ws, -1, fake_ws, fake_ws,
+                                     fake_ws, fake_ws, fake_ws, None) == _lib.FOF_EINVAL  # G < 0
+    assert L.fof_backward_dispersion(gp, fake_ws, None, fake_ws, 3, fake_ws, fake_ws, fake_ws,
+                                     fake_ws, fake_ws, None) == _lib.FOF_EINVAL   # pos NULL
     assert L.fof_groups(gp, fake_ws, 20, None, 10, None, fake_ws, fake_ws, None, None, None,
                         None) == _lib.FOF_EINVAL                                  # group_id NULL
     assert L.fof_groups(gp, fake_ws, 20, None, -1, fake_ws, fake_ws, fake_ws, None, None, None,

@@ -120,3 +120,41 @@ def test_estimator_mean_matches_enumeration():
     ests = np.array(ests)
     z = np.abs(ests.mean(0) - g_exact) / np.maximum(ests.std(0, ddof=1) / np.sqrt(reps), 1e-12)
     assert np.all(z < 4.5), z.max()
+
+
+@pytest.mark.parametrize("alpha,which", [(5.0, "clumpy"), (0.5, "uniform")])
+def test_quadratic_form_matches_oracle(alpha, which):
+    """The paper's Bernoulli form p = sigmoid(alpha (b^2 - d^2) / b^2): candidate edges, sampled
+    labels and the score gradient against the oracle (alpha 5 and 0.5 as in Sec. 3.2)."""
+    import torch
+    from paper_2510_26851_amd.reinforce import Sampler, sum_sq_sizes
+
+    if which == "clumpy":
+        pos, L, b = W.clumpy_box(8000, 16.0, 6, 78), 16.0, 0.3
+    else:
+        pos, L, b = W.uniform_box(3000, (12.0,) * 3, 79), 12.0, 0.4
+    K, seed = 16, 4321
+    r_c = b * (1.0 + 10.0 / alpha) ** 0.5  # where z = -10
+    say(f"reinforce quadratic form alpha={alpha} {which}: n={pos.shape[0]} r_c={r_c:.3f}")
+    smp = Sampler(torch.from_numpy(pos).cuda(), L, b, None, K, seed, alpha=alpha)
+    assert smp.r_cut == r_c
+    root = smp.sample()
+    ei, ej, d2, total = smp.edges()
+    torch.cuda.synchronize()
+    assert smp.plan.status() == 0 and total == ei.shape[0] > 0
+    oei, oej, od2 = RF.candidate_edges(pos, L, r_c)
+    assert edge_set(ei.cpu().numpy(), ej.cpu().numpy(), d2.cpu().numpy()) == \
+        edge_set(oei, oej, od2)
+    p = RF.edge_prob_quadratic(od2, b, alpha)
+    oroot, keep = RF.sample_labels(pos.shape[0], oei, oej, p, seed, K)
+    mism = np.nonzero((root.cpu().numpy() != oroot).any(axis=1))[0]
+    if mism.size:
+        u = np.array([[RF.uniform(seed, s, a, c) for a, c in zip(oei, oej)] for s in mism])
+        near = np.abs(u - p[None, :]) <= 8 * 2.0 ** -53
+        pytest.fail(f"samples {mism.tolist()} differ; near ties there: {int(near.sum())}")
+    losses = sum_sq_sizes(root, 2)
+    g = smp.grad(losses, baseline="loo").cpu().numpy()
+    delta, d = RF.edge_geometry(pos, L, oei, oej)
+    ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, None, keep,
+                            losses.cpu().numpy(), "loo", c=RF.dz_factor(d, b, alpha=alpha))
+    assert np.abs(g - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1e-30)

@@ -185,3 +185,68 @@ def test_estimator_is_unbiased(baseline):
     se = ests.std(axis=0, ddof=1) / np.sqrt(reps)
     z = np.abs(mean - g_exact) / np.maximum(se, 1e-12)
     assert np.all(z < 4.5), z.max()
+
+
+# --- the paper's own Bernoulli form, p = sigmoid(alpha (b^2 - d^2) / b^2) -------------------
+
+def test_quadratic_probability_closed_forms():
+    b, alpha = 0.25, 3.0
+    p = RF.edge_prob_quadratic(np.array([b * b, 0.0, 2 * b * b]), b, alpha)
+    assert p[0] == 0.5                                   # z = 0 at d = b
+    assert abs(p[1] - 1.0 / (1.0 + np.exp(-alpha))) < 1e-15   # z = alpha at d = 0
+    assert abs(p[2] - 1.0 / (1.0 + np.exp(alpha))) < 1e-15    # z = -alpha at d = b sqrt 2
+
+
+def test_quadratic_single_edge_closed_form():
+    pos = np.array([[1.0, 1.0, 1.0], [1.18, 1.0, 1.0]], np.float32)
+    b, alpha, L = 0.2, 2.0, 8.0
+    EL, g = RF.enumerate_gradient(pos, L, b, None, 0.5, loss_pair, alpha=alpha)
+    d = float(np.float32(1.18)) - float(np.float32(1.0))
+    p = 1.0 / (1.0 + np.exp(-alpha * (b * b - d * d) / (b * b)))
+    assert abs(EL - p) < 1e-14
+    # dz/dx_0 = -2 alpha (x0 - x1) / b^2 = +2 alpha d / b^2 along x
+    np.testing.assert_allclose(g[0], [p * (1 - p) * 2 * alpha * d / (b * b), 0, 0],
+                               rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(g[1], -g[0], rtol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_quadratic_enumerated_gradient_matches_finite_differences(seed):
+    pos = small_graph(seed)
+    L, b, alpha, r_c = 8.0, 0.32, 3.0, 0.55   # 11 edges: axis pairs and diagonals
+    lossf = lambda root: RF.loss_sum_sq(root, 2)
+    ei, ej, _ = RF.candidate_edges(pos, L, r_c)
+    assert 2 <= ei.shape[0] <= 12
+    EL, g = RF.enumerate_gradient(pos, L, b, None, r_c, lossf, alpha=alpha)
+    for i in range(pos.shape[0]):
+        for a in range(3):
+            h = 2e-4
+            p1, p2 = pos.copy(), pos.copy()
+            p1[i, a] = np.float32(float(p1[i, a]) + h)
+            p2[i, a] = np.float32(float(p2[i, a]) - h)
+            den = float(p1[i, a]) - float(p2[i, a])
+            fd = (RF.expected_loss(p1, L, b, None, r_c, lossf, alpha=alpha) -
+                  RF.expected_loss(p2, L, b, None, r_c, lossf, alpha=alpha)) / den
+            assert abs(fd - g[i, a]) <= 1e-3 * max(abs(g).max(), 1e-9), (i, a, fd, g[i, a])
+
+
+def test_quadratic_estimator_is_unbiased():
+    pos = small_graph(4)
+    L, b, alpha, r_c = 8.0, 0.32, 3.0, 0.55
+    lossf = lambda root: RF.loss_sum_sq(root, 2)
+    _, g_exact = RF.enumerate_gradient(pos, L, b, None, r_c, lossf, alpha=alpha)
+    ei, ej, d2 = RF.candidate_edges(pos, L, r_c)
+    delta, d = RF.edge_geometry(pos, L, ei, ej)
+    p = RF.edge_prob_quadratic(d2, b, alpha)
+    c = RF.dz_factor(d, b, alpha=alpha)
+    K, reps = 16, 400
+    ests = []
+    for rep in range(reps):
+        root, keep = RF.sample_labels(pos.shape[0], ei, ej, p, 3000 + rep, K)
+        losses = [lossf(root[s]) for s in range(K)]
+        ests.append(RF.score_gradient(pos.shape[0], ei, ej, delta, d, p, None, keep, losses,
+                                      "loo", c=c))
+    ests = np.array(ests)
+    se = ests.std(axis=0, ddof=1) / np.sqrt(reps)
+    z = np.abs(ests.mean(axis=0) - g_exact) / np.maximum(se, 1e-12)
+    assert np.all(z < 4.5), z.max()
