@@ -162,7 +162,9 @@ int fof_link(const fof_grid *grid, void *ws /*dev*/, const fof_sample *sample /*
              int32_t *root /*dev*/, void *stream);
 
 /* Group catalogue (paper Sec. 2 step (vi); Alg. 2 compaction; Sec. 3.1 halo position).
- * Must follow fof_link on the same workspace.  Components with at least min_size members
+ * Must follow fof_link without a sample (the labelling pass) on the same workspace: it reads
+ * the union-find state and the list of linked particles that call leaves.  Components with at
+ * least min_size members
  * are kept and numbered 0..G-1 in ascending order of their label (the smallest member
  * index); group_id (dev, int32 [n]) gets that number, or -1 for particles of cut
  * components.  *n_groups (dev, one int32) receives G.  For g < min(G, cap):
