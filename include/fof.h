@@ -37,7 +37,7 @@ extern "C" {
 #define FOF_ENOMEM (-2)     /* workspace smaller than fof_workspace_bytes asked for          */
 #define FOF_EOVERFLOW (-3)  /* more groups than `cap`; counts still hold the true totals    */
 #define FOF_EDEVICE (-4)    /* a HIP launch failed                                            */
-#define FOF_ENOTSUP (-5)    /* option not supported by this build                             */
+#define FOF_ENOTSUP (-5)    /* option not supported by this library                           */
 
 /* Bits of the device status word (see fof_status). */
 #define FOF_STATUS_RANGE 1u     /* some coordinate was NaN or outside [0, L)                  */

@@ -3,7 +3,7 @@
 Paper Sec. 3.2: every candidate edge between nearby particles is a Bernoulli variable and
 the gradient of an expected loss is estimated by (1/S) sum_s (L_s - baseline) grad log p(y_s).
 
-Readings fixed for this build (the paper is silent or uses other symbols):
+Readings fixed here (the paper is silent or uses other symbols):
   * edge probability p_e = sigmoid(z_e), z_e = (b - d_e) / tau, d_e the minimum-image
     distance (the paper's own form sigmoid(alpha (b^2 - d^2) / b^2) agrees near d = b with
     alpha = b / (2 tau));

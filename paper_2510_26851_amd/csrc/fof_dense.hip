@@ -70,17 +70,6 @@ __device__ __forceinline__ int fine_key(const BoxDesc &B, const CellXYZ &cc, flo
     return (fz * m + fy) * m + fx;
 }
 
-__device__ __forceinline__ int table_rank(const int32_t *T, int words, int k)
-{
-    uint32_t w = (uint32_t)T[kTableHeader + (k >> 5)];
-    return T[kTableHeader + words + (k >> 5)] + __popc(w & ((1u << (k & 31)) - 1u));
-}
-
-__device__ __forceinline__ bool table_has(const int32_t *T, int k)
-{
-    return ((uint32_t)T[kTableHeader + (k >> 5)] >> (k & 31)) & 1u;
-}
-
 // LDS union-find over fine keys: hook the larger root under the smaller.
 __device__ __forceinline__ int lfind(int *uf, int x)
 {
@@ -347,7 +336,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_sort(Work w)
         if (threadIdx.x == 0)
             koff[K] = n;
         __syncthreads();
-        if (threadIdx.x < W) {
+        if ((int)threadIdx.x < W) {
             int pre = 0;
             for (int q = 0; q < (int)threadIdx.x; ++q)
                 pre += __popc(kbits[q]);

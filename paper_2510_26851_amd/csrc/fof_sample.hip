@@ -476,12 +476,13 @@ hipError_t launch_sample(const Work &w, const fof_sample &S, int32_t *root, hipS
     e = launch_fill_i32(a.vflag, w.n, 0, s);
     if (e != hipSuccess)
         return e;
-    if (w.n > 0)
+    if (w.n > 0) {
         if (w.ntiles > 0)
             hipLaunchKernelGGL(k_edges_tiled, dim3((unsigned)w.ntiles), dim3(kTileBlock), 0, s,
                                w, a);
         else
             hipLaunchKernelGGL(k_edges, dim3(blocks_for(w.n)), dim3(kBlock), 0, s, w, a);
+    }
     // edges at most edge_cap: the grid of the following kernels is sized for the cap
     hipLaunchKernelGGL(k_touch, dim3(edge_blocks(S.edge_cap)), dim3(kBlock), 0, s, a);
     e = launch_scan_i32(a.vflag, a.vmap, w.n, a.scan, s);
