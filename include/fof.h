@@ -122,6 +122,7 @@ typedef struct fof_grid {
     int64_t ncell;        /* total coarse cells over all boxes                                */
     int64_t dense_cap;    /* dense cells that can get clique tables                           */
     int64_t ntiles;       /* link tiles (blocks of the LDS-tiled link kernel)                 */
+    int64_t n_plain;      /* particles of the boxes too small for link tiles                  */
     int32_t dense_threshold;
     int32_t table_words;  /* 32-bit words of one clique bitmask                               */
     int64_t link_edges;   /* capacity of the deferred link hooks (pairs)                      */

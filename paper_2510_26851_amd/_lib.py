@@ -63,7 +63,7 @@ class fof_sample(ctypes.Structure):
 class fof_grid(ctypes.Structure):
     _fields_ = [("nbox", ctypes.c_int32), ("block", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("ncell", ctypes.c_int64), ("dense_cap", ctypes.c_int64),
-                ("ntiles", ctypes.c_int64),
+                ("ntiles", ctypes.c_int64), ("n_plain", ctypes.c_int64),
                 ("dense_threshold", ctypes.c_int32), ("table_words", ctypes.c_int32),
                 ("link_edges", ctypes.c_int64), ("ws_bytes", ctypes.c_size_t), ("desc_bytes", ctypes.c_size_t),
                 ("off_desc", ctypes.c_size_t)] + [

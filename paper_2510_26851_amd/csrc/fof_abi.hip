@@ -227,6 +227,7 @@ Work resolve(const fof_grid *g, void *ws)
     w.n = g->n;
     w.ncell = g->ncell;
     w.ntiles = g->ntiles;
+    w.n_plain = g->n_plain;
     return w;
 }
 
@@ -268,7 +269,7 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
                  tune->block < 0 || (tune->block % kWave) != 0 ||
                  tune->block > 1024 || !(tune->cell_side >= 0.0)))
         return FOF_EINVAL;
-    int64_t n = 0, ncell = 0, ntiles = 0;
+    int64_t n = 0, ncell = 0, ntiles = 0, n_plain = 0;
     int32_t mmax = 1, any_dense = 0;
     BoxDesc *out = (BoxDesc *)desc;
     const size_t need = sizeof(BoxDesc) * (size_t)nbox;
@@ -285,6 +286,8 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
         d.tile_base = ntiles;
         if (d.tiled)
             ntiles += (int64_t)d.ntile[0] * d.ntile[1] * d.ntile[2];
+        else
+            n_plain += count[k];
         n += count[k];
         ncell += (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
         if (n > INT32_MAX || ncell > INT32_MAX - 1)
@@ -321,6 +324,7 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
     grid->ncell = ncell;
     grid->dense_threshold = thr;
     grid->ntiles = ntiles;
+    grid->n_plain = n_plain;
     grid->link_edges = link_edges;
     grid->dense_cap = dense_cap;
     grid->table_words = words;

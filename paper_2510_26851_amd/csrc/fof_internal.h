@@ -388,6 +388,7 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
     int64_t n;
     int64_t ncell;
     int64_t ntiles;           // link tiles over all tiled boxes
+    int64_t n_plain;          // particles of boxes without link tiles
     int32_t dense_threshold;  // cells with more particles take the clique path (< 0: never)
     int32_t dense_cap;        // dense cells with tables
     int32_t table_words;      // words of one key bitmask

@@ -563,7 +563,8 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideSt
         const unsigned wb = (unsigned)(w.ntiles < kWindowBlocks ? w.ntiles : kWindowBlocks);
         hipLaunchKernelGGL(k_link_windows, dim3(wb), dim3(kTileBlock), 0, s, w, root);
     }
-    hipLaunchKernelGGL(k_link, dim3(nb), dim3(w.block), 0, s, w, root);
+    if (w.n_plain > 0)  // boxes too small for tiles
+        hipLaunchKernelGGL(k_link, dim3(nb), dim3(w.block), 0, s, w, root);
     if (fork && (e = hipStreamWaitEvent(s, side->cc, 0)) != hipSuccess)
         return e;
     e = launch_dense_sparse(w, s);  // after every plain store of the tiled kernel

@@ -281,3 +281,14 @@ def test_one_hip_runtime_per_process():
                        timeout=300)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip() == "1"
+
+
+def test_plan_counts_the_particles_of_boxes_without_tiles():
+    # a 3-wide box is too small for link tiles (it needs 18 cells along z), a 40-wide one is
+    rc, g, buf = plan([100, 40000], [(3.0, 0.4), (40.0, 0.4)])
+    assert rc == 0 and decode(buf, 0)["tiled"] == 0 and decode(buf, 1)["tiled"] == 1
+    assert g.n_plain == 100 and g.ntiles > 0
+    t = _lib.fof_tune()
+    t.flags = _lib.FOF_TUNE_NO_TILES
+    rc, g, _ = plan([100, 40000], [(3.0, 0.4), (40.0, 0.4)], tune=t)
+    assert rc == 0 and g.n_plain == 40100 and g.ntiles == 0
