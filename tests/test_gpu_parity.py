@@ -220,3 +220,38 @@ def test_grid_over_2_27_cells_takes_the_per_particle_binning():
     np.testing.assert_array_equal(g0["sizes"], g1["sizes"])
     from gpu_util import com_close
     assert com_close(g0["com"], g1["com"], L, L / n ** (1 / 3))
+
+
+@pytest.mark.parametrize("n", [5000, 40000])
+def test_all_particles_at_one_point(n):
+    """Degenerate input: one cell holds every particle (the bucketed binning then sorts one
+    bucket larger than a block's register chunk, and the dense path stages through HBM).
+    Closed form: one group of n, labelled 0, centred on the point."""
+    say(f"all {n} particles at one point")
+    pos = np.full((n, 3), 3.3, np.float32)
+    root, g, status = run_gpu(pos, 10.0, 0.5, 2)
+    assert status == 0
+    assert np.all(root == 0) and g["n_groups"] == 1 and g["sizes"][0] == n
+    np.testing.assert_array_equal(g["com"][0], np.float64(np.float32(3.3)) * np.ones(3))
+
+
+def test_two_points_and_the_box_edge():
+    """Two points of 20000 particles each, and pairs straddling the periodic edge: one at
+    0.0, one at the largest float32 below L (closer than b through the boundary)."""
+    say("two points + edge pairs")
+    L = 10.0
+    below = np.nextafter(np.float32(L), np.float32(0))
+    a = np.full((20000, 3), 2.0, np.float32)
+    b_ = np.full((20000, 3), 7.0, np.float32)
+    edge = np.array([[0.0, 5.0, 5.0], [below, 5.0, 5.0],
+                     [5.0, 0.0, 1.0], [5.0, below, 1.0]], np.float32)
+    pos = np.concatenate([a, b_, edge])
+    root, g, status = run_gpu(pos, L, 0.5, 2)
+    assert status == 0
+    assert np.all(root[:20000] == 0) and np.all(root[20000:40000] == 20000)
+    np.testing.assert_array_equal(root[40000:], [40000, 40000, 40002, 40002])
+    assert g["n_groups"] == 4
+    np.testing.assert_array_equal(g["sizes"], [20000, 20000, 2, 2])
+    # the edge pairs' centres sit on the boundary (wrapped into [0, L))
+    c = g["com"][2]
+    assert min(c[0], L - c[0]) < 1e-5 and abs(c[1] - 5.0) < 1e-6 and abs(c[2] - 5.0) < 1e-6
