@@ -66,3 +66,13 @@ def test_full_size_zeldovich_nfw_512():
             assert ref["n_groups"] == 1
             assert com_close(com[rank[mem[0]]][None], ref["com"], box.L, spacing), s
     idx.close()
+
+
+def test_zeldovich_256_against_the_full_oracle():
+    """The 256^3 Zel'dovich box (16.8M particles): every label, group id, size and centre of
+    mass against the oracle run on the whole box."""
+    from gpu_util import compare_with_oracle
+
+    box = W.make(1)
+    say(f"full oracle comparison {box.name}: n={box.n}")
+    compare_with_oracle(box.pos, box.L, box.b, box.min_size)
