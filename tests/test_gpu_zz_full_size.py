@@ -2,7 +2,10 @@
 the same launch configuration (default tuning, helper stream), checked by properties that
 hold at any size and, on 200 seeded particles (half of them in groups), against the oracle's
 exact single-component search over the whole box.  (Collected last: it takes about two
-minutes, most of it generating the box and indexing it for the oracle.)"""
+minutes, most of it generating the box and indexing it for the oracle.)  The same check at
+1024^3 runs only when FOF_TEST_1024=1 is set."""
+import os
+
 import numpy as np
 import pytest
 
@@ -21,10 +24,60 @@ def _gpu():
 
 
 def test_full_size_zeldovich_nfw_512():
+    check_full_size(W.make(2))
+
+
+@pytest.mark.skipif(os.environ.get("FOF_TEST_1024") != "1",
+                    reason="the 1024^3 box takes minutes and about 100 GB of host memory to "
+                           "draw and index; set FOF_TEST_1024=1 to run it")
+def test_full_size_zeldovich_nfw_1024():
+    """1024^3 particles (1.07e9, int32 indices near their limit, 2^30 cells: the
+    per-particle binning path) with 400,000 NFW clumps, in one box on one GPU."""
+    check_full_size(W.make(5, progress=say), whole_box_oracle=False)
+
+
+def check_slab(box, root, cnt, rank, com, z0, width):
+    """Every component that lies inside the slab z0 <= z < z0 + width, more than b from both
+    of its faces, against the oracle run on the slab alone (in a periodic box padded to
+    width + 2 along z, so nothing links across the cut): such a component is the same set in
+    the slab as in the whole box, since every particle outside the slab is more than b away
+    from each of its members along z."""
+    z = box.pos[:, 2].astype(np.float64)
+    sel = np.nonzero((z >= z0) & (z < z0 + width))[0]          # ascending original indices
+    sub = np.ascontiguousarray(box.pos[sel])
+    assert z0 == float(np.float32(z0)) and width <= z0
+    sub[:, 2] -= np.float32(z0)        # exact (z0 <= z < 2 z0), so every distance is unchanged
+    Lpad = (box.L[0], box.L[1], float(width) + 2.0)
+    say(f"slab oracle: {sel.size} particles")
+    oroot, _ = oracle.fof(sub, Lpad, box.b)
+    oroot = oroot.astype(np.int64)
+    zs = z[sel] - z0
+    margin = box.b * 1.001
+    edge = (zs < margin) | (zs >= width - margin)
+    touched = np.bincount(oroot[edge], minlength=sel.size) > 0
+    inner = ~touched[oroot]                                     # members of interior components
+    assert inner.mean() > 0.5
+    # labels: the smallest original index of the component (ascending map local -> original)
+    np.testing.assert_array_equal(root[sel[inner]], sel[oroot[inner]])
+    osize = np.bincount(oroot[inner], minlength=sel.size)
+    lab = np.nonzero(osize)[0]
+    np.testing.assert_array_equal(cnt[sel[lab]], osize[lab])   # no member outside the slab
+    ref = oracle.groups(sub, oroot.astype(np.int32), Lpad, box.min_size)
+    glab = np.nonzero(np.bincount(oroot, minlength=sel.size) >= box.min_size)[0]
+    keep = ~touched[glab]
+    spacing = float(box.L[0]) / round(box.n ** (1 / 3))
+    gcom = com[rank[sel[glab[keep]]]]
+    rcom = ref["com"][:ref["n_groups"]][keep].copy()
+    rcom[:, 2] += z0
+    rcom[:, 2] = np.mod(rcom[:, 2], box.L[2])
+    assert com_close(gcom, rcom, box.L, spacing)
+    say(f"slab: {lab.size} interior components, {int(keep.sum())} groups")
+
+
+def check_full_size(box, whole_box_oracle=True):
     import torch
     from paper_2510_26851_amd import Plan, trim
 
-    box = W.make(2)
     n = box.n
     say(f"full size {box.name}: n={n}")
     dev = torch.device("cuda:0")
@@ -34,6 +87,8 @@ def test_full_size_zeldovich_nfw_512():
     res = trim(plan.groups(box.min_size))
     torch.cuda.synchronize()
     assert plan.status() == 0
+    say("linked")
+    del plan
     root = root.cpu().numpy()
     gid = res["group_id"].cpu().numpy()
     sizes = res["sizes"].cpu().numpy()
@@ -48,6 +103,10 @@ def test_full_size_zeldovich_nfw_512():
     rank = np.full(n, -1, np.int64)
     rank[kept] = np.arange(kept.size)
     np.testing.assert_array_equal(gid, rank[root])
+    width = 64.0 * (512.0 / box.L[0]) ** 2                     # about 16.8M particles
+    check_slab(box, root, cnt, rank, com, 0.375 * box.L[2], width)
+    if not whole_box_oracle:
+        return
     say("oracle index")
     idx = oracle.Index(box.pos, box.L, box.b)
     rng = np.random.default_rng(2026)

@@ -17,6 +17,8 @@ Configurations (sizes as in the workload table of the design notes):
   2  zeldovich:  512^3 lattice, L = 512, b = 0.2, rms 0.8 + 50,000 NFW clumps
   3  zeldovich:  128^3 lattice, L = 128, b = 0.2, rms 0.5, Gaussian velocities (sigma = 1)
   4  batch:      256 boxes, N_b log-uniform in [16^3, 128^3], clump generator per box
+  5  zeldovich:  1024^3 lattice, L = 1024, b = 0.2, rms 0.8 + 400,000 NFW clumps (the 512^3
+                 recipe at eight times the volume; about 80 GB of host memory while drawn)
 """
 from __future__ import annotations
 
@@ -110,7 +112,13 @@ def config0() -> Box:
 # --------------------------------------------------------------------------------------
 # Zel'dovich lattice generator (configs 1-3)
 # --------------------------------------------------------------------------------------
-def zeldovich_displacement(rng: np.random.Generator, n: int, rms: float) -> np.ndarray:
+def _say(progress, msg):
+    if progress is not None:
+        progress(msg)
+
+
+def zeldovich_displacement(rng: np.random.Generator, n: int, rms: float,
+                           progress=None) -> np.ndarray:
     """Displacement field psi on an n^3 lattice (spacing 1) with P_psi(k) ~ k^-2.
 
     White noise w -> w_hat; psi_hat = i k w_hat / k^2 (so div psi = -delta with a white
@@ -120,7 +128,9 @@ def zeldovich_displacement(rng: np.random.Generator, n: int, rms: float) -> np.n
     import scipy.fft as sfft
 
     w = rng.standard_normal((n, n, n))
+    _say(progress, "white noise drawn")
     wk = sfft.rfftn(w, workers=_threads())
+    _say(progress, "forward FFT done")
     del w
     k1 = 2.0 * np.pi * np.fft.fftfreq(n)
     kz1 = 2.0 * np.pi * np.fft.rfftfreq(n)
@@ -140,6 +150,7 @@ def zeldovich_displacement(rng: np.random.Generator, n: int, rms: float) -> np.n
         comp = sfft.irfftn(1j * kc * wk, s=(n, n, n), workers=_threads())
         psi[:, c] = comp.reshape(-1)
         del comp
+        _say(progress, f"displacement component {c} done")
     del wk
     cur = math.sqrt(float(np.mean(np.sum(psi * psi, axis=1))))
     psi *= rms / cur
@@ -170,7 +181,7 @@ def nfw_radius(u: np.ndarray, c: float) -> np.ndarray:
 
 
 def config_zeldovich(cfg: int, n: int, rms: float, *, with_vel: bool = False,
-                     n_nfw: int = 0) -> Box:
+                     n_nfw: int = 0, progress=None) -> Box:
     """Draw order: white noise (n^3); [velocities (n^3, 3)]; then for the NFW clumps:
     centres (n_nfw, 3), r200 log-uniform on [0.5, 3] (n_nfw), member counts from the
     truncated power law dN/dn ~ n^-2 on [100, 1e4] (n_nfw), a permutation of all particles
@@ -178,10 +189,11 @@ def config_zeldovich(cfg: int, n: int, rms: float, *, with_vel: bool = False,
     member directions standard normal (members, 3)."""
     rng = np.random.default_rng(SEED_BASE + cfg)
     L = float(n)
-    psi = zeldovich_displacement(rng, n, rms)
+    psi = zeldovich_displacement(rng, n, rms, progress)
     x = lattice(n)
     x += psi
     del psi
+    _say(progress, "lattice displaced")
     vel = None
     if with_vel:
         vel = rng.standard_normal((n * n * n, 3)).astype(np.float32)
@@ -193,15 +205,22 @@ def config_zeldovich(cfg: int, n: int, rms: float, *, with_vel: bool = False,
         cnt = np.rint(1.0 / (1.0 / lo - u * (1.0 / lo - 1.0 / hi))).astype(np.int64)
         total = int(cnt.sum())
         perm = rng.permutation(n * n * n)[:total]
+        _say(progress, "clump members chosen")
         rad = nfw_radius(rng.random(total), 10.0)
         owner = np.repeat(np.arange(n_nfw), cnt)
         rad *= (r200 / 10.0)[owner]
         d = rng.standard_normal((total, 3))
         d /= np.sqrt(np.sum(d * d, axis=1))[:, None]
         x[perm] = centres[owner] + d * rad[:, None]
+        del perm, rad, owner, d
+        _say(progress, "clumps placed")
     b = linking_length(0.2, L, n ** 3)
-    names = {1: "zeldovich-256^3", 2: "zeldovich-nfw-512^3", 3: "zeldovich-128^3-vel"}
-    return Box(wrap_to_f32(x, (L, L, L)), (L, L, L), b, 2 if with_vel else 20, vel=vel,
+    names = {1: "zeldovich-256^3", 2: "zeldovich-nfw-512^3", 3: "zeldovich-128^3-vel",
+             5: "zeldovich-nfw-1024^3"}
+    pos = wrap_to_f32(x, (L, L, L))
+    del x
+    _say(progress, "wrapped to float32")
+    return Box(pos, (L, L, L), b, 2 if with_vel else 20, vel=vel,
                name=names.get(cfg, f"zeldovich-{n}^3"))
 
 
@@ -211,6 +230,10 @@ def config1() -> Box:
 
 def config2() -> Box:
     return config_zeldovich(2, 512, 0.8, n_nfw=50000)
+
+
+def config5(progress=None) -> Box:
+    return config_zeldovich(5, 1024, 0.8, n_nfw=400000, progress=progress)
 
 
 def config3() -> Box:
@@ -242,7 +265,9 @@ def config4(nbox: int = 256, n_lo: int = 16 ** 3, n_hi: int = 128 ** 3) -> list:
     return boxes
 
 
-def make(cfg: int):
+def make(cfg: int, progress=None):
+    if cfg == 5:
+        return config5(progress)
     return {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}[cfg]()
 
 
