@@ -13,6 +13,8 @@ Functions and the passages they follow (paper section / algorithm):
   dispersion_backward    Sec. 3.1 decorated frozen assignment: the particle standard
                          deviation of each halo as the decoration, and its gradient
   component              BFS closure of one particle under the same predicate (sampled checks)
+  subhalos               Sec. 2 sub-halo finding: a second, six-dimensional pass inside
+                         each host halo with the phase-space distance of that passage
   philox4x64, uniforms,
   candidate_edges,
   sample_labels,
@@ -237,3 +239,47 @@ def dispersion_backward(pos, group_id, sizes, com, sigx, g_sigx, L):
     grad[m] = (g_sigx[g] / (3.0 * sizes[g] * sigx[g]))[:, None] * d
     return grad
 
+
+
+def subhalos(pos, vel, group_id, norm_x, norm_v, b6, L):
+    """Six-dimensional sub-halo pass (Sec. 2, sub-halo finding).
+
+    Inside each host g (the particles with group_id == g >= 0) two particles are phase-space
+    friends when d(i, j) < b6, where
+        d^2 = |mi(x_i - x_j)|^2 / norm_x[g] + |v_i - v_j|^2 / norm_v[g],
+    the paper's metric with its normalisation factors dividing the squared separations as
+    printed; mi is the per-axis minimum image.  A host whose factors are not both positive
+    is left as singletons (the metric is undefined there).  Particles of different hosts never link.
+    Each squared norm is summed as ((c0*c0 + c1*c1) + c2*c2) in FP64 from the float32 inputs.
+    Returns int32[n]: the smallest original index of the particle's phase-space component,
+    -1 for particles outside every host.  Brute force over the pairs of each host (plain
+    numpy + a library connected-components routine), so hosts must stay small (a few
+    thousand members)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    pos = _pos(pos)
+    vel = np.asarray(vel, dtype=np.float32).reshape(-1, 3).astype(np.float64)
+    gid = np.asarray(group_id, dtype=np.int64).reshape(-1)
+    L3 = _L(L)
+    n = pos.shape[0]
+    out = np.full(n, -1, dtype=np.int32)
+    bb = float(b6) * float(b6)
+    for g in np.unique(gid[gid >= 0]):
+        m = np.nonzero(gid == g)[0]
+        if not (float(norm_x[g]) > 0.0 and float(norm_v[g]) > 0.0):
+            out[m] = m
+            continue
+        x, v = pos[m].astype(np.float64), vel[m]
+        dx = _min_image(x[:, None, :] - x[None, :, :], L3)
+        sx = (dx[..., 0] * dx[..., 0] + dx[..., 1] * dx[..., 1]) + dx[..., 2] * dx[..., 2]
+        del dx
+        dv = v[:, None, :] - v[None, :, :]
+        sv = (dv[..., 0] * dv[..., 0] + dv[..., 1] * dv[..., 1]) + dv[..., 2] * dv[..., 2]
+        del dv
+        d2 = sx / float(norm_x[g]) + sv / float(norm_v[g])
+        _, lab = connected_components(csr_matrix(d2 < bb), directed=False)
+        first = np.full(lab.max() + 1, m.size, dtype=np.int64)
+        np.minimum.at(first, lab, np.arange(m.size))
+        out[m] = m[first[lab]]
+    return out

@@ -274,6 +274,36 @@ def make(cfg: int, progress=None):
 # --------------------------------------------------------------------------------------
 # Small structured inputs for tests
 # --------------------------------------------------------------------------------------
+def phase_space_hosts(n_hosts: int, L: float, seed: int, n_sub: int = 3,
+                      members=(30, 400), n_background: int = 0):
+    """Hosts made of sub-clumps that overlap in space but move apart in velocity, for the
+    six-dimensional sub-halo pass (a stand-in for the paper's CAMELS halos).
+
+    Draw order: host centres (n_hosts, 3) uniform in [0, L); member counts (n_hosts, n_sub)
+    integers in [members[0], members[1]]; sub-clump offsets (n_hosts, n_sub, 3) normal with
+    sigma 0.25; bulk velocities (n_hosts, n_sub, 3) normal with sigma 4; then per sub-clump,
+    in order, member positions normal about its centre (sigma 0.12) and member velocities
+    normal about its bulk velocity (sigma 0.3); finally n_background uniform positions with
+    normal velocities (sigma 1).  Returns (pos float32 [n, 3], vel float32 [n, 3])."""
+    rng = np.random.default_rng(seed)
+    centres = rng.random((n_hosts, 3)) * L
+    counts = rng.integers(members[0], members[1], (n_hosts, n_sub), endpoint=True)
+    offs = rng.normal(0.0, 0.25, (n_hosts, n_sub, 3))
+    bulk = rng.normal(0.0, 4.0, (n_hosts, n_sub, 3))
+    xs, vs = [], []
+    for h in range(n_hosts):
+        for k in range(n_sub):
+            c = int(counts[h, k])
+            xs.append(centres[h] + offs[h, k] + rng.normal(0.0, 0.12, (c, 3)))
+            vs.append(bulk[h, k] + rng.normal(0.0, 0.3, (c, 3)))
+    if n_background:
+        xs.append(rng.random((n_background, 3)) * L)
+        vs.append(rng.normal(0.0, 1.0, (n_background, 3)))
+    x = np.concatenate(xs)
+    v = np.concatenate(vs).astype(np.float32)
+    return wrap_to_f32(x, (L, L, L)), v
+
+
 def uniform_box(n: int, L, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     L = np.asarray(L, dtype=np.float64).reshape(1, 3)
