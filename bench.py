@@ -177,6 +177,46 @@ def decorated_rate(torch, plan, pos, out, cap, ng, stream, workload, reps=10):
                 timed="fof_group_dispersion; fof_backward_dispersion (adds into grad_pos)")
 
 
+def subhalo_rate(torch, dev, reps=5):
+    """Six-dimensional sub-halo pass over the hosts of a phase-space box: 2000 hosts of three
+    sub-clumps (30-400 members each) in a 96^3 box with 2M background particles, b = 0.2,
+    min size 20, factors 0.04 and 1.0, b6 = 1.  Times fof_subhalo alone (HIP events on the
+    launch stream) and counts the member pairs it tests."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2510_26851_amd import Plan, trim
+
+    L, b = 96.0, 0.2
+    pos, vel = W.phase_space_hosts(2000, L, W.SEED_BASE + 200, n_background=2_000_000)
+    tp, tv = torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev)
+    plan = Plan([pos.shape[0]], [(L, b)], device=dev)
+    plan.build_grid(tp)
+    plan.link()
+    res = trim(plan.groups(20))
+    G = int(res["n_groups"])
+    nx = torch.full((G,), 0.04, dtype=torch.float64, device=dev)
+    nv = torch.ones(G, dtype=torch.float64, device=dev)
+    sub = torch.empty(pos.shape[0], dtype=torch.int32, device=dev)
+    plan.subhalo(tp, tv, res["group_id"], G, res["sizes"], nx, nv, 1.0, sub=sub)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        plan.subhalo(tp, tv, res["group_id"], G, res["sizes"], nx, nv, 1.0, sub=sub)
+    e.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e) / reps
+    m = res["sizes"].cpu().numpy().astype(np.float64)
+    pairs = float(np.sum(m * (m - 1) / 2))
+    s = sub.cpu().numpy()
+    return dict(workload=f"phase-space hosts: 2000 x 3 sub-clumps + 2M background, L={L:g}",
+                n=int(pos.shape[0]), hosts=G, subhalos=int(np.unique(s[s >= 0]).size),
+                ms=round(ms, 4), pairs=int(pairs), gpairs_per_s=round(pairs / ms / 1e6, 2),
+                timed="fof_subhalo (scatter into hosts, all-pairs 6-D test, labels)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +232,7 @@ def main():
     ap.add_argument("--no-tiles", action="store_true", help="link without LDS tiles")
     ap.add_argument("--no-reinforce", action="store_true")
     ap.add_argument("--reinforce-reps", type=int, default=20)
+    ap.add_argument("--no-subhalo", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -302,6 +343,9 @@ def main():
     if not args.no_reinforce:
         log("timing batched REINFORCE ...")
         line["reinforce"] = reinforce_rate(torch, dev, args.reinforce_reps)
+    if not args.no_subhalo:
+        log("timing the sub-halo pass ...")
+        line["subhalo"] = subhalo_rate(torch, dev)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         zmax = args.cpu_zmax or 64.0 * (512.0 / box.L[0]) * (512.0 / box.L[1])

@@ -224,6 +224,28 @@ int fof_backward_dispersion(const fof_grid *grid, void *ws /*dev*/, const float 
                             const double *com, const double *sigx, const double *g_sigx,
                             float *grad_pos, void *stream);
 
+/* Six-dimensional sub-halo pass (paper Sec. 2, sub-halo finding): inside each host halo g
+ * (the particles with group_id[i] == g, 0 <= g < G, as fof_groups labels them) a second
+ * Friends-of-Friends pass in phase space, two members linking when
+ *   |mi(x_i - x_j)|^2 / norm_x[g] + |v_i - v_j|^2 / norm_v[g] < b6^2,
+ * the paper's metric with its normalisation factors dividing the squared separations as
+ * printed (pass variances, e.g. sigx^2 and sigv^2, for a dispersion-scaled metric); mi is the
+ * per-axis minimum image of the particle's box; each squared norm is summed
+ * ((c0*c0 + c1*c1) + c2*c2) in FP64 from the float32 inputs.  Particles of different hosts
+ * never link.  sub (dev int32 [n]) receives the smallest original index of each member's
+ * phase-space component and -1 outside every host.  pos, vel (dev float32 [n][3]), group_id
+ * (dev int32 [n]), sizes (dev int32 [G], the member count of each host), norm_x, norm_v
+ * (dev double [G]; a host whose factors are not both positive splits into singletons).  scratch: dev, 256-byte aligned, >= fof_subhalo_scratch_bytes(n, G) bytes,
+ * owned by the caller, contents not preserved.  Every pair of a host is tested (cost grows
+ * with the square of the host's size).  Sizes that disagree with group_id drop the extra
+ * members and set FOF_STATUS_RANGE (cleared by fof_build_grid).  FOF_EINVAL for b6 not
+ * positive and finite, G < 0 or G > n, or missing buffers. */
+size_t fof_subhalo_scratch_bytes(int64_t n, int32_t G);
+int fof_subhalo(const fof_grid *grid, void *ws /*dev*/, const float *pos, const float *vel,
+                const int32_t *group_id, int32_t G, const int32_t *sizes, const double *norm_x,
+                const double *norm_v, double b6, void *scratch, size_t scratch_bytes,
+                int32_t *sub, void *stream);
+
 /* Device address of the int32 status word inside ws (FOF_STATUS_* bits; 0 = clean).  It is
  * cleared by fof_build_grid; read it after synchronising the stream. */
 int fof_status(const fof_grid *grid, void *ws /*dev*/, int32_t **status /*host out: dev ptr*/);

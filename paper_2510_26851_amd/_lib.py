@@ -38,8 +38,8 @@ def sample_scratch_bytes(n: int, K: int, edge_cap: int) -> int:
 
 # Every symbol include/fof.h declares.
 EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",
-           "fof_group_dispersion", "fof_backward_dispersion", "fof_status", "fof_strerror",
-           "fof_last_device_error", "fof_init")
+           "fof_group_dispersion", "fof_backward_dispersion", "fof_subhalo_scratch_bytes",
+           "fof_subhalo", "fof_status", "fof_strerror", "fof_last_device_error", "fof_init")
 
 
 class fof_box(ctypes.Structure):
@@ -106,6 +106,9 @@ def load():
     L.fof_backward.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, i32, P, P, P]
     L.fof_group_dispersion.argtypes = [P, P, i32, P, P, P, P, P]
     L.fof_backward_dispersion.argtypes = [P, P, P, P, i32, P, P, P, P, P, P]
+    L.fof_subhalo_scratch_bytes.argtypes = [i64, i32]
+    L.fof_subhalo_scratch_bytes.restype = sz
+    L.fof_subhalo.argtypes = [P, P, P, P, P, i32, P, P, P, ctypes.c_double, P, sz, P, P]
     L.fof_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_void_p)]
     L.fof_strerror.argtypes = [ctypes.c_int]
     L.fof_strerror.restype = ctypes.c_char_p

@@ -463,6 +463,30 @@ int fof_backward_dispersion(const fof_grid *grid, void *ws, const float *pos,
                                               grad_pos, (hipStream_t)stream));
 }
 
+size_t fof_subhalo_scratch_bytes(int64_t n, int32_t G)
+{
+    return n < 0 || G < 0 ? 0 : subhalo_scratch_bytes(n, G);
+}
+
+int fof_subhalo(const fof_grid *grid, void *ws, const float *pos, const float *vel,
+                const int32_t *group_id, int32_t G, const int32_t *sizes, const double *norm_x,
+                const double *norm_v, double b6, void *scratch, size_t scratch_bytes,
+                int32_t *sub, void *stream)
+{
+    if (!ws_ok(grid, ws) || G < 0 || G > grid->n || !(b6 > 0.0) || !isfinite(b6))
+        return FOF_EINVAL;
+    if (grid->n > 0 && !sub)
+        return FOF_EINVAL;
+    if (grid->n > 0 && G > 0 &&
+        (!pos || !vel || !group_id || !sizes || !norm_x || !norm_v || !scratch ||
+         ((uintptr_t)scratch % 256) != 0 || scratch_bytes < subhalo_scratch_bytes(grid->n, G)))
+        return FOF_EINVAL;
+    Work w = resolve(grid, ws);
+    clear_stale_error();
+    return dev_err(launch_subhalo(w, pos, vel, group_id, G, sizes, norm_x, norm_v, b6, scratch,
+                                  sub, (hipStream_t)stream));
+}
+
 int fof_status(const fof_grid *grid, void *ws, int32_t **status)
 {
     if (!ws_ok(grid, ws) || !status)

@@ -421,6 +421,11 @@ hipError_t launch_flag_list(const Work &w, hipStream_t s);
 hipError_t launch_group_dispersion(const Work &w, int32_t cap, const int32_t *n_groups,
                                    const int32_t *sizes, const double *com, double *sigx,
                                    hipStream_t s);
+size_t subhalo_scratch_bytes(int64_t n, int32_t G);
+hipError_t launch_subhalo(const Work &w, const float *pos, const float *vel,
+                          const int32_t *group_id, int32_t G, const int32_t *sizes,
+                          const double *norm_x, const double *norm_v, double b6, void *scratch,
+                          int32_t *sub, hipStream_t s);
 hipError_t launch_backward_dispersion(const Work &w, const float *pos, const int32_t *group_id,
                                       int32_t G, const int32_t *sizes, const double *com,
                                       const double *sigx, const double *g_sigx, float *grad_pos,

@@ -1,0 +1,173 @@
+// Six-dimensional sub-halo pass (paper Sec. 2, sub-halo finding): a second Friends-of-Friends
+// pass inside each host halo in phase space, two members linking when
+//   d^2 = |mi(x_i - x_j)|^2 / norm_x[g] + |v_i - v_j|^2 / norm_v[g] < b6^2.
+// Hosts are small next to the box (tens to thousands of members), so every pair of a host is
+// tested: one block per host, the host's members staged 256 at a time through LDS (positions
+// and velocities) against each thread's own member held in registers, hooks into the packed
+// lock-free union-find over the host's member slots.  The label is the smallest original
+// index of the phase-space component (the union-find's root key).
+#include <algorithm>
+
+#include "fof_internal.h"
+
+namespace fof {
+
+namespace {
+
+constexpr int kSubBlock = 256;
+
+// Every slot starts as a root of its own holding a valid particle index, so that a slot no
+// particle fills (sizes inconsistent with group_id) is still safe to read.
+__global__ void k_sub_init(int64_t n, uint64_t *__restrict__ par, int32_t *__restrict__ member)
+{
+    for (int64_t s = gtid(); s < n; s += (int64_t)gridDim.x * blockDim.x) {
+        par[s] = (uint64_t)(uint32_t)s;
+        member[s] = 0;
+    }
+}
+
+// Members of each host, host by host: slot = off[g] + arrival order (any order within a host;
+// the label does not depend on it).  Slots beyond the host's size or the buffer are dropped
+// and flagged, so inconsistent sizes can never write out of bounds.  A union-find entry holds
+// its parent's packed value, so the member's own index is kept beside it in member[].
+__global__ void k_sub_scatter(int64_t n, const int32_t *__restrict__ group_id, int32_t G,
+                              const int32_t *__restrict__ sizes, const int32_t *__restrict__ off,
+                              int32_t *__restrict__ cur, uint64_t *__restrict__ par,
+                              int32_t *__restrict__ member, Counters *__restrict__ ctr)
+{
+    const int64_t i = gtid();
+    if (i >= n)
+        return;
+    const int32_t g = group_id[i];
+    if (g < 0 || g >= G)
+        return;
+    const int32_t k = atomicAdd(cur + g, 1);
+    const int64_t slot = (int64_t)off[g] + k;
+    if (k >= sizes[g] || off[g] < 0 || slot >= n) {
+        atomicOr(&ctr->status, (int32_t)FOF_STATUS_RANGE);
+        return;
+    }
+    par[slot] = ((uint64_t)(uint32_t)i << 32) | (uint32_t)slot;
+    member[slot] = (int32_t)i;
+}
+
+// d^2 of the six-dimensional metric, each squared norm summed ((c0*c0 + c1*c1) + c2*c2) in
+// FP64 without contraction, so that the decision is the same as a plain evaluation.
+__device__ __forceinline__ bool phase_friends(const BoxDesc &B, const float (&xi)[6],
+                                              const float (&xj)[6], double inx, double inv,
+                                              double bb)
+{
+#pragma clang fp contract(off)
+    double d[6];
+    for (int a = 0; a < 3; ++a)
+        d[a] = min_image((double)xi[a] - (double)xj[a], B.L[a], B.halfL[a]);
+    for (int a = 3; a < 6; ++a)
+        d[a] = (double)xi[a] - (double)xj[a];
+    const double sx = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    const double sv = (d[3] * d[3] + d[4] * d[4]) + d[5] * d[5];
+    return sx / inx + sv / inv < bb;
+}
+
+__device__ __forceinline__ void load_member(const float *__restrict__ pos,
+                                            const float *__restrict__ vel, int64_t o, float (&p)[6])
+{
+    for (int a = 0; a < 3; ++a) {
+        p[a] = pos[3 * o + a];
+        p[3 + a] = vel[3 * o + a];
+    }
+}
+
+__global__ __launch_bounds__(kSubBlock) void k_sub_link(
+    int64_t n, const BoxDesc *__restrict__ desc, int nbox, const float *__restrict__ pos,
+    const float *__restrict__ vel, int32_t G, const int32_t *__restrict__ sizes,
+    const int32_t *__restrict__ off, const int32_t *__restrict__ cur,
+    const double *__restrict__ norm_x, const double *__restrict__ norm_v, double bb,
+    uint64_t *__restrict__ par, const int32_t *__restrict__ member, int32_t *__restrict__ sub)
+{
+    __shared__ float tile[6][kSubBlock];
+    const int32_t g = blockIdx.x;
+    const int64_t base = off[g];
+    int64_t m = min(cur[g], sizes[g]);
+    if (base < 0 || base >= n)
+        m = 0;
+    else if (m > n - base)
+        m = n - base;
+    if (m <= 0)
+        return;  // block-uniform
+    uint64_t *P = par;
+    const BoxDesc &B = desc[find_box(desc, nbox, member[base])];
+    const double inx = norm_x[g], inv = norm_v[g];
+    const bool metric_ok = inx > 0.0 && inv > 0.0;  // otherwise the host stays singletons
+    for (int64_t i0 = 0; i0 < m; i0 += kSubBlock) {
+        const int64_t i = i0 + threadIdx.x;
+        float mine[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (i < m)
+            load_member(pos, vel, member[base + i], mine);
+        for (int64_t j0 = i0; j0 < m; j0 += kSubBlock) {
+            __syncthreads();  // the previous tile is no longer read
+            const int64_t jl = j0 + threadIdx.x;
+            if (jl < m) {
+                float q[6];
+                load_member(pos, vel, member[base + jl], q);
+                for (int a = 0; a < 6; ++a)
+                    tile[a][threadIdx.x] = q[a];
+            }
+            __syncthreads();
+            if (i < m && metric_ok) {
+                const int cnt = (int)min((int64_t)kSubBlock, m - j0);
+                for (int t = 0; t < cnt; ++t) {
+                    if (j0 + t <= i)
+                        continue;
+                    const float other[6] = {tile[0][t], tile[1][t], tile[2][t],
+                                            tile[3][t], tile[4][t], tile[5][t]};
+                    if (phase_friends(B, mine, other, inx, inv, bb))
+                        uf_union(P, (uint32_t)(base + i), (uint32_t)(base + j0 + t));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < m; k += kSubBlock)
+        sub[member[base + k]] = (int32_t)uf_key(uf_find_ro(P, (uint32_t)(base + k)));
+}
+
+}  // namespace
+
+size_t subhalo_scratch_bytes(int64_t n, int32_t G)
+{
+    return 256 + 12 * (size_t)n + 4 * (2 * (size_t)G + (size_t)scan_scratch_elems(G) + 2);
+}
+
+hipError_t launch_subhalo(const Work &w, const float *pos, const float *vel,
+                          const int32_t *group_id, int32_t G, const int32_t *sizes,
+                          const double *norm_x, const double *norm_v, double b6, void *scratch,
+                          int32_t *sub, hipStream_t s)
+{
+    if (w.n <= 0)
+        return hipSuccess;
+    hipError_t e = launch_fill_i32(sub, w.n, -1, s);
+    if (e != hipSuccess || G <= 0)
+        return e;
+    char *p = (char *)scratch;
+    uint64_t *par = (uint64_t *)p;
+    int32_t *member = (int32_t *)(p + 8 * (size_t)w.n);
+    int32_t *off = member + w.n;
+    int32_t *cur = off + G;
+    int32_t *scan = cur + G;
+    if ((e = launch_scan_i32(sizes, off, G, scan, s)) != hipSuccess)
+        return e;
+    if ((e = launch_fill_i32(cur, G, 0, s)) != hipSuccess)
+        return e;
+    const unsigned ib = (unsigned)std::min<int64_t>((w.n + 1023) / 1024, 65536);
+    hipLaunchKernelGGL(k_sub_init, dim3(ib), dim3(1024), 0, s, w.n, par, member);
+    const unsigned nb = (unsigned)((w.n + w.block - 1) / w.block);
+    hipLaunchKernelGGL(k_sub_scatter, dim3(nb), dim3(w.block), 0, s, w.n, group_id, G, sizes, off,
+                       cur, par, member, w.ctr);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sub_link, dim3((unsigned)G), dim3(kSubBlock), 0, s, w.n, w.desc, w.nbox,
+                       pos, vel, G, sizes, off, cur, norm_x, norm_v, b6 * b6, par, member, sub);
+    return hipGetLastError();
+}
+
+}  // namespace fof

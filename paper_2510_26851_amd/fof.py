@@ -143,6 +143,31 @@ class Plan:
                                                   _ptr(grad_pos), _stream(stream)))
         return grad_pos
 
+    def subhalo(self, pos, vel, group_id, G, sizes, norm_x, norm_v, b6, sub=None,
+                stream=None):
+        """Six-dimensional sub-halo labels (device int32 [n]) inside the G host groups that
+        group_id / sizes describe (as groups() returns them): the smallest original index of
+        each member's phase-space component, -1 outside the hosts.  norm_x, norm_v: one
+        factor per host dividing the squared position and velocity separations."""
+        lib = _lib.load()
+        G = int(G)
+        if sub is None:
+            sub = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        nbytes = int(lib.fof_subhalo_scratch_bytes(self.n, G))
+        scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-scratch.data_ptr()) % 256
+        nx = torch.as_tensor(norm_x, dtype=torch.float64, device=self.device).reshape(-1)
+        nv = torch.as_tensor(norm_v, dtype=torch.float64, device=self.device).reshape(-1)
+        if G > 0 and (nx.numel() < G or nv.numel() < G):
+            raise ValueError("norm_x and norm_v need one factor per host")
+        check("fof_subhalo",
+              lib.fof_subhalo(self._gref, _ptr(self.ws), _ptr(pos), _ptr(vel), _ptr(group_id),
+                              G, _ptr(sizes), _ptr(nx), _ptr(nv), float(b6),
+                              ctypes.c_void_p(scratch.data_ptr() + off), nbytes, _ptr(sub),
+                              _stream(stream)))
+        self._keep = (scratch, nx, nv)   # alive until the next call on this plan
+        return sub
+
     def status(self) -> int:
         p = ctypes.c_void_p()
         check("fof_status", _lib.load().fof_status(self._gref, _ptr(self.ws), ctypes.byref(p)))

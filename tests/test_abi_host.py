@@ -263,6 +263,27 @@ def test_entry_points_reject_bad_arguments_before_launch():
                           None, 0, None, None, None) == _lib.FOF_EINVAL          # bad mode
     assert L.fof_backward(gp, fake_ws, _lib.FOF_SCORE, None, 0, None, *nul, None, None, None,
                           None, fake_ws, 2, fake_ws, None, None) == _lib.FOF_EINVAL  # no sample
+    need = L.fof_subhalo_scratch_bytes(100, 3)
+    assert need >= 12 * 100 + 4 * 2 * 3
+    sub_args = [fake_ws, fake_ws, fake_ws, 3, fake_ws, fake_ws, fake_ws, 1.0, fake_ws, need,
+                fake_ws, None]
+
+    def subhalo(**kw):
+        a = list(sub_args)
+        names = ["pos", "vel", "gid", "G", "sizes", "nx", "nv", "b6", "scratch", "nbytes", "sub",
+                 "stream"]
+        for k, v in kw.items():
+            a[names.index(k)] = v
+        return L.fof_subhalo(gp, fake_ws, *a)
+
+    assert subhalo(b6=0.0) == _lib.FOF_EINVAL                                    # b6 <= 0
+    assert subhalo(b6=float("nan")) == _lib.FOF_EINVAL                           # b6 not finite
+    assert subhalo(G=-1) == _lib.FOF_EINVAL                                      # G < 0
+    assert subhalo(G=101) == _lib.FOF_EINVAL                                     # G > n
+    assert subhalo(sub=None) == _lib.FOF_EINVAL                                  # sub NULL
+    assert subhalo(vel=None) == _lib.FOF_EINVAL                                  # vel NULL
+    assert subhalo(nbytes=need - 1) == _lib.FOF_EINVAL                           # scratch small
+    assert subhalo(scratch=misaligned) == _lib.FOF_EINVAL                        # alignment
     p = ctypes.c_void_p()
     assert L.fof_status(gp, misaligned, ctypes.byref(p)) == _lib.FOF_EINVAL
     assert L.fof_status(gp, fake_ws, ctypes.byref(p)) == 0

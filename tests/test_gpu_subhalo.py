@@ -1,0 +1,75 @@
+"""Six-dimensional sub-halo pass (paper Sec. 2, sub-halo finding) on the GPU against the
+oracle: hosts from each side's own three-dimensional pass, then every sub-halo label compared
+exactly (the phase-space predicate is evaluated in FP64 in the same order on both sides)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def run(pos, vel, L, b, min_size, nx, nv, b6):
+    import torch
+    from paper_2510_26851_amd import Plan, trim
+
+    dev = torch.device("cuda:0")
+    plan = Plan([pos.shape[0]], [(L, b)], device=dev)
+    tp = torch.from_numpy(pos).to(dev)
+    tv = torch.from_numpy(vel).to(dev)
+    plan.build_grid(tp)
+    plan.link()
+    res = trim(plan.groups(min_size))
+    G = int(res["n_groups"])
+    fx = nx(G) if callable(nx) else nx
+    fv = nv(G) if callable(nv) else nv
+    sub = plan.subhalo(tp, tv, res["group_id"], G, res["sizes"], fx, fv, b6)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    return res["group_id"].cpu().numpy(), G, sub.cpu().numpy()
+
+
+@pytest.mark.parametrize("seed,hosts,members", [(11, 6, (30, 400)), (12, 3, (600, 1100))])
+def test_subhalo_matches_oracle(seed, hosts, members):
+    L, b = 24.0, 0.2
+    pos, vel = W.phase_space_hosts(hosts, L, seed, members=members, n_background=6000)
+    say(f"sub-halo seed={seed} n={pos.shape[0]}")
+    rng = np.random.default_rng(seed)
+    fx = rng.uniform(0.02, 0.06, 4096)
+    fv = rng.uniform(0.5, 2.0, 4096)
+    gid, G, sub = run(pos, vel, L, b, 20, lambda G: fx[:G], lambda G: fv[:G], 1.0)
+    root, _ = oracle.fof(pos, L, b)
+    ref = oracle.groups(pos, root, L, 20)
+    assert G == ref["n_groups"] >= hosts
+    np.testing.assert_array_equal(gid, ref["group_id"])
+    want = oracle.subhalos(pos, vel, ref["group_id"], fx[:G], fv[:G], 1.0, L)
+    np.testing.assert_array_equal(sub, want)
+    inh = gid >= 0
+    assert np.unique(sub[inh]).size > G          # velocities split hosts
+
+
+def test_subhalo_without_velocity_weight_is_the_host():
+    L, b = 24.0, 0.2
+    pos, vel = W.phase_space_hosts(4, L, 13, n_background=3000)
+    gid, G, sub = run(pos, vel, L, b, 20, lambda G: np.ones(G), lambda G: np.full(G, np.inf), b)
+    root, _ = oracle.fof(pos, L, b)
+    inh = gid >= 0
+    np.testing.assert_array_equal(sub[inh], root[inh])
+    assert np.all(sub[~inh] == -1)
+
+
+def test_subhalo_with_no_hosts():
+    L, b = 24.0, 0.2
+    pos = W.uniform_box(2000, L, 14)
+    vel = np.zeros_like(pos)
+    gid, G, sub = run(pos, vel, L, b, 20, np.ones(1), np.ones(1), 1.0)
+    assert G == 0 and np.all(sub == -1)
