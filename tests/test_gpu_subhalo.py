@@ -69,7 +69,7 @@ def test_subhalo_without_velocity_weight_is_the_host():
 
 def test_subhalo_with_no_hosts():
     L, b = 24.0, 0.2
-    pos = W.uniform_box(2000, L, 14)
+    pos = W.uniform_box(2000, (L, L, L), 14)
     vel = np.zeros_like(pos)
     gid, G, sub = run(pos, vel, L, b, 20, np.ones(1), np.ones(1), 1.0)
     assert G == 0 and np.all(sub == -1)
