@@ -2,9 +2,10 @@
 // pass inside each host halo in phase space, two members linking when
 //   d^2 = |mi(x_i - x_j)|^2 / norm_x[g] + |v_i - v_j|^2 / norm_v[g] < b6^2.
 // Hosts are small next to the box (tens to thousands of members), so every pair of a host is
-// tested: one block per host, the host's members staged 256 at a time through LDS (positions
-// and velocities) against each thread's own member held in registers, hooks into the packed
-// lock-free union-find over the host's member slots.  The label is the smallest original
+// tested, one block per host.  A host of up to kSubLds members is held whole in LDS with its
+// union-find; a larger one streams its members 256 at a time through LDS (positions and
+// velocities) against each thread's own member held in registers, with hooks into the packed
+// lock-free union-find over the host's member slots in HBM.  The label is the smallest original
 // index of the phase-space component (the union-find's root key).
 #include <algorithm>
 
@@ -15,6 +16,7 @@ namespace fof {
 namespace {
 
 constexpr int kSubBlock = 256;
+constexpr int kSubLds = 1024;  // hosts up to this size keep members and union-find in LDS
 
 // Every slot starts as a root of its own holding a valid particle index, so that a slot no
 // particle fills (sizes inconsistent with group_id) is still safe to read.
@@ -68,6 +70,69 @@ __device__ __forceinline__ bool phase_friends(const BoxDesc &B, const float (&xi
     return sx / inx + sv / inv < bb;
 }
 
+// The same decision without the divisions for all but near-ties: with rx = 1/norm_x and
+// rv = 1/norm_v rounded, sx*rx + sv*rv is within a few units in the last place of the exact
+// expression's rounded value (every term is non-negative), far inside the 1e-12 margin; a
+// NaN (0 * inf) fails both tests and falls through to the exact form.
+__device__ __forceinline__ bool phase_friends_fast(const BoxDesc &B, const float (&xi)[6],
+                                                   const float (&xj)[6], double inx,
+                                                   double inv, double rx, double rv, double bb,
+                                                   double lo, double hi)
+{
+#pragma clang fp contract(off)
+    double d[6];
+    for (int a = 0; a < 3; ++a)
+        d[a] = min_image((double)xi[a] - (double)xj[a], B.L[a], B.halfL[a]);
+    for (int a = 3; a < 6; ++a)
+        d[a] = (double)xi[a] - (double)xj[a];
+    const double sx = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    const double sv = (d[3] * d[3] + d[4] * d[4]) + d[5] * d[5];
+    const double approx = sx * rx + sv * rv;
+    if (approx > hi)
+        return false;
+    if (approx < lo)
+        return true;
+    return sx / inx + sv / inv < bb;
+}
+
+// Union-find over local member slots in LDS: larger root hooked under the smaller, path
+// halving rewrites only non-root entries.
+__device__ __forceinline__ int lds_ld(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int lds_find(int *p, int x)
+{
+    int px = lds_ld(p + x);
+    while (px != x) {
+        const int py = lds_ld(p + px);
+        if (py != px)
+            __hip_atomic_store(p + x, py, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = px;
+        px = py;
+    }
+    return x;
+}
+
+__device__ __forceinline__ void lds_union(int *p, int a, int b)
+{
+    a = lds_find(p, a);
+    b = lds_find(p, b);
+    while (a != b) {
+        if (a > b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicCAS(p + b, b, a);
+        if (old == b)
+            return;
+        b = lds_find(p, b);
+        a = lds_find(p, a);
+    }
+}
+
 __device__ __forceinline__ void load_member(const float *__restrict__ pos,
                                             const float *__restrict__ vel, int64_t o, float (&p)[6])
 {
@@ -84,7 +149,9 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
     const double *__restrict__ norm_x, const double *__restrict__ norm_v, double bb,
     uint64_t *__restrict__ par, const int32_t *__restrict__ member, int32_t *__restrict__ sub)
 {
-    __shared__ float tile[6][kSubBlock];
+    __shared__ float hx[6][kSubLds];  // the whole host, or one tile of 256 on the HBM path
+    __shared__ int lpar[kSubLds];
+    __shared__ int lmin[kSubLds];
     const int32_t g = blockIdx.x;
     const int64_t base = off[g];
     int64_t m = min(cur[g], sizes[g]);
@@ -98,6 +165,57 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
     const BoxDesc &B = desc[find_box(desc, nbox, member[base])];
     const double inx = norm_x[g], inv = norm_v[g];
     const bool metric_ok = inx > 0.0 && inv > 0.0;  // otherwise the host stays singletons
+    if (m <= kSubLds) {  // block-uniform
+        for (int k = threadIdx.x; k < m; k += kSubBlock) {
+            float q[6];
+            load_member(pos, vel, member[base + k], q);
+            for (int a = 0; a < 6; ++a)
+                hx[a][k] = q[a];
+            lpar[k] = k;
+            lmin[k] = INT32_MAX;
+        }
+        __syncthreads();
+        if (metric_ok) {
+            const double rx = 1.0 / inx, rv = 1.0 / inv;
+            const double lo = bb * (1.0 - 1e-12), hi = bb * (1.0 + 1e-12);
+            const int mi = (int)m;
+            for (int i0 = 0; i0 < mi; i0 += kSubBlock) {
+                const int i = i0 + (int)threadIdx.x;
+                const int wave_lo = i0 + (int)(threadIdx.x & ~(kWave - 1));
+                float mine[6];
+                for (int a = 0; a < 6; ++a)
+                    mine[a] = i < mi ? hx[a][i] : 0.f;
+                int ri = i < mi ? i : 0;  // a root i had (it may have been hooked since)
+                // all lanes of a wave read the same j (an LDS broadcast); j > i is masked.
+                // Most friend pairs of a clump are already joined: j's root is looked up once
+                // per wave, and a lane hooks only when its own root differs from it.
+                for (int j = wave_lo + 1; j < mi; ++j) {
+                    const float other[6] = {hx[0][j], hx[1][j], hx[2][j],
+                                            hx[3][j], hx[4][j], hx[5][j]};
+                    const bool f = j > i && i < mi &&
+                                   phase_friends_fast(B, mine, other, inx, inv, rx, rv, bb, lo, hi);
+                    if (ballot(f)) {
+                        const int rj = lds_find(lpar, j);
+                        if (f && ri != rj) {
+                            ri = lds_find(lpar, i);
+                            if (ri != rj) {
+                                lds_union(lpar, i, j);
+                                ri = lds_find(lpar, i);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < m; k += kSubBlock)
+            atomicMin(lmin + lds_find(lpar, k), member[base + k]);
+        __syncthreads();
+        for (int k = threadIdx.x; k < m; k += kSubBlock)
+            sub[member[base + k]] = lmin[lds_find(lpar, k)];
+        return;
+    }
+    float (*tile)[kSubLds] = hx;
     for (int64_t i0 = 0; i0 < m; i0 += kSubBlock) {
         const int64_t i = i0 + threadIdx.x;
         float mine[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
