@@ -79,3 +79,43 @@ def test_subhalo_with_no_hosts():
     vel = np.zeros_like(pos)
     gid, G, sub = run(pos, vel, L, b, 20, np.ones(1), np.ones(1), 1.0)
     assert G == 0 and np.all(sub == -1)
+
+
+def test_subhalo_in_a_batch_of_two_boxes():
+    """Two boxes of different sizes in one plan: each host uses its own box's minimum image,
+    and hosts of different boxes never link."""
+    import torch
+    from paper_2510_26851_amd import Plan, trim
+
+    b = 0.2
+    boxes = [(24.0, W.phase_space_hosts(4, 24.0, 21, n_background=3000)),
+             (16.0, W.phase_space_hosts(3, 16.0, 22, n_background=2000))]
+    n1 = boxes[0][1][0].shape[0]
+    pos = np.concatenate([p for _, (p, _) in boxes])
+    vel = np.concatenate([v for _, (_, v) in boxes])
+    dev = torch.device("cuda:0")
+    plan = Plan([p.shape[0] for _, (p, _) in boxes], [(L, b) for L, _ in boxes], device=dev)
+    tp, tv = torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev)
+    plan.build_grid(tp)
+    plan.link()
+    res = trim(plan.groups(20))
+    G = int(res["n_groups"])
+    rng = np.random.default_rng(23)
+    fx, fv = rng.uniform(0.02, 0.06, G), rng.uniform(0.5, 2.0, G)
+    sub = plan.subhalo(tp, tv, res["group_id"], G, res["sizes"], fx, fv, 1.0)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    sub, gid = sub.cpu().numpy(), res["group_id"].cpu().numpy()
+    refs, base, g0 = [], 0, 0
+    for L, (p, v) in boxes:
+        root, _ = oracle.fof(p, L, b)
+        ref = oracle.groups(p, root, L, 20)
+        rg = ref["group_id"].astype(np.int64)
+        np.testing.assert_array_equal(gid[base:base + p.shape[0]], np.where(rg >= 0, rg + g0, -1))
+        k = ref["n_groups"]
+        want = oracle.subhalos(p, v, ref["group_id"], fx[g0:g0 + k], fv[g0:g0 + k], 1.0, L)
+        np.testing.assert_array_equal(sub[base:base + p.shape[0]],
+                                      np.where(want >= 0, want + base, -1))
+        base += p.shape[0]
+        g0 += k
+    assert g0 == G and base == pos.shape[0] and n1 < base
