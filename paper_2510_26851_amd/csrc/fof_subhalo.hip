@@ -16,7 +16,8 @@ namespace fof {
 namespace {
 
 constexpr int kSubBlock = 256;
-constexpr int kSubLds = 1024;  // hosts up to this size keep members and union-find in LDS
+constexpr int kSubLds = 2048;  // hosts up to this size keep members and union-find in LDS
+constexpr int kSubJ = 4;       // partners tested per step of the LDS path
 
 // Every slot starts as a root of its own holding a valid particle index, so that a slot no
 // particle fills (sizes inconsistent with group_id) is still safe to read.
@@ -189,14 +190,25 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
                 // all lanes of a wave read the same j (an LDS broadcast); j > i is masked.
                 // Most friend pairs of a clump are already joined: j's root is looked up once
                 // per wave, and a lane hooks only when its own root differs from it.
-                for (int j = wave_lo + 1; j < mi; ++j) {
-                    const float other[6] = {hx[0][j], hx[1][j], hx[2][j],
-                                            hx[3][j], hx[4][j], hx[5][j]};
-                    const bool f = j > i && i < mi &&
-                                   phase_friends_fast(B, mine, other, inx, inv, rx, rv, bb, lo, hi);
-                    if (ballot(f)) {
+                // kSubJ values of j per step: their reads and tests are issued before any
+                // hook, so the LDS latency of one overlaps the arithmetic of the others.
+                for (int j0 = wave_lo + 1; j0 < mi; j0 += kSubJ) {
+                    bool f[kSubJ];
+#pragma unroll
+                    for (int u = 0; u < kSubJ; ++u) {
+                        const int j = min(j0 + u, mi - 1);
+                        const float other[6] = {hx[0][j], hx[1][j], hx[2][j],
+                                                hx[3][j], hx[4][j], hx[5][j]};
+                        f[u] = j0 + u < mi && j0 + u > i && i < mi &&
+                               phase_friends_fast(B, mine, other, inx, inv, rx, rv, bb, lo, hi);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kSubJ; ++u) {
+                        if (!ballot(f[u]))
+                            continue;
+                        const int j = j0 + u;
                         const int rj = lds_find(lpar, j);
-                        if (f && ri != rj) {
+                        if (f[u] && ri != rj) {
                             ri = lds_find(lpar, i);
                             if (ri != rj) {
                                 lds_union(lpar, i, j);

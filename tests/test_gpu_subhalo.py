@@ -41,8 +41,8 @@ def run(pos, vel, L, b, min_size, nx, nv, b6):
 @pytest.mark.parametrize("seed,hosts,members,in_lds",
                          [(11, 6, (30, 400), True), (12, 3, (600, 1100), False)])
 def test_subhalo_matches_oracle(seed, hosts, members, in_lds):
-    """Seed 11 has hosts of at most 1024 members (whole host and union-find in LDS) and
-    larger ones; seed 12 only hosts above 1024 (tiles through LDS, union-find in HBM)."""
+    """Seed 11 has hosts of at most 2048 members (whole host and union-find in LDS); seed 12
+    only hosts above 2048 (tiles through LDS, union-find in HBM)."""
     L, b = 24.0, 0.2
     pos, vel = W.phase_space_hosts(hosts, L, seed, members=members, n_background=6000)
     say(f"sub-halo seed={seed} n={pos.shape[0]}")
@@ -56,7 +56,7 @@ def test_subhalo_matches_oracle(seed, hosts, members, in_lds):
     np.testing.assert_array_equal(gid, ref["group_id"])
     sz = ref["sizes"][:G]
     say(f"host sizes {sz.min()}..{sz.max()}")
-    assert (sz.min() <= 1024) == in_lds and sz.max() > 1024
+    assert (sz.max() <= 2048) if in_lds else (sz.min() > 2048)
     want = oracle.subhalos(pos, vel, ref["group_id"], fx[:G], fv[:G], 1.0, L)
     np.testing.assert_array_equal(sub, want)
     inh = gid >= 0
