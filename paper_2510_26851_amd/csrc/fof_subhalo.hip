@@ -3,7 +3,7 @@
 //   d^2 = |mi(x_i - x_j)|^2 / norm_x[g] + |v_i - v_j|^2 / norm_v[g] < b6^2.
 // Hosts are small next to the box (tens to thousands of members), so every pair of a host is
 // tested, one block per host.  A host of up to kSubLds members is held whole in LDS with its
-// union-find; a larger one streams its members 256 at a time through LDS (positions and
+// union-find; a larger one streams its members a block at a time through LDS (positions and
 // velocities) against each thread's own member held in registers, with hooks into the packed
 // lock-free union-find over the host's member slots in HBM.  The label is the smallest original
 // index of the phase-space component (the union-find's root key).
@@ -15,7 +15,7 @@ namespace fof {
 
 namespace {
 
-constexpr int kSubBlock = 256;
+constexpr int kSubBlock = 1024;
 constexpr int kSubLds = 2048;  // hosts up to this size keep members and union-find in LDS
 constexpr int kSubJ = 4;       // partners tested per step of the LDS path
 
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
     const double *__restrict__ norm_x, const double *__restrict__ norm_v, double bb,
     uint64_t *__restrict__ par, const int32_t *__restrict__ member, int32_t *__restrict__ sub)
 {
-    __shared__ float hx[6][kSubLds];  // the whole host, or one tile of 256 on the HBM path
+    __shared__ float hx[6][kSubLds];  // the whole host, or one tile per block on the HBM path
     __shared__ int lpar[kSubLds];
     __shared__ int lmin[kSubLds];
     const int32_t g = blockIdx.x;
