@@ -119,3 +119,41 @@ def test_subhalo_in_a_batch_of_two_boxes():
         base += p.shape[0]
         g0 += k
     assert g0 == G and base == pos.shape[0] and n1 < base
+
+
+def test_subhalo_sizes_that_disagree_with_the_ids():
+    """Host sizes from another catalogue: a host declared larger than it is keeps every
+    label exact; one declared smaller drops its extra members (label -1) and raises
+    FOF_STATUS_RANGE, and the other hosts are unaffected."""
+    import torch
+    from paper_2510_26851_amd import Plan, trim, _lib
+
+    L, b = 24.0, 0.2
+    pos, vel = W.phase_space_hosts(4, L, 31, n_background=3000)
+    dev = torch.device("cuda:0")
+    plan = Plan([pos.shape[0]], [(L, b)], device=dev)
+    tp, tv = torch.from_numpy(pos).to(dev), torch.from_numpy(vel).to(dev)
+    plan.build_grid(tp)
+    plan.link()
+    res = trim(plan.groups(20))
+    G = int(res["n_groups"])
+    gid = res["group_id"].cpu().numpy()
+    root, _ = oracle.fof(pos, L, b)
+    ref = oracle.groups(pos, root, L, 20)
+    np.testing.assert_array_equal(gid, ref["group_id"])
+    nx, nv = np.full(G, 0.04), np.ones(G)
+    want = oracle.subhalos(pos, vel, ref["group_id"], nx, nv, 1.0, L)
+    big = res["sizes"].clone()
+    big[0] += 5
+    sub = plan.subhalo(tp, tv, res["group_id"], G, big, nx, nv, 1.0).cpu().numpy()
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    np.testing.assert_array_equal(sub, want)
+    small = res["sizes"].clone()
+    small[0] -= 3
+    sub = plan.subhalo(tp, tv, res["group_id"], G, small, nx, nv, 1.0).cpu().numpy()
+    torch.cuda.synchronize()
+    assert plan.status() & _lib.FOF_STATUS_RANGE
+    h0 = gid == 0
+    assert np.sum(sub[h0] == -1) == 3
+    np.testing.assert_array_equal(sub[~h0], want[~h0])
