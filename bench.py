@@ -113,35 +113,70 @@ METRIC = "Mparticles/s end-to-end FoF at 512\u00b3 + % HBM peak; batched REINFOR
 
 
 def reinforce_rate(torch, dev, reps):
-    """Stochastic linking of the 128^3 velocity box: K = 64 sampled graphs in one launch plus
-    the score-function gradient.  The per-sample losses (the caller's function of the labels)
-    are computed once, outside the timed region."""
+    """Stochastic linking of the 128^3 velocity box, timed per batch of K = 64 samples: the
+    candidate edges, the K sampled graphs and their components (fof_link with the sample),
+    every sample's halos (fof_groups with the sample: sizes and centres), the loss of each
+    sample (sum of squared halo sizes, from the tables) and the score-function gradient
+    (fof_backward FOF_SCORE).  Beside it the same 64 graphs drawn by 64 sequential calls of
+    one sample each (s_first = 0..63: edges rebuilt every call), their halos and losses, then
+    one gradient over the 64 losses; both give the same losses exactly."""
     import workloads as W
     from paper_2510_26851_amd.reinforce import Sampler, sum_sq_sizes
 
     box = W.config3()
+    K = W.CONFIG3_K
     tau = W.CONFIG3_TAU_FRAC * box.b
     pos = torch.from_numpy(box.pos).to(dev)
-    smp = Sampler(pos, box.L, box.b, tau, W.CONFIG3_K, W.REINFORCE_SEED)
-    root = smp.sample()              # sizes the edge buffers
-    smp.auto_grow = False
-    losses = sum_sq_sizes(root, 2)
-    smp.grad(losses)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        smp.sample(root)
-        smp.grad(losses)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    if smp.plan.status() != 0:
-        raise SystemExit(f"device status {smp.plan.status()} in the REINFORCE leg")
-    return {"workload": box.name, "n": box.n, "K": W.CONFIG3_K, "tau": tau,
-            "edges": int(smp.n_edges.item()), "ms_per_batch": round(ms, 4),
-            "samples_per_s": round(W.CONFIG3_K / (ms / 1e3), 1),
-            "timed": "fof_link(sample) + fof_backward(FOF_SCORE) per batch of K"}
+    smp = Sampler(pos, box.L, box.b, tau, K, W.REINFORCE_SEED)
+    smp.sample()                     # fits the edge capacity (one read-back)
+    halos = smp.groups(2)
+    gp = torch.empty((box.n, 3), dtype=torch.float32, device=dev)
+
+    def batched():
+        smp.sample()
+        h = smp.groups(2, out=halos)
+        smp.grad(sum_sq_sizes(h), out=gp)
+
+    one = Sampler(pos, box.L, box.b, tau, 1, W.REINFORCE_SEED, edge_cap=smp.S.edge_cap)
+    seq_losses = torch.empty(K, dtype=torch.float64, device=dev)
+    out1 = {}
+
+    def sequential():
+        for k in range(K):
+            one.S.s_first = k
+            one.sample()
+            h = one.groups(2, cap=halos["cap"], out=out1)
+            out1.update(h)
+            seq_losses[k:k + 1] = sum_sq_sizes(h)
+        smp.grad(seq_losses, out=gp)
+
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, fn, r in (("batched", batched, reps), ("sequential", sequential, max(2, reps // 4))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(r):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / r
+        res[name] = {"ms_per_batch": round(ms, 4), "samples_per_s": round(K / (ms / 1e3), 1),
+                     "reps": r}
+    if smp.plan.status() != 0 or one.plan.status() != 0:
+        raise SystemExit("device status set in the REINFORCE leg")
+    smp.sample()
+    same = bool(torch.equal(sum_sq_sizes(smp.groups(2, out=halos)), seq_losses))
+    if not same:
+        raise SystemExit("batched and sequential REINFORCE losses differ")
+    return {"workload": box.name, "n": box.n, "K": K, "tau": tau,
+            "edges": int(smp.n_edges.item()), "ms_per_batch": res["batched"]["ms_per_batch"],
+            "samples_per_s": res["batched"]["samples_per_s"],
+            "sequential": res["sequential"], "same_losses": same,
+            "timed": "batched: fof_link(sample K=64) + fof_groups(sample) + loss from the halo "
+                     "tables + fof_backward(FOF_SCORE); sequential: 64 x [fof_link(sample K=1, "
+                     "s_first=k) + fof_groups(sample) + loss] + one fof_backward(FOF_SCORE)"}
 
 
 def decorated_rate(torch, plan, pos, out, cap, ng, stream, workload, reps=10):
@@ -233,6 +268,9 @@ def main():
     ap.add_argument("--no-reinforce", action="store_true")
     ap.add_argument("--reinforce-reps", type=int, default=20)
     ap.add_argument("--no-subhalo", action="store_true")
+    ap.add_argument("--no-decorated", action="store_true")
+    ap.add_argument("--cache-dir", default="",
+                    help="store / reuse the drawn positions here (.npy; none by default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -247,7 +285,7 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    box = W.make(args.config, progress=log)
+    box = W.make(args.config, progress=log, cache_dir=args.cache_dir or None)
     log(f"generated {box.name}: n={box.n} L={box.L} b={box.b} in {time.perf_counter() - t0:.1f}s")
 
     pos = torch.from_numpy(box.pos).to(dev)
@@ -339,7 +377,8 @@ def main():
         "hbm_peak_frac_link": round(achieved / HBM_PEAK_GBS, 4),
         "copy_gbs": round(copy_gbs, 1),
     }
-    line["decorated"] = decorated_rate(torch, plan, pos, out, cap, ng, stream, box.name)
+    if not args.no_decorated:
+        line["decorated"] = decorated_rate(torch, plan, pos, out, cap, ng, stream, box.name)
     if not args.no_reinforce:
         log("timing batched REINFORCE ...")
         line["reinforce"] = reinforce_rate(torch, dev, args.reinforce_reps)

@@ -15,7 +15,10 @@
  *    stream that fof_link forks from and joins back to `stream`.
  *  - Return value: FOF_OK (0) or a negative FOF_E* code.  Argument errors are detected on the
  *    host before anything is enqueued.  Data errors that only the device can see
- *    (coordinates outside [0, L) or NaN) set bits of the device status word (fof_status).
+ *    (coordinates outside [0, L) or NaN, more groups than the caller's table holds) set bits
+ *    of the device status word (fof_status).
+ *  - Every call that takes the workspace `ws` also takes its size `ws_bytes`: FOF_ENOMEM when
+ *    it is below grid->ws_bytes (nothing is enqueued).
  *  - Particle indices are int32: n <= 2^31 - 1 in total.
  *  - Several boxes can be processed in one call ("batch"): box k owns the particles
  *    [offset_k, offset_k + count_k) of the concatenated arrays, with offset_0 = 0 and
@@ -43,6 +46,8 @@ extern "C" {
 #define FOF_STATUS_RANGE 1u     /* some coordinate was NaN or outside [0, L)                  */
 #define FOF_STATUS_DENSE_CAP 2u /* dense-cell tables overflowed; those cells took the plain path */
 #define FOF_STATUS_EDGE_CAP 4u  /* more candidate edges than fof_sample.edge_cap              */
+#define FOF_STATUS_OVERFLOW 8u  /* fof_groups found more groups than `cap` (in some sample); the
+                                   group counts hold the true totals, the tables the first cap */
 
 /* fof_backward modes */
 #define FOF_FROZEN 0 /* frozen assignment (paper Sec. 3.1)                                     */
@@ -84,8 +89,9 @@ typedef struct fof_tune {
  *                            form, evaluated in this order in FP64),
  * when u(seed, s, i, j) < p_e, where u is the first word of
  * Philox4x64-10 (Salmon et al. 2011) at counter (i | j << 32, s, 0, 0) and key (seed, 0),
- * shifted right by 11 and scaled by 2^-53, on original indices i < j.  All pointers are
- * device pointers owned by the caller. */
+ * shifted right by 11 and scaled by 2^-53, on original indices i < j.  A call covers the
+ * samples s = s_first .. s_first + K - 1 (local sample k = s - s_first), so a batch of K
+ * equals K calls of one sample each.  All pointers are device pointers owned by the caller. */
 typedef struct fof_sample {
     double b;           /* linking length of the probability                                   */
     double tau;         /* temperature, > 0                                                    */
@@ -99,19 +105,23 @@ typedef struct fof_sample {
     size_t scratch_bytes;
     int32_t form;       /* FOF_PROB_DISTANCE (0) or FOF_PROB_QUADRATIC (1)                     */
     double alpha;       /* relaxation of FOF_PROB_QUADRATIC, > 0 (tau is then unused)          */
+    int32_t s_first;    /* index of the first sample, >= 0, s_first + K <= 2^31 - 1            */
 } fof_sample;
 
 #define FOF_PROB_DISTANCE 0
 #define FOF_PROB_QUADRATIC 1
 
 /* Scratch of the sampled labelling: a vertex map over all particles, the sorted ends of
- * every edge, and one union-find per sample over the particles that touch a candidate edge
- * (at most min(n, 2 edge_cap) of them). */
+ * every edge, and per sample a union-find, member counts and group numbering over the
+ * particles that touch a candidate edge (at most vcap = min(n, 2 edge_cap) of them, so the
+ * scratch and the per-sample passes scale with the edge capacity the caller chooses). */
 #define FOF_SAMPLE_VCAP(n, edge_cap)                                                          \
     (2 * (size_t)(edge_cap) < (size_t)(n) ? 2 * (size_t)(edge_cap) : (size_t)(n))
 #define FOF_SAMPLE_SCRATCH_BYTES(n, K, edge_cap)                                              \
-    (4096 + 8 * ((size_t)(n) + 1) + 4 * ((size_t)(n) / 2048 + 2) + 8 * (size_t)(edge_cap) +   \
-     8 * (size_t)(K) + 4 * ((size_t)(K) + 1) * FOF_SAMPLE_VCAP(n, edge_cap))
+    (8192 + 8 * ((size_t)(n) + 1) + 4 * ((size_t)(n) / 2048 + 2) + 8 * (size_t)(edge_cap) +   \
+     8 * (size_t)(K) + 8 * FOF_SAMPLE_VCAP(n, edge_cap) +                                     \
+     12 * (size_t)(K) * FOF_SAMPLE_VCAP(n, edge_cap) +                                        \
+     4 * ((size_t)(K) * FOF_SAMPLE_VCAP(n, edge_cap) / 2048 + 3))
 
 /* Host-side plan of one batch: filled by fof_workspace_bytes, then passed unchanged to the
  * other calls.  Plain data; the byte offsets locate the regions of the caller's workspace. */
@@ -148,7 +158,7 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count /*host*/, const fof_b
  * Builds, inside ws (dev, grid->ws_bytes bytes, 256-byte aligned), the per-cell offsets and
  * the cell-sorted particle copy used by fof_link and fof_groups.  Clears the status word. */
 int fof_build_grid(const fof_grid *grid, const float *pos /*dev*/, void *ws /*dev*/,
-                   void *stream);
+                   size_t ws_bytes, void *stream);
 
 /* Friends-of-Friends labels (paper Sec. 2 steps (iii)-(v); Alg. 2 candidate search, minimum
  * image filter and label propagation, run here to convergence as a union-find).
@@ -156,11 +166,13 @@ int fof_build_grid(const fof_grid *grid, const float *pos /*dev*/, void *ws /*de
  * connected component of i (so root[root[i]] == root[i]).  The link predicate is exact:
  * per axis d = (double)x_i - (double)x_j wrapped once by +-L when |d| > L/2, then
  * ((dx*dx + dy*dy) + dz*dz) < b*b in IEEE double without fused multiply-add.
- * With sample != NULL (single-box plans only): writes the candidate edges into the sample
- * buffers and, when root is not NULL, root (dev, int32 [K][n]) receives the smallest-index
- * labels of each of the K sampled graphs. */
-int fof_link(const fof_grid *grid, void *ws /*dev*/, const fof_sample *sample /*host or NULL*/,
-             int32_t *root /*dev*/, void *stream);
+ * With sample != NULL (single-box plans only; Sec. 3.2 stochastic linking): writes the
+ * candidate edges into the sample buffers, links the K sampled graphs in the sample's
+ * scratch (which fof_groups and fof_backward(FOF_SCORE) then read), and, only when root is
+ * not NULL, writes root (dev, int32 [K][n]) the smallest-index labels of every sampled graph
+ * (K * n words: leave it NULL when the per-sample group tables suffice). */
+int fof_link(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes,
+             const fof_sample *sample /*host or NULL*/, int32_t *root /*dev*/, void *stream);
 
 /* Group catalogue (paper Sec. 2 step (vi); Alg. 2 compaction; Sec. 3.1 halo position).
  * Must follow fof_link without a sample (the labelling pass) on the same workspace: it reads
@@ -175,9 +187,21 @@ int fof_link(const fof_grid *grid, void *ws /*dev*/, const fof_sample *sample /*
  *   vmean[g][3], sigv[g]       (dev double, only when vel != NULL) mean velocity and the
  *                              1-D dispersion sqrt(sum_i sum_c (v_ic - vmean_c)^2 / (3 n))
  * vel (dev) is float32 [n][3] or NULL; vmean and sigv may be NULL when vel is NULL.
- * Returns FOF_OK even when G > cap: the device cannot report that without a sync, so the
- * caller compares *n_groups with cap (group ids >= cap then have no table entries). */
-int fof_groups(const fof_grid *grid, void *ws /*dev*/, int32_t min_size, const float *vel,
+ * When G > cap the call sets FOF_STATUS_OVERFLOW in the status word (the device alone knows
+ * G, and no call synchronises); *n_groups still holds G and group ids >= cap have no table
+ * entries.
+ *
+ * Sampled form, sample != NULL (Sec. 3.2: the loss of each sampled graph is a function of its
+ * halos): must follow fof_link with the same sample.  For each local sample k < K, the
+ * components of that sampled graph with at least min_size >= 2 members, numbered in
+ * ascending order of their label as above: n_groups (dev int32 [K]) gets G_k, and for
+ * g < min(G_k, cap), sizes[k * cap + g] and com[(k * cap + g) * 3 + c] as above (FP64,
+ * members unwrapped about the label particle).  Particles that touch no candidate edge are
+ * singletons in every sample, so groups are built over the touched particles only; no K * n
+ * array is written.  vel, vmean, sigv and group_id must be NULL.  G_k > cap sets
+ * FOF_STATUS_OVERFLOW. */
+int fof_groups(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes,
+               const fof_sample *sample /*host or NULL*/, int32_t min_size, const float *vel,
                int32_t cap, int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com,
                double *vmean, double *sigv, void *stream);
 
@@ -191,12 +215,13 @@ int fof_groups(const fof_grid *grid, void *ws /*dev*/, int32_t min_size, const f
  * the forward's outputs; G is the number of groups the tables hold (<= cap).
  * mode = FOF_SCORE (Sec. 3.2, REINFORCE): with the edges of the last fof_link(sample) and the
  * sampled graphs' losses loss[K] (dev double),
- *   grad_pos = (1/K) sum_s (loss_s - beta_s) sum_e (y_es - p_e) dz_e/dx,
- *   z_e as in fof_sample, dz_e/dx_i = -dz_e/dx_j = -(x_i - x_j)/(tau d_e) (FOF_PROB_DISTANCE)
- *   or -2 alpha (x_i - x_j)/b^2 (FOF_PROB_QUADRATIC), x_i - x_j the minimum image,
+ *   grad_pos = (1/K) sum_k (loss_k - beta_k) sum_e (y_e,s_first+k - p_e) dz_e/dx,
+ *   z_e as in fof_sample, dz_e/dx_i = -dz_e/dx_j = -(x_i - x_j)/(tau d_e) (FOF_PROB_DISTANCE;
+ *   0 for an edge with d_e = 0, where the direction is undefined) or -2 alpha (x_i - x_j)/b^2
+ *   (FOF_PROB_QUADRATIC), x_i - x_j the minimum image,
  * beta_s per `baseline` (FOF_BASELINE_*); the frozen-mode arguments are ignored and grad_vel
  * is not written.  grad_pos and grad_vel (dev float32 [n][3]) may be NULL to skip them. */
-int fof_backward(const fof_grid *grid, void *ws /*dev*/, int32_t mode,
+int fof_backward(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes, int32_t mode,
                  const int32_t *group_id /*dev*/, int32_t G, const int32_t *sizes /*dev*/,
                  const double *vmean /*dev*/, const double *sigv /*dev*/, const float *vel /*dev*/,
                  const double *g_mass, const double *g_com, const double *g_sigv,
@@ -209,7 +234,7 @@ int fof_backward(const fof_grid *grid, void *ws /*dev*/, int32_t mode,
  * image, FP64, the same 1-D reading as sigv; groups of one get 0.  Must follow fof_groups on
  * the same workspace with the same cap, and reads that call's n_groups, sizes and com (dev);
  * sigx (dev double [cap]) receives min(G, cap) values and zeros beyond. */
-int fof_group_dispersion(const fof_grid *grid, void *ws /*dev*/, int32_t cap,
+int fof_group_dispersion(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes, int32_t cap,
                          const int32_t *n_groups, const int32_t *sizes, const double *com,
                          double *sigx, void *stream);
 
@@ -219,7 +244,8 @@ int fof_group_dispersion(const fof_grid *grid, void *ws /*dev*/, int32_t cap,
  * (the terms through com cancel).  ADDS to grad_pos (dev float32 [n][3]), so it composes with
  * fof_backward(FOF_FROZEN).  pos (dev float32 [n][3]) is the forward's input; group_id,
  * sizes, com and sigx are the forward's outputs (dev); g_sigx (dev double [G]). */
-int fof_backward_dispersion(const fof_grid *grid, void *ws /*dev*/, const float *pos,
+int fof_backward_dispersion(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes,
+                            const float *pos,
                             const int32_t *group_id, int32_t G, const int32_t *sizes,
                             const double *com, const double *sigx, const double *g_sigx,
                             float *grad_pos, void *stream);
@@ -238,17 +264,20 @@ int fof_backward_dispersion(const fof_grid *grid, void *ws /*dev*/, const float 
  * (dev double [G]; a host whose factors are not both positive splits into singletons).  scratch: dev, 256-byte aligned, >= fof_subhalo_scratch_bytes(n, G) bytes,
  * owned by the caller, contents not preserved.  Every pair of a host is tested (cost grows
  * with the square of the host's size).  Sizes that disagree with group_id drop the extra
- * members and set FOF_STATUS_RANGE (cleared by fof_build_grid).  FOF_EINVAL for b6 not
+ * members and set FOF_STATUS_RANGE (cleared by fof_build_grid); a negative size counts as 0
+ * (all of that host's members are dropped), so the other hosts are unaffected.  FOF_EINVAL for b6 not
  * positive and finite, G < 0 or G > n, or missing buffers. */
 size_t fof_subhalo_scratch_bytes(int64_t n, int32_t G);
-int fof_subhalo(const fof_grid *grid, void *ws /*dev*/, const float *pos, const float *vel,
+int fof_subhalo(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes, const float *pos,
+                const float *vel,
                 const int32_t *group_id, int32_t G, const int32_t *sizes, const double *norm_x,
                 const double *norm_v, double b6, void *scratch, size_t scratch_bytes,
                 int32_t *sub, void *stream);
 
 /* Device address of the int32 status word inside ws (FOF_STATUS_* bits; 0 = clean).  It is
  * cleared by fof_build_grid; read it after synchronising the stream. */
-int fof_status(const fof_grid *grid, void *ws /*dev*/, int32_t **status /*host out: dev ptr*/);
+int fof_status(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes,
+               int32_t **status /*host out: dev ptr*/);
 
 /* Optional, once per device (the current one), before fof_link is called from a captured
  * or performance-critical context: creates a helper stream (default priority) and three

@@ -94,11 +94,17 @@ def edge_prob_quadratic(d2, b, alpha):
 
 
 def dz_factor(d, b, tau=None, alpha=None):
-    """c_e with dz_e/dx_j = c_e (x_i - x_j) = -dz_e/dx_i: 1/(tau d_e), or 2 alpha / b^2 for
-    the quadratic form."""
+    """c_e with dz_e/dx_j = c_e (x_i - x_j) = -dz_e/dx_i: 1/(tau d_e) (0 when d_e = 0), or
+    2 alpha / b^2 for the quadratic form."""
     d = np.asarray(d, np.float64)
     if alpha is None:
-        return 1.0 / (tau * d)
+        # The distance is not differentiable where two particles coincide (d = 0); there
+        # the direction (x_i - x_j)/d is undefined and the edge contributes no gradient
+        # (the symmetric subgradient).
+        out = np.zeros(d.shape)
+        nz = d > 0.0
+        out[nz] = 1.0 / (tau * d[nz])
+        return out
     return np.full(d.shape, 2.0 * float(alpha) / (float(b) * float(b)))
 
 

@@ -23,6 +23,7 @@ FOF_PROB_QUADRATIC = 1
 FOF_TUNE_NO_TILES = 1
 FOF_STATUS_DENSE_CAP = 2
 FOF_STATUS_EDGE_CAP = 4
+FOF_STATUS_OVERFLOW = 8
 FOF_FROZEN = 0
 FOF_SCORE = 1
 FOF_BASELINE_NONE = 0
@@ -33,8 +34,8 @@ FOF_BASELINE_LOO = 2
 def sample_scratch_bytes(n: int, K: int, edge_cap: int) -> int:
     """FOF_SAMPLE_SCRATCH_BYTES of include/fof.h."""
     vcap = min(2 * edge_cap, n)
-    return (4096 + 8 * (n + 1) + 4 * (n // 2048 + 2) + 8 * edge_cap + 8 * K +
-            4 * (K + 1) * vcap)
+    return (8192 + 8 * (n + 1) + 4 * (n // 2048 + 2) + 8 * edge_cap + 8 * K + 8 * vcap +
+            12 * K * vcap + 4 * (K * vcap // 2048 + 3))
 
 # Every symbol include/fof.h declares.
 EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",
@@ -57,7 +58,8 @@ class fof_sample(ctypes.Structure):
                 ("K", ctypes.c_int32), ("edge_cap", ctypes.c_int32), ("ei", ctypes.c_void_p),
                 ("ej", ctypes.c_void_p), ("d2", ctypes.c_void_p), ("n_edges", ctypes.c_void_p),
                 ("scratch", ctypes.c_void_p), ("scratch_bytes", ctypes.c_size_t),
-                ("form", ctypes.c_int32), ("alpha", ctypes.c_double)]
+                ("form", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("s_first", ctypes.c_int32)]
 
 
 class fof_grid(ctypes.Structure):
@@ -100,16 +102,16 @@ def load():
     L = ctypes.CDLL(LIB_PATH)
     P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     L.fof_workspace_bytes.argtypes = [i32, P, P, P, P, P, sz]
-    L.fof_build_grid.argtypes = [P, P, P, P]
-    L.fof_link.argtypes = [P, P, P, P, P]
-    L.fof_groups.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P, P]
-    L.fof_backward.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P, P, P, P, i32, P, P, P]
-    L.fof_group_dispersion.argtypes = [P, P, i32, P, P, P, P, P]
-    L.fof_backward_dispersion.argtypes = [P, P, P, P, i32, P, P, P, P, P, P]
+    L.fof_build_grid.argtypes = [P, P, P, sz, P]
+    L.fof_link.argtypes = [P, P, sz, P, P, P]
+    L.fof_groups.argtypes = [P, P, sz, P, i32, P, i32, P, P, P, P, P, P, P]
+    L.fof_backward.argtypes = [P, P, sz, i32, P, i32, P, P, P, P, P, P, P, P, P, i32, P, P, P]
+    L.fof_group_dispersion.argtypes = [P, P, sz, i32, P, P, P, P, P]
+    L.fof_backward_dispersion.argtypes = [P, P, sz, P, P, i32, P, P, P, P, P, P]
     L.fof_subhalo_scratch_bytes.argtypes = [i64, i32]
     L.fof_subhalo_scratch_bytes.restype = sz
-    L.fof_subhalo.argtypes = [P, P, P, P, P, i32, P, P, P, ctypes.c_double, P, sz, P, P]
-    L.fof_status.argtypes = [P, P, ctypes.POINTER(ctypes.c_void_p)]
+    L.fof_subhalo.argtypes = [P, P, sz, P, P, P, i32, P, P, P, ctypes.c_double, P, sz, P, P]
+    L.fof_status.argtypes = [P, P, sz, ctypes.POINTER(ctypes.c_void_p)]
     L.fof_strerror.argtypes = [ctypes.c_int]
     L.fof_strerror.restype = ctypes.c_char_p
     L.fof_last_device_error.argtypes = [ctypes.POINTER(ctypes.c_char_p)]

@@ -181,11 +181,15 @@ Layout layout(int32_t nbox, int64_t n, int64_t ncell, int64_t dense_cap, int32_t
     return L;
 }
 
-bool ws_ok(const fof_grid *g, const void *ws)
+// FOF_OK, FOF_EINVAL (no plan, no or misaligned workspace, a plan no fof_workspace_bytes
+// could have made) or FOF_ENOMEM (a workspace smaller than the plan needs).
+int ws_check(const fof_grid *g, const void *ws, size_t ws_bytes)
 {
-    return g && ws && ((uintptr_t)ws % kAlign) == 0 && g->nbox >= 1 && g->n >= 0 &&
-           g->link_edges >= 0 && g->link_edges <= INT32_MAX &&
-           g->block >= kWave && g->block % kWave == 0 && g->block <= 1024;
+    if (!(g && ws && ((uintptr_t)ws % kAlign) == 0 && g->nbox >= 1 && g->n >= 0 &&
+          g->link_edges >= 0 && g->link_edges <= INT32_MAX && g->block >= kWave &&
+          g->block % kWave == 0 && g->block <= 1024))
+        return FOF_EINVAL;
+    return ws_bytes < g->ws_bytes ? FOF_ENOMEM : FOF_OK;
 }
 
 Work resolve(const fof_grid *g, void *ws)
@@ -348,9 +352,12 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
     return FOF_OK;
 }
 
-int fof_build_grid(const fof_grid *grid, const float *pos, void *ws, void *stream)
+int fof_build_grid(const fof_grid *grid, const float *pos, void *ws, size_t ws_bytes,
+                   void *stream)
 {
-    if (!ws_ok(grid, ws) || (grid->n > 0 && !pos))
+    if (int rc = ws_check(grid, ws, ws_bytes))
+        return rc;
+    if (grid->n > 0 && !pos)
         return FOF_EINVAL;
     Work w = resolve(grid, ws);
     clear_stale_error();
@@ -365,16 +372,18 @@ static bool sample_ok(const fof_grid *grid, const fof_sample *S)
             : S->form == FOF_PROB_QUADRATIC && S->alpha > 0.0 && isfinite(S->alpha) &&
                   S->b > 0.0 && isfinite(S->b);
     return grid->nbox == 1 && S->K >= 1 && S->K <= 65535 && S->edge_cap >= 0 && prob_ok &&
+           S->s_first >= 0 && S->s_first <= INT32_MAX - S->K &&
            S->n_edges && S->scratch && ((uintptr_t)S->scratch % 256) == 0 &&
            (S->edge_cap == 0 || (S->ei && S->ej && S->d2)) &&
            S->scratch_bytes >= FOF_SAMPLE_SCRATCH_BYTES(grid->n, S->K, S->edge_cap) &&
            sample_layout_ok(*S, grid->n);
 }
 
-int fof_link(const fof_grid *grid, void *ws, const fof_sample *sample, int32_t *root, void *stream)
+int fof_link(const fof_grid *grid, void *ws, size_t ws_bytes, const fof_sample *sample,
+             int32_t *root, void *stream)
 {
-    if (!ws_ok(grid, ws))
-        return FOF_EINVAL;
+    if (int rc = ws_check(grid, ws, ws_bytes))
+        return rc;
     Work w = resolve(grid, ws);
     clear_stale_error();
     if (sample) {
@@ -392,12 +401,23 @@ int fof_link(const fof_grid *grid, void *ws, const fof_sample *sample, int32_t *
     return dev_err(launch_link(w, root, (hipStream_t)stream, nullptr));
 }
 
-int fof_groups(const fof_grid *grid, void *ws, int32_t min_size, const float *vel, int32_t cap,
-               int32_t *group_id, int32_t *n_groups, int32_t *sizes, double *com, double *vmean,
-               double *sigv, void *stream)
+int fof_groups(const fof_grid *grid, void *ws, size_t ws_bytes, const fof_sample *sample,
+               int32_t min_size, const float *vel, int32_t cap, int32_t *group_id,
+               int32_t *n_groups, int32_t *sizes, double *com, double *vmean, double *sigv,
+               void *stream)
 {
-    if (!ws_ok(grid, ws) || !n_groups || cap < 0 || (grid->n > 0 && !group_id) ||
-        (cap > 0 && !sizes))
+    if (int rc = ws_check(grid, ws, ws_bytes))
+        return rc;
+    if (sample) {  // per-sample catalogues of the K sampled graphs
+        if (!sample_ok(grid, sample) || min_size < 2 || !n_groups || cap < 0 ||
+            (cap > 0 && (!sizes || !com)) || vel || vmean || sigv || group_id)
+            return FOF_EINVAL;
+        Work w = resolve(grid, ws);
+        clear_stale_error();
+        return dev_err(launch_groups_sampled(w, *sample, min_size, cap, n_groups, sizes, com,
+                                             (hipStream_t)stream));
+    }
+    if (!n_groups || cap < 0 || (grid->n > 0 && !group_id) || (cap > 0 && !sizes))
         return FOF_EINVAL;
     if ((vmean == nullptr) != (sigv == nullptr) || (vel == nullptr && vmean != nullptr))
         return FOF_EINVAL;
@@ -407,7 +427,8 @@ int fof_groups(const fof_grid *grid, void *ws, int32_t min_size, const float *ve
                                  sigv, (hipStream_t)stream));
 }
 
-int fof_backward(const fof_grid *grid, void *ws, int32_t mode, const int32_t *group_id, int32_t G,
+int fof_backward(const fof_grid *grid, void *ws, size_t ws_bytes, int32_t mode,
+                 const int32_t *group_id, int32_t G,
                  const int32_t *sizes, const double *vmean, const double *sigv, const float *vel,
                  const double *g_mass, const double *g_com, const double *g_sigv,
                  const fof_sample *sample, const double *loss, int32_t baseline, float *grad_pos,
@@ -417,7 +438,9 @@ int fof_backward(const fof_grid *grid, void *ws, int32_t mode, const int32_t *gr
     if (!grid || grid->n < 0)
         return FOF_EINVAL;
     if (mode == FOF_SCORE) {
-        if (!ws_ok(grid, ws) || !sample || !sample_ok(grid, sample) || !loss ||
+        if (int rc = ws_check(grid, ws, ws_bytes))
+            return rc;
+        if (!sample || !sample_ok(grid, sample) || !loss ||
             baseline < FOF_BASELINE_NONE || baseline > FOF_BASELINE_LOO)
             return FOF_EINVAL;
         Work w = resolve(grid, ws);
@@ -436,10 +459,13 @@ int fof_backward(const fof_grid *grid, void *ws, int32_t mode, const int32_t *gr
                                    g_sigv, grad_pos, grad_vel, (hipStream_t)stream));
 }
 
-int fof_group_dispersion(const fof_grid *grid, void *ws, int32_t cap, const int32_t *n_groups,
-                         const int32_t *sizes, const double *com, double *sigx, void *stream)
+int fof_group_dispersion(const fof_grid *grid, void *ws, size_t ws_bytes, int32_t cap,
+                         const int32_t *n_groups, const int32_t *sizes, const double *com,
+                         double *sigx, void *stream)
 {
-    if (!ws_ok(grid, ws) || cap < 0 || !n_groups || (cap > 0 && (!sizes || !com || !sigx)))
+    if (int rc = ws_check(grid, ws, ws_bytes))
+        return rc;
+    if (cap < 0 || !n_groups || (cap > 0 && (!sizes || !com || !sigx)))
         return FOF_EINVAL;
     Work w = resolve(grid, ws);
     clear_stale_error();
@@ -447,12 +473,14 @@ int fof_group_dispersion(const fof_grid *grid, void *ws, int32_t cap, const int3
                                            (hipStream_t)stream));
 }
 
-int fof_backward_dispersion(const fof_grid *grid, void *ws, const float *pos,
+int fof_backward_dispersion(const fof_grid *grid, void *ws, size_t ws_bytes, const float *pos,
                             const int32_t *group_id, int32_t G, const int32_t *sizes,
                             const double *com, const double *sigx, const double *g_sigx,
                             float *grad_pos, void *stream)
 {
-    if (!ws_ok(grid, ws) || G < 0)
+    if (int rc = ws_check(grid, ws, ws_bytes))
+        return rc;
+    if (G < 0)
         return FOF_EINVAL;
     if (grid->n > 0 && G > 0 && (!pos || !group_id || !sizes || !com || !sigx || !g_sigx ||
                                  !grad_pos))
@@ -468,12 +496,14 @@ size_t fof_subhalo_scratch_bytes(int64_t n, int32_t G)
     return n < 0 || G < 0 ? 0 : subhalo_scratch_bytes(n, G);
 }
 
-int fof_subhalo(const fof_grid *grid, void *ws, const float *pos, const float *vel,
-                const int32_t *group_id, int32_t G, const int32_t *sizes, const double *norm_x,
-                const double *norm_v, double b6, void *scratch, size_t scratch_bytes,
-                int32_t *sub, void *stream)
+int fof_subhalo(const fof_grid *grid, void *ws, size_t ws_bytes, const float *pos,
+                const float *vel, const int32_t *group_id, int32_t G, const int32_t *sizes,
+                const double *norm_x, const double *norm_v, double b6, void *scratch,
+                size_t scratch_bytes, int32_t *sub, void *stream)
 {
-    if (!ws_ok(grid, ws) || G < 0 || G > grid->n || !(b6 > 0.0) || !isfinite(b6))
+    if (int rc = ws_check(grid, ws, ws_bytes))
+        return rc;
+    if (G < 0 || G > grid->n || !(b6 > 0.0) || !isfinite(b6))
         return FOF_EINVAL;
     if (grid->n > 0 && !sub)
         return FOF_EINVAL;
@@ -487,9 +517,11 @@ int fof_subhalo(const fof_grid *grid, void *ws, const float *pos, const float *v
                                   sub, (hipStream_t)stream));
 }
 
-int fof_status(const fof_grid *grid, void *ws, int32_t **status)
+int fof_status(const fof_grid *grid, void *ws, size_t ws_bytes, int32_t **status)
 {
-    if (!ws_ok(grid, ws) || !status)
+    if (int rc = ws_check(grid, ws, ws_bytes))
+        return rc;
+    if (!status)
         return FOF_EINVAL;
     *status = (int32_t *)((char *)ws + grid->off_status);
     return FOF_OK;

@@ -417,10 +417,14 @@ __global__ void g_sig(const int32_t *__restrict__ n_groups, int32_t cap,
 }
 
 __global__ void g_total(const int32_t *__restrict__ keep_prefix, int64_t nwords,
-                        int32_t *__restrict__ n_groups)
+                        int32_t *__restrict__ n_groups, int32_t cap, Counters *__restrict__ ctr)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        *n_groups = keep_prefix[nwords];
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int32_t G = keep_prefix[nwords];
+        *n_groups = G;
+        if (G > cap)
+            atomicOr(&ctr->status, (int32_t)FOF_STATUS_OVERFLOW);
+    }
 }
 
 }  // namespace
@@ -489,7 +493,8 @@ hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int3
     e = launch_scan_popc(w.keep, w.keep_prefix, nwords, w.scan, s);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(g_total, dim3(1), dim3(64), 0, s, w.keep_prefix, nwords, n_groups);
+    hipLaunchKernelGGL(g_total, dim3(1), dim3(64), 0, s, w.keep_prefix, nwords, n_groups, cap,
+                       w.ctr);
     if (w.n == 0)
         return hipGetLastError();
     GroupOut o;

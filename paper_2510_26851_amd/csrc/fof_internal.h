@@ -401,6 +401,17 @@ hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch,
                            hipStream_t s);
+// exclusive scan of max(in[i], 0)
+hipError_t launch_scan_nonneg(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch,
+                              hipStream_t s);
+// exclusive scan of (in[i] != 0)
+hipError_t launch_scan_nonzero(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch,
+                               hipStream_t s);
+// exclusive scan over [K][vcap] of "(k, v) is the root of a component of at least min_size
+// members" in per-sample forests, v < *nv (a device count)
+hipError_t launch_scan_sample_keep(const int32_t *forest, const int32_t *cnt, const int32_t *nv,
+                                   int64_t vcap, int32_t K, int32_t min_size, int32_t *out,
+                                   int32_t *scratch, hipStream_t s);
 hipError_t launch_scan_popc(const uint32_t *in, int32_t *out, int64_t n, int32_t *scratch,
                             hipStream_t s);
 int64_t scan_scratch_elems(int64_t n);
@@ -437,6 +448,9 @@ int sample_layout_ok(const fof_sample &S, int64_t n);
 hipError_t launch_sample(const Work &w, const fof_sample &S, int32_t *root, hipStream_t s);
 hipError_t launch_score(const Work &w, const fof_sample &S, const double *loss, int32_t baseline,
                         float *grad_pos, hipStream_t s);
+hipError_t launch_groups_sampled(const Work &w, const fof_sample &S, int32_t min_size,
+                                 int32_t cap, int32_t *n_groups, int32_t *sizes, double *com,
+                                 hipStream_t s);
 hipError_t launch_backward(int64_t n, int32_t block, const int32_t *group_id, int32_t G,
                            const int32_t *sizes, const double *vmean, const double *sigv,
                            const float *vel, const double *g_com, const double *g_sigv,

@@ -12,7 +12,11 @@
 //                  those only, in original-index order
 //   k_sample_union one thread per (edge, sample): Philox uniform, keep, hook
 //   k_sample_label labels of every particle in every sample (smallest member index): a
-//                  stream of identity labels, then the particles that touch an edge
+//                  stream of identity labels, then the particles that touch an edge (only
+//                  when the caller asks for the K x n label arrays)
+//   k_sg_*, scan   per-sample groups over the touched particles: flatten each forest and
+//                  count members, number the kept roots in ascending order (one scan over
+//                  all samples), FP64 minimum-image sums about the root, centre and size
 //   k_score        per edge: w_e = (1/K) sum_s adv_s (y_es - p_e), scattered as
 //                  -+ w_e (x_i - x_j) c_e into the position gradient, c_e = 1/(tau d_e)
 //                  or 2 alpha / b^2
@@ -60,17 +64,22 @@ struct SampleArgs {
     double b, tau, alpha;
     int32_t form;  // FOF_PROB_DISTANCE or FOF_PROB_QUADRATIC
     uint64_t seed;
+    uint32_t s_first;  // global index of local sample 0
     int32_t K, edge_cap;
     int32_t *ei, *ej;
     double *d2;
     int32_t *n_edges;
     // scratch
-    int32_t *vflag;  // [n] 1 if the particle touches an edge
-    int32_t *vmap;   // [n + 1] exclusive scan of vflag: local index
-    int32_t *scan;   // scan tile sums
-    int32_t *vlist;  // [vcap] local index -> original index
+    int32_t *vflag;    // [n] 1 + sorted index if the particle touches an edge, else 0
+    int32_t *vmap;     // [n + 1] exclusive scan of (vflag != 0): local index
+    int32_t *scan;     // scan tile sums
+    int32_t *vlist;    // [vcap] local index -> original index (ascending)
+    int32_t *vsorted;  // [vcap] local index -> sorted index
     int32_t *si, *sj;  // [edge_cap] sorted indices of the edge ends
     int32_t *forest;   // [K][vcap]
+    int32_t *cnt;      // [K][vcap] members per root (per-sample groups)
+    int32_t *gpre;     // [K * vcap + 1] exclusive scan of the kept roots
+    int32_t *gscan;    // scan tile sums of gpre
     double *adv;       // [K] loss minus baseline
     int64_t vcap;
 };
@@ -260,21 +269,28 @@ __global__ void k_edges(Work w, SampleArgs a)
         edges_of(w, a, i);
 }
 
+// Marks the particles that touch an edge with 1 + their sorted index (every writer of one
+// entry stores the same value).
 __global__ void k_touch(SampleArgs a)
 {
     const int64_t m = edge_count(a), stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = gtid(); e < m; e += stride) {
-        a.vflag[a.ei[e]] = 1;
-        a.vflag[a.ej[e]] = 1;
+        a.vflag[a.ei[e]] = a.si[e] + 1;
+        a.vflag[a.ej[e]] = a.sj[e] + 1;
     }
 }
 
 __global__ void k_vlist(int64_t n, SampleArgs a)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = gtid(); i < n; i += stride)
-        if (a.vflag[i])
-            a.vlist[a.vmap[i]] = (int32_t)i;
+    for (int64_t i = gtid(); i < n; i += stride) {
+        const int32_t f = a.vflag[i];
+        if (f) {
+            const int32_t v = a.vmap[i];
+            a.vlist[v] = (int32_t)i;
+            a.vsorted[v] = f - 1;
+        }
+    }
 }
 
 __global__ void k_forest_init(int64_t n, SampleArgs a)
@@ -328,7 +344,7 @@ __global__ void k_sample_union(SampleArgs a)
         const int32_t vi = a.vmap[i], vj = a.vmap[j];
         const double p = edge_prob(a.d2[e], a);
         for (int32_t s = s0; s < s1; ++s)
-            if (edge_uniform(a.seed, (uint32_t)s, (uint32_t)i, (uint32_t)j) < p)
+            if (edge_uniform(a.seed, a.s_first + (uint32_t)s, (uint32_t)i, (uint32_t)j) < p)
                 funion(a.forest + (int64_t)s * a.vcap, vi, vj);
     }
 }
@@ -351,6 +367,109 @@ __global__ void k_sample_label(int64_t n, SampleArgs a, int32_t *__restrict__ ro
     const int32_t *f = a.forest + (int64_t)s * a.vcap;
     for (int64_t v = gtid(); v < nv; v += stride)
         root[(int64_t)s * n + a.vlist[v]] = a.vlist[ffind(f, (int32_t)v)];
+}
+
+// ---- per-sample groups (the halos of each sampled graph) ----------------------------
+// Sample blockIdx.y, touched particles v < nv.  The forests are final (every union is done),
+// so pointing each entry at its root cannot mislead a concurrent find: it only ever sees a
+// parent or the root.
+__global__ void k_sg_zero(int64_t n, SampleArgs a)
+{
+    const int64_t nv = a.vmap[n], stride = (int64_t)gridDim.x * blockDim.x;
+    int32_t *c = a.cnt + (int64_t)blockIdx.y * a.vcap;
+    for (int64_t v = gtid(); v < nv; v += stride)
+        c[v] = 0;
+}
+
+__global__ void k_sg_flatten(int64_t n, SampleArgs a)
+{
+    const int64_t nv = a.vmap[n], stride = (int64_t)gridDim.x * blockDim.x;
+    int32_t *f = a.forest + (int64_t)blockIdx.y * a.vcap;
+    int32_t *c = a.cnt + (int64_t)blockIdx.y * a.vcap;
+    for (int64_t v = gtid(); v < nv; v += stride) {
+        const int32_t r = ffind(f, (int32_t)v);
+        if (r != (int32_t)v)
+            __hip_atomic_store(f + v, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicAdd(c + r, 1);
+    }
+}
+
+// Group number of the kept root r of sample k (its rank among that sample's kept roots).
+__device__ __forceinline__ int32_t sg_group(const SampleArgs &a, int64_t k, int32_t r)
+{
+    const int64_t base = k * a.vcap;
+    return a.gpre[base + r] - a.gpre[base];
+}
+
+// n_groups[k], the overflow flag, and the sums: each member adds its minimum-image offset
+// from the root particle to its group's row of com (FP64); each kept root leaves its local
+// index in its group's sizes slot for k_sg_final.
+__global__ void k_sg_sum(int64_t n, Work w, SampleArgs a, int32_t min_size, int32_t cap,
+                         int32_t *__restrict__ n_groups, int32_t *__restrict__ sizes,
+                         double *__restrict__ com)
+{
+    const int64_t k = blockIdx.y, nv = a.vmap[n], stride = (int64_t)gridDim.x * blockDim.x;
+    if (gtid() == 0) {
+        const int32_t G = a.gpre[(k + 1) * a.vcap] - a.gpre[k * a.vcap];
+        n_groups[k] = G;
+        if (G > cap)
+            atomicOr(&w.ctr->status, (int32_t)FOF_STATUS_OVERFLOW);
+    }
+    const int32_t *f = a.forest + k * a.vcap;
+    const int32_t *c = a.cnt + k * a.vcap;
+    const BoxDesc &B = w.desc[0];
+    for (int64_t v = gtid(); v < nv; v += stride) {
+        const int32_t r = f[v];
+        if (c[r] < min_size)
+            continue;
+        const int32_t g = sg_group(a, k, r);
+        if (g >= cap)
+            continue;
+        double *acc = com + 3 * (k * cap + g);
+        if (r == (int32_t)v) {
+            sizes[k * cap + g] = r;
+            continue;  // the root's own offset is 0
+        }
+        const float4 p = w.sorted[a.vsorted[v]], q = w.sorted[a.vsorted[r]];
+        atomicAdd(acc + 0, min_image((double)p.x - (double)q.x, B.L[0], B.halfL[0]));
+        atomicAdd(acc + 1, min_image((double)p.y - (double)q.y, B.L[1], B.halfL[1]));
+        atomicAdd(acc + 2, min_image((double)p.z - (double)q.z, B.L[2], B.halfL[2]));
+    }
+}
+
+__global__ void k_sg_clear(SampleArgs a, int32_t cap, double *__restrict__ com)
+{
+    const int64_t k = blockIdx.y, stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t G = a.gpre[(k + 1) * a.vcap] - a.gpre[k * a.vcap];
+    const int64_t m = 3 * (G < cap ? G : cap);
+    double *row = com + 3 * k * cap;
+    for (int64_t t = gtid(); t < m; t += stride)
+        row[t] = 0.0;
+}
+
+// centre = wrap(x_root + sum / n), as the hard catalogue; sizes from the member counts.
+__global__ void k_sg_final(Work w, SampleArgs a, int32_t cap, const int32_t *__restrict__ n_groups,
+                           int32_t *__restrict__ sizes, double *__restrict__ com)
+{
+    const int64_t k = blockIdx.y, stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t G = n_groups[k] < cap ? n_groups[k] : cap;
+    const BoxDesc &B = w.desc[0];
+    for (int64_t g = gtid(); g < G; g += stride) {
+        const int32_t r = sizes[k * cap + g];
+        const int32_t m = a.cnt[k * a.vcap + r];
+        const float4 q = w.sorted[a.vsorted[r]];
+        const double x[3] = {(double)q.x, (double)q.y, (double)q.z};
+        double *c = com + 3 * (k * cap + g);
+        for (int d = 0; d < 3; ++d) {
+            double v = x[d] + c[d] / (double)m;
+            if (v >= B.L[d])
+                v -= B.L[d];
+            if (v < 0.0)
+                v += B.L[d];
+            c[d] = v;
+        }
+        sizes[k * cap + g] = m;
+    }
 }
 
 // Advantage of each sample: loss minus baseline.
@@ -377,7 +496,7 @@ __device__ void score_edge(const Work &w, const SampleArgs &a, int64_t e, float 
     const double p = edge_prob(a.d2[e], a);
     double wsum = 0.0;
     for (int32_t s = 0; s < a.K; ++s) {
-        const double u = edge_uniform(a.seed, (uint32_t)s, (uint32_t)i, (uint32_t)j);
+        const double u = edge_uniform(a.seed, a.s_first + (uint32_t)s, (uint32_t)i, (uint32_t)j);
         wsum += a.adv[s] * ((u < p ? 1.0 : 0.0) - p);
     }
     const double wgt = wsum / (double)a.K;
@@ -386,8 +505,11 @@ __device__ void score_edge(const Work &w, const SampleArgs &a, int64_t e, float 
     const double dx = min_image((double)pi.x - (double)pj.x, B.L[0], B.halfL[0]);
     const double dy = min_image((double)pi.y - (double)pj.y, B.L[1], B.halfL[1]);
     const double dz = min_image((double)pi.z - (double)pj.z, B.L[2], B.halfL[2]);
+    // distance form: (x_i - x_j)/d has no direction where the two particles coincide; such
+    // an edge contributes no gradient (the symmetric subgradient of d at 0)
+    const double d2e = a.d2[e];
     const double f = a.form == FOF_PROB_QUADRATIC ? wgt * (2.0 * a.alpha / (a.b * a.b))
-                                                  : wgt / (a.tau * sqrt(a.d2[e]));
+                     : (d2e > 0.0 ? wgt / (a.tau * sqrt(d2e)) : 0.0);
     atomicAdd(grad + 3 * (int64_t)i + 0, (float)(-f * dx));
     atomicAdd(grad + 3 * (int64_t)i + 1, (float)(-f * dy));
     atomicAdd(grad + 3 * (int64_t)i + 2, (float)(-f * dz));
@@ -436,10 +558,15 @@ static bool carve(const fof_sample &S, int64_t n, SampleArgs &a)
     a.vflag = (int32_t *)take(4 * (size_t)n);
     a.vmap = (int32_t *)take(4 * ((size_t)n + 1));
     a.scan = (int32_t *)take(4 * (size_t)scan_scratch_elems(n));
-    a.vlist = (int32_t *)take(4 * (size_t)(a.vcap > 0 ? a.vcap : 1));
+    const size_t vc = (size_t)(a.vcap > 0 ? a.vcap : 1);
+    a.vlist = (int32_t *)take(4 * vc);
+    a.vsorted = (int32_t *)take(4 * vc);
     a.si = (int32_t *)take(4 * (size_t)(S.edge_cap > 0 ? S.edge_cap : 1));
     a.sj = (int32_t *)take(4 * (size_t)(S.edge_cap > 0 ? S.edge_cap : 1));
-    a.forest = (int32_t *)take(4 * (size_t)S.K * (size_t)(a.vcap > 0 ? a.vcap : 1));
+    a.forest = (int32_t *)take(4 * (size_t)S.K * vc);
+    a.cnt = (int32_t *)take(4 * (size_t)S.K * vc);
+    a.gpre = (int32_t *)take(4 * ((size_t)S.K * vc + 1));
+    a.gscan = (int32_t *)take(4 * (size_t)scan_scratch_elems((int64_t)S.K * (int64_t)vc));
     a.adv = (double *)take(8 * (size_t)S.K);
     return o <= S.scratch_bytes;
 }
@@ -451,6 +578,7 @@ static void fill_args(const fof_sample &S, SampleArgs &a)
     a.alpha = S.alpha;
     a.form = S.form;
     a.seed = S.seed;
+    a.s_first = (uint32_t)S.s_first;
     a.K = S.K;
     a.edge_cap = S.edge_cap;
     a.ei = S.ei;
@@ -485,7 +613,7 @@ hipError_t launch_sample(const Work &w, const fof_sample &S, int32_t *root, hipS
     }
     // edges at most edge_cap: the grid of the following kernels is sized for the cap
     hipLaunchKernelGGL(k_touch, dim3(edge_blocks(S.edge_cap)), dim3(kBlock), 0, s, a);
-    e = launch_scan_i32(a.vflag, a.vmap, w.n, a.scan, s);
+    e = launch_scan_nonzero(a.vflag, a.vmap, w.n, a.scan, s);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_vlist, dim3(blocks_for(w.n)), dim3(kBlock), 0, s, w.n, a);
@@ -501,6 +629,31 @@ hipError_t launch_sample(const Work &w, const fof_sample &S, int32_t *root, hipS
         hipLaunchKernelGGL(k_sample_label, dim3(blocks_for(a.vcap), rows), dim3(kBlock), 0, s,
                            w.n, a, root);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_groups_sampled(const Work &w, const fof_sample &S, int32_t min_size,
+                                 int32_t cap, int32_t *n_groups, int32_t *sizes, double *com,
+                                 hipStream_t s)
+{
+    SampleArgs a;
+    fill_args(S, a);
+    carve(S, w.n, a);
+    const unsigned K = (unsigned)S.K, vb = edge_blocks(a.vcap);
+    const unsigned cb = edge_blocks(cap);
+    hipLaunchKernelGGL(k_sg_zero, dim3(vb, K), dim3(kBlock), 0, s, w.n, a);
+    hipLaunchKernelGGL(k_sg_flatten, dim3(vb, K), dim3(kBlock), 0, s, w.n, a);
+    hipError_t e = launch_scan_sample_keep(a.forest, a.cnt, a.vmap + w.n, a.vcap > 0 ? a.vcap : 1,
+                                           S.K, min_size, a.gpre, a.gscan, s);
+    if (e != hipSuccess)
+        return e;
+    if (cap > 0)
+        hipLaunchKernelGGL(k_sg_clear, dim3(cb, K), dim3(kBlock), 0, s, a, cap, com);
+    hipLaunchKernelGGL(k_sg_sum, dim3(vb, K), dim3(kBlock), 0, s, w.n, w, a, min_size, cap,
+                       n_groups, sizes, com);
+    if (cap > 0)
+        hipLaunchKernelGGL(k_sg_final, dim3(cb, K), dim3(kBlock), 0, s, w, a, cap, n_groups,
+                           sizes, com);
     return hipGetLastError();
 }
 

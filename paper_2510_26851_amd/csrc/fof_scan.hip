@@ -23,6 +23,29 @@ struct LoadI32 {
     __device__ int32_t operator()(int64_t i) const { return p[i]; }
 };
 
+struct LoadNonNeg {
+    const int32_t *p;
+    __device__ int32_t operator()(int64_t i) const { return max(p[i], 0); }
+};
+
+struct LoadNonZero {
+    const int32_t *p;
+    __device__ int32_t operator()(int64_t i) const { return p[i] != 0 ? 1 : 0; }
+};
+
+// Roots of kept components in per-sample forests laid out [K][vcap]: entry (k, v) counts
+// when v is below the device count *nv, is its tree's root and has at least min_size members.
+struct LoadSampleKeep {
+    const int32_t *forest, *cnt, *nv;
+    int64_t vcap;
+    int32_t min_size;
+    __device__ int32_t operator()(int64_t i) const
+    {
+        const int64_t v = i % vcap;
+        return (v < *nv && forest[i] == (int32_t)v && cnt[i] >= min_size) ? 1 : 0;
+    }
+};
+
 struct LoadPopc {
     const uint32_t *p;
     __device__ int32_t operator()(int64_t i) const { return __popc(p[i]); }
@@ -152,6 +175,26 @@ hipError_t launch_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *
                            hipStream_t s)
 {
     return scan_impl(LoadI32{in}, out, n, scratch, s);
+}
+
+hipError_t launch_scan_nonneg(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch,
+                              hipStream_t s)
+{
+    return scan_impl(LoadNonNeg{in}, out, n, scratch, s);
+}
+
+hipError_t launch_scan_nonzero(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch,
+                               hipStream_t s)
+{
+    return scan_impl(LoadNonZero{in}, out, n, scratch, s);
+}
+
+hipError_t launch_scan_sample_keep(const int32_t *forest, const int32_t *cnt, const int32_t *nv,
+                                   int64_t vcap, int32_t K, int32_t min_size, int32_t *out,
+                                   int32_t *scratch, hipStream_t s)
+{
+    return scan_impl(LoadSampleKeep{forest, cnt, nv, vcap, min_size}, out, (int64_t)K * vcap,
+                     scratch, s);
 }
 
 hipError_t launch_scan_popc(const uint32_t *in, int32_t *out, int64_t n, int32_t *scratch,

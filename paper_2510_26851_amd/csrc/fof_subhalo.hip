@@ -284,7 +284,9 @@ hipError_t launch_subhalo(const Work &w, const float *pos, const float *vel,
     int32_t *off = member + w.n;
     int32_t *cur = off + G;
     int32_t *scan = cur + G;
-    if ((e = launch_scan_i32(sizes, off, G, scan, s)) != hipSuccess)
+    // a negative size counts as 0, so host ranges never overlap; its members are dropped
+    // and flagged by the scatter (k >= sizes[g])
+    if ((e = launch_scan_nonneg(sizes, off, G, scan, s)) != hipSuccess)
         return e;
     if ((e = launch_fill_i32(cur, G, 0, s)) != hipSuccess)
         return e;

@@ -23,6 +23,25 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, name, dtype, shape, device, min_rows=None):
+    """Raises ValueError unless t is a contiguous tensor of `dtype` on `device` with `shape`
+    (or, with min_rows, a 1-D tensor of at least that many entries): the library would read
+    a host pointer or a wrong element size as device memory."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if min_rows is not None:
+        if t.dim() != 1 or t.shape[0] < min_rows:
+            raise ValueError(f"{name} needs at least {min_rows} entries, got {tuple(t.shape)}")
+    elif tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -64,24 +83,26 @@ class Plan:
                                     desc.ctypes.data_as(ctypes.c_void_p), desc.shape[0]))
         self.n = int(self.grid.n)
         self.nbox = nbox
-        self.ws = torch.empty(int(self.grid.ws_bytes), dtype=torch.uint8, device=self.device)
+        self.ws_bytes = int(self.grid.ws_bytes)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         o = int(self.grid.off_desc)
         self.ws[o:o + desc.shape[0]].copy_(torch.from_numpy(desc))
         self._gref = ctypes.byref(self.grid)
 
     # -- stages ---------------------------------------------------------------------------
     def build_grid(self, pos, stream=None):
-        assert pos.dtype == torch.float32 and pos.is_contiguous() and pos.shape == (self.n, 3)
-        assert pos.device == self.ws.device
+        _need(pos, "pos", torch.float32, (self.n, 3), self.ws.device)
         self._pos = pos
         check("fof_build_grid",
-              _lib.load().fof_build_grid(self._gref, _ptr(pos), _ptr(self.ws), _stream(stream)))
+              _lib.load().fof_build_grid(self._gref, _ptr(pos), _ptr(self.ws), self.ws_bytes,
+                                         _stream(stream)))
 
     def link(self, root=None, stream=None):
         if root is None:
             root = torch.empty(self.n, dtype=torch.int32, device=self.device)
         check("fof_link",
-              _lib.load().fof_link(self._gref, _ptr(self.ws), None, _ptr(root), _stream(stream)))
+              _lib.load().fof_link(self._gref, _ptr(self.ws), self.ws_bytes, None, _ptr(root),
+                                   _stream(stream)))
         return root
 
     def groups(self, min_size, vel=None, cap=None, out=None, stream=None):
@@ -103,7 +124,7 @@ class Plan:
             com = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=d)
         vm = sv = None
         if vel is not None:
-            assert vel.dtype == torch.float32 and vel.shape == (self.n, 3) and vel.is_contiguous()
+            _need(vel, "vel", torch.float32, (self.n, 3), self.ws.device)
             vm = o.get("vmean")
             if vm is None:
                 vm = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=d)
@@ -111,7 +132,8 @@ class Plan:
             if sv is None:
                 sv = torch.empty(max(cap, 1), dtype=torch.float64, device=d)
         check("fof_groups",
-              _lib.load().fof_groups(self._gref, _ptr(self.ws), int(min_size), _ptr(vel), cap,
+              _lib.load().fof_groups(self._gref, _ptr(self.ws), self.ws_bytes, None,
+                                     int(min_size), _ptr(vel), cap,
                                      _ptr(gid), _ptr(ng), _ptr(sizes), _ptr(com), _ptr(vm),
                                      _ptr(sv), _stream(stream)))
         res = dict(group_id=gid, n_groups=ng, sizes=sizes, com=com, cap=cap)
@@ -127,7 +149,8 @@ class Plan:
         if sigx is None:
             sigx = torch.empty(max(cap, 1), dtype=torch.float64, device=self.device)
         check("fof_group_dispersion",
-              _lib.load().fof_group_dispersion(self._gref, _ptr(self.ws), cap,
+              _lib.load().fof_group_dispersion(self._gref, _ptr(self.ws), self.ws_bytes,
+                                               cap,
                                                _ptr(res["n_groups"]), _ptr(res["sizes"]),
                                                _ptr(res["com"]), _ptr(sigx), _stream(stream)))
         return sigx
@@ -135,9 +158,18 @@ class Plan:
     def backward_dispersion(self, pos, group_id, G, sizes, com, sigx, g_sigx, grad_pos,
                             stream=None):
         """Adds the frozen-assignment gradient of the dispersion to grad_pos (in place)."""
+        d, G = self.ws.device, int(G)
         g_sigx = g_sigx.to(torch.float64).contiguous()
+        _need(pos, "pos", torch.float32, (self.n, 3), d)
+        _need(group_id, "group_id", torch.int32, (self.n,), d)
+        _need(grad_pos, "grad_pos", torch.float32, (self.n, 3), d)
+        _need(sizes, "sizes", torch.int32, None, d, min_rows=G)
+        _need(sigx, "sigx", torch.float64, None, d, min_rows=G)
+        _need(g_sigx, "g_sigx", torch.float64, None, d, min_rows=G)
+        _need(com.reshape(-1), "com", torch.float64, None, d, min_rows=3 * G)
         check("fof_backward_dispersion",
-              _lib.load().fof_backward_dispersion(self._gref, _ptr(self.ws), _ptr(pos),
+              _lib.load().fof_backward_dispersion(self._gref, _ptr(self.ws), self.ws_bytes,
+                                                  _ptr(pos),
                                                   _ptr(group_id), int(G), _ptr(sizes),
                                                   _ptr(com), _ptr(sigx), _ptr(g_sigx),
                                                   _ptr(grad_pos), _stream(stream)))
@@ -149,10 +181,16 @@ class Plan:
         group_id / sizes describe (as groups() returns them): the smallest original index of
         each member's phase-space component, -1 outside the hosts.  norm_x, norm_v: one
         factor per host dividing the squared position and velocity separations."""
-        lib = _lib.load()
         G = int(G)
+        d = self.ws.device
+        _need(pos, "pos", torch.float32, (self.n, 3), d)
+        _need(vel, "vel", torch.float32, (self.n, 3), d)
+        _need(group_id, "group_id", torch.int32, (self.n,), d)
+        _need(sizes, "sizes", torch.int32, None, d, min_rows=G)
         if sub is None:
-            sub = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+            sub = torch.empty(max(self.n, 1), dtype=torch.int32, device=d)
+        _need(sub, "sub", torch.int32, None, d, min_rows=self.n)
+        lib = _lib.load()
         nbytes = int(lib.fof_subhalo_scratch_bytes(self.n, G))
         scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-scratch.data_ptr()) % 256
@@ -161,7 +199,8 @@ class Plan:
         if G > 0 and (nx.numel() < G or nv.numel() < G):
             raise ValueError("norm_x and norm_v need one factor per host")
         check("fof_subhalo",
-              lib.fof_subhalo(self._gref, _ptr(self.ws), _ptr(pos), _ptr(vel), _ptr(group_id),
+              lib.fof_subhalo(self._gref, _ptr(self.ws), self.ws_bytes, _ptr(pos), _ptr(vel),
+                              _ptr(group_id),
                               G, _ptr(sizes), _ptr(nx), _ptr(nv), float(b6),
                               ctypes.c_void_p(scratch.data_ptr() + off), nbytes, _ptr(sub),
                               _stream(stream)))
@@ -170,19 +209,31 @@ class Plan:
 
     def status(self) -> int:
         p = ctypes.c_void_p()
-        check("fof_status", _lib.load().fof_status(self._gref, _ptr(self.ws), ctypes.byref(p)))
+        check("fof_status", _lib.load().fof_status(self._gref, _ptr(self.ws), self.ws_bytes,
+                                                   ctypes.byref(p)))
         off = p.value - self.ws.data_ptr()
         return int(self.ws[off:off + 4].view(torch.int32).item())
 
     def backward(self, group_id, G, sizes, vmean=None, sigv=None, vel=None, g_mass=None,
                  g_com=None, g_sigv=None, want_pos=True, want_vel=True, stream=None):
-        d = self.device
+        d = self.ws.device
+        G = int(G)
+        _need(group_id, "group_id", torch.int32, (self.n,), d)
+        _need(sizes, "sizes", torch.int32, None, d, min_rows=G)
+        if g_sigv is not None:
+            _need(vel, "vel", torch.float32, (self.n, 3), d)
+            _need(vmean.reshape(-1), "vmean", torch.float64, None, d, min_rows=3 * G)
+            _need(sigv, "sigv", torch.float64, None, d, min_rows=G)
         gp = torch.empty((self.n, 3), dtype=torch.float32, device=d) if want_pos else None
         gv = torch.empty((self.n, 3), dtype=torch.float32, device=d) if want_vel else None
         f64 = lambda t: None if t is None else t.to(torch.float64).contiguous()
         g_mass, g_com, g_sigv = f64(g_mass), f64(g_com), f64(g_sigv)
+        for t, name, k in ((g_mass, "g_mass", 1), (g_com, "g_com", 3), (g_sigv, "g_sigv", 1)):
+            if t is not None:
+                _need(t.reshape(-1), name, torch.float64, None, d, min_rows=k * G)
         check("fof_backward",
-              _lib.load().fof_backward(self._gref, _ptr(self.ws), _lib.FOF_FROZEN, _ptr(group_id),
+              _lib.load().fof_backward(self._gref, _ptr(self.ws), self.ws_bytes,
+                                       _lib.FOF_FROZEN, _ptr(group_id),
                                        int(G), _ptr(sizes), _ptr(vmean), _ptr(sigv), _ptr(vel),
                                        _ptr(g_mass), _ptr(g_com), _ptr(g_sigv), None, None, 0,
                                        _ptr(gp), _ptr(gv), _stream(stream)))

@@ -209,72 +209,91 @@ def test_entry_points_reject_bad_arguments_before_launch():
     gp = ctypes.byref(g)
     fake_ws = ctypes.c_void_p(0x100000)      # never dereferenced: every call below fails first
     misaligned = ctypes.c_void_p(0x100010)
-    assert L.fof_build_grid(None, None, fake_ws, None) == _lib.FOF_EINVAL
-    assert L.fof_build_grid(gp, None, fake_ws, None) == _lib.FOF_EINVAL          # pos NULL
-    assert L.fof_build_grid(gp, fake_ws, misaligned, None) == _lib.FOF_EINVAL    # ws alignment
-    assert L.fof_build_grid(gp, fake_ws, None, None) == _lib.FOF_EINVAL          # ws NULL
-    assert L.fof_link(gp, fake_ws, None, None, None) == _lib.FOF_EINVAL          # root NULL
+    W = g.ws_bytes
+    assert L.fof_build_grid(None, None, fake_ws, W, None) == _lib.FOF_EINVAL
+    assert L.fof_build_grid(gp, None, fake_ws, W, None) == _lib.FOF_EINVAL       # pos NULL
+    assert L.fof_build_grid(gp, fake_ws, misaligned, W, None) == _lib.FOF_EINVAL  # alignment
+    assert L.fof_build_grid(gp, fake_ws, None, W, None) == _lib.FOF_EINVAL       # ws NULL
+    assert L.fof_link(gp, fake_ws, W, None, None, None) == _lib.FOF_EINVAL       # root NULL
     S = _lib.fof_sample()                                                        # K = 0
-    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    assert L.fof_link(gp, fake_ws, W, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
     S.K, S.tau, S.b, S.edge_cap = 4, 0.01, 0.2, 100
     S.n_edges, S.ei, S.ej, S.d2 = 0x100000, 0x100000, 0x100000, 0x100000
     S.scratch, S.scratch_bytes = 0x100000, 10                                   # too small
-    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    assert L.fof_link(gp, fake_ws, W, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
     S.scratch_bytes = _lib.sample_scratch_bytes(100, 4, 100)
     S.tau = 0.0                                                                  # tau <= 0
-    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    assert L.fof_link(gp, fake_ws, W, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
     S.tau, S.K = 0.01, 65536                                                     # K too large
     S.scratch_bytes = _lib.sample_scratch_bytes(100, 65536, 100)
-    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    assert L.fof_link(gp, fake_ws, W, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
     S.K, S.tau = 4, 0.01
     S.scratch_bytes = _lib.sample_scratch_bytes(100, 4, 100)
+    S.s_first = -1                                                               # s_first < 0
+    assert L.fof_link(gp, fake_ws, W, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    S.s_first = 2 ** 31 - 4                                                      # past 2^31 - 1
+    assert L.fof_link(gp, fake_ws, W, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    S.s_first = 0
     S.form, S.alpha = _lib.FOF_PROB_QUADRATIC, 0.0                              # alpha <= 0
-    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    assert L.fof_link(gp, fake_ws, W, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
     S.form, S.alpha = 2, 1.0                                                     # unknown form
-    assert L.fof_link(gp, fake_ws, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
-    S.form, S.tau = _lib.FOF_PROB_DISTANCE, 0.0
-    assert L.fof_group_dispersion(gp, fake_ws, -1, fake_ws, fake_ws, fake_ws, fake_ws,
+    assert L.fof_link(gp, fake_ws, W, ctypes.byref(S), fake_ws, None) == _lib.FOF_EINVAL
+    S.form = _lib.FOF_PROB_DISTANCE
+    # the sampled catalogue: min_size >= 2, no per-particle or velocity outputs
+    Sp = ctypes.byref(S)
+    assert L.fof_groups(gp, fake_ws, W, Sp, 1, None, 10, None, fake_ws, fake_ws, fake_ws, None,
+                        None, None) == _lib.FOF_EINVAL                            # min_size 1
+    assert L.fof_groups(gp, fake_ws, W, Sp, 2, fake_ws, 10, None, fake_ws, fake_ws, fake_ws,
+                        None, None, None) == _lib.FOF_EINVAL                      # vel given
+    assert L.fof_groups(gp, fake_ws, W, Sp, 2, None, 10, fake_ws, fake_ws, fake_ws, fake_ws,
+                        None, None, None) == _lib.FOF_EINVAL                      # group_id
+    assert L.fof_groups(gp, fake_ws, W, Sp, 2, None, 10, None, fake_ws, fake_ws, None, None,
+                        None, None) == _lib.FOF_EINVAL                            # com NULL
+    S.tau = 0.0
+    assert L.fof_groups(gp, fake_ws, W, Sp, 2, None, 10, None, fake_ws, fake_ws, fake_ws, None,
+                        None, None) == _lib.FOF_EINVAL                            # bad sample
+    assert L.fof_group_dispersion(gp, fake_ws, W, -1, fake_ws, fake_ws, fake_ws, fake_ws,
                                   None) == _lib.FOF_EINVAL                        # cap < 0
-    assert L.fof_group_dispersion(gp, fake_ws, 10, None, fake_ws, fake_ws, fake_ws,
+    assert L.fof_group_dispersion(gp, fake_ws, W, 10, None, fake_ws, fake_ws, fake_ws,
                                   None) == _lib.FOF_EINVAL                        # n_groups NULL
-    assert L.fof_group_dispersion(gp, fake_ws, 10, fake_ws, fake_ws, None, fake_ws,
+    assert L.fof_group_dispersion(gp, fake_ws, W, 10, fake_ws, fake_ws, None, fake_ws,
                                   None) == _lib.FOF_EINVAL                        # com NULL
-    assert L.fof_backward_dispersion(gp, fake_ws, fake_ws, fake_ws, -1, fake_ws, fake_ws,
+    assert L.fof_backward_dispersion(gp, fake_ws, W, fake_ws, fake_ws, -1, fake_ws, fake_ws,
                                      fake_ws, fake_ws, fake_ws, None) == _lib.FOF_EINVAL  # G < 0
-    assert L.fof_backward_dispersion(gp, fake_ws, None, fake_ws, 3, fake_ws, fake_ws, fake_ws,
-                                     fake_ws, fake_ws, None) == _lib.FOF_EINVAL   # pos NULL
-    assert L.fof_groups(gp, fake_ws, 20, None, 10, None, fake_ws, fake_ws, None, None, None,
-                        None) == _lib.FOF_EINVAL                                  # group_id NULL
-    assert L.fof_groups(gp, fake_ws, 20, None, -1, fake_ws, fake_ws, fake_ws, None, None, None,
-                        None) == _lib.FOF_EINVAL                                  # cap < 0
-    assert L.fof_groups(gp, fake_ws, 20, None, 10, fake_ws, fake_ws, None, None, None, None,
-                        None) == _lib.FOF_EINVAL                                  # sizes NULL
-    assert L.fof_groups(gp, fake_ws, 20, fake_ws, 10, fake_ws, fake_ws, fake_ws, None, fake_ws,
-                        None, None) == _lib.FOF_EINVAL                            # vmean w/o sigv
+    assert L.fof_backward_dispersion(gp, fake_ws, W, None, fake_ws, 3, fake_ws, fake_ws,
+                                     fake_ws, fake_ws, fake_ws, None) == _lib.FOF_EINVAL
+    assert L.fof_groups(gp, fake_ws, W, None, 20, None, 10, None, fake_ws, fake_ws, None, None,
+                        None, None) == _lib.FOF_EINVAL                            # group_id NULL
+    assert L.fof_groups(gp, fake_ws, W, None, 20, None, -1, fake_ws, fake_ws, fake_ws, None,
+                        None, None, None) == _lib.FOF_EINVAL                      # cap < 0
+    assert L.fof_groups(gp, fake_ws, W, None, 20, None, 10, fake_ws, fake_ws, None, None, None,
+                        None, None) == _lib.FOF_EINVAL                            # sizes NULL
+    assert L.fof_groups(gp, fake_ws, W, None, 20, fake_ws, 10, fake_ws, fake_ws, fake_ws, None,
+                        fake_ws, None, None) == _lib.FOF_EINVAL                   # vmean w/o sigv
     F = _lib.FOF_FROZEN
     nul = [None] * 3
-    assert L.fof_backward(gp, fake_ws, F, None, 1, fake_ws, *nul, None, None, None, None, None,
-                          0, None, None, None) == _lib.FOF_EINVAL                # group_id NULL
-    assert L.fof_backward(gp, fake_ws, F, fake_ws, -1, fake_ws, *nul, None, None, None, None,
+    assert L.fof_backward(gp, fake_ws, W, F, None, 1, fake_ws, *nul, None, None, None, None,
+                          None, 0, None, None, None) == _lib.FOF_EINVAL          # group_id NULL
+    assert L.fof_backward(gp, fake_ws, W, F, fake_ws, -1, fake_ws, *nul, None, None, None, None,
                           None, 0, None, None, None) == _lib.FOF_EINVAL          # G < 0
-    assert L.fof_backward(gp, fake_ws, F, fake_ws, 1, fake_ws, *nul, None, None, fake_ws, None,
-                          None, 0, None, fake_ws, None) == _lib.FOF_EINVAL       # vel missing
-    assert L.fof_backward(gp, fake_ws, 7, fake_ws, 1, fake_ws, *nul, None, None, None, None,
+    assert L.fof_backward(gp, fake_ws, W, F, fake_ws, 1, fake_ws, *nul, None, None, fake_ws,
+                          None, None, 0, None, fake_ws, None) == _lib.FOF_EINVAL  # vel missing
+    assert L.fof_backward(gp, fake_ws, W, 7, fake_ws, 1, fake_ws, *nul, None, None, None, None,
                           None, 0, None, None, None) == _lib.FOF_EINVAL          # bad mode
-    assert L.fof_backward(gp, fake_ws, _lib.FOF_SCORE, None, 0, None, *nul, None, None, None,
+    assert L.fof_backward(gp, fake_ws, W, _lib.FOF_SCORE, None, 0, None, *nul, None, None, None,
                           None, fake_ws, 2, fake_ws, None, None) == _lib.FOF_EINVAL  # no sample
     need = L.fof_subhalo_scratch_bytes(100, 3)
     assert need >= 12 * 100 + 4 * 2 * 3
     sub_args = [fake_ws, fake_ws, fake_ws, 3, fake_ws, fake_ws, fake_ws, 1.0, fake_ws, need,
                 fake_ws, None]
 
-    def subhalo(**kw):
+    def subhalo(ws_bytes=W, **kw):
         a = list(sub_args)
         names = ["pos", "vel", "gid", "G", "sizes", "nx", "nv", "b6", "scratch", "nbytes", "sub",
                  "stream"]
         for k, v in kw.items():
             a[names.index(k)] = v
-        return L.fof_subhalo(gp, fake_ws, *a)
+        return L.fof_subhalo(gp, fake_ws, ws_bytes, *a)
 
     assert subhalo(b6=0.0) == _lib.FOF_EINVAL                                    # b6 <= 0
     assert subhalo(b6=float("nan")) == _lib.FOF_EINVAL                           # b6 not finite
@@ -284,10 +303,34 @@ def test_entry_points_reject_bad_arguments_before_launch():
     assert subhalo(vel=None) == _lib.FOF_EINVAL                                  # vel NULL
     assert subhalo(nbytes=need - 1) == _lib.FOF_EINVAL                           # scratch small
     assert subhalo(scratch=misaligned) == _lib.FOF_EINVAL                        # alignment
+    assert subhalo(ws_bytes=W - 1) == _lib.FOF_ENOMEM                            # ws small
     p = ctypes.c_void_p()
-    assert L.fof_status(gp, misaligned, ctypes.byref(p)) == _lib.FOF_EINVAL
-    assert L.fof_status(gp, fake_ws, ctypes.byref(p)) == 0
+    assert L.fof_status(gp, misaligned, W, ctypes.byref(p)) == _lib.FOF_EINVAL
+    assert L.fof_status(gp, fake_ws, W, ctypes.byref(p)) == 0
     assert p.value == 0x100000 + g.off_status
+
+
+def test_every_workspace_call_reports_a_small_workspace():
+    """FOF_ENOMEM: the workspace the caller passes is smaller than the plan needs; nothing is
+    enqueued (the fake workspace is never touched)."""
+    L = lib()
+    rc, g, _ = plan([100], [(10.0, 0.4)])
+    assert rc == 0
+    gp = ctypes.byref(g)
+    ws = ctypes.c_void_p(0x100000)
+    small = g.ws_bytes - 256
+    E = _lib.FOF_ENOMEM
+    p = ctypes.c_void_p()
+    assert L.fof_build_grid(gp, ws, ws, small, None) == E
+    assert L.fof_link(gp, ws, small, None, ws, None) == E
+    assert L.fof_groups(gp, ws, small, None, 20, None, 10, ws, ws, ws, ws, None, None, None) == E
+    assert L.fof_group_dispersion(gp, ws, small, 10, ws, ws, ws, ws, None) == E
+    assert L.fof_backward_dispersion(gp, ws, small, ws, ws, 1, ws, ws, ws, ws, ws, None) == E
+    assert L.fof_backward(gp, ws, small, _lib.FOF_SCORE, None, 0, None, None, None, None, None,
+                          None, None, None, ws, 2, ws, None, None) == E
+    assert L.fof_status(gp, ws, small, ctypes.byref(p)) == E
+    assert L.fof_status(gp, ws, 0, ctypes.byref(p)) == E
+    assert L.fof_strerror(E) == b"workspace too small"
 
 
 def test_one_hip_runtime_per_process():

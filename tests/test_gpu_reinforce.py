@@ -3,6 +3,8 @@
 * candidate edges: the same set as the oracle, squared distances bit-exact;
 * sampled labels of K graphs: bit-exact to the oracle, which draws the same Philox4x64-10
   uniforms (a near-tie |u - p| of a few ulps, ~1e-9 expected per run, would be reported);
+* per-sample halo tables (the library's sampled fof_groups): counts and sizes bit-exact to the
+  oracle's catalogue of each sampled graph, centres within 1e-5;
 * gradient: equal to the oracle's FP64 estimator on the same samples (1e-5 relative);
 * unbiasedness: the mean over many launches matches the exact gradient by enumeration.
 """
@@ -23,11 +25,30 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def sampler(pos, L, b, tau, K, seed, edge_cap=None):
+def sampler(pos, L, b, tau, K, seed, edge_cap=None, s_first=0):
     import torch
     from paper_2510_26851_amd.reinforce import Sampler
 
-    return Sampler(torch.from_numpy(pos).cuda(), L, b, tau, K, seed, edge_cap=edge_cap)
+    return Sampler(torch.from_numpy(pos).cuda(), L, b, tau, K, seed, edge_cap=edge_cap,
+                   s_first=s_first)
+
+
+def check_tables(halos, pos, L, oroot, min_size, spacing):
+    """Per-sample tables against oracle.groups of each sampled graph's labels."""
+    import oracle
+
+    ng = halos["n_groups"].cpu().numpy()
+    sizes = halos["sizes"].cpu().numpy()
+    com = halos["com"].cpu().numpy()
+    Lv = np.broadcast_to(np.asarray(L, np.float64), (3,))
+    for k in range(oroot.shape[0]):
+        ref = oracle.groups(pos, oroot[k], L, min_size)
+        G = ref["n_groups"]
+        assert ng[k] == G, (k, ng[k], G)
+        np.testing.assert_array_equal(sizes[k, :G], ref["sizes"])
+        d = com[k, :G] - ref["com"]
+        d -= Lv * np.round(d / Lv)
+        assert np.all(np.abs(d) <= 1e-5 * np.maximum(np.abs(ref["com"]), spacing)), k
 
 
 def edge_set(ei, ej, d2):
@@ -35,8 +56,9 @@ def edge_set(ei, ej, d2):
 
 
 @pytest.mark.parametrize("which", ["config3", "clumpy"])
-def test_edges_labels_and_gradient_match_oracle(which):
+def test_edges_labels_groups_and_gradient_match_oracle(which):
     import torch
+    from paper_2510_26851_amd.reinforce import sum_sq_sizes
 
     if which == "config3":
         box = W.config3()
@@ -50,7 +72,8 @@ def test_edges_labels_and_gradient_match_oracle(which):
     r_c = b + 10 * tau
     say(f"reinforce {which}: n={pos.shape[0]} K={K}")
     smp = sampler(pos, L, b, tau, K, seed)
-    root = smp.sample()
+    root = smp.sample(want_labels=True)
+    halos = smp.groups(2)
     ei, ej, d2, total = smp.edges()
     torch.cuda.synchronize()
     assert smp.plan.status() == 0 and total == ei.shape[0]
@@ -65,28 +88,42 @@ def test_edges_labels_and_gradient_match_oracle(which):
         u = np.array([[RF.uniform(seed, s, a, c) for a, c in zip(oei, oej)] for s in mism])
         near = np.abs(u - p[None, :]) <= 8 * 2.0 ** -53
         pytest.fail(f"samples {mism.tolist()} differ; near ties there: {int(near.sum())}")
-    # gradient with a loss computed from the labels
-    from paper_2510_26851_amd.reinforce import sum_sq_sizes
-
-    losses = sum_sq_sizes(root, 2)
+    # per-sample halos, and a larger cut
+    spacing = float(np.cbrt(np.prod(np.broadcast_to(L, (3,))) / pos.shape[0]))
+    check_tables(halos, pos, L, oroot, 2, spacing)
+    check_tables(smp.groups(4), pos, L, oroot, 4, spacing)
+    # gradient with a loss computed from the tables
+    losses = sum_sq_sizes(halos)
+    ref_losses = np.array([RF.loss_sum_sq(r, 2) for r in oroot])
+    np.testing.assert_array_equal(losses.cpu().numpy(), ref_losses)
     g = smp.grad(losses, baseline="loo").cpu().numpy()
     delta, d = RF.edge_geometry(pos, L, oei, oej)
-    ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, tau, keep,
-                            losses.cpu().numpy(), "loo")
+    ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, tau, keep, ref_losses, "loo")
     assert np.abs(g - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1e-30)
     for bl in ("mean", "none"):
         g = smp.grad(losses, baseline=bl).cpu().numpy()
-        ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, tau, keep,
-                                losses.cpu().numpy(), bl)
+        ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, tau, keep, ref_losses, bl)
         assert np.abs(g - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1e-30)
 
 
-def test_sample_zero_of_a_batch_equals_a_single_sample():
+def test_single_sample_calls_equal_one_batch():
+    """Sample s of a batch of K equals a call of one sample with s_first = s: labels and
+    tables are identical (the uniforms are counted by the global sample index)."""
     pos = W.clumpy_box(4000, 12.0, 4, 5)
-    say("K = 32 vs K = 1")
-    r32 = sampler(pos, 12.0, 0.3, 0.015, 32, 9).sample().cpu().numpy()
-    r1 = sampler(pos, 12.0, 0.3, 0.015, 1, 9).sample().cpu().numpy()
-    np.testing.assert_array_equal(r32[0], r1[0])
+    say("K = 32 vs 32 calls of K = 1")
+    big = sampler(pos, 12.0, 0.3, 0.015, 32, 9)
+    r32 = big.sample(want_labels=True).cpu().numpy()
+    t32 = {k: v.cpu().numpy() for k, v in big.groups(2).items() if k != "cap"}
+    for s in (0, 1, 17, 31):
+        one = sampler(pos, 12.0, 0.3, 0.015, 1, 9, s_first=s)
+        r1 = one.sample(want_labels=True).cpu().numpy()
+        np.testing.assert_array_equal(r32[s], r1[0])
+        t1 = one.groups(2, cap=t32["sizes"].shape[1])
+        G = int(t1["n_groups"][0])
+        assert G == t32["n_groups"][s]
+        np.testing.assert_array_equal(t1["sizes"][0, :G].cpu().numpy(), t32["sizes"][s, :G])
+        np.testing.assert_allclose(t1["com"][0, :G].cpu().numpy(), t32["com"][s, :G],
+                                   rtol=1e-12, atol=1e-9)
 
 
 def test_edge_capacity_overflow_sets_status():
@@ -96,6 +133,46 @@ def test_edge_capacity_overflow_sets_status():
     smp.sample()
     _, _, _, total = smp.edges()
     assert total > 10 and smp.plan.status() & 4
+
+
+def test_group_table_overflow_sets_status_and_keeps_counts():
+    from paper_2510_26851_amd import _lib
+
+    pos = W.clumpy_box(6000, 10.0, 5, 8)
+    say("sampled group table overflow")
+    smp = sampler(pos, 10.0, 0.3, 0.015, 4, 3)
+    smp.sample()
+    full = smp.groups(2)
+    ng = full["n_groups"].cpu().numpy()
+    assert smp.plan.status() == 0 and ng.min() > 3
+    small = smp.groups(2, cap=3)
+    assert smp.plan.status() & _lib.FOF_STATUS_OVERFLOW
+    np.testing.assert_array_equal(small["n_groups"].cpu().numpy(), ng)
+    np.testing.assert_array_equal(small["sizes"].cpu().numpy(), full["sizes"][:, :3].cpu().numpy())
+
+
+def test_coincident_particles_give_a_finite_gradient():
+    """Two particles at one point form an edge with d = 0: its direction is undefined, and the
+    estimator gives it no position gradient, like the oracle."""
+    import torch
+
+    pos = W.clumpy_box(2000, 8.0, 3, 12)
+    pos[1] = pos[0]
+    pos[7] = pos[5]
+    L, b, tau, K, seed = 8.0, 0.3, 0.015, 16, 77
+    smp = sampler(pos, L, b, tau, K, seed)
+    smp.sample()
+    oei, oej, od2 = RF.candidate_edges(pos, L, b + 10 * tau)
+    assert (od2 == 0.0).sum() >= 2
+    p = RF.edge_prob(od2, b, tau)
+    oroot, keep = RF.sample_labels(pos.shape[0], oei, oej, p, seed, K)
+    ref_losses = np.array([RF.loss_sum_sq(r, 2) for r in oroot])
+    g = smp.grad(torch.from_numpy(ref_losses), "loo").cpu().numpy()
+    assert np.isfinite(g).all()
+    delta, d = RF.edge_geometry(pos, L, oei, oej)
+    ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, tau, keep, ref_losses, "loo")
+    assert np.isfinite(ref).all()
+    assert np.abs(g - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1e-30)
 
 
 def test_estimator_mean_matches_enumeration():
@@ -114,7 +191,7 @@ def test_estimator_mean_matches_enumeration():
     ests = []
     for rep in range(reps):
         smp = Sampler(t, L, b, tau, K, 5000 + rep)
-        root = smp.sample()
+        root = smp.sample(want_labels=True)
         losses = torch.tensor([lossf(r) for r in root.cpu().numpy()], dtype=torch.float64)
         ests.append(smp.grad(losses, "loo").cpu().numpy().astype(np.float64))
     ests = np.array(ests)
@@ -125,7 +202,8 @@ def test_estimator_mean_matches_enumeration():
 @pytest.mark.parametrize("alpha,which", [(5.0, "clumpy"), (0.5, "uniform")])
 def test_quadratic_form_matches_oracle(alpha, which):
     """The paper's Bernoulli form p = sigmoid(alpha (b^2 - d^2) / b^2): candidate edges, sampled
-    labels and the score gradient against the oracle (alpha 5 and 0.5 as in Sec. 3.2)."""
+    labels, per-sample halos and the score gradient against the oracle (alpha 5 and 0.5 as in
+    Sec. 3.2)."""
     import torch
     from paper_2510_26851_amd.reinforce import Sampler, sum_sq_sizes
 
@@ -138,7 +216,8 @@ def test_quadratic_form_matches_oracle(alpha, which):
     say(f"reinforce quadratic form alpha={alpha} {which}: n={pos.shape[0]} r_c={r_c:.3f}")
     smp = Sampler(torch.from_numpy(pos).cuda(), L, b, None, K, seed, alpha=alpha)
     assert smp.r_cut == r_c
-    root = smp.sample()
+    root = smp.sample(want_labels=True)
+    halos = smp.groups(2)
     ei, ej, d2, total = smp.edges()
     torch.cuda.synchronize()
     assert smp.plan.status() == 0 and total == ei.shape[0] > 0
@@ -152,7 +231,9 @@ def test_quadratic_form_matches_oracle(alpha, which):
         u = np.array([[RF.uniform(seed, s, a, c) for a, c in zip(oei, oej)] for s in mism])
         near = np.abs(u - p[None, :]) <= 8 * 2.0 ** -53
         pytest.fail(f"samples {mism.tolist()} differ; near ties there: {int(near.sum())}")
-    losses = sum_sq_sizes(root, 2)
+    spacing = float(np.cbrt(L ** 3 / pos.shape[0]))
+    check_tables(halos, pos, L, oroot, 2, spacing)
+    losses = sum_sq_sizes(halos)
     g = smp.grad(losses, baseline="loo").cpu().numpy()
     delta, d = RF.edge_geometry(pos, L, oei, oej)
     ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, None, keep,

@@ -157,3 +157,14 @@ def test_subhalo_sizes_that_disagree_with_the_ids():
     h0 = gid == 0
     assert np.sum(sub[h0] == -1) == 3
     np.testing.assert_array_equal(sub[~h0], want[~h0])
+    # a negative size: that host's members are dropped (flagged), the host ranges after it
+    # do not move backwards, and every other host stays exact
+    neg = res["sizes"].clone()
+    neg[1] = -7
+    plan.build_grid(tp)   # clears the status word
+    sub = plan.subhalo(tp, tv, res["group_id"], G, neg, nx, nv, 1.0).cpu().numpy()
+    torch.cuda.synchronize()
+    assert plan.status() & _lib.FOF_STATUS_RANGE
+    h1 = gid == 1
+    assert np.all(sub[h1] == -1)
+    np.testing.assert_array_equal(sub[~h1], want[~h1])

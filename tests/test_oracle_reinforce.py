@@ -250,3 +250,37 @@ def test_quadratic_estimator_is_unbiased():
     se = ests.std(axis=0, ddof=1) / np.sqrt(reps)
     z = np.abs(ests.mean(axis=0) - g_exact) / np.maximum(se, 1e-12)
     assert np.all(z < 4.5), z.max()
+
+
+def test_coincident_pair_gradient_is_finite_and_matches_central_differences():
+    """Two particles at one point: d = 0 has no direction, and the distance form's estimator
+    gives that edge no gradient.  Central differences with a dyadic step see the same: moving
+    either particle by +-h gives the same d = h on both sides, so that edge's part of E[L]
+    cancels exactly."""
+    pos = np.array([[2.0, 2.0, 2.0], [2.0, 2.0, 2.0], [2.3, 2.0, 2.0], [2.0, 2.3, 2.0]],
+                   np.float32)
+    L, b, tau = 8.0, 0.32, 0.02
+    r_c = b + 10 * tau
+    lossf = lambda root: RF.loss_sum_sq(root, 2)
+    ei, ej, d2 = RF.candidate_edges(pos, L, r_c)
+    assert ei.shape[0] == 6 and d2.min() == 0.0
+    EL, g = RF.enumerate_gradient(pos, L, b, tau, r_c, lossf)
+    assert np.isfinite(g).all()
+    h = 2.0 ** -12
+    for i in range(pos.shape[0]):
+        for a in range(3):
+            p1, p2 = pos.copy(), pos.copy()
+            p1[i, a] += np.float32(h)
+            p2[i, a] -= np.float32(h)
+            den = float(p1[i, a]) - float(p2[i, a])
+            assert den == 2 * h
+            fd = (RF.expected_loss(p1, L, b, tau, r_c, lossf) -
+                  RF.expected_loss(p2, L, b, tau, r_c, lossf)) / den
+            assert abs(fd - g[i, a]) <= 1e-3 * max(abs(g).max(), 1e-9), (i, a, fd, g[i, a])
+    # the estimator on sampled graphs stays finite too
+    delta, d = RF.edge_geometry(pos, L, ei, ej)
+    p = RF.edge_prob(d2, b, tau)
+    root, keep = RF.sample_labels(4, ei, ej, p, 7, 16)
+    losses = [lossf(r) for r in root]
+    est = RF.score_gradient(4, ei, ej, delta, d, p, tau, keep, losses, "loo")
+    assert np.isfinite(est).all()

@@ -265,10 +265,38 @@ def config4(nbox: int = 256, n_lo: int = 16 ** 3, n_hi: int = 128 ** 3) -> list:
     return boxes
 
 
-def make(cfg: int, progress=None):
+def make(cfg: int, progress=None, cache_dir=None):
+    """Configuration `cfg` (0-5).  With `cache_dir`, single-box configurations are stored
+    there as .npy files on first use and loaded afterwards (drawing 512^3 takes minutes)."""
+    if cache_dir and cfg != 4:
+        return _cached(cfg, progress, cache_dir)
     if cfg == 5:
         return config5(progress)
     return {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}[cfg]()
+
+
+def _cached(cfg: int, progress, cache_dir) -> Box:
+    import json
+
+    stem = os.path.join(cache_dir, f"config{cfg}")
+    try:
+        with open(stem + ".json") as f:
+            meta = json.load(f)
+        pos = np.load(stem + ".pos.npy", mmap_mode=None)
+        vel = np.load(stem + ".vel.npy") if meta["has_vel"] else None
+        _say(progress, f"loaded {stem}")
+        return Box(pos, tuple(meta["L"]), meta["b"], meta["min_size"], vel=vel, name=meta["name"])
+    except (OSError, ValueError, KeyError):
+        pass
+    box = make(cfg, progress)
+    os.makedirs(cache_dir, exist_ok=True)
+    np.save(stem + ".pos.npy", box.pos)
+    if box.vel is not None:
+        np.save(stem + ".vel.npy", box.vel)
+    with open(stem + ".json", "w") as f:
+        json.dump(dict(L=list(box.L), b=box.b, min_size=box.min_size, name=box.name,
+                       has_vel=box.vel is not None), f)
+    return box
 
 
 # --------------------------------------------------------------------------------------
