@@ -38,13 +38,15 @@
  *                    uniforms drawn from Philox4x64-10 keyed by a seed and counted by
  *                    (edge, sample) so that any implementation can reproduce them.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no -ffast-math: IEEE round-to-nearest,
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no -ffast-math: IEEE round-to-nearest,
  * no contraction, denormals kept).
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#include <omp.h>
 
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
@@ -307,6 +309,178 @@ int64_t oracle_fof(int64_t n, const float *pos, const double *L, double b, int32
     cells_free(&c);
     return ctx.nlinks;
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* Multi-threaded labels (OpenMP): the same definition, for full-size checks and the CPU   */
+/* baseline.  Three steps, each a parallel form of the serial one above:                 */
+/*   1. the cell list: records are dealt into one bucket per z-layer of cells (the key's  */
+/*      slowest axis, so bucket order is key order) and each bucket is sorted on its own; */
+/*      the result is the serial (key, index) order exactly;                              */
+/*   2. the pair enumeration of the serial oracle, over cells in parallel;                */
+/*   3. each friend pair is merged into one shared union-find whose roots only ever move  */
+/*      to a smaller index (a root is re-pointed by compare-and-swap, and only while it is */
+/*      still a root), so every tree's root is its smallest member whatever the order of  */
+/*      the merges, and root[i] equals the serial result.                                  */
+/* ------------------------------------------------------------------------------------ */
+
+static int32_t ufa_find(int32_t *parent, int32_t i)
+{
+    for (;;) {
+        int32_t p = __atomic_load_n(parent + i, __ATOMIC_RELAXED);
+        if (p == i)
+            return i;
+        int32_t g = __atomic_load_n(parent + p, __ATOMIC_RELAXED);
+        if (g == p)
+            return p;
+        /* i is not a root and never becomes one again: pointing it at an ancestor is safe */
+        __atomic_store_n(parent + i, g, __ATOMIC_RELAXED);
+        i = g;
+    }
+}
+
+static void ufa_union(int32_t *parent, int32_t i, int32_t j)
+{
+    for (;;) {
+        int32_t ri = ufa_find(parent, i);
+        int32_t rj = ufa_find(parent, j);
+        if (ri == rj)
+            return;
+        if (ri > rj) {
+            int32_t t = ri;
+            ri = rj;
+            rj = t;
+        }
+        int32_t expect = rj;  /* the larger root goes under the smaller, if still a root */
+        if (__atomic_compare_exchange_n(parent + rj, &expect, ri, 0, __ATOMIC_RELAXED,
+                                        __ATOMIC_RELAXED))
+            return;
+        i = ri;
+        j = rj;
+    }
+}
+
+static int cells_build_par(cell_list *c, int64_t n, const float *pos, const double *L, double r)
+{
+    memset(c, 0, sizeof(*c));
+    c->n = n;
+    for (int a = 0; a < 3; ++a) {
+        double q = floor((L[a] / r) * (1.0 - ldexp(1.0, -20)));
+        c->nc[a] = q < 1.0 ? 1 : (int64_t)q;
+    }
+    const int64_t nb = c->nc[2];
+    keyed *tmp = (keyed *)malloc((size_t)(n > 0 ? n : 1) * sizeof(keyed));
+    int64_t *bstart = (int64_t *)calloc((size_t)nb + 1, sizeof(int64_t));
+    c->rec = (keyed *)malloc((size_t)(n > 0 ? n : 1) * sizeof(keyed));
+    c->ukey = (uint64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint64_t));
+    c->ustart = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    if (!tmp || !bstart || !c->rec || !c->ukey || !c->ustart) {
+        free(tmp);
+        free(bstart);
+        cells_free(c);
+        return ORC_ENOMEM;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t ix[3];
+        for (int a = 0; a < 3; ++a) {
+            double t = floor(((double)pos[3 * i + a] * (double)c->nc[a]) / L[a]);
+            int64_t k = (int64_t)t;
+            if (k > c->nc[a] - 1)
+                k = c->nc[a] - 1;
+            if (k < 0)
+                k = 0;
+            ix[a] = k;
+        }
+        tmp[i].key = (uint64_t)((ix[2] * c->nc[1] + ix[1]) * c->nc[0] + ix[0]);
+        tmp[i].idx = i;
+    }
+    /* one bucket per z-layer; records keep index order inside a bucket */
+    const uint64_t layer = (uint64_t)(c->nc[0] * c->nc[1]);
+    for (int64_t i = 0; i < n; ++i)
+        bstart[tmp[i].key / layer + 1]++;
+    for (int64_t z = 0; z < nb; ++z)
+        bstart[z + 1] += bstart[z];
+    int64_t *cur = (int64_t *)malloc((size_t)(nb > 0 ? nb : 1) * sizeof(int64_t));
+    if (!cur) {
+        free(tmp);
+        free(bstart);
+        cells_free(c);
+        return ORC_ENOMEM;
+    }
+    memcpy(cur, bstart, (size_t)nb * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i)
+        c->rec[cur[tmp[i].key / layer]++] = tmp[i];
+    free(cur);
+    free(tmp);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t z = 0; z < nb; ++z)
+        qsort(c->rec + bstart[z], (size_t)(bstart[z + 1] - bstart[z]), sizeof(keyed), cmp_keyed);
+    free(bstart);
+    int64_t nu = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (i == 0 || c->rec[i].key != c->rec[i - 1].key) {
+            c->ukey[nu] = c->rec[i].key;
+            c->ustart[nu] = i;
+            ++nu;
+        }
+    }
+    c->ustart[nu] = n;
+    c->nu = nu;
+    return ORC_OK;
+}
+
+/* root[i] = smallest index in the component of i, with `threads` OpenMP threads (0: the
+ * runtime's default).  Same result as oracle_fof; returns the number of links or a negative
+ * error code. */
+int64_t oracle_fof_par(int64_t n, const float *pos, const double *L, double b, int32_t *root,
+                       int threads)
+{
+    int rc = check_args(n, pos, L, b);
+    if (rc)
+        return rc;
+    if (threads > 0)
+        omp_set_num_threads(threads);
+    cell_list c;
+    rc = cells_build_par(&c, n, pos, L, b);
+    if (rc)
+        return rc;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        root[i] = (int32_t)i;
+    const double b2 = b * b;
+    int64_t nlinks = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nlinks)
+    for (int64_t u = 0; u < c.nu; ++u) {
+        uint64_t nb[27];
+        int m = cells_neighbours(&c, c.ukey[u], nb);
+        for (int q = 0; q < m; ++q) {
+            if (nb[q] < c.ukey[u])
+                continue;
+            int64_t v = cells_find(&c, nb[q]);
+            if (v < 0)
+                continue;
+            for (int64_t a = c.ustart[u]; a < c.ustart[u + 1]; ++a) {
+                const int64_t i = c.rec[a].idx;
+                int64_t b0 = (v == u) ? a + 1 : c.ustart[v];
+                for (int64_t bb = b0; bb < c.ustart[v + 1]; ++bb) {
+                    const int64_t j = c.rec[bb].idx;
+                    if (oracle_dist2(pos + 3 * i, pos + 3 * j, L) < b2) {
+                        ufa_union(root, (int32_t)i, (int32_t)j);
+                        nlinks++;
+                    }
+                }
+            }
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        root[i] = ufa_find(root, (int32_t)i);
+    cells_free(&c);
+    return nlinks;
+}
+
+/* Threads the OpenMP runtime uses by default (what oracle_fof_par(..., 0) runs with). */
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------------------ */
 /* Component of one particle (breadth-first search through the cell list), for sampled   */

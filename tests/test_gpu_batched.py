@@ -52,7 +52,7 @@ def check_against_oracle(boxes, root, res, min_size, which):
         bx = boxes[k]
         sl = slice(offs[k], offs[k + 1])
         if k in which:
-            ref, _ = oracle.fof(bx.pos, bx.L, bx.b)
+            ref, _ = oracle.fof_par(bx.pos, bx.L, bx.b)
             np.testing.assert_array_equal(root[sl] - offs[k], ref)
             g = oracle.groups(bx.pos, ref, bx.L, min_size)
             local = gid[sl]
@@ -85,15 +85,12 @@ def test_small_batch_mixed_sizes():
 
 @pytest.mark.slow
 def test_config4_batch_of_256_boxes():
+    """All 256 boxes of the batched workload in one plan, every box against the oracle."""
     boxes = W.config4()
     n = sum(bx.n for bx in boxes)
     say(f"config4: {len(boxes)} boxes, {n} particles")
     root, res = run_batch(boxes, 20)
-    rng = np.random.default_rng(0)
-    # the oracle on a sample of boxes: the 6 smallest, the largest and 9 at random
-    order = np.argsort([bx.n for bx in boxes])
-    which = set(order[:6].tolist()) | {int(order[-1])} | set(rng.choice(len(boxes), 9, replace=False).tolist())
-    check_against_oracle(boxes, root, res, 20, which)
+    check_against_oracle(boxes, root, res, 20, set(range(len(boxes))))
     # labels are canonical everywhere: root[root[i]] == root[i] and root[i] <= i
     idx = np.arange(root.shape[0])
     assert np.all(root <= idx) and np.all(root[root] == root)

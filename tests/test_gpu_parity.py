@@ -190,17 +190,22 @@ def test_overflow_paths_of_the_tiled_link(tune):
 
 def test_grid_over_2_27_cells_takes_the_per_particle_binning():
     """A grid of more than 2^27 cells is binned with one rank atomic per particle instead of
-    the bucketed counting sort.  Labels do not depend on the cell side, so a run with such a
-    grid must match, bit for bit, a run of the same particles at the default side (which is
-    binned through buckets and checked against the oracle above)."""
+    the bucketed counting sort (the path a 1024^3 box takes).  Every label, group id, size
+    and centre of mass of the 17M-particle box against the oracle run on the whole box,
+    for that grid and for the default one (bucketed)."""
     import torch
     from paper_2510_26851_amd import Plan, trim
+
+    from gpu_util import com_close
 
     n, L = 17_000_000, 256.0
     b = W.linking_length(0.2, L, n)
     pos = W.clumpy_box(n, L, 4000, 51)
+    say(f"per-particle binning: oracle on n={n}")
+    ref_root, _ = oracle.fof_par(pos, L, b)
+    ref = oracle.groups(pos, ref_root, L, 20)
+    assert ref["n_groups"] > 0
     t = torch.from_numpy(pos).to("cuda:0")
-    runs = []
     for side, over in [(0.25, True), (0.0, False)]:
         say(f"per-particle binning check: n={n} cell_side={side}")
         plan = Plan([n], [(L, b)], device=t.device, tune=dict(cell_side=side))
@@ -210,16 +215,12 @@ def test_grid_over_2_27_cells_takes_the_per_particle_binning():
         res = trim(plan.groups(20))
         torch.cuda.synchronize()
         assert plan.status() == 0
-        runs.append((root.cpu().numpy(),
-                     {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}))
+        np.testing.assert_array_equal(root.cpu().numpy(), ref_root)
+        assert res["n_groups"] == ref["n_groups"]
+        np.testing.assert_array_equal(res["group_id"].cpu().numpy(), ref["group_id"])
+        np.testing.assert_array_equal(res["sizes"].cpu().numpy(), ref["sizes"])
+        assert com_close(res["com"].cpu().numpy(), ref["com"], L, L / n ** (1 / 3))
         del plan, root, res
-    (r0, g0), (r1, g1) = runs
-    np.testing.assert_array_equal(r0, r1)
-    assert g0["n_groups"] == g1["n_groups"] > 0
-    np.testing.assert_array_equal(g0["group_id"], g1["group_id"])
-    np.testing.assert_array_equal(g0["sizes"], g1["sizes"])
-    from gpu_util import com_close
-    assert com_close(g0["com"], g1["com"], L, L / n ** (1 / 3))
 
 
 @pytest.mark.parametrize("n", [5000, 40000])

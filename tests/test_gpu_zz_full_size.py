@@ -1,9 +1,10 @@
 """Full size: the 512^3 Zel'dovich box with 50,000 NFW clumps that bench.py measures, run in
-the same launch configuration (default tuning, helper stream), checked by properties that
-hold at any size and, on 200 seeded particles (half of them in groups), against the oracle's
-exact single-component search over the whole box.  (Collected last: it takes about two
-minutes, most of it generating the box and indexing it for the oracle.)  The same check at
-1024^3 runs only when FOF_TEST_1024=1 is set."""
+the same launch configuration (default tuning, helper stream when the package made one), and
+compared, label by label, group by group, with the oracle run on the whole box (its
+multi-threaded form, pinned to the serial one in test_oracle_par.py).  Collected last: it
+takes about a minute, most of it drawing the box and running the oracle.  The same pipeline
+at 1024^3 runs only when FOF_TEST_1024=1 is set, checked there by properties at any size
+and a 16.8M-particle slab against the oracle."""
 import os
 
 import numpy as np
@@ -24,7 +25,14 @@ def _gpu():
 
 
 def test_full_size_zeldovich_nfw_512():
-    check_full_size(W.make(2))
+    """Every label, group id, size and centre of mass of all 134,217,728 particles."""
+    from gpu_util import compare_with_oracle
+
+    box = W.make(2)
+    say(f"full size {box.name}: oracle on n={box.n}")
+    ref_root, _ = oracle.fof_par(box.pos, box.L, box.b)
+    say("oracle done; GPU")
+    compare_with_oracle(box.pos, box.L, box.b, box.min_size, root_ref=ref_root)
 
 
 @pytest.mark.skipif(os.environ.get("FOF_TEST_1024") != "1",
@@ -134,4 +142,5 @@ def test_zeldovich_256_against_the_full_oracle():
 
     box = W.make(1)
     say(f"full oracle comparison {box.name}: n={box.n}")
-    compare_with_oracle(box.pos, box.L, box.b, box.min_size)
+    ref_root, _ = oracle.fof_par(box.pos, box.L, box.b)
+    compare_with_oracle(box.pos, box.L, box.b, box.min_size, root_ref=ref_root)
