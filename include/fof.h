@@ -288,6 +288,29 @@ int fof_status(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes,
  * index 64 or above). */
 int fof_init(void);
 
+/* For callers that cannot allocate device memory: code under hipGraph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  One box, the whole labelling pipeline of
+ * fof_build_grid + fof_link + fof_groups (same kernels, same results) with the workspace in a
+ * static device array of FOF_STATIC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends, so the call needs no `ws` and allocates nothing.
+ * box, tune: host, as for fof_workspace_bytes (one box of n particles).  pos, vel, root,
+ * group_id, n_groups, sizes, com, vmean, sigv: as for fof_build_grid, fof_link and fof_groups
+ * (dev, caller-owned).  status (dev, one int32) receives the device status word
+ * (FOF_STATUS_* bits) at the end of the call; read it after synchronising.
+ * Errors: FOF_ENOMEM when the plan's workspace exceeds FOF_STATIC_SCRATCH_BYTES (about
+ * 73 bytes per particle: up to roughly 2.2 million particles), FOF_EINVAL as for the calls it
+ * combines, FOF_EDEVICE, FOF_ENOTSUP (device index 64 or above).
+ * Every call on one device shares that device's array, which keeps the last call's
+ * contents: calls that overlap on one device (different streams or threads) race and must
+ * be ordered by the caller.  Runs on `stream` only (no helper stream). */
+#define FOF_STATIC_SCRATCH_BYTES ((size_t)160 << 20)
+int fof_find_groups_static(const fof_box *box /*host*/, int64_t n,
+                           const fof_tune *tune /*host, may be NULL*/, const float *pos /*dev*/,
+                           int32_t min_size, const float *vel /*dev or NULL*/, int32_t cap,
+                           int32_t *root, int32_t *group_id, int32_t *n_groups, int32_t *sizes,
+                           double *com, double *vmean, double *sigv, int32_t *status /*dev*/,
+                           void *stream);
+
 /* Static text for a FOF_E* code. */
 const char *fof_strerror(int code);
 

@@ -40,7 +40,9 @@ def sample_scratch_bytes(n: int, K: int, edge_cap: int) -> int:
 # Every symbol include/fof.h declares.
 EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",
            "fof_group_dispersion", "fof_backward_dispersion", "fof_subhalo_scratch_bytes",
-           "fof_subhalo", "fof_status", "fof_strerror", "fof_last_device_error", "fof_init")
+           "fof_subhalo", "fof_status", "fof_strerror", "fof_last_device_error", "fof_init",
+           "fof_find_groups_static")
+FOF_STATIC_SCRATCH_BYTES = 160 << 20
 
 
 class fof_box(ctypes.Structure):
@@ -116,6 +118,7 @@ def load():
     L.fof_strerror.restype = ctypes.c_char_p
     L.fof_last_device_error.argtypes = [ctypes.POINTER(ctypes.c_char_p)]
     L.fof_init.argtypes = []
+    L.fof_find_groups_static.argtypes = [P, i64, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P]
     for f in EXPORTS:
         if f != "fof_strerror":
             getattr(L, f).restype = ctypes.c_int

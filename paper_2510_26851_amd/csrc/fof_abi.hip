@@ -257,6 +257,57 @@ std::mutex g_side_lock;
 // clear it so that only this call's launches are reported.
 void clear_stale_error() { (void)hipGetLastError(); }
 
+// Device addresses of the static workspace (`scratch` below), one per device: the array's
+// host-side name is only a stand-in, so kernels get the address the runtime reports for
+// the current device.  Looked up once per device, under the lock.
+void *g_scratch[kMaxDevices];
+std::mutex g_scratch_lock;
+
+// Descriptor block of a one-box plan, written into the static workspace by a kernel whose
+// argument carries it (no host copy, nothing allocated).
+__global__ void k_put_desc(BoxDesc d, BoxDesc *dst)
+{
+    if (threadIdx.x == 0)
+        *dst = d;
+}
+
+__global__ void k_copy_status(const Counters *ctr, int32_t *status)
+{
+    if (threadIdx.x == 0)
+        *status = ctr->status;
+}
+
+}  // namespace
+}  // namespace fof
+
+// Workspace of fof_find_groups_static: one copy per device, held until the process ends.
+static __device__ __align__(256) unsigned char scratch[FOF_STATIC_SCRATCH_BYTES];
+
+namespace fof {
+namespace {
+
+// The current device's address of `scratch`, found with hipGetSymbolAddress on first use.
+int static_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+        return FOF_EDEVICE;
+    if (dev >= kMaxDevices)
+        return FOF_ENOTSUP;
+    std::lock_guard<std::mutex> hold(g_scratch_lock);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return dev_err(e);
+        if (!p || ((uintptr_t)p % kAlign) != 0)
+            return FOF_EDEVICE;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return FOF_OK;
+}
+
 }  // namespace
 }  // namespace fof
 
@@ -534,6 +585,9 @@ int fof_init(void)
         return FOF_EDEVICE;
     if (dev >= kMaxDevices)
         return FOF_ENOTSUP;
+    void *sp = nullptr;
+    if (int rc = static_scratch(&sp))
+        return rc;
     std::lock_guard<std::mutex> hold(g_side_lock);
     if (g_side_ok[dev])
         return FOF_OK;
@@ -549,6 +603,43 @@ int fof_init(void)
         return dev_err(e);
     g_side_ok[dev] = true;
     return FOF_OK;
+}
+
+int fof_find_groups_static(const fof_box *box, int64_t n, const fof_tune *tune,
+                           const float *pos, int32_t min_size, const float *vel, int32_t cap,
+                           int32_t *root, int32_t *group_id, int32_t *n_groups, int32_t *sizes,
+                           double *com, double *vmean, double *sigv, int32_t *status,
+                           void *stream)
+{
+    if (!box || n < 0 || !n_groups || !status || cap < 0 || (cap > 0 && (!sizes || !com)) ||
+        (n > 0 && (!pos || !root || !group_id)))
+        return FOF_EINVAL;
+    if ((vmean == nullptr) != (sigv == nullptr) || (vel == nullptr && vmean != nullptr))
+        return FOF_EINVAL;
+    fof_grid grid;
+    BoxDesc desc;
+    if (int rc = fof_workspace_bytes(1, &n, box, tune, &grid, &desc, sizeof(desc)))
+        return rc;
+    if (grid.ws_bytes > (size_t)FOF_STATIC_SCRATCH_BYTES)
+        return FOF_ENOMEM;
+    void *ws = nullptr;
+    if (int rc = static_scratch(&ws))
+        return rc;
+    const hipStream_t s = (hipStream_t)stream;
+    Work w = resolve(&grid, ws);
+    clear_stale_error();
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, desc,
+                       (BoxDesc *)((char *)ws + grid.off_desc));
+    hipError_t e = launch_build(w, pos, s);
+    if (e == hipSuccess)
+        e = launch_link(w, root, s, nullptr);
+    if (e == hipSuccess)
+        e = launch_groups(w, min_size, vel, cap, group_id, n_groups, sizes, com, vmean, sigv, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, w.ctr, status);
+        e = hipGetLastError();
+    }
+    return dev_err(e);
 }
 
 int fof_last_device_error(const char **name)

@@ -356,3 +356,37 @@ def test_plan_counts_the_particles_of_boxes_without_tiles():
     t.flags = _lib.FOF_TUNE_NO_TILES
     rc, g, _ = plan([100, 40000], [(3.0, 0.4), (40.0, 0.4)], tune=t)
     assert rc == 0 and g.n_plain == 40100 and g.ntiles == 0
+
+
+def test_static_workspace_call_rejects_before_launch():
+    """fof_find_groups_static checks its arguments and the plan's size against the static
+    workspace on the host, before it touches a device."""
+    L = lib()
+    box = _lib.fof_box((ctypes.c_double * 3)(64.0, 64.0, 64.0), 0.4)
+    bp = ctypes.byref(box)
+    p = ctypes.c_void_p(0x100000)            # never dereferenced: every call below fails first
+    args = lambda n, **kw: [kw.get("box", bp), n, None, kw.get("pos", p), 20, kw.get("vel"),
+                            kw.get("cap", 10), kw.get("root", p), kw.get("gid", p),
+                            kw.get("ng", p), kw.get("sizes", p), kw.get("com", p),
+                            kw.get("vmean"), kw.get("sigv"), kw.get("status", p), None]
+    f = L.fof_find_groups_static
+    assert f(*args(100, box=None)) == _lib.FOF_EINVAL
+    assert f(*args(-1)) == _lib.FOF_EINVAL
+    assert f(*args(100, pos=None)) == _lib.FOF_EINVAL
+    assert f(*args(100, root=None)) == _lib.FOF_EINVAL
+    assert f(*args(100, gid=None)) == _lib.FOF_EINVAL
+    assert f(*args(100, ng=None)) == _lib.FOF_EINVAL
+    assert f(*args(100, status=None)) == _lib.FOF_EINVAL
+    assert f(*args(100, cap=-1)) == _lib.FOF_EINVAL
+    assert f(*args(100, com=None)) == _lib.FOF_EINVAL
+    assert f(*args(100, vmean=p)) == _lib.FOF_EINVAL                   # vmean without vel
+    assert f(*args(100, vel=p, vmean=p)) == _lib.FOF_EINVAL            # sigv missing
+    bad = _lib.fof_box((ctypes.c_double * 3)(64.0, 64.0, 64.0), 40.0)  # 2b > L
+    assert f(*args(100, box=ctypes.byref(bad))) == _lib.FOF_EINVAL
+    # a plan larger than the static workspace: refused on the host
+    big = _lib.fof_box((ctypes.c_double * 3)(512.0, 512.0, 512.0), 0.2)
+    assert f(*args(3_000_000, box=ctypes.byref(big))) == _lib.FOF_ENOMEM
+    cnt = (ctypes.c_int64 * 1)(3_000_000)
+    g = _lib.fof_grid()
+    assert L.fof_workspace_bytes(1, cnt, ctypes.byref(big), None, ctypes.byref(g), None, 0) == 0
+    assert g.ws_bytes > _lib.FOF_STATIC_SCRATCH_BYTES
