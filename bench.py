@@ -73,9 +73,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(box, zmax):
-    """The oracle as it stands, single-threaded, on the particles with z < zmax treated as a
-    periodic L x L x zmax box (same density, clumps and linking length)."""
+    """The oracle as it stands on the particles with z < zmax, treated as a periodic
+    L x L x zmax box (same density, clumps and linking length): labels + groups, first with
+    the multi-threaded labelling (OpenMP, the runtime's default thread count), then
+    single-threaded."""
     import numpy as np
 
     import oracle
@@ -83,14 +96,26 @@ def cpu_baseline(box, zmax):
     sel = box.pos[:, 2] < np.float32(zmax)
     pos = np.ascontiguousarray(box.pos[sel])
     L = (box.L[0], box.L[1], float(zmax))
+    threads = oracle.max_threads()
     t0 = time.perf_counter()
-    root, _ = oracle.fof(pos, L, box.b)
+    root, _ = oracle.fof_par(pos, L, box.b)
     oracle.groups(pos, root, L, box.min_size)
-    dt = time.perf_counter() - t0
-    return dict(value=pos.shape[0] / dt / 1e6, unit="Mparticles/s", cores=1, kind="oracle",
-                seconds=round(dt, 3),
+    dt_par = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    root1, _ = oracle.fof(pos, L, box.b)
+    oracle.groups(pos, root1, L, box.min_size)
+    dt1 = time.perf_counter() - t0
+    if not np.array_equal(root, root1):
+        raise SystemExit("the two oracle forms disagree")
+    return dict(value=pos.shape[0] / dt_par / 1e6, unit="Mparticles/s", cores=threads,
+                kind="oracle", seconds=round(dt_par, 3), cpu=cpu_model(),
+                affinity_cpus=len(os.sched_getaffinity(0)),
+                single_thread={"value": pos.shape[0] / dt1 / 1e6, "cores": 1,
+                               "seconds": round(dt1, 3)},
                 sample=f"particles with z < {zmax} of the same box ({pos.shape[0]}), "
-                       f"treated as a periodic {L[0]:g}x{L[1]:g}x{L[2]:g} box; labels + groups")
+                       f"treated as a periodic {L[0]:g}x{L[1]:g}x{L[2]:g} box; labels "
+                       f"(pair enumeration on {threads} OpenMP threads, shared union-find) "
+                       f"+ groups (serial)")
 
 
 def copy_bandwidth(torch, dev, nbytes=2 << 30):
@@ -177,6 +202,134 @@ def reinforce_rate(torch, dev, reps):
             "timed": "batched: fof_link(sample K=64) + fof_groups(sample) + loss from the halo "
                      "tables + fof_backward(FOF_SCORE); sequential: 64 x [fof_link(sample K=1, "
                      "s_first=k) + fof_groups(sample) + loss] + one fof_backward(FOF_SCORE)"}
+
+
+def batched_rate(torch, dev, reps, tune=None):
+    """The batched workload: 256 periodic boxes of log-uniform sizes (16^3 to 128^3 particles,
+    clumped, b = 0.2 mean spacing per box, min size 20).  Three forms of the same pipeline
+    (fof_build_grid + fof_link + fof_groups), timed with HIP events on the launch stream:
+      graph:   the whole batch as one plan, captured once in a hipGraph and replayed;
+      batched: the same plan launched eagerly;
+      looped:  one plan per box, the boxes one after another (the single-box path).
+    The looped labels and group counts must equal the batched ones exactly.  Unless given,
+    the tuning (cell size per box spacing, dense threshold, block) is the autotuner's choice
+    for this batch."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2510_26851_amd import Plan
+
+    from paper_2510_26851_amd.tune import autotune_batch
+
+    boxes = W.config4()
+    counts = [bx.n for bx in boxes]
+    n = int(sum(counts))
+    pos = torch.from_numpy(np.concatenate([bx.pos for bx in boxes])).to(dev)
+    if tune is None:  # tuned on this input (no cache), the same choice for every form
+        t0 = time.perf_counter()
+        tune = autotune_batch(pos, counts, [(bx.L, bx.b) for bx in boxes], 20, cache=None,
+                              reps=2)
+        log(f"batch tuned in {time.perf_counter() - t0:.1f}s: {tune}")
+    plan = Plan(counts, [(bx.L, bx.b) for bx in boxes], device=dev, tune=tune)
+    root = torch.empty(n, dtype=torch.int32, device=dev)
+    out = dict(group_id=torch.empty(n, dtype=torch.int32, device=dev),
+               n_groups=torch.empty(1, dtype=torch.int32, device=dev),
+               sizes=torch.empty(n, dtype=torch.int32, device=dev),
+               com=torch.empty((n, 3), dtype=torch.float64, device=dev))
+
+    def step():
+        plan.build_grid(pos)
+        plan.link(root)
+        plan.groups(20, out=out)
+
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    views = [pos[offs[k]:offs[k + 1]] for k in range(len(boxes))]
+    plans = [Plan([bx.n], [(bx.L, bx.b)], device=dev, tune=tune) for bx in boxes]
+    roots = [torch.empty(bx.n, dtype=torch.int32, device=dev) for bx in boxes]
+    outs = [dict(group_id=torch.empty(bx.n, dtype=torch.int32, device=dev),
+                 n_groups=torch.empty(1, dtype=torch.int32, device=dev),
+                 sizes=torch.empty(bx.n, dtype=torch.int32, device=dev),
+                 com=torch.empty((bx.n, 3), dtype=torch.float64, device=dev)) for bx in boxes]
+
+    def looped():
+        for p, v, r, o in zip(plans, views, roots, outs):
+            p.build_grid(v)
+            p.link(r)
+            p.groups(20, out=o)
+
+    stream = torch.cuda.current_stream()
+    step()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        step()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+
+    res = {}
+    for name, fn, r in (("graph", graph.replay, reps), ("batched", step, reps),
+                        ("looped", looped, max(2, reps // 2))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(r):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / r
+        res[name] = {"ms": round(ms, 4), "mparticles_per_s": round(n / (ms / 1e3) / 1e6, 1),
+                     "reps": r}
+    if plan.status() != 0 or any(p.status() != 0 for p in plans):
+        raise SystemExit("device status set in the batched leg")
+    graph.replay()
+    looped()
+    torch.cuda.synchronize()
+    same = all(torch.equal(root[offs[k]:offs[k + 1]] - int(offs[k]), roots[k])
+               for k in range(len(boxes)))
+    ng_loop = sum(int(o["n_groups"].item()) for o in outs)
+    same = same and ng_loop == int(out["n_groups"].item())
+    if not same:
+        raise SystemExit("batched and looped labels differ")
+    return {"workload": f"{len(boxes)} clumped boxes, 16^3-128^3 particles each",
+            "n": n, "boxes": len(boxes), "groups": ng_loop, "tune": tune,
+            "graph": res["graph"], "batched": res["batched"], "looped": res["looped"],
+            "same_labels": same,
+            "timed": "fof_build_grid + fof_link + fof_groups over all boxes: one plan replayed "
+                     "as a hipGraph, the same plan eagerly, and one plan per box in a loop"}
+
+
+def stream_rate(torch, pos, box, in_core_root, in_core_ws, reps=3, nslab=16):
+    """Streaming labels of the same box in z-slabs (fof_link_stream): per-call time (HIP
+    events on the launch stream), its workspace against the in-core plan's, and the labels
+    checked against the in-core labels of the timed step."""
+    from paper_2510_26851_amd import Stream
+
+    st = Stream(pos, box.L, box.b, nslab=nslab)
+    root = torch.empty_like(in_core_root)
+    st.labels(root)
+    torch.cuda.synchronize()
+    if st.status() != 0 or not torch.equal(root, in_core_root):
+        raise SystemExit("streaming labels differ from the in-core labels")
+    stream = torch.cuda.current_stream()
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        st.labels(root)
+    e.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e) / reps
+    return dict(workload=box.name, slabs=nslab, ms=round(ms, 3),
+                mparticles_per_s=round(box.n / (ms / 1e3) / 1e6, 1),
+                workspace_GB=round(st.ws_bytes / 1e9, 3),
+                in_core_workspace_GB=round(in_core_ws / 1e9, 3),
+                workspace_fraction=round(st.ws_bytes / in_core_ws, 4), same_labels=True,
+                timed="fof_link_stream: per slab, gather + fof_build_grid + fof_link + fusion")
 
 
 def decorated_rate(torch, plan, pos, out, cap, ng, stream, workload, reps=10):
@@ -269,6 +422,8 @@ def main():
     ap.add_argument("--reinforce-reps", type=int, default=20)
     ap.add_argument("--no-subhalo", action="store_true")
     ap.add_argument("--no-decorated", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--cache-dir", default="",
                     help="store / reuse the drawn positions here (.npy; none by default)")
     args = ap.parse_args()
@@ -379,9 +534,15 @@ def main():
     }
     if not args.no_decorated:
         line["decorated"] = decorated_rate(torch, plan, pos, out, cap, ng, stream, box.name)
+    if not args.no_stream:
+        log("timing the streaming labels ...")
+        line["stream"] = stream_rate(torch, pos, box, root, plan.ws_bytes)
     if not args.no_reinforce:
         log("timing batched REINFORCE ...")
         line["reinforce"] = reinforce_rate(torch, dev, args.reinforce_reps)
+    if not args.no_batched:
+        log("timing the batch of 256 boxes ...")
+        line["batched"] = batched_rate(torch, dev, 10)
     if not args.no_subhalo:
         log("timing the sub-halo pass ...")
         line["subhalo"] = subhalo_rate(torch, dev)

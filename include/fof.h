@@ -48,6 +48,8 @@ extern "C" {
 #define FOF_STATUS_EDGE_CAP 4u  /* more candidate edges than fof_sample.edge_cap              */
 #define FOF_STATUS_OVERFLOW 8u  /* fof_groups found more groups than `cap` (in some sample); the
                                    group counts hold the true totals, the tables the first cap */
+#define FOF_STATUS_SLAB_CAP 16u /* fof_link_stream: a slab's member count differed from the
+                                   count it was planned with (the labels are not valid)        */
 
 /* fof_backward modes */
 #define FOF_FROZEN 0 /* frozen assignment (paper Sec. 3.1)                                     */
@@ -78,6 +80,9 @@ typedef struct fof_tune {
     int32_t link_edges;      /* capacity of the link pass's deferred cross-tile hooks (pairs);
                                 0 = n/4 + 65536.  Tiles that overflow it are relinked with
                                 direct hooks, so it trades memory for time only             */
+    double cell_factor;      /* when cell_side is 0: the coarse side of every box is this many
+                                of its own mean particle spacings (0 = 1), so one value suits
+                                a batch of boxes of different densities                       */
 } fof_tune;
 
 /* Stochastic linking (paper Sec. 3.2: every potential edge between nearby particles is a
@@ -310,6 +315,39 @@ int fof_find_groups_static(const fof_box *box /*host*/, int64_t n,
                            int32_t *root, int32_t *group_id, int32_t *n_groups, int32_t *sizes,
                            double *com, double *vmean, double *sigv, int32_t *status /*dev*/,
                            void *stream);
+
+/* Streaming labelling of one box in z-slabs, with a workspace bounded by the largest slab
+ * (paper Sec. 2.3: the box is cut into slabs, each slab is processed with a ghost layer of
+ * its neighbours' particles, and groups that meet in the overlap are fused).  Slab k of
+ * nslab owns the particles with k L_z/nslab <= z < (k+1) L_z/nslab; its ghosts are the
+ * particles of the two neighbouring slabs (periodically) within 1.5 b of the shared face, so
+ * every friend pair lies in one slab's set.  Each slab is linked as a periodic box of the
+ * full lengths holding only those particles (same kernels and predicate as fof_link, on the
+ * cell grid the whole box would get), and the slab labels are fused in one union-find over
+ * `root`: root (dev int32 [n]) receives exactly what fof_link gives for the whole box.
+ * Three calls, so that no call synchronises:
+ *   fof_stream_counts           writes the member count (own + ghosts) of every slab into
+ *                               counts (dev int64 [nslab]);
+ *   fof_stream_workspace_bytes  (host) the workspace for those counts (copied to the host
+ *                               by the caller), in *bytes;
+ *   fof_link_stream             the labels, with the same counts (host) and a workspace of
+ *                               at least that size (dev, 256-byte aligned, caller-owned);
+ *                               status (dev, one int32) receives the OR of the slab runs'
+ *                               status bits, FOF_STATUS_SLAB_CAP if a slab's member
+ *                               count differed from counts[k] (then root is not valid).
+ * box: host; pos: dev float32 [n][3] in [0, L); tune: as for fof_workspace_bytes (host, may
+ * be NULL; the slabs always run without link tiles).  Requirements: 1 <= nslab <= 4096 and,
+ * for nslab > 1, L_z / nslab >= 3 b.  Errors: FOF_EINVAL, FOF_ENOMEM (workspace smaller
+ * than fof_stream_workspace_bytes), FOF_EDEVICE. */
+int fof_stream_counts(const fof_box *box /*host*/, int64_t n, const float *pos /*dev*/,
+                      int32_t nslab, int64_t *counts /*dev*/, void *stream);
+int fof_stream_workspace_bytes(const fof_box *box /*host*/, int64_t n, int32_t nslab,
+                               const int64_t *counts /*host*/, const fof_tune *tune /*host*/,
+                               size_t *bytes /*host*/);
+int fof_link_stream(const fof_box *box /*host*/, int64_t n, const float *pos /*dev*/,
+                    int32_t nslab, const int64_t *counts /*host*/, const fof_tune *tune /*host*/,
+                    void *ws /*dev*/, size_t ws_bytes, int32_t *root /*dev*/,
+                    int32_t *status /*dev*/, void *stream);
 
 /* Static text for a FOF_E* code. */
 const char *fof_strerror(int code);

@@ -7,6 +7,6 @@ from . import _lib
 
 _lib.load()
 
-from .fof import Plan, find_groups, trim  # noqa: E402
+from .fof import Plan, Stream, find_groups, trim  # noqa: E402
 
-__all__ = ["Plan", "find_groups", "trim"]
+__all__ = ["Plan", "Stream", "find_groups", "trim"]

@@ -24,6 +24,7 @@ FOF_TUNE_NO_TILES = 1
 FOF_STATUS_DENSE_CAP = 2
 FOF_STATUS_EDGE_CAP = 4
 FOF_STATUS_OVERFLOW = 8
+FOF_STATUS_SLAB_CAP = 16
 FOF_FROZEN = 0
 FOF_SCORE = 1
 FOF_BASELINE_NONE = 0
@@ -41,7 +42,8 @@ def sample_scratch_bytes(n: int, K: int, edge_cap: int) -> int:
 EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",
            "fof_group_dispersion", "fof_backward_dispersion", "fof_subhalo_scratch_bytes",
            "fof_subhalo", "fof_status", "fof_strerror", "fof_last_device_error", "fof_init",
-           "fof_find_groups_static")
+           "fof_find_groups_static", "fof_stream_counts", "fof_stream_workspace_bytes",
+           "fof_link_stream")
 FOF_STATIC_SCRATCH_BYTES = 160 << 20
 
 
@@ -52,7 +54,7 @@ class fof_box(ctypes.Structure):
 class fof_tune(ctypes.Structure):
     _fields_ = [("cell_side", ctypes.c_double), ("dense_threshold", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("link_edges", ctypes.c_int32)]
+                ("link_edges", ctypes.c_int32), ("cell_factor", ctypes.c_double)]
 
 
 class fof_sample(ctypes.Structure):
@@ -119,6 +121,9 @@ def load():
     L.fof_last_device_error.argtypes = [ctypes.POINTER(ctypes.c_char_p)]
     L.fof_init.argtypes = []
     L.fof_find_groups_static.argtypes = [P, i64, P, P, i32, P, i32, P, P, P, P, P, P, P, P, P]
+    L.fof_stream_counts.argtypes = [P, i64, P, i32, P, P]
+    L.fof_stream_workspace_bytes.argtypes = [P, i64, i32, P, P, ctypes.POINTER(sz)]
+    L.fof_link_stream.argtypes = [P, i64, P, i32, P, P, P, sz, P, P, P]
     for f in EXPORTS:
         if f != "fof_strerror":
             getattr(L, f).restype = ctypes.c_int

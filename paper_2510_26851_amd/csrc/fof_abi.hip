@@ -53,8 +53,9 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
     const double a_max = 0.999 * bx.b / sqrt(3.0) - 2.0 * eps;
     if (!(a_max > 0.0))
         return FOF_EINVAL;
+    const double factor = (tune && tune->cell_factor > 0.0) ? tune->cell_factor : 1.0;
     double s = (tune && tune->cell_side > 0.0) ? tune->cell_side
-                                               : (n > 0 ? cbrt(V / (double)n) : Lmax);
+                                               : (n > 0 ? factor * cbrt(V / (double)n) : Lmax);
     // never more than about 8 coarse cells per particle
     s = fmax(s, cbrt(V / (8.0 * (double)n + 64.0)));
     double side_max = 0.0;
@@ -277,6 +278,12 @@ __global__ void k_copy_status(const Counters *ctr, int32_t *status)
         *status = ctr->status;
 }
 
+__global__ void k_copy_word(const int32_t *from, int32_t *to)
+{
+    if (threadIdx.x == 0)
+        *to = *from;
+}
+
 }  // namespace
 }  // namespace fof
 
@@ -322,7 +329,8 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
         return FOF_EINVAL;
     if (tune && ((tune->flags & ~FOF_TUNE_NO_TILES) != 0 || tune->link_edges < 0 ||
                  tune->block < 0 || (tune->block % kWave) != 0 ||
-                 tune->block > 1024 || !(tune->cell_side >= 0.0)))
+                 tune->block > 1024 || !(tune->cell_side >= 0.0) ||
+                 !(tune->cell_factor >= 0.0) || !isfinite(tune->cell_factor)))
         return FOF_EINVAL;
     int64_t n = 0, ncell = 0, ntiles = 0, n_plain = 0;
     int32_t mmax = 1, any_dense = 0;
@@ -637,6 +645,160 @@ int fof_find_groups_static(const fof_box *box, int64_t n, const fof_tune *tune,
         e = launch_groups(w, min_size, vel, cap, group_id, n_groups, sizes, com, vmean, sigv, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, w.ctr, status);
+        e = hipGetLastError();
+    }
+    return dev_err(e);
+}
+
+// Streaming labelling: slab geometry and the tuning every slab run uses (the whole box's
+// cell grid, no link tiles, which would cover the whole grid for each slab).
+static int stream_setup(const fof_box *box, int64_t n, int32_t nslab, const fof_tune *tune,
+                        SlabGeom *G, fof_tune *st)
+{
+    if (!box || !box_ok(*box) || n < 0 || n > INT32_MAX || nslab < 1 || nslab > slab_max())
+        return FOF_EINVAL;
+    G->Lz = box->L[2];
+    G->nslab = nslab;
+    G->width = box->L[2] / (double)nslab;
+    G->ghost = 1.5 * box->b;
+    if (nslab > 1 && !(G->width >= 2.0 * G->ghost))
+        return FOF_EINVAL;
+    memset(st, 0, sizeof(*st));
+    if (tune)
+        *st = *tune;
+    if (!(st->cell_side > 0.0) && n > 0) {
+        const double V = box->L[0] * box->L[1] * box->L[2];
+        const double f = st->cell_factor > 0.0 ? st->cell_factor : 1.0;
+        st->cell_side = f * cbrt(V / (double)n);
+        st->cell_factor = 0.0;
+    }
+    st->flags |= FOF_TUNE_NO_TILES;
+    return FOF_OK;
+}
+
+// Byte offsets of the streaming workspace: the slab plan's workspace (sized for the largest
+// slab), the slab's positions, map to original indices and labels, the gather's chunk
+// counts, offsets and scan scratch, and the stream's status word.
+struct StreamLayout {
+    size_t plan, spos, map, sroot, ccount, coff, scan, status, total;
+    int64_t cap;
+};
+
+static int stream_layout(const fof_box *box, int64_t n, int32_t nslab, const int64_t *counts,
+                         const fof_tune *st, StreamLayout *out)
+{
+    size_t plan = 0;
+    int64_t cap = 0;
+    for (int32_t k = 0; k < nslab; ++k) {
+        if (counts[k] < 0 || counts[k] > INT32_MAX)
+            return FOF_EINVAL;
+        fof_grid g;
+        if (int rc = fof_workspace_bytes(1, &counts[k], box, st, &g, nullptr, 0))
+            return rc;
+        plan = plan > g.ws_bytes ? plan : g.ws_bytes;
+        cap = cap > counts[k] ? cap : counts[k];
+    }
+    const int64_t nch = slab_chunks(n);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + (bytes ? bytes : 1));
+        return at;
+    };
+    out->plan = take(plan);
+    out->spos = take(12 * (size_t)cap);
+    out->map = take(4 * (size_t)cap);
+    out->sroot = take(4 * (size_t)cap);
+    out->ccount = take(4 * (size_t)nch);
+    out->coff = take(4 * (size_t)(nch + 1));
+    out->scan = take(4 * (size_t)scan_scratch_elems(nch));
+    out->status = take(sizeof(int32_t));
+    out->total = o;
+    out->cap = cap;
+    return FOF_OK;
+}
+
+int fof_stream_counts(const fof_box *box, int64_t n, const float *pos, int32_t nslab,
+                      int64_t *counts, void *stream)
+{
+    SlabGeom G;
+    fof_tune st;
+    if (int rc = stream_setup(box, n, nslab, nullptr, &G, &st))
+        return rc;
+    if (!counts || (n > 0 && !pos))
+        return FOF_EINVAL;
+    clear_stale_error();
+    return dev_err(launch_slab_count(pos, n, G, counts, (hipStream_t)stream));
+}
+
+int fof_stream_workspace_bytes(const fof_box *box, int64_t n, int32_t nslab,
+                               const int64_t *counts, const fof_tune *tune, size_t *bytes)
+{
+    SlabGeom G;
+    fof_tune st;
+    if (int rc = stream_setup(box, n, nslab, tune, &G, &st))
+        return rc;
+    if (!counts || !bytes)
+        return FOF_EINVAL;
+    StreamLayout SL;
+    if (int rc = stream_layout(box, n, nslab, counts, &st, &SL))
+        return rc;
+    *bytes = SL.total;
+    return FOF_OK;
+}
+
+int fof_link_stream(const fof_box *box, int64_t n, const float *pos, int32_t nslab,
+                    const int64_t *counts, const fof_tune *tune, void *ws, size_t ws_bytes,
+                    int32_t *root, int32_t *status, void *stream)
+{
+    SlabGeom G;
+    fof_tune st;
+    if (int rc = stream_setup(box, n, nslab, tune, &G, &st))
+        return rc;
+    if (!counts || !ws || ((uintptr_t)ws % kAlign) != 0 || !status || (n > 0 && (!pos || !root)))
+        return FOF_EINVAL;
+    StreamLayout SL;
+    if (int rc = stream_layout(box, n, nslab, counts, &st, &SL))
+        return rc;
+    if (ws_bytes < SL.total)
+        return FOF_ENOMEM;
+    const hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    float *spos = (float *)(base + SL.spos);
+    int32_t *map = (int32_t *)(base + SL.map), *sroot = (int32_t *)(base + SL.sroot);
+    int32_t *ccount = (int32_t *)(base + SL.ccount), *coff = (int32_t *)(base + SL.coff);
+    int32_t *scan = (int32_t *)(base + SL.scan), *sstat = (int32_t *)(base + SL.status);
+    clear_stale_error();
+    hipError_t e = launch_fill_i32(sstat, 1, 0, s);
+    if (e == hipSuccess)
+        e = launch_fuse_init(root, n, s);
+    for (int32_t k = 0; k < nslab && e == hipSuccess; ++k) {
+        const int64_t m = counts[k];
+        if (m == 0)
+            continue;
+        e = launch_slab_gather(pos, n, G, k, ccount, coff, scan, m, spos, map, sstat, s);
+        if (e != hipSuccess)
+            break;
+        fof_grid grid;
+        BoxDesc desc;
+        if (int rc = fof_workspace_bytes(1, &m, box, &st, &grid, &desc, sizeof(desc)))
+            return rc;
+        void *pws = base + SL.plan;
+        Work w = resolve(&grid, pws);
+        hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, desc,
+                           (BoxDesc *)((char *)pws + grid.off_desc));
+        e = launch_build(w, spos, s);
+        if (e == hipSuccess)
+            e = launch_link(w, sroot, s, nullptr);
+        if (e == hipSuccess)
+            e = launch_or_status(w.ctr, sstat, s);
+        if (e == hipSuccess)
+            e = launch_slab_fuse(map, sroot, m, root, s);
+    }
+    if (e == hipSuccess)
+        e = launch_fuse_final(root, n, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_copy_word, dim3(1), dim3(64), 0, s, sstat, status);
         e = hipGetLastError();
     }
     return dev_err(e);

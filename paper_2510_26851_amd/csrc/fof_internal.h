@@ -451,6 +451,25 @@ hipError_t launch_score(const Work &w, const fof_sample &S, const double *loss, 
 hipError_t launch_groups_sampled(const Work &w, const fof_sample &S, int32_t min_size,
                                  int32_t cap, int32_t *n_groups, int32_t *sizes, double *com,
                                  hipStream_t s);
+// Streaming labelling in z-slabs (fof_stream.hip).
+struct SlabGeom {
+    double Lz;     // box length along z
+    double width;  // slab thickness, Lz / nslab
+    double ghost;  // ghost layer on each side, >= b
+    int32_t nslab;
+};
+int64_t slab_chunks(int64_t n);
+int slab_max();
+hipError_t launch_slab_count(const float *pos, int64_t n, const SlabGeom &G, int64_t *counts,
+                             hipStream_t s);
+hipError_t launch_slab_gather(const float *pos, int64_t n, const SlabGeom &G, int k,
+                              int32_t *ccount, int32_t *coff, int32_t *scan_scratch, int64_t cap,
+                              float *spos, int32_t *map, int32_t *status, hipStream_t s);
+hipError_t launch_fuse_init(int32_t *root, int64_t n, hipStream_t s);
+hipError_t launch_slab_fuse(const int32_t *map, const int32_t *sroot, int64_t m, int32_t *root,
+                            hipStream_t s);
+hipError_t launch_or_status(const Counters *from, int32_t *to, hipStream_t s);
+hipError_t launch_fuse_final(int32_t *root, int64_t n, hipStream_t s);
 hipError_t launch_backward(int64_t n, int32_t block, const int32_t *group_id, int32_t G,
                            const int32_t *sizes, const double *vmean, const double *sigv,
                            const float *vel, const double *g_com, const double *g_sigv,

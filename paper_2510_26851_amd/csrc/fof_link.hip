@@ -63,37 +63,59 @@ __device__ __forceinline__ bool in_dense_cell(const Work &w, const BoxDesc &B, i
     return w.cell_start[c0 + 1] - w.cell_start[c0] > w.dense_threshold && w.cell_count[c0] >= 0;
 }
 
-// Candidate search of one particle straight from global memory.  Returns true if it has a
-// friend (its hooks are done).
-__device__ bool link_particle_global(const Work &w, const BoxDesc &B, int64_t i, float4 p,
-                                     int ix, int iy, int iz)
+// Candidates of particle p (sorted index i, coarse cell (ix, iy, iz)) straight from global
+// memory, one neighbour row (ox, oy) at a time: with cells z fastest, the row's cells
+// iz + sz.lo .. iz + sz.hi are one contiguous run of particles unless the run wraps around
+// the box along z (then two runs).  Cells with clique tables are cut out of a run (the
+// dense passes make their pairs); a run whose total count is at most the dense threshold
+// holds none, so the dense test costs a load only next to crowded cells.  Returns true if
+// p has a friend; each pair is hooked from the end with the smaller original index, the
+// rule every link path shares (the other end may be staged elsewhere).
+__device__ bool link_particle_global(const Work &w, const BoxDesc &B, const Pred &P, int64_t i,
+                                     float4 p, int ix, int iy, int iz)
 {
     const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
+    const int32_t oi = __float_as_int(p.w);
     bool has_friend = false;
     const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
     const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
     const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
+    const int nz = B.nc[2];
     for (int ox = sx.lo; ox <= sx.hi; ++ox) {
         const int cx = wrap_cell(ix + ox, B.nc[0]);
         for (int oy = sy.lo; oy <= sy.hi; ++oy) {
             const int cy = wrap_cell(iy + oy, B.nc[1]);
-            for (int oz = sz.lo; oz <= sz.hi; ++oz) {
-                const int cz = wrap_cell(iz + oz, B.nc[2]);
-                const int64_t c = coarse_cell(B, cx, cy, cz);
-                const int32_t s = w.cell_start[c], e = w.cell_start[c + 1];
-                if (box_dense && e - s > w.dense_threshold && w.cell_count[c] >= 0)
-                    continue;  // clique-table cell: linked from its side (k_dense_sparse)
-                FOF_STAT(w.ctr, ST_PAIRS_GLOBAL, e - s);
-                for (int32_t j = s; j < e; ++j) {
-                    if (j == i)
-                        continue;
-                    const float4 q = w.sorted[j];
-                    if (linked(B, p.x, p.y, p.z, q.x, q.y, q.z)) {
-                        has_friend = true;
-                        // each pair is hooked from the end with the smaller original index,
-                        // the rule every link path shares (the other end may be staged)
-                        if (__float_as_int(p.w) < __float_as_int(q.w))
-                            uf_union(w.parent, (uint32_t)i, (uint32_t)j);
+            const int64_t row = coarse_cell(B, cx, cy, 0);
+            int oz = sz.lo;
+            while (oz <= sz.hi) {
+                // the longest run of consecutive cells from iz + oz that does not wrap
+                const int za = wrap_cell(iz + oz, nz);
+                int zb = za;
+                while (oz < sz.hi && zb + 1 < nz && wrap_cell(iz + oz + 1, nz) == zb + 1) {
+                    ++oz;
+                    ++zb;
+                }
+                ++oz;
+                const int32_t a = w.cell_start[row + za], e = w.cell_start[row + zb + 1];
+                const bool split = box_dense && e - a > w.dense_threshold;
+                FOF_STAT(w.ctr, ST_PAIRS_GLOBAL, e - a);
+                for (int z = za; z <= (split ? zb : za); ++z) {
+                    int32_t j0 = a, j1 = e;
+                    if (split) {  // one cell at a time, skipping those with clique tables
+                        j0 = w.cell_start[row + z];
+                        j1 = w.cell_start[row + z + 1];
+                        if (j1 - j0 > w.dense_threshold && w.cell_count[row + z] >= 0)
+                            continue;
+                    }
+                    for (int32_t j = j0; j < j1; ++j) {
+                        if (j == i)
+                            continue;
+                        const float4 q = w.sorted[j];
+                        if (linked(P, p.x, p.y, p.z, q.x, q.y, q.z)) {
+                            has_friend = true;
+                            if (oi < __float_as_int(q.w))
+                                uf_union(w.parent, (uint32_t)i, (uint32_t)j);
+                        }
                     }
                 }
             }
@@ -127,7 +149,8 @@ __global__ void k_link(Work w, int32_t *__restrict__ root)
     const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
     if (in_dense_cell(w, B, ix, iy, iz))
         return;
-    finish_particle(w, root, i, __float_as_int(p.w), link_particle_global(w, B, i, p, ix, iy, iz));
+    finish_particle(w, root, i, __float_as_int(p.w),
+                    link_particle_global(w, B, pred_of(B), i, p, ix, iy, iz));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -498,7 +521,7 @@ __global__ __launch_bounds__(kTileBlock) void k_link_windows(Work w, int32_t *__
                                     iy, iz, wbase, za - 1, nullptr, g, DirectHook{w.parent});
                 } else {
                     p = w.sorted[i];
-                    f = link_particle_global(w, B, i, p, ix, iy, iz);
+                    f = link_particle_global(w, B, P, i, p, ix, iy, iz);
                 }
                 finish_particle(w, root, i, __float_as_int(p.w), f);
             }

@@ -258,3 +258,54 @@ def find_groups(pos, L, b, min_size=20, vel=None, cap=None, tune=None):
     root = plan.link()
     res = trim(plan.groups(min_size, vel=vel, cap=cap))
     return root, res
+
+
+def _box(L, b):
+    bx = _lib.fof_box()
+    bx.L[:] = [float(v) for v in np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))]
+    bx.b = float(b)
+    return bx
+
+
+class Stream:
+    """Streaming labels of one box in z-slabs (fof_stream_counts, fof_stream_workspace_bytes,
+    fof_link_stream): the workspace holds one slab at a time, so it is bounded by the
+    largest slab instead of the box.  `counts()` reads the slab sizes back to the host once
+    (the only synchronisation); `labels()` then gives what fof_link gives for the whole box."""
+
+    def __init__(self, pos, L, b, nslab=16, tune=None):
+        _need(pos, "pos", torch.float32, (pos.shape[0], 3), pos.device)
+        self.pos, self.n, self.nslab = pos, int(pos.shape[0]), int(nslab)
+        self.box = _box(L, b)
+        self.tune = _lib.fof_tune()
+        for key, v in (tune or {}).items():
+            setattr(self.tune, key, v)
+        lib = _lib.load()
+        counts = torch.empty(self.nslab, dtype=torch.int64, device=pos.device)
+        check("fof_stream_counts",
+              lib.fof_stream_counts(ctypes.byref(self.box), self.n, _ptr(pos), self.nslab,
+                                    _ptr(counts), _stream()))
+        self.counts = np.ascontiguousarray(counts.cpu().numpy(), dtype=np.int64)
+        nbytes = ctypes.c_size_t()
+        check("fof_stream_workspace_bytes",
+              lib.fof_stream_workspace_bytes(ctypes.byref(self.box), self.n, self.nslab,
+                                             self.counts.ctypes.data_as(ctypes.c_void_p),
+                                             ctypes.byref(self.tune), ctypes.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=pos.device)
+        self.status_word = torch.zeros(1, dtype=torch.int32, device=pos.device)
+
+    def labels(self, root=None, stream=None):
+        if root is None:
+            root = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.pos.device)
+        _need(root, "root", torch.int32, None, self.pos.device, min_rows=self.n)
+        check("fof_link_stream",
+              _lib.load().fof_link_stream(ctypes.byref(self.box), self.n, _ptr(self.pos),
+                                          self.nslab,
+                                          self.counts.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.byref(self.tune), _ptr(self.ws), self.ws_bytes,
+                                          _ptr(root), _ptr(self.status_word), _stream(stream)))
+        return root
+
+    def status(self) -> int:
+        return int(self.status_word.item())

@@ -1,9 +1,12 @@
-"""Autotuner for the tuning knobs of fof_tune (coarse cell side, dense-cell threshold).
+"""Autotuner for the knobs of fof_tune: coarse cell size (relative to each box's own mean
+particle spacing, so one value suits a batch of boxes of different densities), the
+dense-cell threshold, and the block shape of the per-particle kernels.
 
 No knob changes any result; they only move work between the kernels.  The tuner times the
-whole pipeline (build + link + groups) for a few candidates on the caller's own input and
-keeps the fastest, cached in a JSON file keyed by device architecture, particle-count
-bucket and the ratio of mean spacing to linking length.
+whole pipeline (build + link + groups) on the caller's own input, first over (cell factor,
+dense threshold) at the default block, then over the block at the best pair, and keeps the
+fastest.  Choices are cached in a JSON file keyed by device architecture, particle-count
+bucket, number of boxes and the ratio of mean spacing to linking length.
 """
 from __future__ import annotations
 
@@ -11,6 +14,7 @@ import json
 import math
 import os
 
+import numpy as np
 import torch
 
 from .fof import Plan
@@ -18,13 +22,28 @@ from .fof import Plan
 DEFAULT_CACHE = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")),
                              "fof_mi355x", "tune.json")
 
+CELL_FACTORS = (1.0, 1.25, 1.5, 2.0)
+DENSE_THRESHOLDS = (16, 32, 64)
+BLOCKS = (128, 256, 512)
 
-def _key(n, L, b, device):
+
+def _L3(L):
+    return [float(v) for v in (L if hasattr(L, "__len__") else (L, L, L))]
+
+
+def _key(counts, boxes, device):
     props = torch.cuda.get_device_properties(device)
     arch = getattr(props, "gcnArchName", props.name)
-    L3 = [float(v) for v in (L if hasattr(L, "__len__") else (L, L, L))]
-    spacing = (L3[0] * L3[1] * L3[2] / max(n, 1)) ** (1.0 / 3.0)
-    return f"{arch}|n2^{int(math.log2(max(n, 1)))}|s/b={round(spacing / b, 1)}"
+    n = int(sum(counts))
+    ratios = []
+    for c, (L, b) in zip(counts, boxes):
+        L3 = _L3(L)
+        if c > 0:
+            ratios.append((L3[0] * L3[1] * L3[2] / c) ** (1.0 / 3.0) / b)
+    ratio = float(np.median(ratios)) if ratios else 0.0
+    nb = len(counts)
+    nbk = 1 if nb == 1 else 2 ** int(math.ceil(math.log2(nb)))
+    return f"{arch}|n2^{int(math.log2(max(n, 1)))}|boxes<={nbk}|s/b={round(ratio, 1)}"
 
 
 def _load(path):
@@ -35,18 +54,15 @@ def _load(path):
         return {}
 
 
-def candidates(n, L, b):
-    L3 = [float(v) for v in (L if hasattr(L, "__len__") else (L, L, L))]
-    spacing = (L3[0] * L3[1] * L3[2] / max(n, 1)) ** (1.0 / 3.0)
-    out = []
-    for f in (1.0, 1.5, 2.0):
-        for thr in (16, 32, 64):
-            out.append(dict(cell_side=max(f * spacing, 1.01 * b), dense_threshold=thr))
-    return out
+def candidates():
+    """Stage one: (cell factor, dense threshold) at the default block."""
+    return [dict(cell_factor=f, dense_threshold=t) for f in CELL_FACTORS
+            for t in DENSE_THRESHOLDS]
 
 
-def time_pipeline(pos, L, b, tune, min_size=20, reps=3):
-    plan = Plan([pos.shape[0]], [(L, b)], device=pos.device, tune=tune)
+def time_pipeline(pos, counts, boxes, tune, min_size=20, reps=3):
+    """Milliseconds per build + link + groups of the batch under `tune` (HIP events)."""
+    plan = Plan(counts, boxes, device=pos.device, tune=tune)
     root = torch.empty(pos.shape[0], dtype=torch.int32, device=pos.device)
 
     def step():
@@ -65,15 +81,27 @@ def time_pipeline(pos, L, b, tune, min_size=20, reps=3):
     return e0.elapsed_time(e1) / reps
 
 
-def autotune(pos, L, b, min_size=20, cache=DEFAULT_CACHE, reps=3, force=False, log=None):
-    """Best tune dict for this input shape (cached)."""
-    key = _key(pos.shape[0], L, b, pos.device)
+def autotune_batch(pos, counts, boxes, min_size=20, cache=DEFAULT_CACHE, reps=3, force=False,
+                   log=None):
+    """Best tune dict for a batch of boxes (counts[k] particles in box k, boxes[k] = (L, b),
+    pos the concatenated float32 [n, 3] positions on the GPU); cached."""
+    counts = [int(c) for c in counts]
+    key = _key(counts, boxes, pos.device)
     table = _load(cache) if cache else {}
     if key in table and not force:
         return table[key]["tune"]
     best, best_ms = None, float("inf")
-    for tune in candidates(pos.shape[0], L, b):
-        ms = time_pipeline(pos, L, b, tune, min_size, reps)
+    for tune in candidates():
+        ms = time_pipeline(pos, counts, boxes, tune, min_size, reps)
+        if log:
+            log(f"tune {tune}: {ms:.3f} ms")
+        if ms < best_ms:
+            best, best_ms = tune, ms
+    for blk in BLOCKS:
+        tune = dict(best, block=blk)
+        if blk == 256:  # the default block, already timed in stage one
+            continue
+        ms = time_pipeline(pos, counts, boxes, tune, min_size, reps)
         if log:
             log(f"tune {tune}: {ms:.3f} ms")
         if ms < best_ms:
@@ -84,3 +112,9 @@ def autotune(pos, L, b, min_size=20, cache=DEFAULT_CACHE, reps=3, force=False, l
         with open(cache, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)
     return best
+
+
+def autotune(pos, L, b, min_size=20, cache=DEFAULT_CACHE, reps=3, force=False, log=None):
+    """Best tune dict for one box of side(s) L and linking length b (cached)."""
+    return autotune_batch(pos, [pos.shape[0]], [(L, b)], min_size=min_size, cache=cache,
+                          reps=reps, force=force, log=log)

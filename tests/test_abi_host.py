@@ -390,3 +390,26 @@ def test_static_workspace_call_rejects_before_launch():
     g = _lib.fof_grid()
     assert L.fof_workspace_bytes(1, cnt, ctypes.byref(big), None, ctypes.byref(g), None, 0) == 0
     assert g.ws_bytes > _lib.FOF_STATIC_SCRATCH_BYTES
+
+
+def test_cell_factor_scales_the_coarse_side_of_every_box():
+    """fof_tune.cell_factor: the coarse side is that many of each box's own mean spacings."""
+    L = lib()
+    counts = (ctypes.c_int64 * 2)(64 ** 3, 32 ** 3)
+    boxes = (_lib.fof_box * 2)()
+    for k, side in enumerate((64.0, 32.0)):            # mean spacing 1.0 in both
+        boxes[k].L[:] = [side] * 3
+        boxes[k].b = 0.45                              # clique cells allow sides up to 2.59
+    g = _lib.fof_grid()
+    for factor, per_axis in ((0.0, (64, 32)), (1.0, (64, 32)), (2.0, (32, 16)),
+                             (4.0, (25, 13))):         # 4 is capped: 10 clique cells per side
+        t = _lib.fof_tune()
+        t.cell_factor = factor
+        assert L.fof_workspace_bytes(2, counts, boxes, ctypes.byref(t), ctypes.byref(g), None,
+                                     0) == 0
+        assert g.ncell == per_axis[0] ** 3 + per_axis[1] ** 3, factor
+    for bad in (-1.0, float("nan"), float("inf")):
+        t = _lib.fof_tune()
+        t.cell_factor = bad
+        assert L.fof_workspace_bytes(2, counts, boxes, ctypes.byref(t), ctypes.byref(g), None,
+                                     0) == _lib.FOF_EINVAL

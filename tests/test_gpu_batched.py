@@ -107,3 +107,21 @@ def test_batched_equals_looped():
     for k, bx in enumerate(boxes):
         r1, g1 = find_groups(torch.from_numpy(bx.pos).cuda(), bx.L, bx.b, 20)
         np.testing.assert_array_equal(root[offs[k]:offs[k + 1]] - offs[k], r1.cpu().numpy())
+
+
+def test_autotuned_batch_equals_the_oracle(tmp_path):
+    """The autotuner's choice for a batch (cell size relative to each box's spacing, dense
+    threshold, block shape) leaves every box's labels and groups equal to the oracle's."""
+    import torch
+    from paper_2510_26851_amd.tune import autotune_batch
+
+    boxes = W.config4(nbox=24, n_lo=16 ** 3, n_hi=64 ** 3)
+    counts = [bx.n for bx in boxes]
+    pos = torch.from_numpy(np.concatenate([bx.pos for bx in boxes])).cuda()
+    say(f"autotuning a batch of {len(boxes)} boxes")
+    tune = autotune_batch(pos, counts, [(bx.L, bx.b) for bx in boxes], 20,
+                          cache=str(tmp_path / "tune.json"), reps=1, log=say)
+    assert set(tune) >= {"cell_factor", "dense_threshold"}
+    say(f"tuned: {tune}")
+    root, res = run_batch(boxes, 20, tune=tune)
+    check_against_oracle(boxes, root, res, 20, set(range(len(boxes))))

@@ -1,7 +1,8 @@
 """Full size: the 512^3 Zel'dovich box with 50,000 NFW clumps that bench.py measures, run in
 the same launch configuration (default tuning, helper stream when the package made one), and
 compared, label by label, group by group, with the oracle run on the whole box (its
-multi-threaded form, pinned to the serial one in test_oracle_par.py).  Collected last: it
+multi-threaded form, pinned to the serial one in test_oracle_par.py), and again through the
+streaming mode in 16 z-slabs.  Collected last: it
 takes about a minute, most of it drawing the box and running the oracle.  The same pipeline
 at 1024^3 runs only when FOF_TEST_1024=1 is set, checked there by properties at any size
 and a 16.8M-particle slab against the oracle."""
@@ -33,6 +34,25 @@ def test_full_size_zeldovich_nfw_512():
     ref_root, _ = oracle.fof_par(box.pos, box.L, box.b)
     say("oracle done; GPU")
     compare_with_oracle(box.pos, box.L, box.b, box.min_size, root_ref=ref_root)
+    check_stream(box, ref_root)
+
+
+def check_stream(box, ref_root, nslab=16):
+    """Streaming labels in 16 z-slabs: bit-exact to the whole-box labels, with a workspace
+    at most a quarter of the in-core plan's."""
+    import torch
+    from paper_2510_26851_amd import Plan, Stream
+
+    say(f"streaming in {nslab} slabs")
+    t = torch.from_numpy(box.pos).cuda()
+    st = Stream(t, box.L, box.b, nslab=nslab)
+    root = st.labels()
+    torch.cuda.synchronize()
+    assert st.status() == 0
+    np.testing.assert_array_equal(root.cpu().numpy(), ref_root)
+    in_core = Plan([box.n], [(box.L, box.b)], device=t.device).ws_bytes
+    say(f"stream workspace {st.ws_bytes / 1e9:.2f} GB, in core {in_core / 1e9:.2f} GB")
+    assert st.ws_bytes <= in_core / 4
 
 
 @pytest.mark.skipif(os.environ.get("FOF_TEST_1024") != "1",
