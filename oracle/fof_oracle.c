@@ -338,6 +338,19 @@ static int32_t ufa_find(int32_t *parent, int32_t i)
     }
 }
 
+/* Root lookup without writes, for the final pass: there every thread stores the root into
+   its own entry, and a halving store by another thread could replace that root with a stale
+   grandparent, leaving a label that is not the component's smallest index. */
+static int32_t ufa_find_ro(const int32_t *parent, int32_t i)
+{
+    for (;;) {
+        int32_t p = __atomic_load_n(parent + i, __ATOMIC_RELAXED);
+        if (p == i)
+            return i;
+        i = p;
+    }
+}
+
 static void ufa_union(int32_t *parent, int32_t i, int32_t j)
 {
     for (;;) {
@@ -474,7 +487,7 @@ int64_t oracle_fof_par(int64_t n, const float *pos, const double *L, double b, i
     }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
-        root[i] = ufa_find(root, (int32_t)i);
+        __atomic_store_n(root + i, ufa_find_ro(root, (int32_t)i), __ATOMIC_RELAXED);
     cells_free(&c);
     return nlinks;
 }
