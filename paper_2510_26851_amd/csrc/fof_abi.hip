@@ -79,6 +79,7 @@ int plan_box(const fof_box &bx, int64_t n, const fof_tune *tune, int64_t cell_ba
     if (m > kMaxFine)
         return FOF_EINVAL;
     d->m = m;
+    d->mdiv = m > 1 ? (uint32_t)(((1ull << 32) + (uint64_t)m - 1) / (uint64_t)m) : 0u;
     d->off = off;
     d->n = (int32_t)n;
     d->cell_base = cell_base;

@@ -43,9 +43,9 @@ __device__ __forceinline__ CellOf cell_of(const BoxDesc &B, float &x, float &y, 
     x = okx ? x : 0.0f;
     y = oky ? y : 0.0f;
     z = okz ? z : 0.0f;
-    int ix = fine_index(x, B.inv_fine[0], B.nf[0]) / B.m;
-    int iy = fine_index(y, B.inv_fine[1], B.nf[1]) / B.m;
-    int iz = fine_index(z, B.inv_fine[2], B.nf[2]) / B.m;
+    int ix = coarse_index(x, B, 0);
+    int iy = coarse_index(y, B, 1);
+    int iz = coarse_index(z, B, 2);
     return {coarse_cell(B, ix, iy, iz), okx && oky && okz};
 }
 

@@ -603,10 +603,13 @@ __device__ __forceinline__ int gap_budget(const BoxDesc &B)
 // forward half of the nearest shell (offsets in [-1, 1]^3).  pass 1: the units listed in
 // umark[0, nmark) (those outside the largest component), every offset in [-R, R]^3 outside
 // the nearest shell, in both directions (a pair with an unlisted end is then still examined
-// from the other).  The work items are (unit, fine row of offsets) pairs spread over all
-// threads; the occupied neighbours of one row are read as a bit field of the key bitmask,
-// so empty fine cells cost nothing.  A pair already in one component is skipped, otherwise
-// its first friend pair joins it.
+// from the other).  pass 2: every unit, the forward half of the offsets in [-R, R]^3
+// outside the nearest shell (cheaper than pass 1 when the largest component holds fewer
+// than about half the units: each pair once instead of twice from every listed unit).
+// The work items are (unit, fine row of offsets) pairs spread over all threads; the
+// occupied neighbours of one row are read as a bit field of the key bitmask, so empty fine
+// cells cost nothing.  A pair already in one component is skipped, otherwise its first
+// friend pair joins it.
 template <int G, int UMAX, int CAP>
 __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const CellXYZ &cc,
                            int m, int R, int u, int32_t s, const float4 *mem,
@@ -615,18 +618,22 @@ __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const
     const int W = w.table_words;
     const int reach = pass == 0 ? 1 : R;
     const int span = 2 * reach + 1;
-    const int rows = pass == 0 ? 5 : span * span;  // (dz, dy) rows per unit
-    const int nitems = (pass == 0 ? u : L.nmark) * rows;
+    // (dz, dy) rows per unit; pass 2: dz = 0 with dy in [0, R], then dz in [1, R]
+    const int rows = pass == 0 ? 5 : (pass == 1 ? span * span : R + 1 + R * span);
+    const int nitems = (pass == 1 ? L.nmark : u) * rows;
     for (int item = Grp<G>::tid(); item < nitems; item += G) {
-        const int r = pass == 0 ? item / rows : L.umark[item / rows];
+        const int r = pass == 1 ? L.umark[item / rows] : item / rows;
         const int q = item % rows;
         int dz, dy;
         if (pass == 0) {  // forward rows: (0, 0) with dx > 0, (0, 1), (1, -1), (1, 0), (1, 1)
             dz = q < 2 ? 0 : 1;
             dy = q < 2 ? q : q - 3;
-        } else {
+        } else if (pass == 1) {
             dz = q / span - reach;
             dy = q % span - reach;
+        } else {
+            dz = q <= R ? 0 : 1 + (q - R - 1) / span;
+            dy = q <= R ? q : (q - R - 1) % span - R;
         }
         const int xyz = L.uxyz[r];
         const int ax = xyz & 15, ay = (xyz >> 4) & 15, az = xyz >> 8;
@@ -634,9 +641,9 @@ __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const
         if (bz < 0 || bz >= m || by < 0 || by >= m)
             continue;
         int lo = -reach, hi = reach;  // dx range of this row
-        if (pass == 0 && q == 0)
+        if ((pass == 0 || pass == 2) && q == 0)
             lo = 1;
-        const bool skip_core = pass == 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+        const bool skip_core = pass != 0 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
         lo = max(lo, -ax);
         hi = min(hi, m - 1 - ax);
         if (lo > hi)
@@ -732,15 +739,20 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     if (far && t == 0)
         FOF_STAT(w.ctr, ST_CC_FAR_CELLS, 1);
     if (far) {
-        const int giant = L.giant & 0xFFFF;
-        if (t == 0)
-            L.nmark = 0;
-        Grp<G>::sync();
-        for (int r = t; r < u; r += G)  // umark becomes the list of units outside the giant
-            if (lfind(L.uf, r) != giant)
-                L.umark[atomicAdd(&L.nmark, 1)] = r;
-        Grp<G>::sync();
-        join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 1);
+        const int giant = L.giant & 0xFFFF, gsize = L.giant >> 16;
+        const int span = 2 * R + 1;
+        if (span * span * (u - gsize) <= (R + 1 + R * span) * u) {
+            if (t == 0)
+                L.nmark = 0;
+            Grp<G>::sync();
+            for (int r = t; r < u; r += G)  // umark becomes the list of units outside the giant
+                if (lfind(L.uf, r) != giant)
+                    L.umark[atomicAdd(&L.nmark, 1)] = r;
+            Grp<G>::sync();
+            join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 1);
+        } else {
+            join_units<G>(w, B, P, cc, m, R, u, s, mem, L, 2);
+        }
     }
     Grp<G>::sync();
     FOF_PHASE(L, t == 0, 4);
@@ -878,8 +890,10 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
             L.pairbits[q] = 0u;
         if (t == 0)
             L.done = 0;
-        // the neighbour's unit components and member starts, in LDS when they fit
-        const bool staged2 = u2 < UMAX;
+        // the neighbour's unit components and member starts, in LDS when they fit; a pair of
+        // single-component cells stops at its first friend pair, so it reads the few member
+        // starts it needs from global memory instead
+        const bool staged2 = u2 < UMAX && !single;
         int *ncomp_of = L.umark;
         int *nstart = reinterpret_cast<int *>(L.umin);  // 2 * UMAX ints
         if (staged2) {
@@ -936,7 +950,7 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
                 row &= row - 1u;
                 const int bx = rx + lo + bpos;
                 const int rb = rank_in(L.bits, L.pre, key0 + bpos);
-                const int cb = staged2 ? ncomp_of[rb] : w.cnt[s2 + rb];
+                const int cb = single ? 0 : (staged2 ? ncomp_of[rb] : w.cnt[s2 + rb]);
                 const int bit = L.ucomp[r] * ncomp2 + cb;
                 if (dedupe && ((L.pairbits[bit >> 5] >> (bit & 31)) & 1u))
                     continue;

@@ -52,6 +52,7 @@ struct alignas(16) BoxDesc {
     float fine[3];      // fine cell side per axis, L / nf (float)
     float slack;        // margin added to fine-cell boxes before a distance skip
     float Lup[3];       // smallest float >= L: a float x is below L exactly when x < Lup
+    uint32_t mdiv;      // ceil(2^32 / m) for m > 1: fine / m as one multiply-high
 };
 
 // Status bits (public values in fof.h) and the counters block.
@@ -107,6 +108,20 @@ __device__ __forceinline__ int fine_index(float x, float inv, int nf)
     return f < nf - 1 ? f : nf - 1;
 }
 
+// Coarse index of a fine index f: f / m, as the high word of f * ceil(2^32 / m).  With
+// ceil(2^32 / m) m = 2^32 + e, e < m <= 10, the quotient is exact for f < 2^32 / e, far above
+// any fine index (at most 10 * 2^20).
+__device__ __forceinline__ int coarse_of(int f, const BoxDesc &B)
+{
+    return B.m == 1 ? f : (int)__umulhi((uint32_t)f, B.mdiv);
+}
+
+// Coarse cell coordinate of a float coordinate along axis a.
+__device__ __forceinline__ int coarse_index(float x, const BoxDesc &B, int a)
+{
+    return coarse_of(fine_index(x, B.inv_fine[a], B.nf[a]), B);
+}
+
 // Linear coarse cell id with z fastest (C order over (ix, iy, iz)).  The paper's grid uses
 // x fastest; z fastest makes the counting sort nearly sequential for particles stored in
 // C order of a Lagrangian lattice, the usual N-body layout.  No result depends on it.
@@ -127,6 +142,14 @@ __device__ __forceinline__ AxisSpan axis_span(float x, int ix, float side, int n
     if (nc == 2)  // the single other cell is both the lower and the upper neighbour
         return {0, (need_lo || need_hi) ? 1 : 0};
     return {need_lo ? -1 : 0, need_hi ? 1 : 0};
+}
+
+// The k-th offset of a span, own offset first: 0, then lo if it is -1, then hi if it is +1.
+// Walking offsets in this order lets lanes whose positions need different neighbours share
+// loop steps (a wave runs max-over-lanes steps, not the union of the offsets).
+__device__ __forceinline__ int span_offset(const AxisSpan &s, int k)
+{
+    return k == 0 ? 0 : (k == 1 && s.lo < 0 ? -1 : 1);
 }
 
 __device__ __forceinline__ int wrap_cell(int c, int nc)

@@ -81,10 +81,11 @@ __device__ bool link_particle_global(const Work &w, const BoxDesc &B, const Pred
     const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);
     const AxisSpan sz = axis_span(p.z, iz, B.side[2], B.nc[2], B.reach);
     const int nz = B.nc[2];
-    for (int ox = sx.lo; ox <= sx.hi; ++ox) {
-        const int cx = wrap_cell(ix + ox, B.nc[0]);
-        for (int oy = sy.lo; oy <= sy.hi; ++oy) {
-            const int cy = wrap_cell(iy + oy, B.nc[1]);
+    const int nx = sx.hi - sx.lo + 1, ny = sy.hi - sy.lo + 1;
+    for (int kx = 0; kx < nx; ++kx) {
+        const int cx = wrap_cell(ix + span_offset(sx, kx), B.nc[0]);
+        for (int ky = 0; ky < ny; ++ky) {
+            const int cy = wrap_cell(iy + span_offset(sy, ky), B.nc[1]);
             const int64_t row = coarse_cell(B, cx, cy, 0);
             int oz = sz.lo;
             while (oz <= sz.hi) {
@@ -144,9 +145,9 @@ __global__ void k_link(Work w, int32_t *__restrict__ root)
     if (B.tiled)
         return;
     const float4 p = w.sorted[i];
-    const int ix = fine_index(p.x, B.inv_fine[0], B.nf[0]) / B.m;
-    const int iy = fine_index(p.y, B.inv_fine[1], B.nf[1]) / B.m;
-    const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
+    const int ix = coarse_index(p.x, B, 0);
+    const int iy = coarse_index(p.y, B, 1);
+    const int iz = coarse_index(p.z, B, 2);
     if (in_dense_cell(w, B, ix, iy, iz))
         return;
     finish_particle(w, root, i, __float_as_int(p.w),
@@ -212,38 +213,16 @@ __device__ __forceinline__ int lds_find_ro(const int *lpar, int x)
     return x;
 }
 
-// Sets the friend bit of sorted index i for every active lane with has_friend.  The lanes
-// of a wave hold increasing sorted indices, so lanes sharing a 64-bit word are adjacent:
-// their bits are OR-ed across the wave and the first lane of each word does one atomic.
-__device__ __forceinline__ void flag_friends_wave(uint64_t *flags, bool active, int64_t i,
-                                                  bool has_friend)
-{
-    const int lane = lane_id();
-    const int64_t word = active ? (i >> 6) : -1;
-    uint64_t v = (active && has_friend) ? (1ull << (i & 63)) : 0ull;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int64_t w2 = __shfl_down(word, o, kWave);
-        const uint64_t v2 = __shfl_down(v, o, kWave);
-        if (lane + o < kWave && w2 == word)
-            v |= v2;
-    }
-    const int64_t wprev = __shfl_up(word, 1, kWave);
-    if (active && v && (lane == 0 || wprev != word))
-        atomicOr((unsigned long long *)(flags + word), (unsigned long long)v);
-}
-
-// Candidates of own particle p (sorted index i, own halo cell (hx, hy, hz)) in the staged
-// window: neighbour row r's halo cells [z_first, ...] sit at LDS wb[r] + slot - hoff[...].
-// Returns whether p has a friend; pairs are hooked from the smaller original index.
+// Candidates of particle p (sorted index i, own halo cell (hx, hy, hz)) in the staged
+// window of the windowed kernel: neighbour row r's halo cells [z_first, ...] sit at LDS
+// wb[r] + slot - hoff[...].  Returns whether p has a friend; pairs are hooked from the
+// smaller original index.
 template <class Hook>
 __device__ __forceinline__ bool link_staged(const Work &w, const BoxDesc &B, const Pred &P,
-                                            bool box_dense,
                                             const float4 *part, const int *hoff, const int *gst,
-                                            int64_t i, float4 p, int ls,
-                                            int hx, int hy, int hz, int ix, int iy, int iz,
-                                            const int *wb, int z_first, int *lpar,
-                                            const TileGeom &g, const Hook &hook)
+                                            int64_t i, float4 p, int ls, int hx, int hy, int hz,
+                                            int ix, int iy, int iz, const int *wb, int z_first,
+                                            const Hook &hook)
 {
     const int32_t oi = __float_as_int(p.w);
     bool has_friend = false;
@@ -254,15 +233,9 @@ __device__ __forceinline__ bool link_staged(const Work &w, const BoxDesc &B, con
         for (int oy = sy.lo; oy <= sy.hi; ++oy) {
             const int row2 = (hx + ox) * kHY + hy + oy;
             const int rb2 = row2 * kHZ;
-            const int shift = wb ? wb[row2] - hoff[rb2 + z_first] : 0;  // slot -> LDS
+            const int shift = wb[row2] - hoff[rb2 + z_first];  // slot -> LDS
             const int a = hoff[rb2 + hz + sz.lo] + shift;
             const int e = hoff[rb2 + hz + sz.hi + 1] + shift;
-            // own particles of this row (LDS union-find), when the caller keeps one
-            int own_lo = 0, own_hi = 0;
-            if (lpar && hx + ox >= 1 && hx + ox < g.hxe && hy + oy >= 1 && hy + oy < g.hye) {
-                own_lo = hoff[rb2 + 1];
-                own_hi = hoff[rb2 + g.hze];
-            }
             FOF_STAT(w.ctr, ST_PAIRS_TILED, e - a);
             for (int j = a; j < e; ++j) {
                 if (j == ls)
@@ -271,31 +244,123 @@ __device__ __forceinline__ bool link_staged(const Work &w, const BoxDesc &B, con
                 if (linked(P, p.x, p.y, p.z, q4.x, q4.y, q4.z)) {
                     has_friend = true;
                     if (oi < __float_as_int(q4.w)) {  // each pair hooked from one end
-                        if (j >= own_lo && j < own_hi) {
-                            lds_union(lpar, part, ls, j);
-                        } else {
-                            const int sj = j - shift;
-                            const int hj = rb2 + last_le<kHZ>(hoff + rb2, sj);
-                            FOF_STAT(w.ctr, ST_UNIONS, 1);
-                            hook((uint32_t)i, (uint32_t)(gst[hj] + (sj - hoff[hj])));
-                        }
+                        const int sj = j - shift;
+                        const int hj = rb2 + last_le<kHZ>(hoff + rb2, sj);
+                        FOF_STAT(w.ctr, ST_UNIONS, 1);
+                        hook((uint32_t)i, (uint32_t)(gst[hj] + (sj - hoff[hj])));
                     }
                 }
             }
-
         }
     return has_friend;
 }
 
-__global__ __launch_bounds__(kTileBlock, 6) void k_link_tiled(Work w, int32_t *__restrict__ root)
+// Own particle k of wave `wid`'s own rows (the 4 rows with hx = 1 + wid): its staged slot and
+// own halo cell.  c1, c2, c3 are the wave's cumulative own counts after its rows 0, 1, 2, so
+// the row is found with three compares.
+struct OwnSlot {
+    int slot, hs;
+};
+
+__device__ __forceinline__ OwnSlot own_slot(const int *hoff, int wid, int k, int c1, int c2,
+                                            int c3)
 {
+    const int r = (k >= c1) + (k >= c2) + (k >= c3);
+    const int before = r == 0 ? 0 : (r == 1 ? c1 : (r == 2 ? c2 : c3));
+    const int rb = ((1 + wid) * kHY + 1 + r) * kHZ;
+    OwnSlot o;
+    o.slot = hoff[rb + 1] + (k - before);
+    o.hs = rb + 1 + last_le<kTileZ>(hoff + rb + 1, o.slot);
+    return o;
+}
+
+// ---------------------------------------------------------------------------------------
+// Pair queue of one wave.  A particle's candidates in one neighbour row are one contiguous
+// range of staged slots, an item (particle slot, first slot, length).  Lanes test pairs,
+// not particles: items are appended to a ring in LDS in the order the wave produces them,
+// their pairs numbered consecutively, and each round lane l tests pair base + l.  A lane
+// finds its item from markers: the items after `head` write a byte at their first pair's
+// position in the round, and the lane counts the marks at or below its own position.  So
+// every lane tests one pair per round however unequal the candidate counts are, where a
+// loop per particle would keep the wave as long as its busiest lane.
+// ---------------------------------------------------------------------------------------
+constexpr int kRing = 128;  // live items never exceed 64 (pending) + 64 (one new row step)
+constexpr int kSlotBits = 10;
+static_assert(kTileCap <= (1 << kSlotBits), "staged slots are packed in 10 bits");
+
+struct PairQueue {
+    int head;   // ring index of the item holding pair `base` (or ending right at it)
+    int tail;   // ring index past the last item
+    int base;   // first pair not tested yet
+    int total;  // pairs queued so far
+};
+
+struct TileLds {
+    const float4 *part;
+    int *lpar;
+    const int *hoff, *gst;    // the halo table (a slot's sorted index, on the rare deferred hook)
+    const uint64_t *ownw;     // bit per staged slot: an own particle of this tile
+    unsigned char *fbyte;     // staged slots that have a friend
+};
+
+// Sorted index of staged slot sl: the halo cell whose offset range holds it, then its start.
+__device__ __forceinline__ uint32_t slot_index(const int *hoff, const int *gst, int sl)
+{
+    const int h = last_le<kHalo>(hoff, sl);
+    return (uint32_t)(gst[h] + (sl - hoff[h]));
+}
+
+// Tests pairs [q.base, q.base + cnt) of the wave's queue, one per lane (cnt <= kWave).
+template <class Hook>
+__device__ __forceinline__ void queue_round(const Pred &P, const TileLds &T, const int2 *ring,
+                                            volatile unsigned char *mark, PairQueue &q,
+                                            int cnt, const Hook &hook)
+{
+    const int lane = lane_id();
+    const int it = q.head + 1 + lane;
+    const int rel = it < q.tail ? ring[it & (kRing - 1)].x - q.base : kWave;
+    if (rel < kWave)  // items after head start at pair base or later: rel >= 0
+        mark[rel] = 1;
+    __asm__ __volatile__("" ::: "memory");  // the wave's LDS operations complete in order
+    const uint64_t m = __ballot(mark[lane] != 0);
+    mark[lane] = 0;
+    const int mine = q.head + __popcll(m & ((2ull << lane) - 1ull));
+    q.head += __popcll(m);
+    if (lane < cnt) {
+        const int2 iv = ring[mine & (kRing - 1)];
+        const int ps = iv.y >> kSlotBits;
+        const int j = (iv.y & ((1 << kSlotBits) - 1)) + (q.base + lane - iv.x);
+        if (j != ps) {
+            const float4 p = T.part[ps], c = T.part[j];
+            if (linked(P, p.x, p.y, p.z, c.x, c.y, c.z)) {
+                T.fbyte[ps] = 1;
+                if (__float_as_int(p.w) < __float_as_int(c.w)) {  // hooked from one end
+                    if ((T.ownw[j >> 6] >> (j & 63)) & 1ull)
+                        lds_union(T.lpar, T.part, ps, j);
+                    else
+                        hook(slot_index(T.hoff, T.gst, ps), slot_index(T.hoff, T.gst, j));
+                }
+            }
+        }
+    }
+    q.base += cnt;
+}
+
+__global__ __launch_bounds__(kTileBlock, 5) void k_link_tiled(Work w, int32_t *__restrict__ root)
+{
+    constexpr int kWaves = kTileBlock / kWave;
     __shared__ float4 part[kTileCap];
     __shared__ int hoff[kHalo + 1];  // staged offset of each halo cell
     __shared__ int gst[kHalo];       // global (sorted) start, or -1 - dense id
-    __shared__ int ownoff[kOwnRows + 1];
-    __shared__ int scr[kTileBlock / kWave];
+    __shared__ int scr[kWaves];
     __shared__ int lpar[kTileCap];   // LDS union-find over staged slots
     __shared__ int2 lbuf[kLocalEdges];  // deferred hooks of this tile
+    __shared__ int2 ring[kWaves][kRing];
+    __shared__ uint64_t ownw[kTileCap / kWave];
+    __shared__ uint64_t rowbad;      // bit r: halo row r is not one contiguous global run
+    __shared__ int rstart[kRowsH];   // staged offset of each halo row
+    __shared__ unsigned char fbyte[kTileCap];
+    __shared__ unsigned char mark[kWaves][kWave];
     __shared__ int lcnt, lover, gbase;
 
     const int64_t tile = xcd_block();
@@ -305,8 +370,17 @@ __global__ __launch_bounds__(kTileBlock, 6) void k_link_tiled(Work w, int32_t *_
     const Pred P = pred_of(B);
     const TileGeom g = tile_geom(B, tile);
     const bool box_dense = w.dense_cap > 0 && w.dense_threshold >= 0 && B.dense_ok;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
 
+    if (t == 0) {
+        rowbad = 0;
+        lcnt = 0;
+        lover = 0;
+    }
+    mark[wid][lane] = 0;
+#pragma unroll
+    for (int k = 0; k < kStagePerT; ++k)
+        fbyte[t + k * kTileBlock] = 0;
     const int total = build_halo(w, B, g, box_dense, hoff, gst, scr);
     if (t == 0)
         FOF_STAT(w.ctr, ST_TILES, 1);
@@ -317,52 +391,130 @@ __global__ __launch_bounds__(kTileBlock, 6) void k_link_tiled(Work w, int32_t *_
         }
         return;
     }
-    if (t <= kOwnRows) {  // own particles before each own row
-        int acc = 0;
-        for (int r = 0; r < t; ++r) {
-            const int hx = 1 + r / kTileY, hy = 1 + r % kTileY;
-            const int rb = (hx * kHY + hy) * kHZ;
-            if (hx < g.hxe && hy < g.hye)
-                acc += hoff[rb + g.hze] - hoff[rb + 1];
+    // A halo row is staged by plain copying when its cells are one contiguous run of the
+    // sorted particles: every cell starts where the run says (no clique cell cut out, no
+    // wrap of the z index inside the row).
+#pragma unroll
+    for (int k = 0; k < kPerT; ++k) {
+        const int h = t * kPerT + k;
+        if (h < kHalo) {
+            const int r0 = h - h % kHZ;
+            if (gst[h] != gst[r0] + (hoff[h] - hoff[r0]) || gst[r0] < 0)
+                atomicOr((unsigned long long *)&rowbad, 1ull << (h / kHZ));
         }
-        ownoff[t] = acc;
     }
-    if (t == 0) {
-        lcnt = 0;
-        lover = 0;
-    }
+    if (t < kRowsH)
+        rstart[t] = hoff[t * kHZ];
+    __syncthreads();
+    // staging, slot by slot: the row by a search over the 36 row starts, then a plain offset
+    // into the row's run (or, in a row that is not one run, a search over its cells).  The
+    // own-slot bitmap comes out of the same pass: a wave's lanes hold 64 consecutive slots.
+    const uint64_t bad = rowbad;
 #pragma unroll
     for (int k = 0; k < kStagePerT; ++k) {  // LDS stores cannot alias the global loads
         const int sl = t + k * kTileBlock;
+        bool own = false;
         if (sl < total) {
-            const int h = last_le<kHalo>(hoff, sl);
-            part[sl] = w.sorted[gst[h] + (sl - hoff[h])];
+            const int row = last_le<kRowsH>(rstart, sl);
+            const int rb = row * kHZ;
+            int src;
+            if (!((bad >> row) & 1ull)) {
+                src = gst[rb] + (sl - rstart[row]);
+            } else {
+                const int h = rb + last_le<kHZ>(hoff + rb, sl);
+                src = gst[h] + (sl - hoff[h]);
+            }
+            const int hx = row / kHY, hy = row - hx * kHY;
+            own = hx >= 1 && hx < g.hxe && hy >= 1 && hy < g.hye && sl >= hoff[rb + 1] &&
+                  sl < hoff[rb + g.hze];
+            part[sl] = w.sorted[src];
             lpar[sl] = sl;
         }
+        const uint64_t ob = __ballot(own);
+        if (lane == 0)
+            ownw[sl >> 6] = ob;
     }
     __syncthreads();
 
-    const int nown = ownoff[kOwnRows];
-    if (t == 0)
-        FOF_STAT(w.ctr, ST_OWN_STAGED, nown);
-    // phase A: candidate search; pairs of own particles are joined in LDS, every other hook
-    // (halo particles of other tiles, dense cells) goes to the global forest
-    const DeferHook hook{lbuf, &lcnt, &lover, w.edges, &w.ctr->n_link_edges, w.edge_cap};
-    uint32_t fmask = 0;  // bit q: own particle t + q * kTileBlock has a friend
-    for (int k = t, q = 0; k < nown; k += kTileBlock, ++q) {
-        int r = 0;
-        while (ownoff[r + 1] <= k)
-            ++r;
-        const int rb = ((1 + r / kTileY) * kHY + 1 + r % kTileY) * kHZ;
-        const int slot = hoff[rb + 1] + (k - ownoff[r]);
-        const int hs = rb + 1 + last_le<kTileZ>(hoff + rb + 1, slot);  // own halo cell
-        const int64_t i = gst[hs] + (slot - hoff[hs]);
-        const float4 p = part[slot];
-        const int hz = hs % kHZ, hy = (hs / kHZ) % kHY, hx = hs / (kHZ * kHY);
-        if (link_staged(w, B, P, box_dense, part, hoff, gst, i, p, slot, hx, hy, hz, g.x0 - 1 + hx,
-                        g.y0 - 1 + hy, g.z0 - 1 + hz, nullptr, 0, lpar, g, hook))
-            fmask |= 1u << q;
+    // own particles: wave wid takes the own rows with hx = 1 + wid
+    const bool own_plane = 1 + wid < g.hxe;
+    int c1 = 0, c2 = 0, c3 = 0, nown = 0;
+    if (own_plane) {
+        int acc = 0;
+#pragma unroll
+        for (int r = 0; r < kTileY; ++r) {
+            const int rb = ((1 + wid) * kHY + 1 + r) * kHZ;
+            if (1 + r < g.hye)
+                acc += hoff[rb + g.hze] - hoff[rb + 1];
+            if (r == 0)
+                c1 = acc;
+            else if (r == 1)
+                c2 = acc;
+            else if (r == 2)
+                c3 = acc;
+        }
+        nown = acc;
     }
+    if (lane == 0)
+        FOF_STAT(w.ctr, ST_OWN_STAGED, nown);
+    // phase A: candidate search through the wave's pair queue; pairs of own particles are
+    // joined in LDS, every other hook (halo particles of other tiles) is deferred to the
+    // edge list
+    const DeferHook hook{lbuf, &lcnt, &lover, w.edges, &w.ctr->n_link_edges, w.edge_cap};
+    const TileLds T{part, lpar, hoff, gst, ownw, fbyte};
+    int2 *wring = ring[wid];
+    volatile unsigned char *wmark = mark[wid];
+    PairQueue q{0, 0, 0, 0};
+    for (int k0 = 0; k0 < nown; k0 += kWave) {  // wave-uniform
+        const int k = k0 + lane;
+        const bool act = k < nown;
+        int slot = 0, hx = 0, hy = 0, hz = 0, nrow = 0, ny = 1;
+        AxisSpan sx{0, 0}, sy{0, 0}, sz{0, 0};
+        if (act) {
+            const OwnSlot o = own_slot(hoff, wid, k, c1, c2, c3);
+            slot = o.slot;
+            const float4 p = part[slot];
+            hz = o.hs % kHZ;
+            hy = (o.hs / kHZ) % kHY;
+            hx = o.hs / (kHZ * kHY);
+            sx = axis_span(p.x, g.x0 - 1 + hx, B.side[0], B.nc[0], B.reach);
+            sy = axis_span(p.y, g.y0 - 1 + hy, B.side[1], B.nc[1], B.reach);
+            sz = axis_span(p.z, g.z0 - 1 + hz, B.side[2], B.nc[2], B.reach);
+            ny = sy.hi - sy.lo + 1;
+            nrow = (sx.hi - sx.lo + 1) * ny;
+        }
+        for (int s = 0; __ballot(s < nrow) != 0; ++s) {
+            int a = 0, len = 0;
+            if (s < nrow) {
+                const int kx = s / ny, ky = s - kx * ny;
+                const int rb2 = ((hx + span_offset(sx, kx)) * kHY + hy + span_offset(sy, ky)) * kHZ;
+                a = hoff[rb2 + hz + sz.lo];
+                len = hoff[rb2 + hz + sz.hi + 1] - a;
+            }
+            int x = len;  // inclusive scan over the wave
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(x, o, kWave);
+                if (lane >= o)
+                    x += y;
+            }
+            const int ts = __shfl(x, kWave - 1, kWave);
+            const uint64_t ne = __ballot(len > 0);
+            if (len > 0) {
+                const int idx = q.tail + __popcll(ne & ((1ull << lane) - 1ull));
+                wring[idx & (kRing - 1)] = make_int2(q.total + x - len, a | (slot << kSlotBits));
+            }
+            q.tail += __popcll(ne);
+            q.total += ts;
+            if (lane == 0)
+                FOF_STAT(w.ctr, ST_PAIRS_TILED, ts);
+            __asm__ __volatile__("" ::: "memory");  // ring stores before the round's loads
+            while (q.total - q.base >= kWave)
+                queue_round(P, T, wring, wmark, q, kWave, hook);
+        }
+    }
+    if (q.total > q.base)
+        queue_round(P, T, wring, wmark, q, q.total - q.base, hook);
     __syncthreads();
     {  // move the LDS edge buffer to the global list
         const int nl = min(lcnt, kLocalEdges);
@@ -376,39 +528,24 @@ __global__ __launch_bounds__(kTileBlock, 6) void k_link_tiled(Work w, int32_t *_
                 lover = 1;
         }
     }
-    static_assert(kTileCap / kTileBlock <= 32, "friend bits of one thread fit one word");
     __syncthreads();
     // phase B: publish the local forest.  No thread of this kernel hooks in the global
     // forest, so every own entry still holds itself and a plain store points it at its local
-    // root.  Particles with no friend write their final label.
-    for (int base = 0, q = 0; base < nown; base += kTileBlock, ++q) {
-        const int k = base + t;
-        const bool active = k < nown;
-        int64_t i = 0;
-        bool f = false;
-        if (active) {
-            int r = 0;
-            while (ownoff[r + 1] <= k)
-                ++r;
-            const int rb = ((1 + r / kTileY) * kHY + 1 + r % kTileY) * kHZ;
-            const int slot = hoff[rb + 1] + (k - ownoff[r]);
-            const int hs = rb + 1 + last_le<kTileZ>(hoff + rb + 1, slot);
-            i = gst[hs] + (slot - hoff[hs]);
-            const int32_t oi = __float_as_int(part[slot].w);
-            f = (fmask >> q) & 1u;
-            if (!f) {
-                root[oi] = oi;
-            } else {
-                FOF_STAT(w.ctr, ST_SPARE, 1);
-                const int lr = lds_find_ro(lpar, slot);
-                if (lr != slot) {
-                    const int hr = last_le<kHalo>(hoff, lr);
-                    const uint32_t ir = (uint32_t)(gst[hr] + (lr - hoff[hr]));
-                    w.parent[i] = ((uint64_t)(uint32_t)__float_as_int(part[lr].w) << 32) | ir;
-                }
-            }
+    // root.  Particles with no friend write their final label; the others set their bit of
+    // the flag bitmap.
+    for (int k = lane; k < nown; k += kWave) {
+        const OwnSlot o = own_slot(hoff, wid, k, c1, c2, c3);
+        const int64_t i = gst[o.hs] + (o.slot - hoff[o.hs]);
+        const int32_t oi = __float_as_int(part[o.slot].w);
+        if (!fbyte[o.slot]) {
+            root[oi] = oi;
+        } else {
+            const int lr = lds_find_ro(lpar, o.slot);
+            if (lr != o.slot)
+                w.parent[i] = ((uint64_t)(uint32_t)__float_as_int(part[lr].w) << 32) |
+                              slot_index(hoff, gst, lr);
+            atomicOr((unsigned long long *)(w.flags + (i >> 6)), 1ull << (i & 63));
         }
-        flag_friends_wave(w.flags, active, i, f);
     }
     __syncthreads();
     if (t == 0 && lover)  // some hooks were lost: the windowed kernel redoes the tile
@@ -517,8 +654,8 @@ __global__ __launch_bounds__(kTileBlock) void k_link_windows(Work w, int32_t *__
                 if (fits) {
                     const int ls = wbase[row] + slot - hoff[rb + za - 1];
                     p = part[ls];
-                    f = link_staged(w, B, P, box_dense, part, hoff, gst, i, p, ls, hx, hy, hz, ix,
-                                    iy, iz, wbase, za - 1, nullptr, g, DirectHook{w.parent});
+                    f = link_staged(w, B, P, part, hoff, gst, i, p, ls, hx, hy, hz, ix, iy, iz,
+                                    wbase, za - 1, DirectHook{w.parent});
                 } else {
                     p = w.sorted[i];
                     f = link_particle_global(w, B, P, i, p, ix, iy, iz);

@@ -120,9 +120,9 @@ __device__ void edges_of(const Work &w, const SampleArgs &a, int64_t i)
     const BoxDesc &B = w.desc[0];
     const float4 p = w.sorted[i];
     const int32_t oi = __float_as_int(p.w);
-    const int ix = fine_index(p.x, B.inv_fine[0], B.nf[0]) / B.m;
-    const int iy = fine_index(p.y, B.inv_fine[1], B.nf[1]) / B.m;
-    const int iz = fine_index(p.z, B.inv_fine[2], B.nf[2]) / B.m;
+    const int ix = coarse_index(p.x, B, 0);
+    const int iy = coarse_index(p.y, B, 1);
+    const int iz = coarse_index(p.z, B, 2);
     // neighbour cells within reach of the particle (the cut radius plus the index error)
     const AxisSpan sx = axis_span(p.x, ix, B.side[0], B.nc[0], B.reach);
     const AxisSpan sy = axis_span(p.y, iy, B.side[1], B.nc[1], B.reach);

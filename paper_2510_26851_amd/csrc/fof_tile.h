@@ -58,11 +58,12 @@ struct TileGeom {
 
 __device__ __forceinline__ TileGeom tile_geom(const BoxDesc &B, int64_t tile)
 {
-    int64_t tl = tile - B.tile_base;
-    const int tz = (int)(tl % B.ntile[2]);
+    // a box has fewer tiles than cells (< 2^31), so 32-bit division suffices
+    int tl = (int)(tile - B.tile_base);
+    const int tz = tl % B.ntile[2];
     tl /= B.ntile[2];
-    const int ty = (int)(tl % B.ntile[1]);
-    const int tx = (int)(tl / B.ntile[1]);
+    const int ty = tl % B.ntile[1];
+    const int tx = tl / B.ntile[1];
     TileGeom g;
     g.x0 = tx * kTileX;
     g.y0 = ty * kTileY;
@@ -79,20 +80,25 @@ __device__ __forceinline__ TileGeom tile_geom(const BoxDesc &B, int64_t tile)
 __device__ int build_halo(const Work &w, const BoxDesc &B, const TileGeom &g, bool box_dense,
                           int *hoff, int *gst, int *scr)
 {
+    static_assert(kHZ % kPerT == 0, "a thread's halo cells share one row");
     const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
     int cnt_local[kPerT];
     int sum = 0;
+    const int h0 = t * kPerT;
+    const int hz0 = h0 % kHZ, row = h0 / kHZ, hy = row % kHY, hx = row / kHY;
+    const bool row_in = h0 < kHalo && hx <= g.hxe && hy <= g.hye;
+    // the row's (x, y) column, once per thread
+    const int64_t col = row_in ? coarse_cell(B, wrap_cell(g.x0 - 1 + hx, B.nc[0]),
+                                             wrap_cell(g.y0 - 1 + hy, B.nc[1]), 0)
+                               : 0;
 #pragma unroll
     for (int k = 0; k < kPerT; ++k) {
-        const int h = t * kPerT + k;
+        const int h = h0 + k, hz = hz0 + k;
         int cnt = 0;
         if (h < kHalo) {
-            const int hz = h % kHZ, row = h / kHZ, hy = row % kHY, hx = row / kHY;
             int tag = -1, s = 0;
-            if (hx <= g.hxe && hy <= g.hye && hz <= g.hze) {
-                const int64_t c = coarse_cell(B, wrap_cell(g.x0 - 1 + hx, B.nc[0]),
-                                              wrap_cell(g.y0 - 1 + hy, B.nc[1]),
-                                              wrap_cell(g.z0 - 1 + hz, B.nc[2]));
+            if (row_in && hz <= g.hze) {
+                const int64_t c = col + wrap_cell(g.z0 - 1 + hz, B.nc[2]);
                 s = w.cell_start[c];
                 cnt = w.cell_start[c + 1] - s;
                 if (box_dense && cnt > w.dense_threshold && w.cell_count[c] >= 0) {

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # kernel name fragment -> minimum waves per SIMD
-MIN_OCCUPANCY = {"k_link_tiled": 6, "k_count": 8, "k_scatter": 8, "k_compress": 8}
+MIN_OCCUPANCY = {"k_link_tiled": 5, "k_count": 8, "k_scatter": 8, "k_compress": 8}
 
 
 def resources():

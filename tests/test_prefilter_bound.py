@@ -56,3 +56,15 @@ def test_prefilter_agrees_with_the_double_predicate():
         sel = dec >= 0
         assert np.array_equal(dec[sel] == 1, exact(xi[sel], xk[sel], tuple(L3), b))
     assert checked > 50000
+
+
+def test_coarse_index_by_multiply_high_is_exact():
+    """The kernels take the coarse index f / m of a fine index f as the high word of
+    f * ceil(2^32 / m) (m = 2..10 fine cells per coarse cell).  Exact for every fine index a
+    box can have (nf <= 10 * 2^20), checked here for all of them."""
+    import numpy as np
+
+    f = np.arange(10 * 2 ** 20 + 1, dtype=np.uint64)
+    for m in range(2, 11):
+        M = np.uint64(((1 << 32) + m - 1) // m)
+        np.testing.assert_array_equal((f * M) >> np.uint64(32), f // np.uint64(m))
