@@ -16,8 +16,12 @@
 // Particles stored in lattice order land in few buckets per block, so the staging writes and
 // the final scatter stay local, whatever the displacement of each particle from its cell.
 //
-// Per-particle form (larger grids): one atomic increment per particle gives its rank in the
-// cell, a scan gives cell_start, and a scatter writes the sorted copy.
+// Grids with more cells than 16384 sorting buckets hold (a 1024^3 box) take one more pass:
+// the placed buckets are larger, and k_bin_split cuts each into its sorting buckets.
+//
+// Per-particle form (still larger grids, or few particles on a huge grid): one atomic
+// increment per particle gives its rank in the cell, a scan gives cell_start, and a
+// scatter writes the sorted copy.
 //
 // Within a cell the order is whatever the atomics produced; no result depends on it.
 #include "fof_internal.h"
@@ -125,6 +129,26 @@ __device__ __forceinline__ BinBatch load_batch(const float *__restrict__ pos, in
     return q;
 }
 
+// Adds one to LDS counter k for every active lane and returns each lane's value before its
+// own increment.  Particles stored in lattice order put a whole wave in one bucket: then a
+// single atomic serves the wave (the lanes of one address would otherwise serialise);
+// otherwise every lane does its own.
+__device__ __forceinline__ int32_t wave_lds_inc(int32_t *cnt, int k)
+{
+    const uint64_t act = __ballot(true);
+    const int k0 = __builtin_amdgcn_readfirstlane(k);
+    if (__ballot(k == k0) == act) {
+        const int lane = lane_id();
+        const int first = __ffsll((unsigned long long)act) - 1;
+        int32_t base = 0;
+        if (lane == first)
+            base = atomicAdd(cnt + k0, __popcll(act));
+        base = __shfl(base, first, kWave);
+        return base + __popcll(act & ((1ull << lane) - 1ull));
+    }
+    return atomicAdd(cnt + k, 1);
+}
+
 __global__ __launch_bounds__(kBinBlock) void k_bin_count(const float *__restrict__ pos,
                                                          const BoxDesc *__restrict__ desc,
                                                          int nbox, int64_t n, BinShape bs,
@@ -147,7 +171,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_count(const float *__restrict
                 with_box(desc, nbox, i, [&](const BoxDesc &B) {
                     const CellOf c = cell_of(B, q.x[u], q.y[u], q.z[u]);
                     bad |= !c.ok;
-                    atomicAdd(lh + (c.cell >> bs.shift), 1);
+                    wave_lds_inc(lh, (int)(c.cell >> bs.shift));
                 });
         }
     }
@@ -178,7 +202,7 @@ __global__ __launch_bounds__(kBinBlock) void k_bin_place(const float *__restrict
             if (i < i1)
                 with_box(desc, nbox, i, [&](const BoxDesc &B) {
                     const CellOf c = cell_of(B, q.x[u], q.y[u], q.z[u]);
-                    stage[atomicAdd(cur + (c.cell >> bs.shift), 1)] =
+                    stage[wave_lds_inc(cur, (int)(c.cell >> bs.shift))] =
                         make_float4(q.x[u], q.y[u], q.z[u], __int_as_float((int32_t)i));
                 });
         }
@@ -218,21 +242,23 @@ __device__ __forceinline__ int staged_cell(const BoxDesc *__restrict__ desc, int
     return lc;
 }
 
+// Sorting bucket b's particles are stage[bounds[b * stride], bounds[(b + 1) * stride]).
 __global__ __launch_bounds__(kSortBlock) void k_bin_sort(const BoxDesc *__restrict__ desc,
                                                          int nbox, int64_t ncell, BinShape bs,
-                                                         const int32_t *__restrict__ off,
+                                                         const int32_t *__restrict__ bounds,
+                                                         int64_t stride,
                                                          const float4 *__restrict__ stage,
                                                          int32_t *__restrict__ cell_start,
                                                          float4 *__restrict__ sorted,
                                                          uint64_t *__restrict__ parent)
 {
-    extern __shared__ int32_t lc[];  // 2^shift per-cell counters, then cursors
+    extern __shared__ int32_t lc[];  // 2^sshift per-cell counters, then cursors
     __shared__ int32_t wsum[kSortBlock / kWave];
     constexpr int64_t kCap = (int64_t)kSortBlock * kSortPer;
     const int64_t b = blockIdx.x;
-    const int64_t c0 = b << bs.shift;
-    const int nc = (int)((c0 + (1ll << bs.shift) < ncell ? (1ll << bs.shift) : ncell - c0));
-    const int64_t base = off[b * bs.G], end = off[(b + 1) * bs.G];
+    const int64_t c0 = b << bs.sshift;
+    const int nc = (int)((c0 + (1ll << bs.sshift) < ncell ? (1ll << bs.sshift) : ncell - c0));
+    const int64_t base = bounds[b * stride], end = bounds[(b + 1) * stride];
     for (int k = threadIdx.x; k < nc; k += kSortBlock)
         lc[k] = 0;
     __syncthreads();
@@ -301,6 +327,48 @@ __global__ __launch_bounds__(kSortBlock) void k_bin_sort(const BoxDesc *__restri
     }
 }
 
+// Two-level binning: placed bucket b (stage[off[b * G], off[(b + 1) * G])) is split into
+// its 2^(shift - sshift) sorting buckets, counted in LDS, then copied into `out` by sorting
+// bucket; the sorting buckets' bounds go to sub_off[b * nsplit + j] (and the total to
+// sub_off[nbk * nsplit]).
+constexpr int kSplitBlock = 1024;
+
+__global__ __launch_bounds__(kSplitBlock) void k_bin_split(const BoxDesc *__restrict__ desc,
+                                                           int nbox, BinShape bs,
+                                                           const int32_t *__restrict__ off,
+                                                           const float4 *__restrict__ in,
+                                                           float4 *__restrict__ out,
+                                                           int32_t *__restrict__ sub_off)
+{
+    __shared__ int32_t cnt[1 << kBinMaxSplit];
+    const int64_t b = blockIdx.x;
+    const int nsplit = 1 << (bs.shift - bs.sshift);
+    const int64_t base = off[b * bs.G], end = off[(b + 1) * bs.G];
+    const int64_t c0 = b << bs.shift;
+    if (threadIdx.x < nsplit)
+        cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t k = base + threadIdx.x; k < end; k += kSplitBlock)
+        wave_lds_inc(cnt, staged_cell(desc, nbox, in[k], c0) >> bs.sshift);
+    __syncthreads();
+    if (threadIdx.x == 0) {  // counts -> starts (at most 64 of them)
+        int32_t run = (int32_t)base;
+        for (int j = 0; j < nsplit; ++j) {
+            const int32_t v = cnt[j];
+            cnt[j] = run;
+            sub_off[b * nsplit + j] = run;
+            run += v;
+        }
+        if (b == bs.nbk - 1)
+            sub_off[bs.nbk * nsplit] = run;
+    }
+    __syncthreads();
+    for (int64_t k = base + threadIdx.x; k < end; k += kSplitBlock) {
+        const float4 p = in[k];
+        out[wave_lds_inc(cnt, staged_cell(desc, nbox, p, c0) >> bs.sshift)] = p;
+    }
+}
+
 __global__ void k_clear_counters(Counters *ctr)
 {
     if (threadIdx.x < sizeof(Counters) / sizeof(int32_t))
@@ -324,11 +392,22 @@ hipError_t launch_build(const Work &w, const float *pos, hipStream_t s)
         e = launch_scan_i32(hist, off, bs.nbk * bs.G, w.scan, s);
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_bin_place, dim3(bs.G), dim3(kBinBlock), lds_b, s, pos, w.desc,
-                           w.nbox, w.n, bs, off, w.temp);
-        hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)bs.nbk), dim3(kSortBlock),
-                           sizeof(int32_t) << bs.shift, s, w.desc, w.nbox, w.ncell, bs, off,
-                           w.temp, w.cell_start, w.sorted, w.parent);
+        if (bs.shift == bs.sshift) {
+            hipLaunchKernelGGL(k_bin_place, dim3(bs.G), dim3(kBinBlock), lds_b, s, pos, w.desc,
+                               w.nbox, w.n, bs, off, w.temp);
+            hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)bs.nsb), dim3(kSortBlock),
+                               sizeof(int32_t) << bs.sshift, s, w.desc, w.nbox, w.ncell, bs,
+                               off, (int64_t)bs.G, w.temp, w.cell_start, w.sorted, w.parent);
+        } else {  // placed buckets staged in `sorted`, split into `temp`, sorted into `sorted`
+            int32_t *sub_off = hist;  // the counts are spent once scanned into off
+            hipLaunchKernelGGL(k_bin_place, dim3(bs.G), dim3(kBinBlock), lds_b, s, pos, w.desc,
+                               w.nbox, w.n, bs, off, w.sorted);
+            hipLaunchKernelGGL(k_bin_split, dim3((unsigned)bs.nbk), dim3(kSplitBlock), 0, s,
+                               w.desc, w.nbox, bs, off, w.sorted, w.temp, sub_off);
+            hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)bs.nsb), dim3(kSortBlock),
+                               sizeof(int32_t) << bs.sshift, s, w.desc, w.nbox, w.ncell, bs,
+                               sub_off, (int64_t)1, w.temp, w.cell_start, w.sorted, w.parent);
+        }
     } else {
         e = launch_fill_i32(w.cell_count, w.ncell, 0, s);
         if (e != hipSuccess)

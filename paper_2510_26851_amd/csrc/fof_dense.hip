@@ -544,7 +544,7 @@ __device__ __forceinline__ bool units_meet(const BoxDesc &B, const Pred &P, cons
 }
 
 // Own units of dense cell d: keys, coordinates, member ranges; bitmask into L.bits.
-template <int G, int UMAX, int CAP>
+template <int G, bool kLds, int UMAX, int CAP>
 __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n, int m, int u,
                            CellLds<UMAX, CAP> &L)
 {
@@ -558,7 +558,7 @@ __device__ void load_units(const Work &w, const int32_t *T, int32_t s, int32_t n
         L.ustart[r] = w.rank[s + r];
     if (t == 0)
         L.ustart[u] = s + n;
-    if (n <= CAP)
+    if (kLds)
         for (int k = t; k < n; k += G)
             L.part[k] = w.sorted[s + k];
     Grp<G>::sync();
@@ -673,7 +673,9 @@ __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const
     }
 }
 
-template <int G, int UMAX, int CAP>
+// kLds: the cell's particles are staged in LDS (it holds at most CAP), else read from HBM;
+// fixed per instantiation, so every member access compiles to one kind of load.
+template <int G, bool kLds, int UMAX, int CAP>
 __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
 {
     const int t = Grp<G>::tid();
@@ -686,11 +688,11 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     const int m = B.m, R = B.R;
     int32_t *T = w.table + (int64_t)d * w.table_stride;
     const int u = T[2];
-    const float4 *mem = n <= CAP ? L.part : w.sorted + s;  // indexed by (sorted index - s)
+    const float4 *mem = kLds ? L.part : w.sorted + s;  // indexed by (sorted index - s)
 
     if (t == 0)
         L.ncomp = 0;
-    load_units<G>(w, T, s, n, m, u, L);
+    load_units<G, kLds>(w, T, s, n, m, u, L);
     FOF_PHASE(L, t == 0, 0);
 
     // unit minima, one thread per member (a unit of a clump core can hold thousands); a
@@ -803,7 +805,9 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     FOF_PHASE(L, t == 0, 6);
 }
 
-template <int G, int UMAX, int CAP>
+// kLds: the cell's particles are staged in LDS (it holds at most CAP), else read from HBM;
+// fixed per instantiation, so every member access compiles to one kind of load.
+template <int G, bool kLds, int UMAX, int CAP>
 __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
 {
     const int t = Grp<G>::tid();
@@ -846,14 +850,14 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
         Grp<G>::sync();
         return;
     }
-    const float4 *mem = n <= CAP ? L.part : w.sorted + s;
+    const float4 *mem = kLds ? L.part : w.sorted + s;
     for (int r = t; r < u; r += G) {
         L.ustart[r] = w.rank[s + r];
         L.ucomp[r] = (short)w.cnt[s + r];
     }
     if (t == 0)
         L.ustart[u] = s + n;
-    if (n <= CAP)
+    if (kLds)
         for (int k = t; k < n; k += G)
             L.part[k] = w.sorted[s + k];
     for (int q = t; q < W; q += G) {
@@ -995,7 +999,9 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
 // (the face test of the sparse search, from q's side), then only against the fine cells
 // within reach of q, one friend per component of this cell.  q is then marked in the flag
 // bitmap, so the compress pass gives it its component's label.
-template <int G, int UMAX, int CAP>
+// kLds: the cell's particles are staged in LDS (it holds at most CAP), else read from HBM;
+// fixed per instantiation, so every member access compiles to one kind of load.
+template <int G, bool kLds, int UMAX, int CAP>
 __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
 {
     const int t = Grp<G>::tid();
@@ -1051,11 +1057,11 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     }
     if (t == 0)
         L.ustart[u] = s + n;
-    if (n <= CAP)
+    if (kLds)
         for (int k = t; k < n; k += G)
             L.part[k] = w.sorted[s + k];
     Grp<G>::sync();
-    const float4 *mem = n <= CAP ? L.part : w.sorted + s;
+    const float4 *mem = kLds ? L.part : w.sorted + s;
     const int total = L.nbp[nnb];
     FOF_PHASE(L, t == 0, 1);
     for (int e = t; e < total; e += G) {
@@ -1166,11 +1172,11 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
         const int64_t c = w.dense_list[d];
         if (w.cell_start[c + 1] - w.cell_start[c] <= kSmallCell) {
             if (kMode == 1)
-                cross_cell<kWave>(w, d, L);
+                cross_cell<kWave, true>(w, d, L);
             else if (kMode == 2)
-                sparse_cell<kWave>(w, d, L);
+                sparse_cell<kWave, true>(w, d, L);
             else
-                cc_cell<kWave>(w, d, L);
+                cc_cell<kWave, true>(w, d, L);
         }
         int nx = 0;
         if (lane_id() == 0)
@@ -1180,7 +1186,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
     }
     FOF_PHASE(L, lane_id() == 0, 7);
     FOF_PHASE_FLUSH(L, lane_id() == 0 && kMode == 0, w.ctr, 0);
-#ifdef FOF_TIMING
+#if defined(FOF_TIMING) && !defined(FOF_TIMING_BIG)
     if (lane_id() == 0 && kMode != 0)
         for (int k = 0; k < 4; ++k)
             atomicAdd(&w.ctr->stats[16 + 4 * (kMode - 1) + k], (unsigned long long)L.phase[k]);
@@ -1198,12 +1204,22 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
     FOF_PHASE_START(L, threadIdx.x == 0);
     for (int k = deal_first(dl, blockIdx.x); k < nb;) {
         const int d = w.big_list[k];
-        if (kMode == 1)
-            cross_cell<kDenseBlock>(w, d, L);
-        else if (kMode == 2)
-            sparse_cell<kDenseBlock>(w, d, L);
-        else
-            cc_cell<kDenseBlock>(w, d, L);
+        const int64_t c = w.dense_list[d];
+        if (w.cell_start[c + 1] - w.cell_start[c] <= kLdsCap) {
+            if (kMode == 1)
+                cross_cell<kDenseBlock, true>(w, d, L);
+            else if (kMode == 2)
+                sparse_cell<kDenseBlock, true>(w, d, L);
+            else
+                cc_cell<kDenseBlock, true>(w, d, L);
+        } else {
+            if (kMode == 1)
+                cross_cell<kDenseBlock, false>(w, d, L);
+            else if (kMode == 2)
+                sparse_cell<kDenseBlock, false>(w, d, L);
+            else
+                cc_cell<kDenseBlock, false>(w, d, L);
+        }
         if (threadIdx.x == 0)
             next = deal_next(dl, nb);
         __syncthreads();
@@ -1213,6 +1229,11 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
     }
     FOF_PHASE(L, threadIdx.x == 0, 7);
     FOF_PHASE_FLUSH(L, threadIdx.x == 0 && kMode == 0, w.ctr, 8);
+#if defined(FOF_TIMING) && defined(FOF_TIMING_BIG)  // diagnostic: big cells' pair passes
+    if (threadIdx.x == 0 && kMode != 0)
+        for (int k = 0; k < 4; ++k)
+            atomicAdd(&w.ctr->stats[16 + 4 * (kMode - 1) + k], (unsigned long long)L.phase[k]);
+#endif
 
 }
 

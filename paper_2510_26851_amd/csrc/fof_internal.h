@@ -340,25 +340,53 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Orders the LDS accesses of a wave's lanes around it (LDS operations of one wave complete
+// in issue order, so no wait is needed beyond keeping the compiler from moving them).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Inclusive sum over the lanes of a wave (lane l gets lanes 0..l): shifts by 1, 2, 4, 8 lanes
+// inside each row of 16, then the totals of rows 0 and 0-1 broadcast into the rows above
+// (data-parallel primitives of the wave64 VALU, no LDS traffic).  Every lane must be active.
+__device__ __forceinline__ int wave_incl_sum(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 }  // namespace fof
 
 // ---------------------------------------------------------------------------------------
 // Host-side launchers (defined in the .hip files, called by the entry points).
 // ---------------------------------------------------------------------------------------
 namespace fof {
-// Shape of the bucketed cell binning (fof_build.hip): cells are grouped into buckets of
-// 2^shift consecutive cell ids (at most kBinMaxBuckets of them, each at most
-// 2^kBinMaxShift cells, so both per-block tables fit in LDS); G blocks each stream one
-// contiguous chunk of particles.  ok = false: too many cells, the per-particle counting
-// sort is used instead.
+// Shape of the bucketed cell binning (fof_build.hip).  Cells are sorted in buckets of
+// 2^sshift consecutive cell ids (sshift <= kBinSortShift, so a sorting block's per-cell
+// table fits in LDS).  Particles are first placed by bucket of 2^shift cells (at most
+// kBinMaxBuckets buckets, so a placing block's histogram fits in LDS); G blocks each stream
+// one contiguous chunk of particles.  When a grid has more cells than kBinMaxBuckets
+// sorting buckets hold, shift > sshift: each placed bucket is split once more, into
+// 2^(shift - sshift) sorting buckets (two-level).  ok = false: too many cells even so,
+// the per-particle counting sort is used instead.
 constexpr int kBinMaxBuckets = 16384;
-constexpr int kBinMaxShift = 13;
+constexpr int kBinSortShift = 13;
+constexpr int kBinMaxSplit = 6;   // at most 64 sorting buckets per placed bucket
 constexpr int kBinMaxBlocks = 512;
 
 struct BinShape {
-    int shift;
+    int shift;    // cells per placed bucket: 2^shift
+    int sshift;   // cells per sorting bucket: 2^sshift
     int G;
-    int64_t nbk;
+    int64_t nbk;  // placed buckets
+    int64_t nsb;  // sorting buckets
     int64_t chunk;
     bool ok;
 };
@@ -368,16 +396,25 @@ __host__ __device__ inline BinShape bin_shape(int64_t n, int64_t ncell)
     BinShape b;
     // buckets of about 8192 particles (what one sorting block holds in registers), then
     // larger ones if there would be too many buckets
-    b.shift = 6;
-    while (b.shift < kBinMaxShift && (ncell >> b.shift) * 8192 > n)
-        ++b.shift;
-    while (b.shift < kBinMaxShift && ((ncell + (1ll << b.shift) - 1) >> b.shift) > kBinMaxBuckets)
+    b.sshift = 6;
+    while (b.sshift < kBinSortShift && (ncell >> b.sshift) * 8192 > n)
+        ++b.sshift;
+    while (b.sshift < kBinSortShift &&
+           ((ncell + (1ll << b.sshift) - 1) >> b.sshift) > kBinMaxBuckets)
+        ++b.sshift;
+    b.shift = b.sshift;
+    while (b.shift < b.sshift + kBinMaxSplit &&
+           ((ncell + (1ll << b.shift) - 1) >> b.shift) > kBinMaxBuckets)
         ++b.shift;
     b.nbk = (ncell + (1ll << b.shift) - 1) >> b.shift;
-    b.ok = n > 0 && ncell > 0 && b.nbk <= kBinMaxBuckets;
+    b.nsb = (ncell + (1ll << b.sshift) - 1) >> b.sshift;
     int64_t g = (n + 32767) / 32768;
     b.G = (int)(g < 1 ? 1 : (g > kBinMaxBlocks ? kBinMaxBlocks : g));
     b.chunk = (n + b.G - 1) / b.G;
+    // a split keeps the sorting buckets' bounds in the (bucket, block) table: nsb + 1 <=
+    // nbk * G entries
+    b.ok = n > 0 && ncell > 0 && b.nbk <= kBinMaxBuckets &&
+           (b.shift == b.sshift || (1ll << (b.shift - b.sshift)) < b.G);
     return b;
 }
 

@@ -4,10 +4,10 @@
 //
 // Each particle tests every candidate in the neighbour cells that its own position can
 // reach (a neighbour cell is skipped when the particle is farther than `reach` from the
-// shared face), so every pair is tested from both ends.  That lets a particle that finds
-// no friend write its final label (itself) at once; only particles with at least one
-// friend are marked in the flag bitmap and resolved by the compress pass.  Each friend
-// pair is hooked once, from its lower original index.
+// shared face), so every pair is tested from both ends (the tiled kernel tests a pair of
+// its own particles once and marks both).  That lets a particle that finds no friend write
+// its final label (itself) at once; only particles with at least one friend are marked in
+// the flag bitmap and resolved by the compress pass.  Each friend pair is hooked once.
 //
 // Cells with clique tables (fof_dense.hip) are skipped here: the dense kernels link their
 // own particles and, after these kernels, the ordinary particles around them
@@ -213,6 +213,27 @@ __device__ __forceinline__ int lds_find_ro(const int *lpar, int x)
     return x;
 }
 
+// Sets the friend bit of sorted index i for every active lane with has_friend.  The lanes
+// of a wave hold increasing sorted indices, so lanes sharing a 64-bit word are adjacent:
+// their bits are OR-ed across the wave and the first lane of each word does one atomic.
+__device__ __forceinline__ void flag_friends_wave(uint64_t *flags, bool active, int64_t i,
+                                                  bool has_friend)
+{
+    const int lane = lane_id();
+    const int64_t word = active ? (i >> 6) : -1;
+    uint64_t v = (active && has_friend) ? (1ull << (i & 63)) : 0ull;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t w2 = __shfl_down(word, o, kWave);
+        const uint64_t v2 = __shfl_down(v, o, kWave);
+        if (lane + o < kWave && w2 == word)
+            v |= v2;
+    }
+    const int64_t wprev = __shfl_up(word, 1, kWave);
+    if (active && v && (lane == 0 || wprev != word))
+        atomicOr((unsigned long long *)(flags + word), (unsigned long long)v);
+}
+
 // Candidates of particle p (sorted index i, own halo cell (hx, hy, hz)) in the staged
 // window of the windowed kernel: neighbour row r's halo cells [z_first, ...] sit at LDS
 // wb[r] + slot - hoff[...].  Returns whether p has a friend; pairs are hooked from the
@@ -310,10 +331,30 @@ __device__ __forceinline__ uint32_t slot_index(const int *hoff, const int *gst, 
     return (uint32_t)(gst[h] + (sl - hoff[h]));
 }
 
+// Appends each lane's item (candidate slots [a, a + len) of the particle in `slot`; len 0:
+// none) to the wave's ring, numbering its pairs after those queued so far.
+__device__ __forceinline__ void queue_push(int2 *ring, PairQueue &q, int a, int len, int slot,
+                                           Counters *ctr)
+{
+    const int lane = lane_id();
+    const int x = wave_incl_sum(len);
+    const int ts = __builtin_amdgcn_readlane(x, kWave - 1);
+    const uint64_t ne = __ballot(len > 0);
+    if (len > 0) {
+        const int idx = q.tail + __popcll(ne & ((1ull << lane) - 1ull));
+        ring[idx & (kRing - 1)] = make_int2(q.total + x - len, a | (slot << kSlotBits));
+    }
+    q.tail += __popcll(ne);
+    q.total += ts;
+    if (lane == 0)
+        FOF_STAT(ctr, ST_PAIRS_TILED, ts);
+    wave_sync();  // ring stores before the rounds' loads
+}
+
 // Tests pairs [q.base, q.base + cnt) of the wave's queue, one per lane (cnt <= kWave).
 template <class Hook>
 __device__ __forceinline__ void queue_round(const Pred &P, const TileLds &T, const int2 *ring,
-                                            volatile unsigned char *mark, PairQueue &q,
+                                            unsigned char *mark, PairQueue &q,
                                             int cnt, const Hook &hook)
 {
     const int lane = lane_id();
@@ -321,7 +362,7 @@ __device__ __forceinline__ void queue_round(const Pred &P, const TileLds &T, con
     const int rel = it < q.tail ? ring[it & (kRing - 1)].x - q.base : kWave;
     if (rel < kWave)  // items after head start at pair base or later: rel >= 0
         mark[rel] = 1;
-    __asm__ __volatile__("" ::: "memory");  // the wave's LDS operations complete in order
+    wave_sync();  // the marks of every lane before any lane reads its own
     const uint64_t m = __ballot(mark[lane] != 0);
     mark[lane] = 0;
     const int mine = q.head + __popcll(m & ((2ull << lane) - 1ull));
@@ -334,11 +375,13 @@ __device__ __forceinline__ void queue_round(const Pred &P, const TileLds &T, con
             const float4 p = T.part[ps], c = T.part[j];
             if (linked(P, p.x, p.y, p.z, c.x, c.y, c.z)) {
                 T.fbyte[ps] = 1;
-                if (__float_as_int(p.w) < __float_as_int(c.w)) {  // hooked from one end
-                    if ((T.ownw[j >> 6] >> (j & 63)) & 1ull)
+                if ((T.ownw[j >> 6] >> (j & 63)) & 1ull) {  // tested only from here
+                    T.fbyte[j] = 1;
+                    if (T.lpar[ps] != T.lpar[j])  // one parent: already one set
                         lds_union(T.lpar, T.part, ps, j);
-                    else
-                        hook(slot_index(T.hoff, T.gst, ps), slot_index(T.hoff, T.gst, j));
+                } else if (__float_as_int(p.w) < __float_as_int(c.w)) {
+                    // a halo particle's own tile tests the pair too: hooked from one end
+                    hook(slot_index(T.hoff, T.gst, ps), slot_index(T.hoff, T.gst, j));
                 }
             }
         }
@@ -463,7 +506,7 @@ __global__ __launch_bounds__(kTileBlock, 5) void k_link_tiled(Work w, int32_t *_
     const DeferHook hook{lbuf, &lcnt, &lover, w.edges, &w.ctr->n_link_edges, w.edge_cap};
     const TileLds T{part, lpar, hoff, gst, ownw, fbyte};
     int2 *wring = ring[wid];
-    volatile unsigned char *wmark = mark[wid];
+    unsigned char *wmark = mark[wid];
     PairQueue q{0, 0, 0, 0};
     for (int k0 = 0; k0 < nown; k0 += kWave) {  // wave-uniform
         const int k = k0 + lane;
@@ -484,33 +527,33 @@ __global__ __launch_bounds__(kTileBlock, 5) void k_link_tiled(Work w, int32_t *_
             nrow = (sx.hi - sx.lo + 1) * ny;
         }
         for (int s = 0; __ballot(s < nrow) != 0; ++s) {
-            int a = 0, len = 0;
+            // the row's candidates, cut to the pairs this particle tests: each pair of own
+            // particles is tested once, from the lower halo row or, in one row, from the
+            // lower slot, so an own row below this particle's row contributes its halo cells
+            // only and its own row the slots above its own
+            int a1 = 0, l1 = 0, a2 = 0, l2 = 0;
             if (s < nrow) {
                 const int kx = s / ny, ky = s - kx * ny;
-                const int rb2 = ((hx + span_offset(sx, kx)) * kHY + hy + span_offset(sy, ky)) * kHZ;
-                a = hoff[rb2 + hz + sz.lo];
-                len = hoff[rb2 + hz + sz.hi + 1] - a;
+                const int qx = hx + span_offset(sx, kx), qy = hy + span_offset(sy, ky);
+                const int rq = qx * kHY + qy, rb2 = rq * kHZ;
+                const int a = hoff[rb2 + hz + sz.lo], e = hoff[rb2 + hz + sz.hi + 1];
+                a1 = a;
+                if (rq > hx * kHY + hy || qx < 1 || qx >= g.hxe || qy < 1 || qy >= g.hye) {
+                    l1 = e - a;
+                } else {
+                    l1 = max(0, min(e, hoff[rb2 + 1]) - a);
+                    a2 = max(a, rq == hx * kHY + hy ? slot + 1 : hoff[rb2 + g.hze]);
+                    l2 = max(0, e - a2);
+                }
             }
-            int x = len;  // inclusive scan over the wave
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int y = __shfl_up(x, o, kWave);
-                if (lane >= o)
-                    x += y;
-            }
-            const int ts = __shfl(x, kWave - 1, kWave);
-            const uint64_t ne = __ballot(len > 0);
-            if (len > 0) {
-                const int idx = q.tail + __popcll(ne & ((1ull << lane) - 1ull));
-                wring[idx & (kRing - 1)] = make_int2(q.total + x - len, a | (slot << kSlotBits));
-            }
-            q.tail += __popcll(ne);
-            q.total += ts;
-            if (lane == 0)
-                FOF_STAT(w.ctr, ST_PAIRS_TILED, ts);
-            __asm__ __volatile__("" ::: "memory");  // ring stores before the round's loads
+            queue_push(wring, q, a1, l1, slot, w.ctr);
             while (q.total - q.base >= kWave)
                 queue_round(P, T, wring, wmark, q, kWave, hook);
+            if (__ballot(l2 > 0) != 0) {
+                queue_push(wring, q, a2, l2, slot, w.ctr);
+                while (q.total - q.base >= kWave)
+                    queue_round(P, T, wring, wmark, q, kWave, hook);
+            }
         }
     }
     if (q.total > q.base)
@@ -532,20 +575,35 @@ __global__ __launch_bounds__(kTileBlock, 5) void k_link_tiled(Work w, int32_t *_
     // phase B: publish the local forest.  No thread of this kernel hooks in the global
     // forest, so every own entry still holds itself and a plain store points it at its local
     // root.  Particles with no friend write their final label; the others set their bit of
-    // the flag bitmap.
+    // the flag bitmap, one atomic per word and wave.  The rings are free now: they hold the
+    // sorted index of every own slot, which local roots (own slots) are looked up in.
+    int *gown = reinterpret_cast<int *>(&ring[0][0]);
+    static_assert(sizeof(ring) >= kTileCap * sizeof(int), "own indices fit the rings");
     for (int k = lane; k < nown; k += kWave) {
         const OwnSlot o = own_slot(hoff, wid, k, c1, c2, c3);
-        const int64_t i = gst[o.hs] + (o.slot - hoff[o.hs]);
-        const int32_t oi = __float_as_int(part[o.slot].w);
-        if (!fbyte[o.slot]) {
-            root[oi] = oi;
-        } else {
-            const int lr = lds_find_ro(lpar, o.slot);
-            if (lr != o.slot)
-                w.parent[i] = ((uint64_t)(uint32_t)__float_as_int(part[lr].w) << 32) |
-                              slot_index(hoff, gst, lr);
-            atomicOr((unsigned long long *)(w.flags + (i >> 6)), 1ull << (i & 63));
+        gown[o.slot] = gst[o.hs] + (o.slot - hoff[o.hs]);
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < nown; k0 += kWave) {  // wave-uniform
+        const int k = k0 + lane;
+        const bool act = k < nown;
+        int64_t i = 0;
+        bool f = false;
+        if (act) {
+            const int slot = own_slot(hoff, wid, k, c1, c2, c3).slot;
+            i = gown[slot];
+            f = fbyte[slot] != 0;
+            if (!f) {
+                const int32_t oi = __float_as_int(part[slot].w);
+                root[oi] = oi;
+            } else {
+                const int lr = lds_find_ro(lpar, slot);
+                if (lr != slot)
+                    w.parent[i] = ((uint64_t)(uint32_t)__float_as_int(part[lr].w) << 32) |
+                                  (uint32_t)gown[lr];
+            }
         }
+        flag_friends_wave(w.flags, act, i, f);
     }
     __syncthreads();
     if (t == 0 && lover)  // some hooks were lost: the windowed kernel redoes the tile

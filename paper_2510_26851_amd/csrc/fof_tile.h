@@ -112,13 +112,7 @@ __device__ int build_halo(const Work &w, const BoxDesc &B, const TileGeom &g, bo
         sum += cnt;
     }
     // exclusive scan of staged counts; each thread owns kPerT consecutive halo cells
-    int x = sum;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        int y = __shfl_up(x, o, kWave);
-        if (lane >= o)
-            x += y;
-    }
+    const int x = wave_incl_sum(sum);
     if (lane == kWave - 1)
         scr[wid] = x;
     __syncthreads();

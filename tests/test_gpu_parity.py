@@ -188,11 +188,12 @@ def test_overflow_paths_of_the_tiled_link(tune):
     compare_with_oracle(pos, 20.0, 0.3, 5, tune=tune)
 
 
-def test_grid_over_2_27_cells_takes_the_per_particle_binning():
-    """A grid of more than 2^27 cells is binned with one rank atomic per particle instead of
-    the bucketed counting sort (the path a 1024^3 box takes).  Every label, group id, size
-    and centre of mass of the 17M-particle box against the oracle run on the whole box,
-    for that grid and for the default one (bucketed)."""
+def test_grid_over_2_27_cells_takes_the_two_level_binning():
+    """A grid of more than 2^27 cells (16384 sorting buckets of 8192 cells) is binned in two
+    levels: placed by buckets of 2^16 cells, then each split into its sorting buckets (the
+    path a 1024^3 box takes).  Every label, group id, size and centre of mass of the
+    17M-particle box against the oracle run on the whole box, for that grid and for the
+    default one (one level)."""
     import torch
     from paper_2510_26851_amd import Plan, trim
 
@@ -201,13 +202,13 @@ def test_grid_over_2_27_cells_takes_the_per_particle_binning():
     n, L = 17_000_000, 256.0
     b = W.linking_length(0.2, L, n)
     pos = W.clumpy_box(n, L, 4000, 51)
-    say(f"per-particle binning: oracle on n={n}")
+    say(f"two-level binning: oracle on n={n}")
     ref_root, _ = oracle.fof_par(pos, L, b)
     ref = oracle.groups(pos, ref_root, L, 20)
     assert ref["n_groups"] > 0
     t = torch.from_numpy(pos).to("cuda:0")
     for side, over in [(0.25, True), (0.0, False)]:
-        say(f"per-particle binning check: n={n} cell_side={side}")
+        say(f"two-level binning check: n={n} cell_side={side}")
         plan = Plan([n], [(L, b)], device=t.device, tune=dict(cell_side=side))
         assert (plan.grid.ncell > (1 << 27)) == over, plan.grid.ncell
         plan.build_grid(t)
@@ -221,6 +222,34 @@ def test_grid_over_2_27_cells_takes_the_per_particle_binning():
         np.testing.assert_array_equal(res["sizes"].cpu().numpy(), ref["sizes"])
         assert com_close(res["com"].cpu().numpy(), ref["com"], L, L / n ** (1 / 3))
         del plan, root, res
+
+
+def test_few_particles_on_a_huge_grid_take_the_per_particle_binning():
+    """200k particles with b = 0.05 in a box of side 256: clique cells of side < b / sqrt(3)
+    force 890^3 coarse cells, and 7 placing blocks are too few to split 16384 buckets into
+    8 sorting buckets each, so the binning takes one rank atomic per particle.  Labels and
+    groups against the oracle."""
+    import torch
+    from paper_2510_26851_amd import Plan, trim
+
+    n, L, b = 200_000, 256.0, 0.05
+    pos = W.clumpy_box(n, L, 300, 53)
+    say(f"per-particle binning: n={n} b={b}")
+    ref_root, _ = oracle.fof_par(pos, L, b)
+    ref = oracle.groups(pos, ref_root, L, 2)
+    t = torch.from_numpy(pos).to("cuda:0")
+    plan = Plan([n], [(L, b)], device=t.device)
+    assert plan.grid.ncell > 1 << 29, plan.grid.ncell
+    plan.build_grid(t)
+    root = plan.link()
+    res = trim(plan.groups(2))
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    np.testing.assert_array_equal(root.cpu().numpy(), ref_root)
+    assert res["n_groups"] == ref["n_groups"] > 0
+    np.testing.assert_array_equal(res["group_id"].cpu().numpy(), ref["group_id"])
+    np.testing.assert_array_equal(res["sizes"].cpu().numpy(), ref["sizes"])
+    del plan, root, res
 
 
 @pytest.mark.parametrize("n", [5000, 40000])
