@@ -224,6 +224,8 @@ Work resolve(const fof_grid *g, void *ws)
     w.classify = (int32_t *)(base + L.off_classify);
     w.bin_hist = (int32_t *)(base + L.off_bin);
     w.edge_cap = (int32_t)L.edge_cap;
+    // the staging buffer holds 2n int2 pairs; the plan's hook capacity bounds both lists
+    w.dense_edge_cap = g->dense_cap > 0 ? std::min<int64_t>(2 * g->n, g->link_edges) : 0;
     w.dense_threshold = g->dense_threshold;
     w.dense_cap = (int32_t)g->dense_cap;
     w.table_words = g->table_words;

@@ -31,6 +31,7 @@ namespace {
 constexpr int kDenseBlock = 256;
 constexpr int kLdsCap = 2048;     // particles a dense cell may hold to be sorted in LDS
 constexpr int kSmallCell = 256;   // dense cells up to this size are linked by one wave
+constexpr int kHookBuf = 64;      // LDS buffer of a worker's deferred sparse-dense hooks
 
 __device__ __forceinline__ int find_box_cell(const BoxDesc *d, int nbox, int64_t c)
 {
@@ -99,6 +100,23 @@ __device__ __forceinline__ void lunion(int *uf, int a, int b)
         if (atomicCAS(uf + a, a, b) == a)
             return;
     }
+}
+
+// Capacity of the sparse-dense pass's deferred hooks (at most the 2n int2 pairs the staging
+// buffer holds, and the plan's hook capacity).
+__device__ __forceinline__ int64_t dense_edge_cap(const Work &w)
+{
+    return w.dense_edge_cap < INT32_MAX ? w.dense_edge_cap : INT32_MAX;
+}
+
+// One hook straight to the deferred list (when a worker's LDS buffer is full).
+__device__ __forceinline__ void defer_dense_hook(const Work &w, int2 h)
+{
+    const int32_t slot = atomicAdd(&w.ctr->n_dense_edges, 1);
+    if ((int64_t)slot < dense_edge_cap(w))
+        reinterpret_cast<int2 *>(w.temp)[slot] = h;
+    else
+        w.ctr->dense_edge_over = 1;
 }
 
 // Block-wide exclusive scan of one int per thread (kDenseBlock threads).
@@ -430,6 +448,8 @@ struct CellLds {
     int pre[kMaxTableWords];
     uint32_t pairbits[32];
     int ncomp, nnb, done, giant, nmark;
+    int2 hk[kHookBuf];              // deferred sparse-dense hooks of the cell, then flushed
+    int nhk, hkbase;
     int nb[26];                     // neighbour dense ids (cross), or sparse cell starts
     short nbo[26];                  // their offsets: (ox+1) | (oy+1) << 2 | (oz+1) << 4
     int nbp[27];                    // sparse neighbours: running particle count
@@ -993,15 +1013,18 @@ __device__ void cross_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
     }
 }
 
-// Ordinary (sparse) particles around dense cell d.  Runs after every sparse link kernel,
-// so hooks go straight into the global forest.  A particle q of a neighbouring cell
+// Ordinary (sparse) particles around dense cell d, after the components.  A particle q of a
+// neighbouring cell
 // without a clique table is tested only if this cell lies within reach of q's position
 // (the face test of the sparse search, from q's side), then only against the fine cells
 // within reach of q, one friend per component of this cell.  q is then marked in the flag
 // bitmap, so the compress pass gives it its component's label.
 // kLds: the cell's particles are staged in LDS (it holds at most CAP), else read from HBM;
 // fixed per instantiation, so every member access compiles to one kind of load.
-template <int G, bool kLds, int UMAX, int CAP>
+// kDefer: hooks are appended to the deferred list (pairs in Work::temp, which the link stage
+// does not otherwise use) for k_dense_edges, so the pass can run beside the tiled kernel,
+// whose plain stores to ordinary particles' parents would overwrite a direct hook.
+template <int G, bool kLds, bool kDefer, int UMAX, int CAP>
 __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
 {
     const int t = Grp<G>::tid();
@@ -1102,7 +1125,15 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
                     const int hit =
                         first_friend(P, q, mem, L.ustart[rb] - s, L.ustart[rb + 1] - s);
                     if (hit >= 0) {
-                        uf_union(w.parent, (uint32_t)j, (uint32_t)(s + hit));
+                        if (kDefer) {
+                            const int k = atomicAdd(&L.nhk, 1);
+                            if (k < kHookBuf)
+                                L.hk[k] = make_int2(j, s + hit);
+                            else
+                                defer_dense_hook(w, make_int2(j, s + hit));
+                        } else {
+                            uf_union(w.parent, (uint32_t)j, (uint32_t)(s + hit));
+                        }
                         any = true;
                         if (comp < 64)
                             seen |= 1ull << comp;
@@ -1116,6 +1147,21 @@ __device__ void sparse_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
             atomicOr((unsigned long long *)(w.flags + (j >> 6)), 1ull << (j & 63));
     }
     Grp<G>::sync();
+    if (kDefer) {  // the cell's buffered hooks go to the list with one global atomic
+        const int nh = min(L.nhk, kHookBuf);
+        if (t == 0 && nh > 0)
+            L.hkbase = atomicAdd(&w.ctr->n_dense_edges, nh);
+        Grp<G>::sync();
+        for (int k = t; k < nh; k += G) {
+            if ((int64_t)(L.hkbase + k) < dense_edge_cap(w))
+                reinterpret_cast<int2 *>(w.temp)[L.hkbase + k] = L.hk[k];
+            else
+                w.ctr->dense_edge_over = 1;
+        }
+        if (t == 0)
+            L.nhk = 0;
+        Grp<G>::sync();
+    }
     FOF_PHASE(L, t == 0, 2);
 }
 
@@ -1156,12 +1202,19 @@ __device__ __forceinline__ int deal_next(const Deal &dl, int n)
 }
 
 // Small cells: one wave per cell, iterating over every dense id and skipping big cells.
-// kMode: 0 components inside the cell, 1 dense neighbours, 2 ordinary neighbours.
+// kMode: 0 components inside the cell, 1 dense neighbours, 2 ordinary neighbours (hooks
+// deferred), 3 ordinary neighbours with direct hooks, run only when the deferred list
+// overflowed.
 template <int kMode>
 __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
 {
+    if (kMode == 3 && !w.ctr->dense_edge_over)  // uniform: every thread reads the same word
+        return;
     __shared__ CellLds<kSmallCell, kSmallCell> lds[Grp<kWave>::per_block];
     CellLds<kSmallCell, kSmallCell> &L = lds[Grp<kWave>::slot()];
+    if (lane_id() == 0)
+        L.nhk = 0;
+    Grp<kWave>::sync();
     const int nd = dense_count(w.ctr, w.dense_cap);
     const int nworkers = gridDim.x * Grp<kWave>::per_block;
     const int worker = blockIdx.x * Grp<kWave>::per_block + Grp<kWave>::slot();
@@ -1173,8 +1226,8 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
         if (w.cell_start[c + 1] - w.cell_start[c] <= kSmallCell) {
             if (kMode == 1)
                 cross_cell<kWave, true>(w, d, L);
-            else if (kMode == 2)
-                sparse_cell<kWave, true>(w, d, L);
+            else if (kMode >= 2)
+                sparse_cell<kWave, true, kMode == 2>(w, d, L);
             else
                 cc_cell<kWave, true>(w, d, L);
         }
@@ -1187,7 +1240,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
     FOF_PHASE(L, lane_id() == 0, 7);
     FOF_PHASE_FLUSH(L, lane_id() == 0 && kMode == 0, w.ctr, 0);
 #if defined(FOF_TIMING) && !defined(FOF_TIMING_BIG)
-    if (lane_id() == 0 && kMode != 0)
+    if (lane_id() == 0 && (kMode == 1 || kMode == 2))
         for (int k = 0; k < 4; ++k)
             atomicAdd(&w.ctr->stats[16 + 4 * (kMode - 1) + k], (unsigned long long)L.phase[k]);
 #endif
@@ -1197,8 +1250,13 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
 template <int kMode>
 __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
 {
+    if (kMode == 3 && !w.ctr->dense_edge_over)
+        return;
     __shared__ CellLds<kMaxFineKeys, kLdsCap> L;
     __shared__ int next;
+    if (threadIdx.x == 0)
+        L.nhk = 0;
+    __syncthreads();
     const int nb = __hip_atomic_load(&w.ctr->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const Deal dl = deal(w.cursors, 2 * kMode + 1, blockIdx.x, gridDim.x);
     FOF_PHASE_START(L, threadIdx.x == 0);
@@ -1208,15 +1266,15 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
         if (w.cell_start[c + 1] - w.cell_start[c] <= kLdsCap) {
             if (kMode == 1)
                 cross_cell<kDenseBlock, true>(w, d, L);
-            else if (kMode == 2)
-                sparse_cell<kDenseBlock, true>(w, d, L);
+            else if (kMode >= 2)
+                sparse_cell<kDenseBlock, true, kMode == 2>(w, d, L);
             else
                 cc_cell<kDenseBlock, true>(w, d, L);
         } else {
             if (kMode == 1)
                 cross_cell<kDenseBlock, false>(w, d, L);
-            else if (kMode == 2)
-                sparse_cell<kDenseBlock, false>(w, d, L);
+            else if (kMode >= 2)
+                sparse_cell<kDenseBlock, false, kMode == 2>(w, d, L);
             else
                 cc_cell<kDenseBlock, false>(w, d, L);
         }
@@ -1230,11 +1288,21 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
     FOF_PHASE(L, threadIdx.x == 0, 7);
     FOF_PHASE_FLUSH(L, threadIdx.x == 0 && kMode == 0, w.ctr, 8);
 #if defined(FOF_TIMING) && defined(FOF_TIMING_BIG)  // diagnostic: big cells' pair passes
-    if (threadIdx.x == 0 && kMode != 0)
+    if (threadIdx.x == 0 && (kMode == 1 || kMode == 2))
         for (int k = 0; k < 4; ++k)
             atomicAdd(&w.ctr->stats[16 + 4 * (kMode - 1) + k], (unsigned long long)L.phase[k]);
 #endif
 
+}
+
+// The sparse-dense pass's deferred hooks, once the tiled kernel's plain stores are done.
+__global__ void k_dense_edges(Work w)
+{
+    const int64_t cap = dense_edge_cap(w);
+    const int64_t m = min((int64_t)w.ctr->n_dense_edges, cap);
+    const int2 *e = reinterpret_cast<const int2 *>(w.temp);
+    for (int64_t k = gtid(); k < m; k += (int64_t)gridDim.x * blockDim.x)
+        uf_union(w.parent, (uint32_t)e[k].x, (uint32_t)e[k].y);
 }
 
 // Blocks of a dense pass: enough to fill the chip, at most one per possible item, and at
@@ -1271,31 +1339,39 @@ hipError_t launch_dense_build(const Work &w, hipStream_t s)
     return hipGetLastError();
 }
 
-// Components, then pairs of dense cells; `cc_done` (optional) is recorded between the two.
-hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t cc_done)
+// Components, the ordinary neighbours of dense cells (hooks deferred), then pairs of dense
+// cells; `hooks_listed` (optional) is recorded once the deferred hooks are all listed.
+hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t hooks_listed)
 {
     if (w.dense_cap <= 0 || w.dense_threshold < 0)
         return hipSuccess;
     hipError_t e = launch_fill_i32(w.cursors, kCursorInts, 0, s);
+    if (e == hipSuccess)
+        e = launch_fill_i32(&w.ctr->n_dense_edges, 2, 0, s);  // n_dense_edges, dense_edge_over
     if (e != hipSuccess)
         return e;
     const unsigned pb = persistent_blocks(w.dense_cap);
     hipLaunchKernelGGL(k_dense_small<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     hipLaunchKernelGGL(k_dense_big<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
-    if (cc_done && (e = hipEventRecord(cc_done, s)) != hipSuccess)
+    hipLaunchKernelGGL(k_dense_small<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_big<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    if (hooks_listed && (e = hipEventRecord(hooks_listed, s)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_dense_small<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     hipLaunchKernelGGL(k_dense_big<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     return hipGetLastError();
 }
 
-hipError_t launch_dense_sparse(const Work &w, hipStream_t s)
+// After every plain store of the tiled kernel: the deferred sparse-dense hooks, then (only
+// if their list overflowed) the sparse-dense pass again with direct hooks.
+hipError_t launch_dense_hooks(const Work &w, hipStream_t s)
 {
     if (w.dense_cap <= 0 || w.dense_threshold < 0)
         return hipSuccess;
+    hipLaunchKernelGGL(k_dense_edges, dim3(1024), dim3(256), 0, s, w);
     const unsigned pb = persistent_blocks(w.dense_cap);
-    hipLaunchKernelGGL(k_dense_small<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
-    hipLaunchKernelGGL(k_dense_big<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_small<3>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_big<3>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     return hipGetLastError();
 }
 

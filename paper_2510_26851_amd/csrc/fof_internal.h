@@ -19,11 +19,11 @@ constexpr int kScanItems = 8;                  // elements per thread in the sca
 constexpr int kMaxFine = 10;                   // fine cells per coarse cell per axis (max)
 constexpr int kMaxFineKeys = kMaxFine * kMaxFine * kMaxFine;
 constexpr int kMaxTableWords = (kMaxFineKeys + 31) / 32;
-// Dense-pass work cursors: per pass (3 modes x small/big cells) kCursorGroups counters, each
+// Dense-pass work cursors: per pass (4 modes x small/big cells) kCursorGroups counters, each
 // on its own 64-byte line so that groups do not contend.
 constexpr int kCursorGroups = 64;
 constexpr int kCursorStride = 16;
-constexpr int kCursorInts = 6 * kCursorGroups * kCursorStride;
+constexpr int kCursorInts = 8 * kCursorGroups * kCursorStride;
 constexpr int kTableHeader = 4;  // dense-cell table: cell, ncomp, units, reserved
 // Link tiles: kTileX x kTileY x kTileZ coarse cells per block (z fastest, like the cells).
 constexpr int kTileX = 4, kTileY = 4, kTileZ = 16;
@@ -63,7 +63,9 @@ struct Counters {
     int32_t n_spill;       // link tiles queued in tile_list for the windowed kernel
     int32_t n_link_edges;  // hooks the tiled kernel deferred to the edge list
     int32_t n_flagged;     // particles with a friend (length of Work::flist)
-    int32_t pad[10];
+    int32_t n_dense_edges; // hooks the sparse-dense pass deferred (pairs in Work::temp)
+    int32_t dense_edge_over;  // set when they did not all fit
+    int32_t pad[8];
     unsigned long long stats[24];  // event counts of diagnostic builds (-DFOF_STATS)
 };
 
@@ -441,6 +443,7 @@ struct Work {  // device pointers resolved from a fof_grid and a workspace base
     int2 *edges;          // hooks deferred by the tiled kernel
     int32_t edge_cap;
     int32_t *cursors;     // work cursors of the dense passes, kCursorStride ints apart
+    int64_t dense_edge_cap;  // deferred sparse-dense hooks Work::temp takes (pairs)
     int32_t *classify;    // per-chunk dense / big counts and their scans (binning)
     int32_t *bin_hist;    // bucketed binning: per (bucket, block) counts, then their scan
     int32_t nbox;
@@ -481,13 +484,13 @@ hipError_t launch_build(const Work &w, const float *pos, hipStream_t s);
 // the helper stream, concurrently with the sparse passes on the caller's stream.
 struct SideStream {
     hipStream_t stream;
-    hipEvent_t fork, cc, join;  // flags cleared; dense components done; dense pairs done
+    hipEvent_t fork, cc, join;  // flags cleared; sparse-dense hooks listed; dense pairs done
 };
 
 hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideStream *side);
 hipError_t launch_dense_build(const Work &w, hipStream_t s);
-hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t cc_done);
-hipError_t launch_dense_sparse(const Work &w, hipStream_t s);
+hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t hooks_listed);
+hipError_t launch_dense_hooks(const Work &w, hipStream_t s);
 hipError_t launch_flag_list(const Work &w, hipStream_t s);
 hipError_t launch_group_dispersion(const Work &w, int32_t cap, const int32_t *n_groups,
                                    const int32_t *sizes, const double *com, double *sigx,

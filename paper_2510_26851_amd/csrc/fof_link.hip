@@ -10,9 +10,9 @@
 // the flag bitmap and resolved by the compress pass.  Each friend pair is hooked once.
 //
 // Cells with clique tables (fof_dense.hip) are skipped here: the dense kernels link their
-// own particles and, after these kernels, the ordinary particles around them
-// (k_dense_sparse), marking those that find a friend there; the compress pass then
-// replaces any label written here for them.
+// own particles, and list the hooks of the ordinary particles around them (applied after
+// these kernels), marking those that find a friend there; the compress pass then replaces
+// any label written here for them.
 #include "fof_internal.h"
 #include "fof_tile.h"
 
@@ -747,13 +747,13 @@ __global__ void k_compress(const float4 *__restrict__ sorted, const int32_t *__r
 }  // namespace
 
 // The components and dense-pair passes touch only dense-cell particles (their parent
-// entries, and flag words through atomic ORs); the tiled pass only ordinary particles, with
-// plain stores to their own entries and no global hooks; the deferred, windowed and global
-// sparse kernels hook ordinary particles only.  So with a helper stream the dense passes
-// run concurrently with all of those: fork after the flag fill.  The sparse-dense pass
-// needs the components (unit components, component counts, dense parents) and every plain
-// store of the tiled kernel, but not the dense pairs: it waits for the components only and
-// runs beside the pair pass (both hook through the lock-free forest).  Join before compress.
+// entries, and flag words through atomic ORs); the sparse-dense pass only lists its hooks
+// (and ORs flag words); the tiled pass touches only ordinary particles, with plain stores to
+// their own entries and no global hooks; the deferred, windowed and global sparse kernels
+// hook ordinary particles only.  So with a helper stream all dense passes run concurrently
+// with those kernels: fork after the flag fill.  The listed sparse-dense hooks are applied
+// once the tiled kernel's plain stores are done (and the list is complete), beside the
+// dense pairs (both hook through the lock-free forest).  Join before compress.
 hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideStream *side)
 {
     if (w.n <= 0)
@@ -785,7 +785,7 @@ hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideSt
         hipLaunchKernelGGL(k_link, dim3(nb), dim3(w.block), 0, s, w, root);
     if (fork && (e = hipStreamWaitEvent(s, side->cc, 0)) != hipSuccess)
         return e;
-    e = launch_dense_sparse(w, s);  // after every plain store of the tiled kernel
+    e = launch_dense_hooks(w, s);  // after every plain store of the tiled kernel
     if (e != hipSuccess)
         return e;
     if (fork) {
