@@ -230,6 +230,32 @@ __device__ __forceinline__ int32_t sort_block_scan(int32_t v, int32_t *wsum)
     return pre + x - v;
 }
 
+// Exclusive scan of one int per thread over a kSortBlock-thread block, with the total.
+__device__ __forceinline__ int32_t sort_block_scan_total(int32_t v, int32_t *wsum, int32_t *total)
+{
+    const int lane = lane_id(), wid = threadIdx.x / kWave;
+    const int32_t x = wave_incl_sum(v);
+    if (lane == kWave - 1)
+        wsum[wid] = x;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+    for (int k = 0; k < kSortBlock / kWave; ++k) {
+        pre += k < wid ? wsum[k] : 0;
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+// Where the sorting blocks put the dense-cell index (cells over the threshold, in boxes that
+// allow clique tables): thr < 0 or cap == 0 means none.
+struct DenseOut {
+    int32_t thr, cap;
+    int32_t *cell_count, *dense_list, *big_list;
+    Counters *ctr;
+};
+
 // Cell of a staged particle relative to the bucket's first cell (coordinates were already
 // made valid by the placing pass, so this is the cell that pass used).
 __device__ __forceinline__ int staged_cell(const BoxDesc *__restrict__ desc, int nbox,
@@ -242,6 +268,68 @@ __device__ __forceinline__ int staged_cell(const BoxDesc *__restrict__ desc, int
     return lc;
 }
 
+// LDS slot of a sorting bucket's cell counter: one pad word after every 32, so the scan's
+// threads, each owning a run of consecutive cells, hit distinct banks.
+__device__ __forceinline__ int lpad(int j) { return j + (j >> 5); }
+
+// Dense cells among a thread's cells [j0, j1) of the bucket: ids from one atomic per block,
+// in cell order inside it, and places in the big list for cells over kSmallCell.  A cell past
+// the table capacity, or in a box without clique tables, gets -1 in cell_count.
+__device__ void number_dense_cells(const DenseOut &dn, const BoxDesc *__restrict__ desc,
+                                   int nbox, int64_t c0, const int32_t *lc, int j0, int j1,
+                                   int32_t *wsum, int32_t *sbase)
+{
+    uint32_t dmask = 0;
+    int a = 0;
+    for (int j = j0; j < j1; ++j)
+        if (lc[lpad(j)] > dn.thr) {
+            if (desc[find_box_cell(desc, nbox, c0 + j)].dense_ok) {
+                dmask |= 1u << (j - j0);
+                ++a;
+            } else {
+                dn.cell_count[c0 + j] = -1;
+            }
+        }
+    int32_t tot;
+    int32_t d = sort_block_scan_total(a, wsum, &tot);
+    if (threadIdx.x == 0)
+        *sbase = tot ? atomicAdd(&dn.ctr->n_dense, tot) : 0;
+    __syncthreads();
+    d += *sbase;
+    uint32_t bmask = 0;
+    int nbig = 0;
+    bool over = false;
+    const int dfirst = d;
+    for (uint32_t m = dmask; m; m &= m - 1u) {
+        const int j = j0 + __ffs(m) - 1;
+        if (d < dn.cap) {
+            dn.cell_count[c0 + j] = d;
+            dn.dense_list[d] = (int32_t)(c0 + j);
+            if (lc[lpad(j)] > kSmallCell) {
+                bmask |= 1u << (j - j0);
+                ++nbig;
+            }
+        } else {
+            dn.cell_count[c0 + j] = -1;
+            over = true;
+        }
+        ++d;
+    }
+    if (over)
+        atomicOr(&dn.ctr->status, (int32_t)FOF_STATUS_DENSE_CAP);
+    __syncthreads();  // every thread has read sbase
+    int32_t bg = sort_block_scan_total(nbig, wsum, &tot);
+    if (threadIdx.x == 0)
+        *sbase = tot ? atomicAdd(&dn.ctr->n_big, tot) : 0;
+    __syncthreads();
+    bg += *sbase;
+    d = dfirst;
+    for (uint32_t m = dmask; m; m &= m - 1u, ++d)
+        if ((bmask >> (__ffs(m) - 1)) & 1u)
+            dn.big_list[bg++] = d;
+    __syncthreads();  // sbase is free again
+}
+
 // Sorting bucket b's particles are stage[bounds[b * stride], bounds[(b + 1) * stride]).
 __global__ __launch_bounds__(kSortBlock) void k_bin_sort(const BoxDesc *__restrict__ desc,
                                                          int nbox, int64_t ncell, BinShape bs,
@@ -250,17 +338,19 @@ __global__ __launch_bounds__(kSortBlock) void k_bin_sort(const BoxDesc *__restri
                                                          const float4 *__restrict__ stage,
                                                          int32_t *__restrict__ cell_start,
                                                          float4 *__restrict__ sorted,
-                                                         uint64_t *__restrict__ parent)
+                                                         uint64_t *__restrict__ parent,
+                                                         DenseOut dn)
 {
-    extern __shared__ int32_t lc[];  // 2^sshift per-cell counters, then cursors
+    extern __shared__ int32_t lc[];  // per-cell counters, then cursors, at lpad(cell)
     __shared__ int32_t wsum[kSortBlock / kWave];
+    __shared__ int32_t sbase;
     constexpr int64_t kCap = (int64_t)kSortBlock * kSortPer;
     const int64_t b = blockIdx.x;
     const int64_t c0 = b << bs.sshift;
     const int nc = (int)((c0 + (1ll << bs.sshift) < ncell ? (1ll << bs.sshift) : ncell - c0));
     const int64_t base = bounds[b * stride], end = bounds[(b + 1) * stride];
     for (int k = threadIdx.x; k < nc; k += kSortBlock)
-        lc[k] = 0;
+        lc[lpad(k)] = 0;
     __syncthreads();
     // Items k0 + threadIdx.x + r * kSortBlock (r < kSortPer) of a chunk live in registers; a
     // bucket of at most kCap particles is read once, larger ones chunk by chunk, twice.
@@ -278,27 +368,30 @@ __global__ __launch_bounds__(kSortBlock) void k_bin_sort(const BoxDesc *__restri
             const int64_t k = k0 + threadIdx.x + (int64_t)r * kSortBlock;
             if (k < end) {
                 cl[r] = staged_cell(desc, nbox, it[r], c0);
-                atomicAdd(lc + cl[r], 1);
+                atomicAdd(lc + lpad(cl[r]), 1);
             }
         }
     }
     __syncthreads();
-    // exclusive scan: thread t owns cells [t * per, (t + 1) * per)
+    // thread t owns cells [t * per, (t + 1) * per) of the bucket (per <= 8)
     const int per = (nc + kSortBlock - 1) / kSortBlock;
     const int j0 = threadIdx.x * per;
     const int j1 = j0 + per < nc ? j0 + per : nc;
+    if (dn.thr >= 0 && dn.cap > 0)  // uniform
+        number_dense_cells(dn, desc, nbox, c0, lc, j0, j1, wsum, &sbase);
+    // exclusive scan of the counts
     int32_t sum = 0;
     for (int j = j0; j < j1; ++j)
-        sum += lc[j];
+        sum += lc[lpad(j)];
     int32_t run = (int32_t)base + sort_block_scan(sum, wsum);
     for (int j = j0; j < j1; ++j) {
-        const int32_t v = lc[j];
-        lc[j] = run;
+        const int32_t v = lc[lpad(j)];
+        lc[lpad(j)] = run;
         run += v;
     }
     __syncthreads();
     for (int j = threadIdx.x; j < nc; j += kSortBlock)
-        cell_start[c0 + j] = lc[j];
+        cell_start[c0 + j] = lc[lpad(j)];
     if (c0 + nc == ncell && threadIdx.x == 0)
         cell_start[ncell] = (int32_t)end;
     __syncthreads();
@@ -318,7 +411,7 @@ __global__ __launch_bounds__(kSortBlock) void k_bin_sort(const BoxDesc *__restri
         for (int r = 0; r < kSortPer; ++r) {
             const int64_t k = k0 + threadIdx.x + (int64_t)r * kSortBlock;
             if (k < end) {
-                const int32_t dst = atomicAdd(lc + cl[r], 1);
+                const int32_t dst = atomicAdd(lc + lpad(cl[r]), 1);
                 const uint32_t i = (uint32_t)__float_as_int(it[r].w);
                 sorted[dst] = it[r];
                 parent[dst] = ((uint64_t)i << 32) | (uint32_t)dst;
@@ -377,6 +470,25 @@ __global__ void k_clear_counters(Counters *ctr)
 
 }  // namespace
 
+// Dynamic LDS of k_bin_sort: one counter per cell of a sorting bucket, padded (lpad).
+static size_t sort_lds(const BinShape &bs)
+{
+    const size_t nc = (size_t)1 << bs.sshift;
+    return sizeof(int32_t) * (nc + nc / 32);
+}
+
+static DenseOut dense_out(const Work &w)
+{
+    DenseOut dn;
+    dn.thr = w.dense_threshold;
+    dn.cap = w.dense_cap;
+    dn.cell_count = w.cell_count;
+    dn.dense_list = w.dense_list;
+    dn.big_list = w.big_list;
+    dn.ctr = w.ctr;
+    return dn;
+}
+
 hipError_t launch_build(const Work &w, const float *pos, hipStream_t s)
 {
     hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, s, w.ctr);
@@ -395,18 +507,18 @@ hipError_t launch_build(const Work &w, const float *pos, hipStream_t s)
         if (bs.shift == bs.sshift) {
             hipLaunchKernelGGL(k_bin_place, dim3(bs.G), dim3(kBinBlock), lds_b, s, pos, w.desc,
                                w.nbox, w.n, bs, off, w.temp);
-            hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)bs.nsb), dim3(kSortBlock),
-                               sizeof(int32_t) << bs.sshift, s, w.desc, w.nbox, w.ncell, bs,
-                               off, (int64_t)bs.G, w.temp, w.cell_start, w.sorted, w.parent);
+            hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)bs.nsb), dim3(kSortBlock), sort_lds(bs),
+                               s, w.desc, w.nbox, w.ncell, bs, off, (int64_t)bs.G, w.temp,
+                               w.cell_start, w.sorted, w.parent, dense_out(w));
         } else {  // placed buckets staged in `sorted`, split into `temp`, sorted into `sorted`
             int32_t *sub_off = hist;  // the counts are spent once scanned into off
             hipLaunchKernelGGL(k_bin_place, dim3(bs.G), dim3(kBinBlock), lds_b, s, pos, w.desc,
                                w.nbox, w.n, bs, off, w.sorted);
             hipLaunchKernelGGL(k_bin_split, dim3((unsigned)bs.nbk), dim3(kSplitBlock), 0, s,
                                w.desc, w.nbox, bs, off, w.sorted, w.temp, sub_off);
-            hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)bs.nsb), dim3(kSortBlock),
-                               sizeof(int32_t) << bs.sshift, s, w.desc, w.nbox, w.ncell, bs,
-                               sub_off, (int64_t)1, w.temp, w.cell_start, w.sorted, w.parent);
+            hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)bs.nsb), dim3(kSortBlock), sort_lds(bs),
+                               s, w.desc, w.nbox, w.ncell, bs, sub_off, (int64_t)1, w.temp,
+                               w.cell_start, w.sorted, w.parent, dense_out(w));
         }
     } else {
         e = launch_fill_i32(w.cell_count, w.ncell, 0, s);
@@ -424,7 +536,7 @@ hipError_t launch_build(const Work &w, const float *pos, hipStream_t s)
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    return launch_dense_build(w, s);
+    return launch_dense_build(w, s, bs.ok);
 }
 
 }  // namespace fof

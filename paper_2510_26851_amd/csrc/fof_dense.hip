@@ -30,21 +30,7 @@ namespace {
 
 constexpr int kDenseBlock = 256;
 constexpr int kLdsCap = 2048;     // particles a dense cell may hold to be sorted in LDS
-constexpr int kSmallCell = 256;   // dense cells up to this size are linked by one wave
 constexpr int kHookBuf = 64;      // LDS buffer of a worker's deferred sparse-dense hooks
-
-__device__ __forceinline__ int find_box_cell(const BoxDesc *d, int nbox, int64_t c)
-{
-    int lo = 0, hi = nbox - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (d[mid].cell_base <= c)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
 
 struct CellXYZ {
     int x, y, z;
@@ -1315,10 +1301,15 @@ unsigned persistent_blocks(int cap)
 
 }  // namespace
 
-hipError_t launch_dense_build(const Work &w, hipStream_t s)
+hipError_t launch_dense_build(const Work &w, hipStream_t s, bool classified)
 {
     if (w.dense_cap <= 0 || w.dense_threshold < 0)
         return hipSuccess;
+    if (classified) {  // the bucketed sort numbered the dense cells already
+        hipLaunchKernelGGL(k_dense_sort, dim3(persistent_blocks(w.dense_cap)), dim3(kDenseBlock),
+                           0, s, w);
+        return hipGetLastError();
+    }
     const int64_t nchunk = (w.ncell + kClassChunk - 1) / kClassChunk;
     int32_t *nd = w.classify, *nd_pre = nd + (nchunk + 1);
     int32_t *nbig = nd_pre + (nchunk + 1), *nbig_pre = nbig + (nchunk + 1);

@@ -85,6 +85,8 @@ enum Stat {
 #define FOF_STAT_MAX(ctr, k, v) ((void)0)
 #endif
 
+constexpr int kSmallCell = 256;  // dense cells up to this size are linked by one wave
+
 // ---------------------------------------------------------------------------------------
 // Box lookup: box k owns global indices [off_k, off_k + n_k); boxes are in order.
 // ---------------------------------------------------------------------------------------
@@ -94,6 +96,20 @@ __device__ __forceinline__ int find_box(const BoxDesc *__restrict__ d, int nbox,
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (d[mid].off <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Box owning coarse cell c (cells are numbered box after box from each box's cell_base).
+__device__ __forceinline__ int find_box_cell(const BoxDesc *d, int nbox, int64_t c)
+{
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (d[mid].cell_base <= c)
             lo = mid;
         else
             hi = mid - 1;
@@ -488,7 +504,7 @@ struct SideStream {
 };
 
 hipError_t launch_link(const Work &w, int32_t *root, hipStream_t s, const SideStream *side);
-hipError_t launch_dense_build(const Work &w, hipStream_t s);
+hipError_t launch_dense_build(const Work &w, hipStream_t s, bool classified);
 hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t hooks_listed);
 hipError_t launch_dense_hooks(const Work &w, hipStream_t s);
 hipError_t launch_flag_list(const Work &w, hipStream_t s);
