@@ -31,6 +31,7 @@ namespace {
 constexpr int kDenseBlock = 256;
 constexpr int kLdsCap = 2048;     // particles a dense cell may hold to be sorted in LDS
 constexpr int kHookBuf = 64;      // LDS buffer of a worker's deferred sparse-dense hooks
+constexpr int kPairCell = 64;     // dense cells up to this size are joined by all their pairs
 
 struct CellXYZ {
     int x, y, z;
@@ -679,6 +680,65 @@ __device__ void join_units(const Work &w, const BoxDesc &B, const Pred &P, const
     }
 }
 
+// Components of a cell of at most kPairCell particles (most of whose clique cells hold one
+// member, so units save nothing): every pair of its particles is tested, pair p of the
+// strict upper triangle on lane p mod 64, into an LDS union-find over the particles.  Then,
+// as for units: every member points at its component's smallest original index, every unit
+// records its component number (a unit is a clique, so all its members share one).
+__device__ __forceinline__ int tri_row_start(int i, int n) { return i * (2 * n - i - 1) / 2; }
+
+template <int G, int UMAX, int CAP>
+__device__ void cc_cell_pairs(const Work &w, const Pred &P, int32_t s, int n, int u,
+                              const float4 *mem, int32_t *T, CellLds<UMAX, CAP> &L)
+{
+    const int t = Grp<G>::tid();
+    for (int k = t; k < n; k += G) {
+        L.uf[k] = k;
+        L.umin[k] = ~0ull;
+    }
+    Grp<G>::sync();
+    const int np = n * (n - 1) / 2;
+    for (int p = t; p < np; p += G) {
+        // row i of pair p: the largest i with tri_row_start(i) <= p (float estimate, then
+        // exact integer correction)
+        const float q = (float)(2 * n - 1);
+        int i = (int)((q - sqrtf(q * q - 8.0f * (float)p)) * 0.5f);
+        i = max(0, min(i, n - 2));
+        while (i > 0 && tri_row_start(i, n) > p)
+            --i;
+        while (i < n - 2 && tri_row_start(i + 1, n) <= p)
+            ++i;
+        const int j = p - tri_row_start(i, n) + i + 1;
+        const float4 a = mem[i], b = mem[j];
+        if (linked(P, a.x, a.y, a.z, b.x, b.y, b.z))
+            lunion(L.uf, i, j);
+    }
+    Grp<G>::sync();
+    for (int k = t; k < n; k += G) {
+        const int r = lfind(L.uf, k);
+        const unsigned long long v =
+            ((unsigned long long)(uint32_t)__float_as_int(mem[k].w) << 32) | (uint32_t)(s + k);
+        atomicMin(L.umin + r, v);
+        if (r == k)
+            L.umark[k] = atomicAdd(&L.ncomp, 1);
+    }
+    Grp<G>::sync();
+    for (int k = t; k < n; k += G)
+        w.parent[s + k] = L.umin[lfind(L.uf, k)];
+    for (int r = t; r < u; r += G)
+        w.cnt[s + r] = L.umark[lfind(L.uf, L.ustart[r] - s)];
+    // mark every particle of the cell for the compress pass
+    for (int64_t q = (s >> 6) + t; q <= ((int64_t)s + n - 1) >> 6; q += G) {
+        const int64_t lo = q << 6, hi = lo + 64;
+        const int64_t a = lo > s ? lo : s, b = hi < s + n ? hi : s + n;
+        const uint64_t mask = (b - a == 64) ? ~0ull : (((1ull << (b - a)) - 1ull) << (a - lo));
+        atomicOr((unsigned long long *)(w.flags + q), (unsigned long long)mask);
+    }
+    if (t == 0)
+        T[1] = L.ncomp;
+    Grp<G>::sync();
+}
+
 // kLds: the cell's particles are staged in LDS (it holds at most CAP), else read from HBM;
 // fixed per instantiation, so every member access compiles to one kind of load.
 template <int G, bool kLds, int UMAX, int CAP>
@@ -700,6 +760,10 @@ __device__ void cc_cell(const Work &w, int d, CellLds<UMAX, CAP> &L)
         L.ncomp = 0;
     load_units<G, kLds>(w, T, s, n, m, u, L);
     FOF_PHASE(L, t == 0, 0);
+    if (G == kWave && n <= kPairCell) {  // uniform
+        cc_cell_pairs<G>(w, P, s, n, u, mem, T, L);
+        return;
+    }
 
     // unit minima, one thread per member (a unit of a clump core can hold thousands); a
     // member's unit is the rank of its fine key, the key the cell was sorted by

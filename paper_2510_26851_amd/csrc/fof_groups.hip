@@ -15,7 +15,9 @@
 //   g_assign   group_id[orig]; with min_size > 1 group_id is filled with -1 first and only
 //              flagged particles are visited (list); per kept group: size, root slot, and
 //              the moment accumulators cleared (singleton groups are finished here)
-//   g_sum      FP64 sums of minimum-image offsets from the root and of velocities (list)
+//   g_sum      FP64 sums of minimum-image offsets from the root and of velocities (list);
+//              with min_size > 1 and centres wanted it also does g_assign's work for the
+//              flagged particles, after g_clear has cleared the kept groups' moments
 //   g_mean     com = wrap(x_root + sum / n), vmean = vsum / n
 //   g_dev      sum of squared velocity deviations (list); g_sig: sigv = sqrt(sum / (3 n))
 #include "fof_internal.h"
@@ -245,12 +247,20 @@ __global__ void g_assign_list(const float4 *__restrict__ sorted, const int32_t *
 }
 
 // Members of non-singleton groups only: singleton groups were finished by the assign pass.
+// With `a.group_id` set (min_size > 1: group_id filled with -1 and the moments cleared
+// beforehand), the same pass also writes each member's group id and each kept root's size
+// and root slot, which saves the separate assign pass over the list.
+struct Assign {
+    int32_t *group_id, *groot, *sizes;
+    const int32_t *cnt;
+};
+
 __global__ void g_sum(const float4 *__restrict__ sorted, const int32_t *__restrict__ list,
                       const Counters *__restrict__ ctr, const BoxDesc *__restrict__ desc,
                       int nbox, const uint64_t *__restrict__ parent,
                       const uint32_t *__restrict__ keep, const int32_t *__restrict__ keep_prefix,
                       const float *__restrict__ vel, int32_t cap, double *__restrict__ com,
-                      double *__restrict__ vmean)
+                      double *__restrict__ vmean, Assign a)
 {
     const int64_t nf = ctr->n_flagged;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -258,10 +268,19 @@ __global__ void g_sum(const float4 *__restrict__ sorted, const int32_t *__restri
         const int64_t k = base + threadIdx.x;
         int32_t g = -1, i = 0;
         uint64_t r = 0;
+        float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (k < nf) {
             i = list[k];
             r = parent[i];
             g = group_of(keep, keep_prefix, uf_key(r));
+            if (a.group_id && g >= 0) {
+                p = sorted[i];
+                a.group_id[__float_as_int(p.w)] = g;
+                if (g < cap && uf_idx(r) == (uint32_t)i) {
+                    a.groot[g] = i;
+                    a.sizes[g] = a.cnt[i];
+                }
+            }
             if (g >= cap)
                 g = -1;
         }
@@ -269,7 +288,8 @@ __global__ void g_sum(const float4 *__restrict__ sorted, const int32_t *__restri
         const Run run = wave_run(in ? (int64_t)g : -1 - (int64_t)lane_id());
         double d[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
         if (in) {
-            const float4 p = sorted[i];
+            if (!a.group_id)
+                p = sorted[i];
             if (com) {
                 const BoxDesc &B = desc[find_box(desc, nbox, i)];
                 const float4 q = sorted[uf_idx(r)];
@@ -298,6 +318,24 @@ __global__ void g_sum(const float4 *__restrict__ sorted, const int32_t *__restri
                     atomicAdd(vmean + 3 * g + a, sa);
             }
         }
+    }
+}
+
+// The moment accumulators of the kept groups, cleared before the fused sum pass.
+__global__ void g_clear(const int32_t *__restrict__ n_groups, int32_t cap,
+                        double *__restrict__ com, double *__restrict__ vmean,
+                        double *__restrict__ sigv)
+{
+    const int64_t G = *n_groups < cap ? *n_groups : cap;
+    for (int64_t g = gtid(); g < G; g += (int64_t)gridDim.x * blockDim.x) {
+        for (int c = 0; c < 3; ++c) {
+            if (com)
+                com[3 * g + c] = 0.0;
+            if (vmean)
+                vmean[3 * g + c] = 0.0;
+        }
+        if (sigv)
+            sigv[g] = 0.0;
     }
 }
 
@@ -506,7 +544,17 @@ hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int3
     o.sigv = sigv;
     o.vel = vel;
     o.cap = cap;
-    if (lonely_cut) {
+    // min_size > 1 with moments wanted: the assignment rides along the sum pass
+    const bool fused = lonely_cut && cap > 0 && com;
+    Assign as{nullptr, nullptr, nullptr, nullptr};
+    if (fused) {
+        e = launch_fill_i32(group_id, w.n, -1, s);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(g_clear, dim3(256), dim3(256), 0, s, n_groups, cap, com,
+                           (vel && vmean) ? vmean : nullptr, (vel && sigv) ? sigv : nullptr);
+        as = Assign{group_id, w.groot, sizes, w.cnt};
+    } else if (lonely_cut) {
         e = launch_fill_i32(group_id, w.n, -1, s);
         if (e != hipSuccess)
             return e;
@@ -521,7 +569,7 @@ hipError_t launch_groups(const Work &w, int32_t min_size, const float *vel, int3
     const unsigned gb = (unsigned)((cap + 255) / 256);
     const float *v = (vmean || sigv) ? vel : nullptr;
     hipLaunchKernelGGL(g_sum, dim3(lb), dim3(w.block), 0, s, w.sorted, w.flist, w.ctr, w.desc,
-                       w.nbox, w.parent, w.keep, w.keep_prefix, v, cap, com, vmean);
+                       w.nbox, w.parent, w.keep, w.keep_prefix, v, cap, com, vmean, as);
     hipLaunchKernelGGL(g_mean, dim3(gb), dim3(256), 0, s, w.sorted, w.desc, w.nbox, n_groups, cap,
                        w.groot, sizes, v, com, vmean);
     if (v && vmean && sigv) {
