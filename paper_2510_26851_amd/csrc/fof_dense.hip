@@ -29,6 +29,7 @@ namespace fof {
 namespace {
 
 constexpr int kDenseBlock = 256;
+constexpr int kBigBlock = 512;    // block of a big cell's components pass: 8 waves
 constexpr int kLdsCap = 2048;     // particles a dense cell may hold to be sorted in LDS
 constexpr int kHookBuf = 64;      // LDS buffer of a worker's deferred sparse-dense hooks
 constexpr int kPairCell = 64;     // dense cells up to this size are joined by all their pairs
@@ -416,6 +417,14 @@ struct Grp<kWave> {
 
 template <>
 struct Grp<kDenseBlock> {
+    static constexpr int per_block = 1;
+    static __device__ int tid() { return threadIdx.x; }
+    static __device__ int slot() { return 0; }
+    static __device__ void sync() { __syncthreads(); }
+};
+
+template <>
+struct Grp<kBigBlock> {
     static constexpr int per_block = 1;
     static __device__ int tid() { return threadIdx.x; }
     static __device__ int slot() { return 0; }
@@ -1296,9 +1305,11 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_small(Work w)
 #endif
 }
 
-// Big cells: one block per cell, over the list of big dense ids.
-template <int kMode>
-__global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
+// Big cells: one block per cell, over the list of big dense ids (BLOCK threads: 512 for the
+// components pass, whose loops over units and members gain from twice the waves per CU;
+// the pair passes run slower that way beside the tiled kernel, so they keep 256).
+template <int kMode, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_dense_big(Work w)
 {
     if (kMode == 3 && !w.ctr->dense_edge_over)
         return;
@@ -1315,18 +1326,18 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_big(Work w)
         const int64_t c = w.dense_list[d];
         if (w.cell_start[c + 1] - w.cell_start[c] <= kLdsCap) {
             if (kMode == 1)
-                cross_cell<kDenseBlock, true>(w, d, L);
+                cross_cell<BLOCK, true>(w, d, L);
             else if (kMode >= 2)
-                sparse_cell<kDenseBlock, true, kMode == 2>(w, d, L);
+                sparse_cell<BLOCK, true, kMode == 2>(w, d, L);
             else
-                cc_cell<kDenseBlock, true>(w, d, L);
+                cc_cell<BLOCK, true>(w, d, L);
         } else {
             if (kMode == 1)
-                cross_cell<kDenseBlock, false>(w, d, L);
+                cross_cell<BLOCK, false>(w, d, L);
             else if (kMode >= 2)
-                sparse_cell<kDenseBlock, false, kMode == 2>(w, d, L);
+                sparse_cell<BLOCK, false, kMode == 2>(w, d, L);
             else
-                cc_cell<kDenseBlock, false>(w, d, L);
+                cc_cell<BLOCK, false>(w, d, L);
         }
         if (threadIdx.x == 0)
             next = deal_next(dl, nb);
@@ -1407,13 +1418,13 @@ hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t hooks_listed)
         return e;
     const unsigned pb = persistent_blocks(w.dense_cap);
     hipLaunchKernelGGL(k_dense_small<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
-    hipLaunchKernelGGL(k_dense_big<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL((k_dense_big<0, kBigBlock>), dim3(pb), dim3(kBigBlock), 0, s, w);
     hipLaunchKernelGGL(k_dense_small<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
-    hipLaunchKernelGGL(k_dense_big<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL((k_dense_big<2, kDenseBlock>), dim3(pb), dim3(kDenseBlock), 0, s, w);
     if (hooks_listed && (e = hipEventRecord(hooks_listed, s)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_dense_small<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
-    hipLaunchKernelGGL(k_dense_big<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL((k_dense_big<1, kDenseBlock>), dim3(pb), dim3(kDenseBlock), 0, s, w);
     return hipGetLastError();
 }
 
@@ -1426,7 +1437,7 @@ hipError_t launch_dense_hooks(const Work &w, hipStream_t s)
     hipLaunchKernelGGL(k_dense_edges, dim3(1024), dim3(256), 0, s, w);
     const unsigned pb = persistent_blocks(w.dense_cap);
     hipLaunchKernelGGL(k_dense_small<3>, dim3(pb), dim3(kDenseBlock), 0, s, w);
-    hipLaunchKernelGGL(k_dense_big<3>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL((k_dense_big<3, kDenseBlock>), dim3(pb), dim3(kDenseBlock), 0, s, w);
     return hipGetLastError();
 }
 
