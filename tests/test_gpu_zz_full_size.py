@@ -60,7 +60,7 @@ def check_stream(box, ref_root, nslab=16):
                            "draw and index; set FOF_TEST_1024=1 to run it")
 def test_full_size_zeldovich_nfw_1024():
     """1024^3 particles (1.07e9, int32 indices near their limit, 2^30 cells: the
-    per-particle binning path) with 400,000 NFW clumps, in one box on one GPU."""
+    two-level bucketed binning) with 400,000 NFW clumps, in one box on one GPU."""
     check_full_size(W.make(5, progress=say), whole_box_oracle=False)
 
 
