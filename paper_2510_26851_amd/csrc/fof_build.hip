@@ -425,6 +425,7 @@ __global__ __launch_bounds__(kSortBlock) void k_bin_sort(const BoxDesc *__restri
 // bucket; the sorting buckets' bounds go to sub_off[b * nsplit + j] (and the total to
 // sub_off[nbk * nsplit]).
 constexpr int kSplitBlock = 1024;
+constexpr int kSplitBatch = 4;
 
 __global__ __launch_bounds__(kSplitBlock) void k_bin_split(const BoxDesc *__restrict__ desc,
                                                            int nbox, BinShape bs,
@@ -441,8 +442,20 @@ __global__ __launch_bounds__(kSplitBlock) void k_bin_split(const BoxDesc *__rest
     if (threadIdx.x < nsplit)
         cnt[threadIdx.x] = 0;
     __syncthreads();
-    for (int64_t k = base + threadIdx.x; k < end; k += kSplitBlock)
-        wave_lds_inc(cnt, staged_cell(desc, nbox, in[k], c0) >> bs.sshift);
+    // kSplitBatch loads in flight per thread in both sweeps
+    for (int64_t k0 = base; k0 < end; k0 += (int64_t)kSplitBatch * kSplitBlock) {
+        float4 p[kSplitBatch];
+#pragma unroll
+        for (int r = 0; r < kSplitBatch; ++r) {
+            const int64_t k = k0 + threadIdx.x + (int64_t)r * kSplitBlock;
+            if (k < end)
+                p[r] = in[k];
+        }
+#pragma unroll
+        for (int r = 0; r < kSplitBatch; ++r)
+            if (k0 + threadIdx.x + (int64_t)r * kSplitBlock < end)
+                wave_lds_inc(cnt, staged_cell(desc, nbox, p[r], c0) >> bs.sshift);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {  // counts -> starts (at most 64 of them)
         int32_t run = (int32_t)base;
@@ -456,9 +469,18 @@ __global__ __launch_bounds__(kSplitBlock) void k_bin_split(const BoxDesc *__rest
             sub_off[bs.nbk * nsplit] = run;
     }
     __syncthreads();
-    for (int64_t k = base + threadIdx.x; k < end; k += kSplitBlock) {
-        const float4 p = in[k];
-        out[wave_lds_inc(cnt, staged_cell(desc, nbox, p, c0) >> bs.sshift)] = p;
+    for (int64_t k0 = base; k0 < end; k0 += (int64_t)kSplitBatch * kSplitBlock) {
+        float4 p[kSplitBatch];
+#pragma unroll
+        for (int r = 0; r < kSplitBatch; ++r) {
+            const int64_t k = k0 + threadIdx.x + (int64_t)r * kSplitBlock;
+            if (k < end)
+                p[r] = in[k];
+        }
+#pragma unroll
+        for (int r = 0; r < kSplitBatch; ++r)
+            if (k0 + threadIdx.x + (int64_t)r * kSplitBlock < end)
+                out[wave_lds_inc(cnt, staged_cell(desc, nbox, p[r], c0) >> bs.sshift)] = p[r];
     }
 }
 
