@@ -180,9 +180,21 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
             const double rx = 1.0 / inx, rv = 1.0 / inv;
             const double lo = bb * (1.0 - 1e-12), hi = bb * (1.0 + 1e-12);
             const int mi = (int)m;
-            for (int i0 = 0; i0 < mi; i0 += kSubBlock) {
-                const int i = i0 + (int)threadIdx.x;
-                const int wave_lo = i0 + (int)(threadIdx.x & ~(kWave - 1));
+            // The pair triangle in 64 x 64 tiles (I <= J), dealt round-robin to the waves, so
+            // that every wave tests about as many pairs (a wave per row of members would leave
+            // the first rows' waves with all the work).  Lane = member i of tile row I.
+            const int nt = (mi + kWave - 1) / kWave;
+            const int ntp = nt * (nt + 1) / 2;
+            const int lane = lane_id();
+            for (int tp = (int)threadIdx.x / kWave; tp < ntp; tp += kSubBlock / kWave) {
+                int I = 0, rem = tp;  // row-major over I: row I holds tiles J = I .. nt - 1
+                while (rem >= nt - I) {
+                    rem -= nt - I;
+                    ++I;
+                }
+                const int J = I + rem;
+                const int i = I * kWave + lane;
+                const int jhi = min(J * kWave + kWave, mi);
                 float mine[6];
                 for (int a = 0; a < 6; ++a)
                     mine[a] = i < mi ? hx[a][i] : 0.f;
@@ -192,14 +204,14 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
                 // per wave, and a lane hooks only when its own root differs from it.
                 // kSubJ values of j per step: their reads and tests are issued before any
                 // hook, so the LDS latency of one overlaps the arithmetic of the others.
-                for (int j0 = wave_lo + 1; j0 < mi; j0 += kSubJ) {
+                for (int j0 = J * kWave; j0 < jhi; j0 += kSubJ) {
                     bool f[kSubJ];
 #pragma unroll
                     for (int u = 0; u < kSubJ; ++u) {
-                        const int j = min(j0 + u, mi - 1);
+                        const int j = min(j0 + u, jhi - 1);
                         const float other[6] = {hx[0][j], hx[1][j], hx[2][j],
                                                 hx[3][j], hx[4][j], hx[5][j]};
-                        f[u] = j0 + u < mi && j0 + u > i && i < mi &&
+                        f[u] = j0 + u < jhi && j0 + u > i && i < mi &&
                                phase_friends_fast(B, mine, other, inx, inv, rx, rv, bb, lo, hi);
                     }
 #pragma unroll
