@@ -3,10 +3,12 @@
 //   d^2 = |mi(x_i - x_j)|^2 / norm_x[g] + |v_i - v_j|^2 / norm_v[g] < b6^2.
 // Hosts are small next to the box (tens to thousands of members), so every pair of a host is
 // tested, one block per host.  A host of up to kSubLds members is held whole in LDS with its
-// union-find; a larger one streams its members a block at a time through LDS (positions and
-// velocities) against each thread's own member held in registers, with hooks into the packed
-// lock-free union-find over the host's member slots in HBM.  The label is the smallest original
-// index of the phase-space component (the union-find's root key).
+// union-find, its pair triangle cut into 64 x 64 tiles spread over the block's waves; a larger
+// one streams its members a block at a time through LDS (positions and velocities) against
+// each thread's own member held in registers, with hooks into the packed lock-free union-find
+// over the host's member slots in HBM.  Every pair is first put to a float prefilter that
+// settles all but near-ties and pairs near a wrap, which the FP64 test decides.  The label is
+// the smallest original index of the phase-space component (the union-find's root key).
 #include <algorithm>
 
 #include "fof_internal.h"
@@ -96,6 +98,58 @@ __device__ __forceinline__ bool phase_friends_fast(const BoxDesc &B, const float
     return sx / inx + sv / inv < bb;
 }
 
+// Float prefilter of the same decision, for the pairs it can settle.  With u = 2^-24: each
+// float difference is within u of the exact one (relative), its square within 3u, each sum
+// of three squares within 5u (all terms non-negative), the factors rx, rv (1/norm rounded
+// to double, then to float) within u + 2^-53, so sx*rx + sv*rv is within about 9u of the
+// exact value E of the metric; FP64 evaluates E within a few 2^-53.  The thresholds
+// b6^2 (1 -+ 2^-16), rounded to float, are 256u away from b6^2: a value below the lower one
+// means E < b6^2, above the upper one E > b6^2.  A pair closer than nowrap (just under half
+// the box) to a wrap on some axis, a NaN, or a host whose factors 1/norm or b6^2 lie
+// outside [1e-15, 1e15] (q.on false; a factor may also be 0) is left to the FP64 test.  In
+// that range a term near the thresholds is a normal float, and a square that underflows
+// adds far less than the margin.
+struct SubPre {
+    float rx, rv, lo, hi, nowrap[3];
+    bool on;
+};
+
+__device__ __forceinline__ SubPre sub_prefilter(const BoxDesc &B, double inx, double inv,
+                                                double bb)
+{
+    SubPre q;
+    q.rx = (float)(1.0 / inx);
+    q.rv = (float)(1.0 / inv);
+    q.lo = (float)(bb * (1.0 - 0x1p-16));
+    q.hi = (float)(bb * (1.0 + 0x1p-16));
+    for (int a = 0; a < 3; ++a)
+        q.nowrap[a] = (float)(B.halfL[a] * (1.0 - 0x1p-20));
+    const auto in_range = [](float f) { return f == 0.0f || (f >= 1e-15f && f <= 1e15f); };
+    q.on = bb >= 1e-15 && bb <= 1e15 && in_range(q.rx) && in_range(q.rv);
+    return q;
+}
+
+// +1: friends, 0: not friends, -1: left to the FP64 test.
+__device__ __forceinline__ int phase_prefilter(const SubPre &q, const float (&xi)[6],
+                                               const float (&xj)[6])
+{
+#pragma clang fp contract(off)
+    float d[6];
+    bool near_wrap = false;
+    for (int a = 0; a < 3; ++a) {
+        d[a] = xi[a] - xj[a];
+        near_wrap |= !(fabsf(d[a]) < q.nowrap[a]);
+    }
+    for (int a = 3; a < 6; ++a)
+        d[a] = xi[a] - xj[a];
+    const float sx = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    const float sv = (d[3] * d[3] + d[4] * d[4]) + d[5] * d[5];
+    const float e = sx * q.rx + sv * q.rv;
+    if (near_wrap)
+        return -1;
+    return e < q.lo ? 1 : (e > q.hi ? 0 : -1);
+}
+
 // Union-find over local member slots in LDS: larger root hooked under the smaller, path
 // halving rewrites only non-root entries.
 __device__ __forceinline__ int lds_ld(const int *p)
@@ -179,6 +233,7 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
         if (metric_ok) {
             const double rx = 1.0 / inx, rv = 1.0 / inv;
             const double lo = bb * (1.0 - 1e-12), hi = bb * (1.0 + 1e-12);
+            const SubPre pre = sub_prefilter(B, inx, inv, bb);
             const int mi = (int)m;
             // The pair triangle in 64 x 64 tiles (I <= J), dealt round-robin to the waves, so
             // that every wave tests about as many pairs (a wave per row of members would leave
@@ -211,8 +266,11 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
                         const int j = min(j0 + u, jhi - 1);
                         const float other[6] = {hx[0][j], hx[1][j], hx[2][j],
                                                 hx[3][j], hx[4][j], hx[5][j]};
+                        const int pf = pre.on ? phase_prefilter(pre, mine, other) : -1;
                         f[u] = j0 + u < jhi && j0 + u > i && i < mi &&
-                               phase_friends_fast(B, mine, other, inx, inv, rx, rv, bb, lo, hi);
+                               (pf == 1 ||
+                                (pf < 0 && phase_friends_fast(B, mine, other, inx, inv, rx, rv,
+                                                              bb, lo, hi)));
                     }
 #pragma unroll
                     for (int u = 0; u < kSubJ; ++u) {
@@ -240,6 +298,7 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
         return;
     }
     float (*tile)[kSubLds] = hx;
+    const SubPre pre = sub_prefilter(B, inx, inv, bb);
     for (int64_t i0 = 0; i0 < m; i0 += kSubBlock) {
         const int64_t i = i0 + threadIdx.x;
         float mine[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -262,7 +321,8 @@ __global__ __launch_bounds__(kSubBlock) void k_sub_link(
                         continue;
                     const float other[6] = {tile[0][t], tile[1][t], tile[2][t],
                                             tile[3][t], tile[4][t], tile[5][t]};
-                    if (phase_friends(B, mine, other, inx, inv, bb))
+                    const int pf = pre.on ? phase_prefilter(pre, mine, other) : -1;
+                    if (pf == 1 || (pf < 0 && phase_friends(B, mine, other, inx, inv, bb)))
                         uf_union(P, (uint32_t)(base + i), (uint32_t)(base + j0 + t));
                 }
             }
