@@ -117,16 +117,18 @@ typedef struct fof_sample {
 #define FOF_PROB_QUADRATIC 1
 
 /* Scratch of the sampled labelling: a vertex map over all particles, the sorted ends of
- * every edge, and per sample a union-find, member counts and group numbering over the
+ * every edge, per sample a union-find, member counts and group numbering over the
  * particles that touch a candidate edge (at most vcap = min(n, 2 edge_cap) of them, so the
- * scratch and the per-sample passes scale with the edge capacity the caller chooses). */
+ * scratch and the per-sample passes scale with the edge capacity the caller chooses), and
+ * the score gradient's fixed-point sums over those particles. */
 #define FOF_SAMPLE_VCAP(n, edge_cap)                                                          \
     (2 * (size_t)(edge_cap) < (size_t)(n) ? 2 * (size_t)(edge_cap) : (size_t)(n))
 #define FOF_SAMPLE_SCRATCH_BYTES(n, K, edge_cap)                                              \
     (8192 + 8 * ((size_t)(n) + 1) + 4 * ((size_t)(n) / 2048 + 2) + 8 * (size_t)(edge_cap) +   \
      8 * (size_t)(K) + 8 * FOF_SAMPLE_VCAP(n, edge_cap) +                                     \
      12 * (size_t)(K) * FOF_SAMPLE_VCAP(n, edge_cap) +                                        \
-     4 * ((size_t)(K) * FOF_SAMPLE_VCAP(n, edge_cap) / 2048 + 3))
+     4 * ((size_t)(K) * FOF_SAMPLE_VCAP(n, edge_cap) / 2048 + 3) +                            \
+     24 * FOF_SAMPLE_VCAP(n, edge_cap) + 8)
 
 /* Host-side plan of one batch: filled by fof_workspace_bytes, then passed unchanged to the
  * other calls.  Plain data; the byte offsets locate the regions of the caller's workspace. */
@@ -225,7 +227,11 @@ int fof_groups(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes,
  *   0 for an edge with d_e = 0, where the direction is undefined) or -2 alpha (x_i - x_j)/b^2
  *   (FOF_PROB_QUADRATIC), x_i - x_j the minimum image,
  * beta_s per `baseline` (FOF_BASELINE_*); the frozen-mode arguments are ignored and grad_vel
- * is not written.  grad_pos and grad_vel (dev float32 [n][3]) may be NULL to skip them. */
+ * is not written.  The sums over edges are taken in 64-bit fixed point (a unit of about
+ * 2^-40 of the largest possible term, max_s |loss_s - beta_s| / tau, or times 2 alpha r / b^2
+ * with r the plan's linking length), so grad_pos is the same bit for bit from run to run
+ * whatever the order of the edges; non-finite losses give NaN for every particle on an edge.
+ * grad_pos and grad_vel (dev float32 [n][3]) may be NULL to skip them. */
 int fof_backward(const fof_grid *grid, void *ws /*dev*/, size_t ws_bytes, int32_t mode,
                  const int32_t *group_id /*dev*/, int32_t G, const int32_t *sizes /*dev*/,
                  const double *vmean /*dev*/, const double *sigv /*dev*/, const float *vel /*dev*/,

@@ -17,9 +17,10 @@
 //   k_sg_*, scan   per-sample groups over the touched particles: flatten each forest and
 //                  count members, number the kept roots in ascending order (one scan over
 //                  all samples), FP64 minimum-image sums about the root, centre and size
-//   k_score        per edge: w_e = (1/K) sum_s adv_s (y_es - p_e), scattered as
-//                  -+ w_e (x_i - x_j) c_e into the position gradient, c_e = 1/(tau d_e)
-//                  or 2 alpha / b^2
+//   k_score        per edge: w_e = (1/K) sum_s adv_s (y_es - p_e), and -+ w_e (x_i - x_j)
+//                  c_e, c_e = 1/(tau d_e) or 2 alpha / b^2, added in 64-bit fixed point to
+//                  the sums of both ends (so the result does not depend on the order)
+//   k_score_out    those sums scaled back into the float position gradient
 #include "fof_internal.h"
 #include "fof_tile.h"
 
@@ -81,6 +82,9 @@ struct SampleArgs {
     int32_t *gpre;     // [K * vcap + 1] exclusive scan of the kept roots
     int32_t *gscan;    // scan tile sums of gpre
     double *adv;       // [K] loss minus baseline
+    unsigned long long *acc;   // [3 vcap] score gradient of each touched particle, fixed point
+    unsigned long long *amax;  // [1] bits of max_s |adv[s]| (non-negative doubles order as
+                               // their bit patterns)
     int64_t vcap;
 };
 
@@ -474,7 +478,7 @@ __global__ void k_sg_final(Work w, SampleArgs a, int32_t cap, const int32_t *__r
 
 // Advantage of each sample: loss minus baseline.
 __global__ void k_advantage(const double *__restrict__ loss, int32_t K, int32_t baseline,
-                            double *__restrict__ adv)
+                            double *__restrict__ adv, unsigned long long *__restrict__ amax)
 {
     const int s = threadIdx.x + blockIdx.x * blockDim.x;
     if (s >= K)
@@ -488,9 +492,37 @@ __global__ void k_advantage(const double *__restrict__ loss, int32_t K, int32_t 
     else if (baseline == FOF_BASELINE_LOO && K > 1)
         beta = (sum - loss[s]) / (double)(K - 1);
     adv[s] = loss[s] - beta;
+    atomicMax(amax, (unsigned long long)__double_as_longlong(fabs(adv[s])));
 }
 
-__device__ void score_edge(const Work &w, const SampleArgs &a, int64_t e, float *grad)
+// Fixed-point unit of the score sums: every term f (x_i - x_j) of an edge is at most
+// max_s |adv_s| times 1/tau (distance form: |x_i - x_j| <= d) or 2 alpha r / b^2 (quadratic
+// form, r the plan's linking length, which bounds d); the unit makes that bound < 2^40, so
+// a particle's 64-bit sum holds 2^23 such terms.  Integer sums are exact and commutative:
+// the gradient does not depend on the order of the edges or of the atomics.
+struct FixedUnit {
+    int ex;     // bound < 2^ex; a term t is stored as llrint(t * 2^(40 - ex))
+    bool zero;  // every advantage is 0: no term
+    bool bad;   // a non-finite advantage
+};
+
+__device__ __forceinline__ FixedUnit fixed_unit(const Work &w, const SampleArgs &a)
+{
+    const double amax = __longlong_as_double((long long)*a.amax);
+    const double r = sqrt(w.desc[0].b2);
+    const double bound = amax * (a.form == FOF_PROB_QUADRATIC ? 2.0 * a.alpha * r / (a.b * a.b)
+                                                              : 1.0 / a.tau);
+    FixedUnit u;
+    u.bad = !isfinite(bound);
+    u.zero = !u.bad && !(bound > 0.0);
+    int ex = 0;
+    if (!u.bad && !u.zero)
+        frexp(bound, &ex);
+    u.ex = ex;
+    return u;
+}
+
+__device__ void score_edge(const Work &w, const SampleArgs &a, int64_t e, const FixedUnit &fu)
 {
     const int32_t i = a.ei[e], j = a.ej[e];
     const double p = edge_prob(a.d2[e], a);
@@ -510,20 +542,41 @@ __device__ void score_edge(const Work &w, const SampleArgs &a, int64_t e, float 
     const double d2e = a.d2[e];
     const double f = a.form == FOF_PROB_QUADRATIC ? wgt * (2.0 * a.alpha / (a.b * a.b))
                      : (d2e > 0.0 ? wgt / (a.tau * sqrt(d2e)) : 0.0);
-    atomicAdd(grad + 3 * (int64_t)i + 0, (float)(-f * dx));
-    atomicAdd(grad + 3 * (int64_t)i + 1, (float)(-f * dy));
-    atomicAdd(grad + 3 * (int64_t)i + 2, (float)(-f * dz));
-    atomicAdd(grad + 3 * (int64_t)j + 0, (float)(f * dx));
-    atomicAdd(grad + 3 * (int64_t)j + 1, (float)(f * dy));
-    atomicAdd(grad + 3 * (int64_t)j + 2, (float)(f * dz));
+    const double d[3] = {dx, dy, dz};
+    unsigned long long *gi = a.acc + 3 * (int64_t)a.vmap[i];
+    unsigned long long *gj = a.acc + 3 * (int64_t)a.vmap[j];
+    for (int c = 0; c < 3; ++c) {
+        const long long q = llrint(ldexp(f * d[c], 40 - fu.ex));
+        atomicAdd(gi + c, (unsigned long long)(-q));
+        atomicAdd(gj + c, (unsigned long long)q);
+    }
 }
 
-
-__global__ void k_score(Work w, SampleArgs a, float *__restrict__ grad)
+__global__ void k_score(Work w, SampleArgs a)
 {
+    const FixedUnit fu = fixed_unit(w, a);
+    if (fu.zero || fu.bad)
+        return;  // no term, or NaN written by k_score_out
     const int64_t m = edge_count(a), stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = gtid(); e < m; e += stride)
-        score_edge(w, a, e, grad);
+        score_edge(w, a, e, fu);
+}
+
+// The fixed-point sums of the touched particles, scaled back (exactly, by a power of two)
+// and rounded to float; the other particles keep the zeros filled before.
+__global__ void k_score_out(int64_t n, Work w, SampleArgs a, float *__restrict__ grad)
+{
+    const FixedUnit fu = fixed_unit(w, a);
+    if (fu.zero)
+        return;
+    const int64_t nv = a.vmap[n], stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = gtid(); v < nv; v += stride) {
+        const int64_t o = a.vlist[v];
+        for (int c = 0; c < 3; ++c)
+            grad[3 * o + c] = fu.bad ? __builtin_nanf("")
+                                     : (float)ldexp((double)(long long)a.acc[3 * v + c],
+                                                    fu.ex - 40);
+    }
 }
 unsigned blocks_for(int64_t n)
 {
@@ -568,6 +621,8 @@ static bool carve(const fof_sample &S, int64_t n, SampleArgs &a)
     a.gpre = (int32_t *)take(4 * ((size_t)S.K * vc + 1));
     a.gscan = (int32_t *)take(4 * (size_t)scan_scratch_elems((int64_t)S.K * (int64_t)vc));
     a.adv = (double *)take(8 * (size_t)S.K);
+    a.acc = (unsigned long long *)take(24 * vc);
+    a.amax = (unsigned long long *)take(8);
     return o <= S.scratch_bytes;
 }
 
@@ -664,13 +719,17 @@ hipError_t launch_score(const Work &w, const fof_sample &S, const double *loss, 
     fill_args(S, a);
     carve(S, w.n, a);
     hipError_t e = hipSuccess;
+    if ((e = launch_fill_u64(reinterpret_cast<uint64_t *>(a.amax), 1, 0ull, s)) != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_advantage, dim3((S.K + 255) / 256), dim3(256), 0, s, loss, S.K, baseline,
-                       a.adv);
+                       a.adv, a.amax);
     if (grad_pos) {
-        e = launch_fill_u32((uint32_t *)grad_pos, 3 * w.n, 0u, s);
-        if (e != hipSuccess)
+        if ((e = launch_fill_u32((uint32_t *)grad_pos, 3 * w.n, 0u, s)) != hipSuccess ||
+            (e = launch_fill_u64(reinterpret_cast<uint64_t *>(a.acc), 3 * (a.vcap > 0 ? a.vcap : 1), 0ull,
+                                 s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_score, dim3(edge_blocks(S.edge_cap)), dim3(kBlock), 0, s, w, a,
+        hipLaunchKernelGGL(k_score, dim3(edge_blocks(S.edge_cap)), dim3(kBlock), 0, s, w, a);
+        hipLaunchKernelGGL(k_score_out, dim3(blocks_for(a.vcap)), dim3(kBlock), 0, s, w.n, w, a,
                            grad_pos);
     }
     return hipGetLastError();

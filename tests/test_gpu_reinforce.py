@@ -239,3 +239,41 @@ def test_quadratic_form_matches_oracle(alpha, which):
     ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, None, keep,
                             losses.cpu().numpy(), "loo", c=RF.dz_factor(d, b, alpha=alpha))
     assert np.abs(g - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1e-30)
+
+
+def test_score_gradient_is_the_same_bit_for_bit():
+    """The score sums are taken in fixed point, so the gradient does not depend on the order
+    in which the edges are found or their terms are added: edges drawn again and the
+    gradient taken again give the same bits, still within the oracle's tolerance."""
+    import torch
+    from paper_2510_26851_amd.reinforce import sum_sq_sizes
+
+    pos = W.clumpy_box(20000, 20.0, 12, 31)
+    L, b, K, seed = 20.0, 0.3, 32, 4321
+    tau = W.CONFIG3_TAU_FRAC * b
+    say(f"score gradient reproducibility: n={pos.shape[0]} K={K}")
+    smp = sampler(pos, L, b, tau, K, seed)
+    grads = []
+    for _ in range(3):
+        smp.sample()
+        losses = sum_sq_sizes(smp.groups(2))
+        grads.append(smp.grad(losses, baseline="loo").clone())
+    torch.cuda.synchronize()
+    assert smp.plan.status() == 0
+    assert all(torch.equal(grads[0], g) for g in grads[1:])
+    oei, oej, od2 = RF.candidate_edges(pos, L, b + 10 * tau)
+    p = RF.edge_prob(od2, b, tau)
+    oroot, keep = RF.sample_labels(pos.shape[0], oei, oej, p, seed, K)
+    ref_losses = np.array([RF.loss_sum_sq(r, 2) for r in oroot])
+    delta, d = RF.edge_geometry(pos, L, oei, oej)
+    ref = RF.score_gradient(pos.shape[0], oei, oej, delta, d, p, tau, keep, ref_losses, "loo")
+    g = grads[0].cpu().numpy()
+    assert np.abs(g - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1e-30)
+    # untouched particles get exact zeros; a NaN loss gives NaN on every touched particle
+    touched = np.zeros(pos.shape[0], bool)
+    touched[oei] = touched[oej] = True
+    assert np.all(g[~touched] == 0.0)
+    bad = torch.tensor(ref_losses, dtype=torch.float64, device="cuda")
+    bad[3] = float("nan")
+    gn = smp.grad(bad, baseline="loo").cpu().numpy()
+    assert np.all(np.isnan(gn[touched])) and np.all(gn[~touched] == 0.0)
