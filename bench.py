@@ -154,12 +154,17 @@ def reinforce_rate(torch, dev, reps):
     pos = torch.from_numpy(box.pos).to(dev)
     smp = Sampler(pos, box.L, box.b, tau, K, W.REINFORCE_SEED)
     smp.sample()                     # fits the edge capacity (one read-back)
-    halos = smp.groups(2)
+    # group tables sized from this first draw (the most groups of any sample, plus a
+    # quarter): a caller's choice that keeps the tables and the loss over them small; an
+    # overflow in the timed draws would set the status bit checked below
+    first = smp.groups(2)
+    cap = int(first["n_groups"].max().item()) * 5 // 4 + 1024
+    halos = smp.groups(2, cap=cap)
     gp = torch.empty((box.n, 3), dtype=torch.float32, device=dev)
 
     def batched():
         smp.sample()
-        h = smp.groups(2, out=halos)
+        h = smp.groups(2, cap=halos["cap"], out=halos)
         smp.grad(sum_sq_sizes(h), out=gp)
 
     one = Sampler(pos, box.L, box.b, tau, 1, W.REINFORCE_SEED, edge_cap=smp.S.edge_cap)
@@ -199,6 +204,7 @@ def reinforce_rate(torch, dev, reps):
             "edges": int(smp.n_edges.item()), "ms_per_batch": res["batched"]["ms_per_batch"],
             "samples_per_s": res["batched"]["samples_per_s"],
             "sequential": res["sequential"], "same_losses": same,
+            "table_cap": halos["cap"],
             "timed": "batched: fof_link(sample K=64) + fof_groups(sample) + loss from the halo "
                      "tables + fof_backward(FOF_SCORE); sequential: 64 x [fof_link(sample K=1, "
                      "s_first=k) + fof_groups(sample) + loss] + one fof_backward(FOF_SCORE)"}

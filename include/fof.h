@@ -119,8 +119,9 @@ typedef struct fof_sample {
 /* Scratch of the sampled labelling: a vertex map over all particles, the sorted ends of
  * every edge, per sample a union-find, member counts and group numbering over the
  * particles that touch a candidate edge (at most vcap = min(n, 2 edge_cap) of them, so the
- * scratch and the per-sample passes scale with the edge capacity the caller chooses), and
- * the score gradient's fixed-point sums over those particles. */
+ * scratch and the per-sample passes scale with the edge capacity the caller chooses), the
+ * keep bits of every edge (K <= 64) and the score gradient's fixed-point sums over those
+ * particles. */
 #define FOF_SAMPLE_VCAP(n, edge_cap)                                                          \
     (2 * (size_t)(edge_cap) < (size_t)(n) ? 2 * (size_t)(edge_cap) : (size_t)(n))
 #define FOF_SAMPLE_SCRATCH_BYTES(n, K, edge_cap)                                              \
@@ -128,7 +129,7 @@ typedef struct fof_sample {
      8 * (size_t)(K) + 8 * FOF_SAMPLE_VCAP(n, edge_cap) +                                     \
      12 * (size_t)(K) * FOF_SAMPLE_VCAP(n, edge_cap) +                                        \
      4 * ((size_t)(K) * FOF_SAMPLE_VCAP(n, edge_cap) / 2048 + 3) +                            \
-     24 * FOF_SAMPLE_VCAP(n, edge_cap) + 8)
+     24 * FOF_SAMPLE_VCAP(n, edge_cap) + 8 + 8 * (size_t)(edge_cap))
 
 /* Host-side plan of one batch: filled by fof_workspace_bytes, then passed unchanged to the
  * other calls.  Plain data; the byte offsets locate the regions of the caller's workspace. */

@@ -36,7 +36,7 @@ def sample_scratch_bytes(n: int, K: int, edge_cap: int) -> int:
     """FOF_SAMPLE_SCRATCH_BYTES of include/fof.h."""
     vcap = min(2 * edge_cap, n)
     return (8192 + 8 * (n + 1) + 4 * (n // 2048 + 2) + 8 * edge_cap + 8 * K + 8 * vcap +
-            12 * K * vcap + 4 * (K * vcap // 2048 + 3) + 24 * vcap + 8)
+            12 * K * vcap + 4 * (K * vcap // 2048 + 3) + 24 * vcap + 8 + 8 * edge_cap)
 
 # Every symbol include/fof.h declares.
 EXPORTS = ("fof_workspace_bytes", "fof_build_grid", "fof_link", "fof_groups", "fof_backward",

@@ -82,6 +82,8 @@ struct SampleArgs {
     int32_t *gpre;     // [K * vcap + 1] exclusive scan of the kept roots
     int32_t *gscan;    // scan tile sums of gpre
     double *adv;       // [K] loss minus baseline
+    uint8_t *keep;             // [edge_cap][8] keep bits of each edge, sample s at bit s of
+                               // the 8 bytes (written when K <= 64)
     unsigned long long *acc;   // [3 vcap] score gradient of each touched particle, fixed point
     unsigned long long *amax;  // [1] bits of max_s |adv[s]| (non-negative doubles order as
                                // their bit patterns)
@@ -347,9 +349,14 @@ __global__ void k_sample_union(SampleArgs a)
         const int32_t i = a.ei[e], j = a.ej[e];
         const int32_t vi = a.vmap[i], vj = a.vmap[j];
         const double p = edge_prob(a.d2[e], a);
+        uint32_t bits = 0;
         for (int32_t s = s0; s < s1; ++s)
-            if (edge_uniform(a.seed, a.s_first + (uint32_t)s, (uint32_t)i, (uint32_t)j) < p)
+            if (edge_uniform(a.seed, a.s_first + (uint32_t)s, (uint32_t)i, (uint32_t)j) < p) {
                 funion(a.forest + (int64_t)s * a.vcap, vi, vj);
+                bits |= 1u << (s - s0);
+            }
+        if (a.K <= 64)  // the score pass reads the draws back instead of repeating them
+            a.keep[8 * e + blockIdx.y] = (uint8_t)bits;
     }
 }
 
@@ -527,9 +534,16 @@ __device__ void score_edge(const Work &w, const SampleArgs &a, int64_t e, const 
     const int32_t i = a.ei[e], j = a.ej[e];
     const double p = edge_prob(a.d2[e], a);
     double wsum = 0.0;
-    for (int32_t s = 0; s < a.K; ++s) {
-        const double u = edge_uniform(a.seed, a.s_first + (uint32_t)s, (uint32_t)i, (uint32_t)j);
-        wsum += a.adv[s] * ((u < p ? 1.0 : 0.0) - p);
+    if (a.K <= 64) {  // the keep bits the union pass recorded
+        const uint64_t y = *reinterpret_cast<const uint64_t *>(a.keep + 8 * e);
+        for (int32_t s = 0; s < a.K; ++s)
+            wsum += a.adv[s] * ((double)((y >> s) & 1ull) - p);
+    } else {
+        for (int32_t s = 0; s < a.K; ++s) {
+            const double u =
+                edge_uniform(a.seed, a.s_first + (uint32_t)s, (uint32_t)i, (uint32_t)j);
+            wsum += a.adv[s] * ((u < p ? 1.0 : 0.0) - p);
+        }
     }
     const double wgt = wsum / (double)a.K;
     const BoxDesc &B = w.desc[0];
@@ -621,6 +635,7 @@ static bool carve(const fof_sample &S, int64_t n, SampleArgs &a)
     a.gpre = (int32_t *)take(4 * ((size_t)S.K * vc + 1));
     a.gscan = (int32_t *)take(4 * (size_t)scan_scratch_elems((int64_t)S.K * (int64_t)vc));
     a.adv = (double *)take(8 * (size_t)S.K);
+    a.keep = (uint8_t *)take(8 * (size_t)(S.edge_cap > 0 ? S.edge_cap : 1));
     a.acc = (unsigned long long *)take(24 * vc);
     a.amax = (unsigned long long *)take(8);
     return o <= S.scratch_bytes;

@@ -106,31 +106,32 @@ class Plan:
         return root
 
     def groups(self, min_size, vel=None, cap=None, out=None, stream=None):
-        """Returns a dict of device tensors; n_groups stays on the device (one int32)."""
-        cap = self.n if cap is None else int(cap)
-        d = self.device
+        """Returns a dict of device tensors; n_groups stays on the device (one int32).
+        Tensors passed in `out` (a previous result) are reused; they must have the shapes of
+        this cap (by default the cap they were made for), else ValueError."""
         o = out or {}
-        gid = o.get("group_id")
-        if gid is None:
-            gid = torch.empty(self.n, dtype=torch.int32, device=d)
-        ng = o.get("n_groups")
-        if ng is None:
-            ng = torch.empty(1, dtype=torch.int32, device=d)
-        sizes = o.get("sizes")
-        if sizes is None:
-            sizes = torch.empty(max(cap, 1), dtype=torch.int32, device=d)
-        com = o.get("com")
-        if com is None:
-            com = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=d)
+        if cap is None:
+            cap = int(o["cap"]) if "cap" in o else self.n
+        cap = int(cap)
+        d = self.device
+        c1 = max(cap, 1)
+
+        def buf(name, dtype, shape):
+            t = o.get(name)
+            if t is None:
+                return torch.empty(shape, dtype=dtype, device=d)
+            _need(t, name, dtype, shape, self.ws.device)
+            return t
+
+        gid = buf("group_id", torch.int32, (self.n,))
+        ng = buf("n_groups", torch.int32, (1,))
+        sizes = buf("sizes", torch.int32, (c1,))
+        com = buf("com", torch.float64, (c1, 3))
         vm = sv = None
         if vel is not None:
             _need(vel, "vel", torch.float32, (self.n, 3), self.ws.device)
-            vm = o.get("vmean")
-            if vm is None:
-                vm = torch.empty((max(cap, 1), 3), dtype=torch.float64, device=d)
-            sv = o.get("sigv")
-            if sv is None:
-                sv = torch.empty(max(cap, 1), dtype=torch.float64, device=d)
+            vm = buf("vmean", torch.float64, (c1, 3))
+            sv = buf("sigv", torch.float64, (c1,))
         check("fof_groups",
               _lib.load().fof_groups(self._gref, _ptr(self.ws), self.ws_bytes, None,
                                      int(min_size), _ptr(vel), cap,

@@ -19,7 +19,7 @@ import torch
 
 from . import _lib
 from ._lib import check
-from .fof import Plan, _ptr, _stream
+from .fof import Plan, _need, _ptr, _stream
 
 _BASELINES = {"none": _lib.FOF_BASELINE_NONE, "mean": _lib.FOF_BASELINE_MEAN,
               "loo": _lib.FOF_BASELINE_LOO}
@@ -100,19 +100,25 @@ class Sampler:
         """Halos of every sampled graph of the last sample(): components with at least
         min_size (>= 2) members, in ascending label order.  Returns device tensors
         n_groups int32 [K], sizes int32 [K, cap], com float64 [K, cap, 3] (entries past
-        n_groups[k] are unspecified) and cap.  The default cap, vcap // 2, cannot overflow."""
-        cap = max(1, self.vcap // 2) if cap is None else int(cap)
-        d, K = self.device, self.K
+        n_groups[k] are unspecified) and cap.  The default cap, vcap // 2, cannot overflow.
+        Tensors passed in `out` (a previous result) are reused; they must have the shapes of
+        this cap (by default the cap they were made for), else ValueError."""
         o = out or {}
-        ng = o.get("n_groups")
-        if ng is None:
-            ng = torch.empty(K, dtype=torch.int32, device=d)
-        sizes = o.get("sizes")
-        if sizes is None:
-            sizes = torch.empty((K, cap), dtype=torch.int32, device=d)
-        com = o.get("com")
-        if com is None:
-            com = torch.empty((K, cap, 3), dtype=torch.float64, device=d)
+        if cap is None:
+            cap = int(o["cap"]) if "cap" in o else max(1, self.vcap // 2)
+        cap = int(cap)
+        d, K = self.device, self.K
+
+        def buf(name, dtype, shape):
+            t = o.get(name)
+            if t is None:
+                return torch.empty(shape, dtype=dtype, device=d)
+            _need(t, name, dtype, shape, d)
+            return t
+
+        ng = buf("n_groups", torch.int32, (K,))
+        sizes = buf("sizes", torch.int32, (K, cap))
+        com = buf("com", torch.float64, (K, cap, 3))
         check("fof_groups",
               _lib.load().fof_groups(self.plan._gref, _ptr(self.plan.ws), self.plan.ws_bytes,
                                      ctypes.byref(self.S), int(min_size), None, cap, None,

@@ -241,15 +241,18 @@ def test_quadratic_form_matches_oracle(alpha, which):
     assert np.abs(g - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1e-30)
 
 
-def test_score_gradient_is_the_same_bit_for_bit():
+@pytest.mark.parametrize("K", [32, 80])
+def test_score_gradient_is_the_same_bit_for_bit(K):
     """The score sums are taken in fixed point, so the gradient does not depend on the order
     in which the edges are found or their terms are added: edges drawn again and the
-    gradient taken again give the same bits, still within the oracle's tolerance."""
+    gradient taken again give the same bits, still within the oracle's tolerance.  With
+    K <= 64 the score pass reads the keep bits the union pass recorded; with more samples
+    it draws the uniforms again: both against the oracle."""
     import torch
     from paper_2510_26851_amd.reinforce import sum_sq_sizes
 
     pos = W.clumpy_box(20000, 20.0, 12, 31)
-    L, b, K, seed = 20.0, 0.3, 32, 4321
+    L, b, seed = 20.0, 0.3, 4321
     tau = W.CONFIG3_TAU_FRAC * b
     say(f"score gradient reproducibility: n={pos.shape[0]} K={K}")
     smp = sampler(pos, L, b, tau, K, seed)
@@ -277,3 +280,23 @@ def test_score_gradient_is_the_same_bit_for_bit():
     bad[3] = float("nan")
     gn = smp.grad(bad, baseline="loo").cpu().numpy()
     assert np.all(np.isnan(gn[touched])) and np.all(gn[~touched] == 0.0)
+
+
+def test_reused_tables_must_match_the_cap():
+    """Group tables passed back in `out` are reused with the cap they were made for; tables
+    of another shape are refused on the host, before any launch could write past them."""
+    import torch
+
+    pos = W.clumpy_box(3000, 8.0, 3, 6)
+    smp = sampler(pos, 8.0, 0.3, 0.015, 8, 2)
+    smp.sample()
+    small = smp.groups(2, cap=64)
+    again = smp.groups(2, out=small)           # the cap comes with the tables
+    assert again["cap"] == 64 and again["sizes"] is small["sizes"]
+    with pytest.raises(ValueError):
+        smp.groups(2, cap=128, out=small)      # tables made for 64 entries
+    bad = dict(small, com=torch.empty((8, 64, 3), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        smp.groups(2, out=bad)
+    torch.cuda.synchronize()
+    assert smp.plan.status() in (0, 8)        # an overflow of the small tables is reported
