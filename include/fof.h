@@ -83,6 +83,10 @@ typedef struct fof_tune {
     double cell_factor;      /* when cell_side is 0: the coarse side of every box is this many
                                 of its own mean particle spacings (0 = 1), so one value suits
                                 a batch of boxes of different densities                       */
+    int64_t dense_cells;     /* at most this many dense cells get clique tables (0 = as many
+                                as the threshold allows, up to 2 GiB of tables); cells beyond
+                                it take the plain path and set FOF_STATUS_DENSE_CAP, so it
+                                trades memory for time only                                   */
 } fof_tune;
 
 /* Stochastic linking (paper Sec. 3.2: every potential edge between nearby particles is a

@@ -54,7 +54,8 @@ class fof_box(ctypes.Structure):
 class fof_tune(ctypes.Structure):
     _fields_ = [("cell_side", ctypes.c_double), ("dense_threshold", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("link_edges", ctypes.c_int32), ("cell_factor", ctypes.c_double)]
+                ("link_edges", ctypes.c_int32), ("cell_factor", ctypes.c_double),
+                ("dense_cells", ctypes.c_int64)]
 
 
 class fof_sample(ctypes.Structure):

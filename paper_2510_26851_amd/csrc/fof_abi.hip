@@ -333,7 +333,8 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
     if (tune && ((tune->flags & ~FOF_TUNE_NO_TILES) != 0 || tune->link_edges < 0 ||
                  tune->block < 0 || (tune->block % kWave) != 0 ||
                  tune->block > 1024 || !(tune->cell_side >= 0.0) ||
-                 !(tune->cell_factor >= 0.0) || !isfinite(tune->cell_factor)))
+                 !(tune->cell_factor >= 0.0) || !isfinite(tune->cell_factor) ||
+                 tune->dense_cells < 0))
         return FOF_EINVAL;
     int64_t n = 0, ncell = 0, ntiles = 0, n_plain = 0;
     int32_t mmax = 1, any_dense = 0;
@@ -365,8 +366,8 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
             out[k] = d;
     }
     // Dense (clique-cell) path: cells holding more than `thr` particles.  The table count is
-    // the exact bound n / (thr + 1), limited to 2 GiB of tables; cells beyond the cap take
-    // the plain path and set FOF_STATUS_DENSE_CAP.
+    // the exact bound n / (thr + 1), limited to 2 GiB of tables and to tune->dense_cells;
+    // cells beyond the cap take the plain path and set FOF_STATUS_DENSE_CAP.
     int32_t thr = (tune && tune->dense_threshold) ? tune->dense_threshold : kDefaultDense;
     int32_t words = (mmax * mmax * mmax + 31) / 32;
     int64_t dense_cap = 0;
@@ -377,6 +378,8 @@ int fof_workspace_bytes(int32_t nbox, const int64_t *count, const fof_box *box,
         int64_t lim = ((int64_t)2 << 30) / (4 * (int64_t)table_stride(words));
         if (dense_cap > lim)
             dense_cap = lim;
+        if (tune && tune->dense_cells > 0 && dense_cap > tune->dense_cells)
+            dense_cap = tune->dense_cells;
     }
     if (thr <= 0)
         thr = -1;

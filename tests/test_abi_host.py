@@ -170,6 +170,24 @@ def test_plan_rejects_bad_tune():
     t.link_edges = -1
     rc, _, _ = plan([10], [(10.0, 0.4)], tune=t, desc=False)
     assert rc == _lib.FOF_EINVAL
+    t = _lib.fof_tune()
+    t.dense_cells = -1
+    rc, _, _ = plan([10], [(10.0, 0.4)], tune=t, desc=False)
+    assert rc == _lib.FOF_EINVAL
+
+
+def test_dense_table_cap_follows_the_tune():
+    """The clique tables are sized for n / (threshold + 1) dense cells, or for the tune's
+    dense_cells when that is smaller (the rest take the plain path on the device)."""
+    t = _lib.fof_tune()
+    rc, g0, _ = plan([40000], [(40.0, 0.4)], tune=t, desc=False)
+    assert rc == 0 and g0.dense_cap == 40000 // (g0.dense_threshold + 1) + 1
+    t.dense_cells = 7
+    rc, g1, _ = plan([40000], [(40.0, 0.4)], tune=t, desc=False)
+    assert rc == 0 and g1.dense_cap == 7 and g1.ws_bytes < g0.ws_bytes
+    t.dense_cells = 10 ** 9
+    rc, g2, _ = plan([40000], [(40.0, 0.4)], tune=t, desc=False)
+    assert rc == 0 and g2.dense_cap == g0.dense_cap
 
 
 def test_link_edge_capacity_sets_the_workspace():

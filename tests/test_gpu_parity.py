@@ -285,3 +285,21 @@ def test_two_points_and_the_box_edge():
     # the edge pairs' centres sit on the boundary (wrapped into [0, L))
     c = g["com"][2]
     assert min(c[0], L - c[0]) < 1e-5 and abs(c[1] - 5.0) < 1e-6 and abs(c[2] - 5.0) < 1e-6
+
+
+def test_dense_cells_beyond_the_table_cap_take_the_plain_path():
+    """With clique tables for only a few dense cells, the others are linked as ordinary
+    cells (tiles, z-windows, global search) and the status word says so: labels, groups
+    and centres still equal the oracle's."""
+    pos = W.clumpy_box(60000, 24.0, 14, 4242)
+    L, b = 24.0, 0.35
+    say("dense table cap: 6 tables")
+    for tune in (dict(dense_cells=6), dict(dense_cells=6, dense_threshold=16)):
+        root, g, status = run_gpu(pos, L, b, 20, tune=tune)
+        assert status == 2, status   # FOF_STATUS_DENSE_CAP
+        ref_root, _ = oracle.fof(pos, L, b)
+        np.testing.assert_array_equal(root, ref_root)
+        ref = oracle.groups(pos, ref_root, L, 20)
+        assert g["n_groups"] == ref["n_groups"]
+        np.testing.assert_array_equal(g["sizes"], ref["sizes"])
+        np.testing.assert_array_equal(g["group_id"], ref["group_id"])
