@@ -1,5 +1,6 @@
 """The whole pipeline (build + link + groups) for a batch of boxes captured in one hipGraph
-and replayed; every replay must equal the eager result (labels, group ids, sizes bit-exact).
+and replayed; the eager labels equal the oracle's box by box, and every replay must equal
+the eager result (labels, group ids, sizes bit-exact).
 The library clears its buffers with fill kernels, never hipMemsetAsync."""
 import numpy as np
 import pytest
@@ -43,6 +44,14 @@ def test_batched_pipeline_graph_replays_match_eager():
     torch.cuda.synchronize()
     ref = (root.clone(), out["group_id"].clone(), int(out["n_groups"].item()))
     refsz = out["sizes"][:ref[2]].clone()
+    # the eager batch itself against the oracle, box by box (labels are batch indices)
+    import oracle
+
+    got, off = ref[0].cpu().numpy(), 0
+    for bx in boxes:
+        r, _ = oracle.fof(bx.pos, bx.L, bx.b)
+        np.testing.assert_array_equal(got[off:off + bx.n], r + off)
+        off += bx.n
 
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
