@@ -50,3 +50,19 @@ def test_backward_and_dispersion_reject_host_tensors():
                               meta((1,), torch.int32), meta((1, 3), torch.float64),
                               meta((1,), torch.float64), meta((1,), torch.float64),
                               torch.zeros((n, 3)))
+
+
+def test_groups_refuses_reused_tables_of_another_shape():
+    """Tables passed back in `out` must match the cap (by default the cap they came with)
+    and the element types; otherwise the library would write past them."""
+    p, n = fake_plan(), 8
+    good = dict(group_id=meta((n,), torch.int32), n_groups=meta((1,), torch.int32),
+                sizes=meta((4,), torch.int32), com=meta((4, 3), torch.float64), cap=4)
+    for key, bad, msg in (("sizes", meta((3,), torch.int32), "sizes must have shape"),
+                          ("com", meta((4, 3), torch.float32), "com must be torch.float64"),
+                          ("group_id", torch.zeros(n, dtype=torch.int32), "group_id must be on"),
+                          ("n_groups", meta((2,), torch.int32), "n_groups must have shape")):
+        with pytest.raises(ValueError, match=msg):
+            p.groups(20, out=dict(good, **{key: bad}))
+    with pytest.raises(ValueError, match="sizes must have shape"):
+        p.groups(20, cap=5, out=good)
