@@ -273,124 +273,235 @@ __global__ __launch_bounds__(kClassBlock) void k_classify_assign(Work w, int64_t
 // ---------------------------------------------------------------------------------------
 // Sort one dense cell by fine key and write its tables.
 // ---------------------------------------------------------------------------------------
+// LDS of one cell's sort: per-key counts and offsets, the key bitmask and its popcount
+// prefix.
+struct SortLds {
+    int kcnt[kMaxFineKeys];
+    int koff[kMaxFineKeys + 1];
+    uint32_t kbits[kMaxTableWords];
+    int kpre[kMaxTableWords];
+};
+
+// One cell of at most kSmallCell particles, by the calling wave (every particle in
+// registers, kSmallCell / kWave per lane; wave barriers only).
+__device__ void sort_small_cell(const Work &w, int d, SortLds &S)
+{
+    constexpr int kPer = kSmallCell / kWave;
+    constexpr int kKeysPerLane = (kMaxFineKeys + kWave - 1) / kWave;
+    const int lane = lane_id();
+    const int64_t c = w.dense_list[d];
+    const int32_t s = w.cell_start[c];
+    const int32_t n = w.cell_start[c + 1] - s;
+    const BoxDesc &B = uniform_box(w.desc, find_box(w.desc, w.nbox, s));
+    const CellXYZ cc = cell_xyz(B, c);
+    const int K = B.m * B.m * B.m;
+    const int W = w.table_words;
+    int32_t *T = w.table + (int64_t)d * w.table_stride;
+
+    for (int k = lane; k < K; k += kWave)
+        S.kcnt[k] = 0;
+    for (int k = lane; k < kMaxTableWords; k += kWave)
+        S.kbits[k] = 0u;
+    wave_sync();
+    // keys and per-key ranks
+    float4 preg[kPer];
+    int kreg[kPer], rreg[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int t = lane + j * kWave;
+        if (t < n) {
+            preg[j] = w.sorted[s + t];
+            kreg[j] = fine_key(B, cc, preg[j]);
+            rreg[j] = atomicAdd(S.kcnt + kreg[j], 1);
+        }
+    }
+    wave_sync();
+    // exclusive scan over keys: lane l owns keys [l * per, (l + 1) * per)
+    const int per = (K + kWave - 1) / kWave;
+    const int k0 = lane * per;
+    int sum = 0;
+    for (int q = 0; q < per && q < kKeysPerLane; ++q)
+        sum += k0 + q < K ? S.kcnt[k0 + q] : 0;
+    int run = wave_incl_sum(sum) - sum;
+    for (int q = 0; q < per && q < kKeysPerLane; ++q) {
+        const int k = k0 + q;
+        if (k < K) {
+            const int v = S.kcnt[k];
+            S.koff[k] = run;
+            if (v > 0)
+                atomicOr(S.kbits + (k >> 5), 1u << (k & 31));
+            run += v;
+        }
+    }
+    if (lane == 0)
+        S.koff[K] = n;
+    wave_sync();
+    // popcount prefix of the bitmask words (W <= kWave)
+    const int pc = lane < W ? __popc(S.kbits[lane]) : 0;
+    const int pre = wave_incl_sum(pc) - pc;
+    if (lane < W)
+        S.kpre[lane] = pre;
+    wave_sync();
+    // place the particles in key order (all of them are in registers)
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int t = lane + j * kWave;
+        if (t < n)
+            w.sorted[s + S.koff[kreg[j]] + rreg[j]] = preg[j];
+    }
+    // tables: header, bitmask, popcount prefix, unit starts (absolute sorted index)
+    if (lane == 0) {
+        T[0] = (int32_t)c;
+        T[1] = 0;
+        T[2] = S.kpre[W - 1] + __popc(S.kbits[W - 1]);
+        T[3] = 0;
+    }
+    for (int q = lane; q < W; q += kWave) {
+        T[kTableHeader + q] = (int32_t)S.kbits[q];
+        T[kTableHeader + W + q] = S.kpre[q];
+    }
+    for (int k = lane; k < K; k += kWave) {
+        if ((S.kbits[k >> 5] >> (k & 31)) & 1u) {
+            const int r = S.kpre[k >> 5] + __popc(S.kbits[k >> 5] & ((1u << (k & 31)) - 1u));
+            w.rank[s + r] = s + S.koff[k];
+        }
+    }
+    wave_sync();  // the LDS of this cell is read before the next cell overwrites it
+}
+
+// One cell of more than kSmallCell particles, by the whole block (those of at most kLdsCap
+// held in registers, larger ones sorted through the staging buffer).
+__device__ void sort_big_cell(const Work &w, int d, SortLds &S, int *scr)
+{
+    int *kcnt = S.kcnt, *koff = S.koff, *kpre = S.kpre;
+    uint32_t *kbits = S.kbits;
+    constexpr int kPer = kLdsCap / kDenseBlock;
+    const int64_t c = w.dense_list[d];
+    const int32_t s = w.cell_start[c];
+    const int32_t n = w.cell_start[c + 1] - s;
+    const BoxDesc &B = uniform_box(w.desc, find_box(w.desc, w.nbox, s));
+    const CellXYZ cc = cell_xyz(B, c);
+    const int K = B.m * B.m * B.m;
+    const int W = w.table_words;
+    int32_t *T = w.table + (int64_t)d * w.table_stride;
+    const bool lds = n <= kLdsCap;
+
+    for (int k = threadIdx.x; k < K; k += kDenseBlock)
+        kcnt[k] = 0;
+    for (int k = threadIdx.x; k < kMaxTableWords; k += kDenseBlock)
+        kbits[k] = 0u;
+    __syncthreads();
+
+    // keys and per-key ranks
+    float4 preg[kPer];
+    int kreg[kPer], rreg[kPer];
+    if (lds) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int t = threadIdx.x + j * kDenseBlock;
+            if (t < n) {
+                preg[j] = w.sorted[s + t];
+                kreg[j] = fine_key(B, cc, preg[j]);
+                rreg[j] = atomicAdd(kcnt + kreg[j], 1);
+            }
+        }
+    } else {
+        for (int t = threadIdx.x; t < n; t += kDenseBlock)
+            atomicAdd(kcnt + fine_key(B, cc, w.sorted[s + t]), 1);
+    }
+    __syncthreads();
+
+    // exclusive scan over keys (each thread owns 4 consecutive keys: K <= 1024)
+    int loc[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = threadIdx.x * 4 + q;
+        loc[q] = k < K ? kcnt[k] : 0;
+        sum += loc[q];
+    }
+    int tot;
+    int run = block_scan(sum, &tot, scr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = threadIdx.x * 4 + q;
+        if (k < K) {
+            koff[k] = run;
+            if (loc[q] > 0)
+                atomicOr(kbits + (k >> 5), 1u << (k & 31));
+        }
+        run += loc[q];
+    }
+    if (threadIdx.x == 0)
+        koff[K] = n;
+    __syncthreads();
+    if ((int)threadIdx.x < W) {
+        int pre = 0;
+        for (int q = 0; q < (int)threadIdx.x; ++q)
+            pre += __popc(kbits[q]);
+        kpre[threadIdx.x] = pre;
+    }
+    __syncthreads();
+
+    // place the particles in key order
+    if (lds) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int t = threadIdx.x + j * kDenseBlock;
+            if (t < n)
+                w.sorted[s + koff[kreg[j]] + rreg[j]] = preg[j];
+        }
+    } else {
+        for (int k = threadIdx.x; k < K; k += kDenseBlock)
+            kcnt[k] = 0;  // reused as per-key cursors
+        __syncthreads();
+        for (int t = threadIdx.x; t < n; t += kDenseBlock) {
+            const float4 p = w.sorted[s + t];
+            const int k = fine_key(B, cc, p);
+            w.temp[s + koff[k] + atomicAdd(kcnt + k, 1)] = p;
+        }
+        __threadfence();
+        __syncthreads();
+        for (int t = threadIdx.x; t < n; t += kDenseBlock)
+            w.sorted[s + t] = w.temp[s + t];
+    }
+
+    // tables: header, bitmask, popcount prefix, unit starts (absolute sorted index)
+    if (threadIdx.x == 0) {
+        T[0] = (int32_t)c;
+        T[1] = 0;
+        T[2] = kpre[W - 1] + __popc(kbits[W - 1]);
+        T[3] = 0;
+    }
+    for (int q = threadIdx.x; q < W; q += kDenseBlock) {
+        T[kTableHeader + q] = (int32_t)kbits[q];
+        T[kTableHeader + W + q] = kpre[q];
+    }
+    for (int k = threadIdx.x; k < K; k += kDenseBlock) {
+        if ((kbits[k >> 5] >> (k & 31)) & 1u) {
+            const int r = kpre[k >> 5] + __popc(kbits[k >> 5] & ((1u << (k & 31)) - 1u));
+            w.rank[s + r] = s + koff[k];
+        }
+    }
+    __syncthreads();
+}
+
+// Dense-cell sort: the big cells first, one block each (few, long), then the cells of at
+// most kSmallCell particles one wave each (many, short: they even out the blocks' ends).
 __global__ __launch_bounds__(kDenseBlock) void k_dense_sort(Work w)
 {
-    __shared__ int kcnt[kMaxFineKeys];
-    __shared__ int koff[kMaxFineKeys + 1];
-    __shared__ uint32_t kbits[kMaxTableWords];
-    __shared__ int kpre[kMaxTableWords];
+    __shared__ SortLds lds[kDenseBlock / kWave];
     __shared__ int scr[kDenseBlock / kWave];
-    constexpr int kPer = kLdsCap / kDenseBlock;
-
+    const int nb = __hip_atomic_load(&w.ctr->n_big, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int kb = blockIdx.x; kb < nb; kb += gridDim.x)
+        sort_big_cell(w, w.big_list[kb], lds[0], scr);
+    __syncthreads();
     const int nd = dense_count(w.ctr, w.dense_cap);
-    for (int d = blockIdx.x; d < nd; d += gridDim.x) {
+    const int nw = gridDim.x * (kDenseBlock / kWave);
+    SortLds &S = lds[threadIdx.x / kWave];
+    for (int d = blockIdx.x * (kDenseBlock / kWave) + (int)threadIdx.x / kWave; d < nd; d += nw) {
         const int64_t c = w.dense_list[d];
-        const int32_t s = w.cell_start[c];
-        const int32_t n = w.cell_start[c + 1] - s;
-        const BoxDesc &B = uniform_box(w.desc, find_box(w.desc, w.nbox, s));
-        const CellXYZ cc = cell_xyz(B, c);
-        const int K = B.m * B.m * B.m;
-        const int W = w.table_words;
-        int32_t *T = w.table + (int64_t)d * w.table_stride;
-        const bool lds = n <= kLdsCap;
-
-        for (int k = threadIdx.x; k < K; k += kDenseBlock)
-            kcnt[k] = 0;
-        for (int k = threadIdx.x; k < kMaxTableWords; k += kDenseBlock)
-            kbits[k] = 0u;
-        __syncthreads();
-
-        // keys and per-key ranks
-        float4 preg[kPer];
-        int kreg[kPer], rreg[kPer];
-        if (lds) {
-#pragma unroll
-            for (int j = 0; j < kPer; ++j) {
-                const int t = threadIdx.x + j * kDenseBlock;
-                if (t < n) {
-                    preg[j] = w.sorted[s + t];
-                    kreg[j] = fine_key(B, cc, preg[j]);
-                    rreg[j] = atomicAdd(kcnt + kreg[j], 1);
-                }
-            }
-        } else {
-            for (int t = threadIdx.x; t < n; t += kDenseBlock)
-                atomicAdd(kcnt + fine_key(B, cc, w.sorted[s + t]), 1);
-        }
-        __syncthreads();
-
-        // exclusive scan over keys (each thread owns 4 consecutive keys: K <= 1024)
-        int loc[4], sum = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = threadIdx.x * 4 + q;
-            loc[q] = k < K ? kcnt[k] : 0;
-            sum += loc[q];
-        }
-        int tot;
-        int run = block_scan(sum, &tot, scr);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = threadIdx.x * 4 + q;
-            if (k < K) {
-                koff[k] = run;
-                if (loc[q] > 0)
-                    atomicOr(kbits + (k >> 5), 1u << (k & 31));
-            }
-            run += loc[q];
-        }
-        if (threadIdx.x == 0)
-            koff[K] = n;
-        __syncthreads();
-        if ((int)threadIdx.x < W) {
-            int pre = 0;
-            for (int q = 0; q < (int)threadIdx.x; ++q)
-                pre += __popc(kbits[q]);
-            kpre[threadIdx.x] = pre;
-        }
-        __syncthreads();
-
-        // place the particles in key order
-        if (lds) {
-#pragma unroll
-            for (int j = 0; j < kPer; ++j) {
-                const int t = threadIdx.x + j * kDenseBlock;
-                if (t < n)
-                    w.sorted[s + koff[kreg[j]] + rreg[j]] = preg[j];
-            }
-        } else {
-            for (int k = threadIdx.x; k < K; k += kDenseBlock)
-                kcnt[k] = 0;  // reused as per-key cursors
-            __syncthreads();
-            for (int t = threadIdx.x; t < n; t += kDenseBlock) {
-                const float4 p = w.sorted[s + t];
-                const int k = fine_key(B, cc, p);
-                w.temp[s + koff[k] + atomicAdd(kcnt + k, 1)] = p;
-            }
-            __threadfence();
-            __syncthreads();
-            for (int t = threadIdx.x; t < n; t += kDenseBlock)
-                w.sorted[s + t] = w.temp[s + t];
-        }
-
-        // tables: header, bitmask, popcount prefix, unit starts (absolute sorted index)
-        if (threadIdx.x == 0) {
-            T[0] = (int32_t)c;
-            T[1] = 0;
-            T[2] = kpre[W - 1] + __popc(kbits[W - 1]);
-            T[3] = 0;
-        }
-        for (int q = threadIdx.x; q < W; q += kDenseBlock) {
-            T[kTableHeader + q] = (int32_t)kbits[q];
-            T[kTableHeader + W + q] = kpre[q];
-        }
-        for (int k = threadIdx.x; k < K; k += kDenseBlock) {
-            if ((kbits[k >> 5] >> (k & 31)) & 1u) {
-                const int r = kpre[k >> 5] + __popc(kbits[k >> 5] & ((1u << (k & 31)) - 1u));
-                w.rank[s + r] = s + koff[k];
-            }
-        }
-        __syncthreads();
+        if (w.cell_start[c + 1] - w.cell_start[c] <= kSmallCell)  // wave-uniform
+            sort_small_cell(w, d, S);
     }
 }
 
@@ -1374,6 +1485,12 @@ unsigned persistent_blocks(int cap)
     return (unsigned)(b > kCursorGroups ? b : kCursorGroups);
 }
 
+void launch_dense_sorts(const Work &w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dense_sort, dim3(persistent_blocks(w.dense_cap)), dim3(kDenseBlock), 0, s,
+                       w);
+}
+
 }  // namespace
 
 hipError_t launch_dense_build(const Work &w, hipStream_t s, bool classified)
@@ -1381,8 +1498,7 @@ hipError_t launch_dense_build(const Work &w, hipStream_t s, bool classified)
     if (w.dense_cap <= 0 || w.dense_threshold < 0)
         return hipSuccess;
     if (classified) {  // the bucketed sort numbered the dense cells already
-        hipLaunchKernelGGL(k_dense_sort, dim3(persistent_blocks(w.dense_cap)), dim3(kDenseBlock),
-                           0, s, w);
+        launch_dense_sorts(w, s);
         return hipGetLastError();
     }
     const int64_t nchunk = (w.ncell + kClassChunk - 1) / kClassChunk;
@@ -1400,8 +1516,7 @@ hipError_t launch_dense_build(const Work &w, hipStream_t s, bool classified)
                        nbig_pre);
     hipLaunchKernelGGL(k_classify_assign, dim3(cb), dim3(kClassBlock), 0, s, w, nchunk, nd_pre,
                        nbig_pre);
-    hipLaunchKernelGGL(k_dense_sort, dim3(persistent_blocks(w.dense_cap)), dim3(kDenseBlock), 0, s,
-                       w);
+    launch_dense_sorts(w, s);
     return hipGetLastError();
 }
 
