@@ -1532,14 +1532,16 @@ hipError_t launch_dense(const Work &w, hipStream_t s, hipEvent_t hooks_listed)
     if (e != hipSuccess)
         return e;
     const unsigned pb = persistent_blocks(w.dense_cap);
-    hipLaunchKernelGGL(k_dense_small<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    // in each pass the big cells first: their few long blocks then overlap the small cells'
+    // many short ones of the next pass instead of ending the chain (about 0.07 ms at 512^3)
     hipLaunchKernelGGL((k_dense_big<0, kBigBlock>), dim3(pb), dim3(kBigBlock), 0, s, w);
-    hipLaunchKernelGGL(k_dense_small<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_small<0>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     hipLaunchKernelGGL((k_dense_big<2, kDenseBlock>), dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_small<2>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     if (hooks_listed && (e = hipEventRecord(hooks_listed, s)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_dense_small<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     hipLaunchKernelGGL((k_dense_big<1, kDenseBlock>), dim3(pb), dim3(kDenseBlock), 0, s, w);
+    hipLaunchKernelGGL(k_dense_small<1>, dim3(pb), dim3(kDenseBlock), 0, s, w);
     return hipGetLastError();
 }
 
